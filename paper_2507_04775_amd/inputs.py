@@ -1,0 +1,177 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the smoke check.
+
+This module holds no CKKS arithmetic: it chooses NTT-friendly primes (a
+parameter choice, by a fixed scan and a Miller-Rabin test), and it draws
+uniform residues, ternary secrets, rounded Gaussian errors and complex slot
+vectors from numpy's PCG64 with fixed seeds.  The GPU library and the oracle
+both consume these arrays; neither is imported here.
+
+Parameter sets (sizes from the paper's evaluation, Sec. IV, and the workloads
+this library is measured on):
+
+* ``small``    : N = 2^12, q = 1 x 60-bit + 3 x 40-bit, dnum = 2, K = 1 special prime.
+* ``small-nv`` : as ``small`` with K = 2 (the smallest K whose P exceeds the
+                 largest digit, so decryptions after key switching are meaningful).
+* ``large``    : N = 2^16, q = 1 x 60-bit + 30 x 50-bit, dnum = 3, K = 4.
+* ``large-nv`` : as ``large`` with K = 10.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+BASE_SEED = 250704775
+
+_MR_BASES = (2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37)
+
+
+def is_prime(n: int) -> bool:
+    """Deterministic Miller-Rabin for n < 3.3e24 (covers every 64-bit word)."""
+    if n < 2:
+        return False
+    for b in _MR_BASES:
+        if n % b == 0:
+            return n == b
+    d, s = n - 1, 0
+    while d % 2 == 0:
+        d //= 2
+        s += 1
+    for b in _MR_BASES:
+        x = pow(b, d, n)
+        if x in (1, n - 1):
+            continue
+        for _ in range(s - 1):
+            x = x * x % n
+            if x == n - 1:
+                break
+        else:
+            return False
+    return True
+
+
+def ntt_primes(bits: int, count: int, logn: int, skip: int = 0) -> list[int]:
+    """The primes q = 2^bits - t*2N + 1, t = 1, 2, ..., in descending order.
+
+    Every such prime is 1 mod 2N, so a primitive 2N-th root of unity exists.
+    ``skip`` drops that many primes from the front of the scan.
+    """
+    two_n = 2 << logn
+    out: list[int] = []
+    t = 1
+    while len(out) < skip + count:
+        q = (1 << bits) - t * two_n + 1
+        if q < (1 << (bits - 1)):
+            raise ValueError("ran out of %d-bit primes" % bits)
+        if is_prime(q):
+            out.append(q)
+        t += 1
+    return out[skip:]
+
+
+@dataclass
+class ParamSet:
+    name: str
+    logn: int
+    q: list[int]
+    p: list[int]
+    dnum: int
+    log_scale: int
+    sigma: float = 3.2
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def N(self) -> int:
+        return 1 << self.logn
+
+    @property
+    def L(self) -> int:
+        return len(self.q) - 1
+
+    @property
+    def K(self) -> int:
+        return len(self.p)
+
+    @property
+    def alpha(self) -> int:
+        return -(-len(self.q) // self.dnum)
+
+    def beta(self, level: int) -> int:
+        return -(-(level + 1) // self.alpha)
+
+
+def make_params(logn: int, small_bits: int, L: int, K: int, dnum: int, log_scale: int, name: str) -> ParamSet:
+    """q_0 = first 60-bit prime, p_0..p_{K-1} = the next K 60-bit primes,
+    q_1..q_L = the first L primes of ``small_bits`` bits."""
+    big = ntt_primes(60, 1 + K, logn)
+    small = ntt_primes(small_bits, L, logn)
+    return ParamSet(name=name, logn=logn, q=[big[0]] + small, p=big[1:], dnum=dnum, log_scale=log_scale)
+
+
+def params(name: str) -> ParamSet:
+    if name == "small":
+        return make_params(12, 40, 3, 1, 2, 40, name)
+    if name == "small-nv":
+        return make_params(12, 40, 3, 2, 2, 40, name)
+    if name == "large":
+        return make_params(16, 50, 30, 4, 3, 50, name)
+    if name == "large-nv":
+        return make_params(16, 50, 30, 10, 3, 50, name)
+    if name == "tiny":  # N = 2^6, for brute-force pins
+        return make_params(6, 30, 3, 2, 2, 20, name)
+    raise KeyError(name)
+
+
+def rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def uniform_residues(g: np.random.Generator, moduli, N: int) -> np.ndarray:
+    """Rows of uniform residues, row i in [0, moduli[i])."""
+    out = np.empty((len(moduli), N), dtype=np.uint64)
+    for i, m in enumerate(moduli):
+        out[i] = g.integers(0, int(m), size=N, dtype=np.uint64)
+    return out
+
+
+def random_poly(seed: int, ps: ParamSet, level: int) -> np.ndarray:
+    """A uniform eval-domain polynomial at ``level`` (rows q_0..q_level)."""
+    return uniform_residues(rng(seed), ps.q[: level + 1], ps.N)
+
+
+def random_ct(seed: int, ps: ParamSet, level: int):
+    g = rng(seed)
+    return (uniform_residues(g, ps.q[: level + 1], ps.N), uniform_residues(g, ps.q[: level + 1], ps.N))
+
+
+def random_key(seed: int, ps: ParamSet) -> np.ndarray:
+    """A uniform top-level key [dnum][2][L+1+K][N] (bit-level parity does not
+    depend on whether the key is a valid encryption)."""
+    g = rng(seed)
+    mods = list(ps.q) + list(ps.p)
+    key = np.empty((ps.dnum, 2, len(mods), ps.N), dtype=np.uint64)
+    for j in range(ps.dnum):
+        for t in range(2):
+            key[j, t] = uniform_residues(g, mods, ps.N)
+    return key
+
+
+def ternary(g: np.random.Generator, N: int) -> np.ndarray:
+    """Secret coefficients iid uniform in {-1, 0, 1}."""
+    return g.integers(-1, 2, size=N).astype(np.int64)
+
+
+def gaussian(g: np.random.Generator, N: int, sigma: float = 3.2) -> np.ndarray:
+    """Rounded Gaussian errors, truncated at 6 sigma."""
+    e = np.rint(g.normal(0.0, sigma, size=N))
+    bound = np.floor(6 * sigma)
+    return np.clip(e, -bound, bound).astype(np.int64)
+
+
+def complex_slots(g: np.random.Generator, n: int) -> np.ndarray:
+    """Slots with real and imaginary parts iid uniform on [-1, 1]."""
+    return g.uniform(-1, 1, size=n) + 1j * g.uniform(-1, 1, size=n)
+
+
+def rotation_index(seed: int, logn: int) -> int:
+    return int(rng(seed).integers(1, 1 << (logn - 1)))
