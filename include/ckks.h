@@ -1,0 +1,234 @@
+/*
+ * ckks.h - C ABI of the MI355X (gfx950) RNS-CKKS key-switching library.
+ *
+ * The operations are the server-side CKKS primitives of the FIDESlib paper
+ * (arXiv 2507.04775), Table I, and the steps of hybrid key switching they are
+ * built from (Sec. II-A; Sec. III-F.3 to III-F.6).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - N = 2^log_n.  The ciphertext basis is q_0..q_L (n_q = L+1 primes), the
+ *   special basis p_0..p_{K-1} (n_p = K primes).  Every prime is below 2^61
+ *   and congruent to 1 mod 2N.
+ * - A polynomial at level l has l+1 limbs q_0..q_l.  Limbs are u64 arrays of N
+ *   canonical residues in [0, q), stored limb-major and contiguous:
+ *   poly[i*N + k] is coefficient / evaluation k of limb i.  The evaluation
+ *   domain holds A(psi^(2 br(k) + 1)) at position k (bit-reversed order), psi
+ *   being the smallest primitive 2N-th root of unity modulo the limb's prime.
+ * - "Extended" polynomials (ModUp output, inner-product accumulators, ModDown
+ *   input) have l+1+K rows: q_0..q_l, then p_0..p_{K-1}.
+ * - Key-switching keys are top-level keys laid out [dnum][2][n_q+n_p][N]
+ *   (rows q_0..q_L, then p_0..p_{K-1}); at level l rows 0..l and the K special
+ *   rows are read.  Digit j covers q_{j alpha}..q_{min((j+1) alpha, l+1)-1}
+ *   with alpha = ceil(n_q / dnum).
+ * - Every data pointer is a device pointer owned by the caller (the library
+ *   never allocates per call).  Workspaces are caller-owned device buffers of
+ *   at least ckks_workspace_bytes() bytes.  The context owns only its
+ *   precomputed tables.
+ * - Every call is asynchronous on the given HIP stream (a hipStream_t passed as
+ *   void*; NULL is the default stream).  Arguments are validated on the host
+ *   before anything is launched; on an error nothing is written and the call
+ *   returns a negative status; ckks_last_error() gives the reason.  Device-side
+ *   faults surface as CKKS_E_DEVICE from ckks_sync().
+ * - Outputs must not overlap inputs unless a call says otherwise.
+ * - A context may be used from several host threads on distinct streams with
+ *   disjoint buffers and workspaces.
+ */
+#ifndef CKKS_H
+#define CKKS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CKKS_OK = 0,
+    CKKS_E_ARG = -1,         /* null pointer, bad size, misalignment, forbidden aliasing */
+    CKKS_E_LEVEL = -2,       /* level out of range or operands at different levels */
+    CKKS_E_KEY = -3,         /* wrong key kind or Galois element */
+    CKKS_E_NOMEM = -4,       /* table allocation failed at context creation */
+    CKKS_E_DEVICE = -5,      /* a HIP runtime call failed */
+    CKKS_E_UNSUPPORTED = -6  /* parameter shape this build does not handle */
+} ckks_status;
+
+typedef struct ckks_ctx ckks_ctx;
+typedef struct ckks_key ckks_key;
+
+/* A ciphertext: two caller-owned device polynomials at `level`. */
+typedef struct {
+    uint64_t *c0;
+    uint64_t *c1;
+    uint32_t level;
+    double scale; /* host-side metadata, carried but never read by kernels */
+} ckks_ct;
+
+/* Operation codes for ckks_workspace_bytes. */
+enum {
+    CKKS_OP_MODUP = 1,
+    CKKS_OP_MODDOWN = 2,
+    CKKS_OP_KEYSWITCH = 3,
+    CKKS_OP_HMULT = 4,
+    CKKS_OP_RESCALE = 5,
+    CKKS_OP_ROTATE = 6,
+    CKKS_OP_HOISTED = 7 /* per call, independent of the number of rotations */
+};
+
+/*
+ * Context creation (Sec. III-E: precomputation at context creation).
+ * q[0..n_q-1], p[0..n_p-1]: host arrays of the primes.  dnum: number of digits
+ * of the hybrid key-switching decomposition (1 <= dnum <= n_q).  Builds, on the
+ * host, the twiddle tables with their Shoup companions and the constants of the
+ * base conversions, ModDown and Rescale, and uploads them to `hip_device`.
+ * Supported: log_n in {12, 16}; n_q + n_p <= 64; every digit and the special
+ * basis have at most 16 primes.  *out receives the context; free it with
+ * ckks_ctx_destroy.  Synchronous.
+ */
+ckks_status ckks_ctx_create(uint32_t log_n, const uint64_t *q, uint32_t n_q, const uint64_t *p, uint32_t n_p,
+                            uint32_t dnum, int hip_device, ckks_ctx **out);
+void ckks_ctx_destroy(ckks_ctx *ctx);
+
+/* Thread-local text of the last error, never NULL. */
+const char *ckks_last_error(void);
+
+/* Waits for the stream and reports any asynchronous device error. */
+ckks_status ckks_sync(ckks_ctx *ctx, void *stream);
+
+/* Workspace bytes needed by an operation at `level` (0 for an unknown op). */
+size_t ckks_workspace_bytes(const ckks_ctx *ctx, uint32_t op, uint32_t level);
+
+/* Copies one prime's forward twiddle table psi^br(k), k < N, into host memory
+ * (for table checks); limb indexes q_0..q_L then p_0..p_{K-1}. Synchronous. */
+ckks_status ckks_get_twiddles(const ckks_ctx *ctx, uint32_t limb, uint64_t *host_out);
+
+/*
+ * Negacyclic NTT / inverse NTT in place (Sec. III-F.4): radix-2 Cooley-Tukey
+ * forward (natural coefficients to bit-reversed evaluations) and Gentleman-
+ * Sande inverse (back, scaled by N^-1).  poly holds n_limbs limbs; limb i is
+ * transformed under the prime with limb index limb0 + i (q_0..q_L are
+ * 0..n_q-1, p_0..p_{K-1} are n_q..n_q+n_p-1).
+ */
+ckks_status ckks_ntt(ckks_ctx *ctx, uint64_t *poly, uint32_t limb0, uint32_t n_limbs, void *stream);
+ckks_status ckks_intt(ckks_ctx *ctx, uint64_t *poly, uint32_t limb0, uint32_t n_limbs, void *stream);
+
+/*
+ * ModUp of hybrid key switching (Sec. II-A, III-F.3, Eq. (1)):
+ * d [l+1][N] (evaluation domain) -> ext [beta][l+1+K][N] (evaluation domain),
+ * beta = ceil((l+1)/alpha).  Row r of ext[j] is d's row r for r in digit j;
+ * every other row is NTT(Conv_{D_j -> row}(INTT(d)|D_j)) with the fast base
+ * conversion y_i = [x_i (D_j/d_i)^-1]_{d_i}, out = [sum_i y_i [D_j/d_i]]_row.
+ * ws: ckks_workspace_bytes(CKKS_OP_MODUP, l).
+ */
+ckks_status ckks_modup(ckks_ctx *ctx, const uint64_t *d, uint32_t level, uint64_t *ext, void *ws, void *stream);
+
+/*
+ * Key inner product (dot-product step of hybrid key switching, III-F.5):
+ * acc[t][r] = sum_{j<beta} phi_g(ext_j)[r] * key[j][t][row r], t = 0, 1.
+ * ext [beta][l+1+K][N], acc [2][l+1+K][N].  galois 1 is the plain product;
+ * another odd g < 2N applies the automorphism X -> X^g to the digits first
+ * (hoisted rotation, III-F.6).  The key's own Galois element is not checked.
+ */
+ckks_status ckks_inner_product(ckks_ctx *ctx, const uint64_t *ext, uint32_t level, const ckks_key *key,
+                               uint32_t galois, uint64_t *acc, void *stream);
+
+/*
+ * ModDown (III-F.3, ModDown fusion of III-F.5): x [l+1+K][N] evaluation domain
+ * -> out [l+1][N], out_i = [P^-1]_{q_i} (x_i - NTT(Conv_{P->q_i}(INTT(x|P)))).
+ * ws: ckks_workspace_bytes(CKKS_OP_MODDOWN, l).
+ */
+ckks_status ckks_moddown(ckks_ctx *ctx, const uint64_t *x, uint32_t level, uint64_t *out, void *ws, void *stream);
+
+/*
+ * Wraps a caller-owned device key [dnum][2][n_q+n_p][N] (evaluation domain).
+ * galois = 0 marks a relinearisation key (for s^2); an odd g < 2N marks the
+ * key for the automorphism X -> X^g.  Nothing is copied: the buffer must stay
+ * valid while the handle is used.  Release with ckks_key_release.
+ */
+ckks_status ckks_key_wrap(ckks_ctx *ctx, const uint64_t *dev_key, uint32_t galois, ckks_key **out);
+void ckks_key_release(ckks_key *key);
+
+/*
+ * Hybrid key switching: (out0, out1) = ModDown(InnerProduct(ModUp(d), key))
+ * for both key halves; d, out0, out1 are [l+1][N] evaluation domain.
+ * ws: ckks_workspace_bytes(CKKS_OP_KEYSWITCH, l).
+ */
+ckks_status ckks_keyswitch(ckks_ctx *ctx, const uint64_t *d, uint32_t level, const ckks_key *key, uint64_t *out0,
+                           uint64_t *out1, void *ws, void *stream);
+
+/*
+ * HMult with relinearisation (Table I): d0 = a0 b0, d1 = a0 b1 + a1 b0,
+ * d2 = a1 b1, (k0, k1) = KeySwitch(d2, rlk), out = (d0 + k0, d1 + k1).
+ * a, b at the same level (else CKKS_E_LEVEL); rlk must have galois 0
+ * (else CKKS_E_KEY).  No rescale; out->level = level, out->scale = a.scale *
+ * b.scale.  out may not alias a or b.  ws: CKKS_OP_HMULT.
+ */
+ckks_status ckks_hmult_relin(ckks_ctx *ctx, const ckks_ct *a, const ckks_ct *b, const ckks_key *rlk, ckks_ct *out,
+                             void *ws, void *stream);
+
+/*
+ * Rescale (Table I; rescale fusion of III-F.5): for each half c at level l >= 1,
+ * v = INTT_{q_l}(c_l) lifted centred into q_i, out_i =
+ * [q_l^-1]_{q_i} (c_i - NTT_{q_i}(v)), i < l.  out->level = l - 1,
+ * out->scale = in->scale / q_l.  out may be the same buffers as in (in place);
+ * any other overlap is an error.  ws: CKKS_OP_RESCALE.
+ */
+ckks_status ckks_rescale(ckks_ctx *ctx, const ckks_ct *in, ckks_ct *out, void *ws, void *stream);
+
+/*
+ * Automorphism plus key switch (HRotate and Conjugate, Table I):
+ * out = (phi_g(c0) + k0, k1) with (k0, k1) = KeySwitch(phi_g(c1), key_g).
+ * g odd, 1 < g < 2N; the key's galois must equal g (else CKKS_E_KEY).
+ * ws: CKKS_OP_ROTATE.
+ */
+ckks_status ckks_apply_galois(ckks_ctx *ctx, const ckks_ct *in, uint32_t galois, const ckks_key *key, ckks_ct *out,
+                              void *ws, void *stream);
+
+/* HRotate by k slots to the left: g = 5^k mod 2N (negative k allowed). */
+ckks_status ckks_hrotate(ckks_ctx *ctx, const ckks_ct *in, int32_t k, const ckks_key *key, ckks_ct *out, void *ws,
+                         void *stream);
+
+/* Conjugate: g = 2N - 1. */
+ckks_status ckks_conjugate(ckks_ctx *ctx, const ckks_ct *in, const ckks_key *key, ckks_ct *out, void *ws,
+                           void *stream);
+
+/*
+ * Hoisted rotations (III-F.6): one ModUp of in->c1 is shared by n rotations;
+ * for each i: acc = sum_j phi_g(ext_j) * key_i, (k0, k1) = ModDown(acc),
+ * out[i] = (phi_g(c0) + k0, k1) with g = 5^k[i] mod 2N.  keys[i] must carry
+ * that g.  ws: CKKS_OP_HOISTED (independent of n).
+ */
+ckks_status ckks_hrotate_hoisted(ckks_ctx *ctx, const ckks_ct *in, uint32_t n, const int32_t *k,
+                                 const ckks_key *const *keys, ckks_ct *out, void *ws, void *stream);
+
+/*
+ * Limb-wise support operations of Table I on evaluation-domain data; all
+ * operands at `level` (l+1 limbs), out may alias an input exactly.
+ *   ckks_poly_add/sub/mul : out = a (+,-,*) b              (HAdd, PtAdd, PtMult per polynomial)
+ *   ckks_poly_mul_add     : out = a * b + c                (PtMulAdd per polynomial)
+ *   ckks_poly_scalar_mul  : out = a * s[i] on limb i       (ScalarMult; s: host array [l+1], s[i] < q_i)
+ *   ckks_poly_scalar_add  : out = a + s[i] on limb i       (ScalarAdd on c0; s[i] < q_i)
+ */
+ckks_status ckks_poly_add(ckks_ctx *ctx, const uint64_t *a, const uint64_t *b, uint64_t *out, uint32_t level,
+                          void *stream);
+ckks_status ckks_poly_sub(ckks_ctx *ctx, const uint64_t *a, const uint64_t *b, uint64_t *out, uint32_t level,
+                          void *stream);
+ckks_status ckks_poly_mul(ckks_ctx *ctx, const uint64_t *a, const uint64_t *b, uint64_t *out, uint32_t level,
+                          void *stream);
+ckks_status ckks_poly_mul_add(ckks_ctx *ctx, const uint64_t *a, const uint64_t *b, const uint64_t *c, uint64_t *out,
+                              uint32_t level, void *stream);
+ckks_status ckks_poly_scalar_mul(ckks_ctx *ctx, const uint64_t *a, const uint64_t *s, uint64_t *out, uint32_t level,
+                                 void *stream);
+ckks_status ckks_poly_scalar_add(ckks_ctx *ctx, const uint64_t *a, const uint64_t *s, uint64_t *out, uint32_t level,
+                                 void *stream);
+
+/* Eval-domain automorphism alone: out[k] = in[br(((2 br(k)+1) g mod 2N - 1)/2)] on n_limbs limbs. */
+ckks_status ckks_automorph(ckks_ctx *ctx, const uint64_t *in, uint32_t galois, uint64_t *out, uint32_t n_limbs,
+                           void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CKKS_H */

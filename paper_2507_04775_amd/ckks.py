@@ -1,0 +1,301 @@
+"""Python binding of the gfx950 CKKS library (include/ckks.h).
+
+Argument marshalling only: every step of every operation runs in the HIP
+kernels of libckks.so.  PyTorch supplies device memory (uint64 tensors) and
+streams; nothing here computes on the data.  If the library has not been built
+the import fails: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libckks.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libckks.so is not built: run paper_2507_04775_amd/build.py (or __graft_entry__.build())")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+_vp = ctypes.c_void_p
+_u32 = ctypes.c_uint32
+_i32 = ctypes.c_int32
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+
+
+class _Ct(ctypes.Structure):
+    _fields_ = [("c0", _vp), ("c1", _vp), ("level", _u32), ("scale", ctypes.c_double)]
+
+
+OP_MODUP, OP_MODDOWN, OP_KEYSWITCH, OP_HMULT, OP_RESCALE, OP_ROTATE, OP_HOISTED = 1, 2, 3, 4, 5, 6, 7
+
+_sigs = {
+    "ckks_ctx_create": (ctypes.c_int, [_u32, _u64p, _u32, _u64p, _u32, _u32, ctypes.c_int, ctypes.POINTER(_vp)]),
+    "ckks_ctx_destroy": (None, [_vp]),
+    "ckks_last_error": (ctypes.c_char_p, []),
+    "ckks_sync": (ctypes.c_int, [_vp, _vp]),
+    "ckks_workspace_bytes": (ctypes.c_size_t, [_vp, _u32, _u32]),
+    "ckks_get_twiddles": (ctypes.c_int, [_vp, _u32, _u64p]),
+    "ckks_ntt": (ctypes.c_int, [_vp, _vp, _u32, _u32, _vp]),
+    "ckks_intt": (ctypes.c_int, [_vp, _vp, _u32, _u32, _vp]),
+    "ckks_modup": (ctypes.c_int, [_vp, _vp, _u32, _vp, _vp, _vp]),
+    "ckks_inner_product": (ctypes.c_int, [_vp, _vp, _u32, _vp, _u32, _vp, _vp]),
+    "ckks_moddown": (ctypes.c_int, [_vp, _vp, _u32, _vp, _vp, _vp]),
+    "ckks_key_wrap": (ctypes.c_int, [_vp, _vp, _u32, ctypes.POINTER(_vp)]),
+    "ckks_key_release": (None, [_vp]),
+    "ckks_keyswitch": (ctypes.c_int, [_vp, _vp, _u32, _vp, _vp, _vp, _vp, _vp]),
+    "ckks_hmult_relin": (ctypes.c_int, [_vp, ctypes.POINTER(_Ct), ctypes.POINTER(_Ct), _vp, ctypes.POINTER(_Ct), _vp, _vp]),
+    "ckks_rescale": (ctypes.c_int, [_vp, ctypes.POINTER(_Ct), ctypes.POINTER(_Ct), _vp, _vp]),
+    "ckks_apply_galois": (ctypes.c_int, [_vp, ctypes.POINTER(_Ct), _u32, _vp, ctypes.POINTER(_Ct), _vp, _vp]),
+    "ckks_hrotate": (ctypes.c_int, [_vp, ctypes.POINTER(_Ct), _i32, _vp, ctypes.POINTER(_Ct), _vp, _vp]),
+    "ckks_conjugate": (ctypes.c_int, [_vp, ctypes.POINTER(_Ct), _vp, ctypes.POINTER(_Ct), _vp, _vp]),
+    "ckks_hrotate_hoisted": (ctypes.c_int, [_vp, ctypes.POINTER(_Ct), _u32, ctypes.POINTER(_i32), ctypes.POINTER(_vp),
+                                            ctypes.POINTER(_Ct), _vp, _vp]),
+    "ckks_poly_add": (ctypes.c_int, [_vp, _vp, _vp, _vp, _u32, _vp]),
+    "ckks_poly_sub": (ctypes.c_int, [_vp, _vp, _vp, _vp, _u32, _vp]),
+    "ckks_poly_mul": (ctypes.c_int, [_vp, _vp, _vp, _vp, _u32, _vp]),
+    "ckks_poly_mul_add": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _u32, _vp]),
+    "ckks_poly_scalar_mul": (ctypes.c_int, [_vp, _vp, _u64p, _vp, _u32, _vp]),
+    "ckks_poly_scalar_add": (ctypes.c_int, [_vp, _vp, _u64p, _vp, _u32, _vp]),
+    "ckks_automorph": (ctypes.c_int, [_vp, _vp, _u32, _vp, _u32, _vp]),
+}
+for _name, (_res, _args) in _sigs.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+EXPORTED = tuple(_sigs)
+
+
+class CkksError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__("%s failed with status %d: %s" % (where, status, _lib.ckks_last_error().decode()))
+
+
+def _check(status: int, where: str):
+    if status != 0:
+        raise CkksError(status, where)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    assert t.dtype == torch.uint64 and t.is_contiguous(), "expects contiguous uint64 tensors"
+    return t.data_ptr()
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def _u64arr(xs):
+    a = (ctypes.c_uint64 * len(xs))(*[int(x) for x in xs])
+    return a
+
+
+@dataclass
+class Ciphertext:
+    """Two device polynomials [level+1][N] (uint64) at `level`."""
+    c0: torch.Tensor
+    c1: torch.Tensor
+    level: int
+    scale: float = 1.0
+
+    def _c(self) -> _Ct:
+        return _Ct(_ptr(self.c0), _ptr(self.c1), self.level, self.scale)
+
+
+class Key:
+    """Device key [dnum][2][nq+np][N] wrapped for the library (kept alive here)."""
+
+    def __init__(self, ctx: "Context", data: torch.Tensor, galois: int):
+        self.ctx = ctx
+        self.data = data
+        self.galois = galois
+        h = _vp()
+        _check(_lib.ckks_key_wrap(ctx.handle, _ptr(data), galois, ctypes.byref(h)), "ckks_key_wrap")
+        self.handle = h
+
+    def __del__(self, _release=_lib.ckks_key_release):
+        h = getattr(self, "handle", None)
+        if h:
+            _release(h)
+            self.handle = None
+
+
+class Context:
+    """A parameter set [N, q_0..q_L, p_0..p_{K-1}, dnum] with its device tables."""
+
+    def __init__(self, logn: int, q: Sequence[int], p: Sequence[int], dnum: int, device: int = 0):
+        self.logn, self.N = int(logn), 1 << int(logn)
+        self.q, self.p, self.dnum = [int(x) for x in q], [int(x) for x in p], int(dnum)
+        self.nq, self.np = len(self.q), len(self.p)
+        self.alpha = -(-self.nq // self.dnum)
+        self.device = torch.device("cuda", device)
+        h = _vp()
+        _check(_lib.ckks_ctx_create(self.logn, _u64arr(self.q), self.nq, _u64arr(self.p), self.np, self.dnum,
+                                    device, ctypes.byref(h)), "ckks_ctx_create")
+        self.handle = h
+        self._ws = {}
+
+    def close(self, _destroy=_lib.ckks_ctx_destroy):
+        if getattr(self, "handle", None):
+            _destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        self.close()
+
+    # ------------------------------------------------------------ helpers
+    def beta(self, level: int) -> int:
+        return -(-(level + 1) // self.alpha)
+
+    def workspace_bytes(self, op: int, level: int) -> int:
+        return int(_lib.ckks_workspace_bytes(self.handle, op, level))
+
+    def workspace(self, op: int, level: int) -> torch.Tensor:
+        """A cached device workspace large enough for `op` at `level`."""
+        need = (self.workspace_bytes(op, level) + 7) // 8
+        ws = self._ws.get(op)
+        if ws is None or ws.numel() < need:
+            ws = torch.empty(need, dtype=torch.uint64, device=self.device)
+            self._ws[op] = ws
+        return ws
+
+    def empty_poly(self, level: int) -> torch.Tensor:
+        return torch.empty((level + 1, self.N), dtype=torch.uint64, device=self.device)
+
+    def empty_ct(self, level: int) -> Ciphertext:
+        return Ciphertext(self.empty_poly(level), self.empty_poly(level), level)
+
+    def key(self, data: torch.Tensor, galois: int) -> Key:
+        return Key(self, data, galois)
+
+    def sync(self, stream=None):
+        _check(_lib.ckks_sync(self.handle, _stream(stream)), "ckks_sync")
+
+    def twiddles(self, limb: int):
+        import numpy as np
+        out = np.zeros(self.N, dtype=np.uint64)
+        _check(_lib.ckks_get_twiddles(self.handle, limb, out.ctypes.data_as(_u64p)), "ckks_get_twiddles")
+        return out
+
+    # ---------------------------------------------------------- the C ABI
+    def ckks_ntt(self, poly: torch.Tensor, limb0: int = 0, n_limbs: Optional[int] = None, stream=None):
+        n_limbs = poly.shape[0] if n_limbs is None else n_limbs
+        _check(_lib.ckks_ntt(self.handle, _ptr(poly), limb0, n_limbs, _stream(stream)), "ckks_ntt")
+
+    def ckks_intt(self, poly: torch.Tensor, limb0: int = 0, n_limbs: Optional[int] = None, stream=None):
+        n_limbs = poly.shape[0] if n_limbs is None else n_limbs
+        _check(_lib.ckks_intt(self.handle, _ptr(poly), limb0, n_limbs, _stream(stream)), "ckks_intt")
+
+    def ckks_modup(self, d: torch.Tensor, level: int, ext: torch.Tensor, ws=None, stream=None):
+        ws = self.workspace(OP_MODUP, level) if ws is None else ws
+        _check(_lib.ckks_modup(self.handle, _ptr(d), level, _ptr(ext), _ptr(ws), _stream(stream)), "ckks_modup")
+
+    def ckks_inner_product(self, ext: torch.Tensor, level: int, key: Key, galois: int, acc: torch.Tensor,
+                           stream=None):
+        _check(_lib.ckks_inner_product(self.handle, _ptr(ext), level, key.handle, galois, _ptr(acc),
+                                       _stream(stream)), "ckks_inner_product")
+
+    def ckks_moddown(self, x: torch.Tensor, level: int, out: torch.Tensor, ws=None, stream=None):
+        ws = self.workspace(OP_MODDOWN, level) if ws is None else ws
+        _check(_lib.ckks_moddown(self.handle, _ptr(x), level, _ptr(out), _ptr(ws), _stream(stream)), "ckks_moddown")
+
+    def ckks_keyswitch(self, d: torch.Tensor, level: int, key: Key, out0: torch.Tensor, out1: torch.Tensor, ws=None,
+                       stream=None):
+        ws = self.workspace(OP_KEYSWITCH, level) if ws is None else ws
+        _check(_lib.ckks_keyswitch(self.handle, _ptr(d), level, key.handle, _ptr(out0), _ptr(out1), _ptr(ws),
+                                   _stream(stream)), "ckks_keyswitch")
+
+    def ckks_hmult_relin(self, a: Ciphertext, b: Ciphertext, rlk: Key, out: Ciphertext, ws=None, stream=None):
+        ws = self.workspace(OP_HMULT, a.level) if ws is None else ws
+        ca, cb, co = a._c(), b._c(), out._c()
+        _check(_lib.ckks_hmult_relin(self.handle, ctypes.byref(ca), ctypes.byref(cb), rlk.handle, ctypes.byref(co),
+                                     _ptr(ws), _stream(stream)), "ckks_hmult_relin")
+        out.level, out.scale = co.level, co.scale
+
+    def ckks_rescale(self, inp: Ciphertext, out: Ciphertext, ws=None, stream=None):
+        ws = self.workspace(OP_RESCALE, inp.level) if ws is None else ws
+        ci, co = inp._c(), out._c()
+        _check(_lib.ckks_rescale(self.handle, ctypes.byref(ci), ctypes.byref(co), _ptr(ws), _stream(stream)),
+               "ckks_rescale")
+        out.level, out.scale = co.level, co.scale
+
+    def ckks_apply_galois(self, inp: Ciphertext, galois: int, key: Key, out: Ciphertext, ws=None, stream=None):
+        ws = self.workspace(OP_ROTATE, inp.level) if ws is None else ws
+        ci, co = inp._c(), out._c()
+        _check(_lib.ckks_apply_galois(self.handle, ctypes.byref(ci), galois, key.handle, ctypes.byref(co), _ptr(ws),
+                                      _stream(stream)), "ckks_apply_galois")
+        out.level, out.scale = co.level, co.scale
+
+    def ckks_hrotate(self, inp: Ciphertext, k: int, key: Key, out: Ciphertext, ws=None, stream=None):
+        ws = self.workspace(OP_ROTATE, inp.level) if ws is None else ws
+        ci, co = inp._c(), out._c()
+        _check(_lib.ckks_hrotate(self.handle, ctypes.byref(ci), k, key.handle, ctypes.byref(co), _ptr(ws),
+                                 _stream(stream)), "ckks_hrotate")
+        out.level, out.scale = co.level, co.scale
+
+    def ckks_conjugate(self, inp: Ciphertext, key: Key, out: Ciphertext, ws=None, stream=None):
+        ws = self.workspace(OP_ROTATE, inp.level) if ws is None else ws
+        ci, co = inp._c(), out._c()
+        _check(_lib.ckks_conjugate(self.handle, ctypes.byref(ci), key.handle, ctypes.byref(co), _ptr(ws),
+                                   _stream(stream)), "ckks_conjugate")
+        out.level, out.scale = co.level, co.scale
+
+    def ckks_hrotate_hoisted(self, inp: Ciphertext, ks: Sequence[int], keys: Sequence[Key],
+                             outs: Sequence[Ciphertext], ws=None, stream=None):
+        n = len(ks)
+        ws = self.workspace(OP_HOISTED, inp.level) if ws is None else ws
+        ci = inp._c()
+        karr = (_i32 * n)(*ks)
+        harr = (_vp * n)(*[k.handle for k in keys])
+        oarr = (_Ct * n)(*[o._c() for o in outs])
+        _check(_lib.ckks_hrotate_hoisted(self.handle, ctypes.byref(ci), n, karr, harr, oarr, _ptr(ws),
+                                         _stream(stream)), "ckks_hrotate_hoisted")
+        for i, o in enumerate(outs):
+            o.level, o.scale = oarr[i].level, oarr[i].scale
+
+    def ckks_poly_add(self, a, b, out, level, stream=None):
+        _check(_lib.ckks_poly_add(self.handle, _ptr(a), _ptr(b), _ptr(out), level, _stream(stream)), "ckks_poly_add")
+
+    def ckks_poly_sub(self, a, b, out, level, stream=None):
+        _check(_lib.ckks_poly_sub(self.handle, _ptr(a), _ptr(b), _ptr(out), level, _stream(stream)), "ckks_poly_sub")
+
+    def ckks_poly_mul(self, a, b, out, level, stream=None):
+        _check(_lib.ckks_poly_mul(self.handle, _ptr(a), _ptr(b), _ptr(out), level, _stream(stream)), "ckks_poly_mul")
+
+    def ckks_poly_mul_add(self, a, b, c, out, level, stream=None):
+        _check(_lib.ckks_poly_mul_add(self.handle, _ptr(a), _ptr(b), _ptr(c), _ptr(out), level, _stream(stream)),
+               "ckks_poly_mul_add")
+
+    def ckks_poly_scalar_mul(self, a, scalars, out, level, stream=None):
+        _check(_lib.ckks_poly_scalar_mul(self.handle, _ptr(a), _u64arr(scalars), _ptr(out), level, _stream(stream)),
+               "ckks_poly_scalar_mul")
+
+    def ckks_poly_scalar_add(self, a, scalars, out, level, stream=None):
+        _check(_lib.ckks_poly_scalar_add(self.handle, _ptr(a), _u64arr(scalars), _ptr(out), level, _stream(stream)),
+               "ckks_poly_scalar_add")
+
+    def ckks_automorph(self, inp, galois, out, n_limbs=None, stream=None):
+        n_limbs = inp.shape[0] if n_limbs is None else n_limbs
+        _check(_lib.ckks_automorph(self.handle, _ptr(inp), galois, _ptr(out), n_limbs, _stream(stream)),
+               "ckks_automorph")
+
+
+def to_device(a, device="cuda") -> torch.Tensor:
+    """numpy uint64 -> contiguous device tensor (plain copy)."""
+    import numpy as np
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint64)).to(device)
+
+
+def to_host(t: torch.Tensor):
+    return t.cpu().numpy()

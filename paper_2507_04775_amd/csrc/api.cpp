@@ -1,0 +1,695 @@
+// C-ABI entry points: host-side validation, then the launch sequence of each
+// operation on the caller's stream.  The composition of key switching follows
+// hybrid key switching (paper Sec. II-A, III-F.3): INTT -> ModUp base
+// conversion -> NTT -> key inner product -> INTT of the special rows ->
+// ModDown base conversion -> NTT with the fused P^-1 (x - .) epilogue
+// (III-F.5), into which the HMult / rotation additions are folded as well.
+#include <string.h>
+
+#include <string>
+
+#include "internal.h"
+
+namespace ckks {
+ckks_status fail(ckks_status s, const std::string &msg);
+}
+
+using namespace ckks;
+
+namespace {
+
+hipStream_t S(void *stream) { return (hipStream_t)stream; }
+
+ckks_status dev(hipError_t e, const char *what)
+{
+    if (e == hipSuccess) return CKKS_OK;
+    return fail(CKKS_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+bool aligned(const void *p) { return ((uintptr_t)p & 7) == 0; }
+
+bool overlap(const void *a, size_t an, const void *b, size_t bn)
+{
+    uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    return x < y + bn && y < x + an;
+}
+
+ckks_status check_ptr(const void *p, const char *what)
+{
+    if (!p) return fail(CKKS_E_ARG, std::string(what) + ": null pointer");
+    if (!aligned(p)) return fail(CKKS_E_ARG, std::string(what) + ": pointer not 8-byte aligned");
+    return CKKS_OK;
+}
+
+#define TRY(x)                              \
+    do {                                    \
+        ckks_status _s = (x);               \
+        if (_s != CKKS_OK) return _s;       \
+    } while (0)
+
+struct KsSizes {
+    uint32_t n, rows, beta;
+    size_t N;
+};
+
+KsSizes ks_sizes(const ckks_ctx *c, uint32_t level)
+{
+    KsSizes s;
+    s.n = level + 1;
+    s.rows = s.n + c->np;
+    s.beta = (s.n + c->alpha - 1) / c->alpha;
+    s.N = c->N;
+    return s;
+}
+
+// workspace layout of the key-switching core (elements)
+struct KsWs {
+    uint64_t *dc, *ext, *acc, *pc, *conv;
+};
+
+size_t ks_ws_elems(const ckks_ctx *c, uint32_t level)
+{
+    KsSizes s = ks_sizes(c, level);
+    return ((size_t)s.n + (size_t)s.beta * s.rows + 2 * (size_t)s.rows + 2 * (size_t)c->np + 2 * (size_t)s.n) * s.N;
+}
+
+KsWs ks_ws(const ckks_ctx *c, uint32_t level, void *ws)
+{
+    KsSizes s = ks_sizes(c, level);
+    KsWs w;
+    w.dc = (uint64_t *)ws;
+    w.ext = w.dc + (size_t)s.n * s.N;
+    w.acc = w.ext + (size_t)s.beta * s.rows * s.N;
+    w.pc = w.acc + 2 * (size_t)s.rows * s.N;
+    w.conv = w.pc + 2 * (size_t)c->np * s.N;
+    return w;
+}
+
+NttArgs base_args(const ckks_ctx *c, bool inverse)
+{
+    NttArgs a;
+    memset(&a, 0, sizeof(a));
+    a.primes = c->d_primes;
+    a.tw = inverse ? c->d_tw_inv : c->d_tw_fwd;
+    a.logn = c->logn;
+    a.galois = 1;
+    a.map.nq = c->nq;
+    a.map.level = kAllPrimes;
+    return a;
+}
+
+// INTT of d (optionally gathered through X -> X^g) into dc.
+hipError_t modup_intt(const ckks_ctx *c, const uint64_t *d, uint32_t g, uint32_t level, uint64_t *dc, hipStream_t st)
+{
+    NttArgs a = base_args(c, true);
+    a.src = d;
+    a.dst = dc;
+    a.galois = g;
+    a.map.rows = level + 1;
+    a.map.prime0 = 0;
+    return launch_ntt_inv(a, level + 1, g == 1 ? PRO_PLAIN : PRO_GALOIS, st, dc, 0);
+}
+
+// ModUp from the coefficient-domain dc: base conversion of every digit into
+// ext, own rows copied (gathered through g) from the evaluation-domain d,
+// then the forward NTT of every converted row.
+hipError_t modup_from_coeffs(const ckks_ctx *c, const uint64_t *d, uint32_t g, uint32_t level, const uint64_t *dc,
+                             uint64_t *ext, hipStream_t st)
+{
+    KsSizes s = ks_sizes(c, level);
+    BconvArgs b;
+    memset(&b, 0, sizeof(b));
+    const size_t hm_stride = (size_t)(c->nq + c->np) * kMaxDigitPrimes;
+    for (uint32_t j = 0; j < s.beta; ++j) {
+        uint32_t lo = j * c->alpha, hi = lo + c->alpha < s.n ? lo + c->alpha : s.n;
+        uint32_t set = c->set_index(j, hi - lo);
+        BconvJob &J = b.job[j];
+        J.src = dc + (size_t)lo * s.N;
+        J.dst = ext + (size_t)j * s.rows * s.N;
+        J.copy_src = d;
+        J.hinv = c->d_bc_hinv + (size_t)set * kMaxDigitPrimes;
+        J.hmod = c->d_bc_hmod + (size_t)set * hm_stride;
+        J.ns = hi - lo;
+        J.src_prime0 = lo;
+        J.lo = lo;
+        J.hi = hi;
+    }
+    b.primes = c->d_primes;
+    b.nrows = s.rows;
+    b.level = level;
+    b.nq = c->nq;
+    b.N = c->N;
+    b.logn = c->logn;
+    b.copy_galois = g;
+    hipError_t e = launch_bconv(b, s.beta, st);
+    if (e != hipSuccess) return e;
+    NttArgs a = base_args(c, false);
+    a.src = ext;
+    a.dst = ext;
+    a.map.rows = s.rows;
+    a.map.level = level;
+    a.map.skip_alpha = c->alpha;
+    a.map.src_poly_stride = a.map.dst_poly_stride = (int64_t)s.rows * s.N;
+    return launch_ntt_fwd(a, s.beta * s.rows, PRO_PLAIN, EPI_PLAIN, st, ext, (int64_t)s.rows * s.N);
+}
+
+hipError_t inner_product(const ckks_ctx *c, const uint64_t *ext, uint32_t level, const uint64_t *key, uint32_t g,
+                         uint64_t *acc, hipStream_t st)
+{
+    KsSizes s = ks_sizes(c, level);
+    IpArgs a;
+    a.ext = ext;
+    a.key = key;
+    a.acc = acc;
+    a.primes = c->d_primes;
+    a.beta = s.beta;
+    a.rows = s.rows;
+    a.level = level;
+    a.nq = c->nq;
+    a.np = c->np;
+    a.logn = c->logn;
+    a.galois = g;
+    return launch_inner_product(a, st);
+}
+
+// ModDown of npoly accumulators acc[t] (rows q_0..q_l, p_0..p_{K-1}, stride
+// acc_stride) into out[t] = P^-1 (acc_t - conv_t) + add_t (gathered through g).
+hipError_t moddown(const ckks_ctx *c, const uint64_t *acc, int64_t acc_stride, uint32_t npoly, uint32_t level,
+                   uint64_t *const *out, const uint64_t *const *add, uint32_t g, uint64_t *pc, uint64_t *conv,
+                   hipStream_t st)
+{
+    KsSizes s = ks_sizes(c, level);
+    const int64_t kN = (int64_t)c->np * s.N, nN = (int64_t)s.n * s.N;
+    NttArgs ia = base_args(c, true);
+    ia.src = acc + nN;
+    ia.dst = pc;
+    ia.map.rows = c->np;
+    ia.map.level = level;
+    ia.map.row0 = s.n;
+    ia.map.src_poly_stride = acc_stride;
+    ia.map.dst_poly_stride = kN;
+    hipError_t e = launch_ntt_inv(ia, npoly * c->np, PRO_PLAIN, st, pc, kN);
+    if (e != hipSuccess) return e;
+    BconvArgs b;
+    memset(&b, 0, sizeof(b));
+    const size_t hm_stride = (size_t)(c->nq + c->np) * kMaxDigitPrimes;
+    for (uint32_t t = 0; t < npoly; ++t) {
+        BconvJob &J = b.job[t];
+        J.src = pc + t * kN;
+        J.dst = conv + t * nN;
+        J.hinv = c->d_bc_hinv + (size_t)c->pset_index() * kMaxDigitPrimes;
+        J.hmod = c->d_bc_hmod + (size_t)c->pset_index() * hm_stride;
+        J.ns = c->np;
+        J.src_prime0 = c->nq;
+    }
+    b.primes = c->d_primes;
+    b.nrows = s.n;
+    b.level = level;
+    b.nq = c->nq;
+    b.N = c->N;
+    b.logn = c->logn;
+    b.copy_galois = 1;
+    e = launch_bconv(b, npoly, st);
+    if (e != hipSuccess) return e;
+    NttArgs a = base_args(c, false);
+    a.src = conv;
+    a.dst = conv;
+    a.map.rows = s.n;
+    a.map.level = level;
+    a.map.src_poly_stride = a.map.dst_poly_stride = nN;
+    a.galois = g;
+    a.cst = c->d_pinv;
+    for (uint32_t t = 0; t < npoly; ++t) {
+        a.aux[t] = acc + t * acc_stride;
+        a.add[t] = add ? add[t] : nullptr;
+        a.out[t] = out[t];
+    }
+    return launch_ntt_fwd(a, npoly * s.n, PRO_PLAIN, EPI_MODDOWN, st, conv, nN);
+}
+
+// Full key switch of d (gathered through g_in) with `key`; outputs
+// out_t = KS_t + add_t (add gathered through g_add).
+hipError_t keyswitch_core(const ckks_ctx *c, const uint64_t *d, uint32_t g_in, uint32_t level, const uint64_t *key,
+                          uint64_t *out0, uint64_t *out1, const uint64_t *add0, const uint64_t *add1, uint32_t g_add,
+                          void *ws, hipStream_t st)
+{
+    KsSizes s = ks_sizes(c, level);
+    KsWs w = ks_ws(c, level, ws);
+    hipError_t e = modup_intt(c, d, g_in, level, w.dc, st);
+    if (e == hipSuccess) e = modup_from_coeffs(c, d, g_in, level, w.dc, w.ext, st);
+    if (e == hipSuccess) e = inner_product(c, w.ext, level, key, 1, w.acc, st);
+    if (e != hipSuccess) return e;
+    uint64_t *outs[2] = {out0, out1};
+    const uint64_t *adds[2] = {add0, add1};
+    return moddown(c, w.acc, (int64_t)s.rows * s.N, 2, level, outs, adds, g_add, w.pc, w.conv, st);
+}
+
+ckks_status check_ctx(const ckks_ctx *c)
+{
+    if (!c) return fail(CKKS_E_ARG, "null context");
+    return CKKS_OK;
+}
+
+ckks_status check_level(const ckks_ctx *c, uint32_t level)
+{
+    if (level >= c->nq) return fail(CKKS_E_LEVEL, "level " + std::to_string(level) + " out of range");
+    return CKKS_OK;
+}
+
+ckks_status check_ct(const ckks_ctx *c, const ckks_ct *ct, const char *what)
+{
+    if (!ct) return fail(CKKS_E_ARG, std::string(what) + ": null ciphertext");
+    TRY(check_ptr(ct->c0, what));
+    TRY(check_ptr(ct->c1, what));
+    TRY(check_level(c, ct->level));
+    size_t bytes = (size_t)(ct->level + 1) * c->N * 8;
+    if (overlap(ct->c0, bytes, ct->c1, bytes))
+        return fail(CKKS_E_ARG, std::string(what) + ": c0 and c1 overlap");
+    return CKKS_OK;
+}
+
+ckks_status check_key(const ckks_ctx *c, const ckks_key *k)
+{
+    if (!k || !k->data) return fail(CKKS_E_KEY, "null key");
+    if (k->ctx != c) return fail(CKKS_E_KEY, "key belongs to another context");
+    return CKKS_OK;
+}
+
+size_t poly_bytes(const ckks_ctx *c, uint32_t level) { return (size_t)(level + 1) * c->N * 8; }
+
+ckks_status check_disjoint(const ckks_ctx *c, const ckks_ct *out, const ckks_ct *in, uint32_t lvl_out,
+                           uint32_t lvl_in, const char *what)
+{
+    size_t bo = poly_bytes(c, lvl_out), bi = poly_bytes(c, lvl_in);
+    const void *o[2] = {out->c0, out->c1}, *i[2] = {in->c0, in->c1};
+    for (int x = 0; x < 2; ++x)
+        for (int y = 0; y < 2; ++y)
+            if (overlap(o[x], bo, i[y], bi)) return fail(CKKS_E_ARG, std::string(what) + ": output overlaps input");
+    return CKKS_OK;
+}
+
+uint32_t galois_of_rotation(const ckks_ctx *c, int32_t k)
+{
+    const uint64_t two_n = 2ull * c->N, half = c->N / 2;
+    int64_t kk = k % (int64_t)half;
+    if (kk < 0) kk += half;
+    uint64_t g = 1, b = 5;
+    for (uint64_t e = (uint64_t)kk; e; e >>= 1, b = b * b % two_n)
+        if (e & 1) g = g * b % two_n;
+    return (uint32_t)g;
+}
+
+}  // namespace
+
+extern "C" ckks_status ckks_sync(ckks_ctx *ctx, void *stream)
+{
+    TRY(check_ctx(ctx));
+    hipError_t e = hipStreamSynchronize(S(stream));
+    if (e == hipSuccess) e = hipGetLastError();
+    return dev(e, "ckks_sync");
+}
+
+extern "C" size_t ckks_workspace_bytes(const ckks_ctx *c, uint32_t op, uint32_t level)
+{
+    if (!c || level >= c->nq) return 0;
+    const size_t N = c->N, n = level + 1;
+    switch (op) {
+    case CKKS_OP_MODUP: return n * N * 8;
+    case CKKS_OP_MODDOWN: return ((size_t)c->np + n) * N * 8;
+    case CKKS_OP_KEYSWITCH:
+    case CKKS_OP_ROTATE:
+    case CKKS_OP_HOISTED: return ks_ws_elems(c, level) * 8;
+    case CKKS_OP_HMULT: return (ks_ws_elems(c, level) + n * N) * 8;
+    case CKKS_OP_RESCALE: return (2 * N + 2 * (size_t)level * N) * 8;
+    default: return 0;
+    }
+}
+
+static ckks_status ntt_common(ckks_ctx *ctx, uint64_t *poly, uint32_t limb0, uint32_t n_limbs, void *stream,
+                              bool inverse)
+{
+    TRY(check_ctx(ctx));
+    TRY(check_ptr(poly, inverse ? "ckks_intt" : "ckks_ntt"));
+    if (n_limbs == 0 || limb0 + n_limbs > ctx->nq + ctx->np)
+        return fail(CKKS_E_ARG, "ckks_(i)ntt: limb range outside q_0..q_L, p_0..p_{K-1}");
+    NttArgs a = base_args(ctx, inverse);
+    a.src = poly;
+    a.dst = poly;
+    a.map.rows = n_limbs;
+    a.map.prime0 = limb0;
+    hipError_t e = inverse ? launch_ntt_inv(a, n_limbs, PRO_PLAIN, S(stream), poly, 0)
+                           : launch_ntt_fwd(a, n_limbs, PRO_PLAIN, EPI_PLAIN, S(stream), poly, 0);
+    return dev(e, inverse ? "ckks_intt" : "ckks_ntt");
+}
+
+extern "C" ckks_status ckks_ntt(ckks_ctx *ctx, uint64_t *poly, uint32_t limb0, uint32_t n_limbs, void *stream)
+{
+    return ntt_common(ctx, poly, limb0, n_limbs, stream, false);
+}
+
+extern "C" ckks_status ckks_intt(ckks_ctx *ctx, uint64_t *poly, uint32_t limb0, uint32_t n_limbs, void *stream)
+{
+    return ntt_common(ctx, poly, limb0, n_limbs, stream, true);
+}
+
+extern "C" ckks_status ckks_modup(ckks_ctx *ctx, const uint64_t *d, uint32_t level, uint64_t *ext, void *ws,
+                                  void *stream)
+{
+    TRY(check_ctx(ctx));
+    TRY(check_level(ctx, level));
+    TRY(check_ptr(d, "ckks_modup d"));
+    TRY(check_ptr(ext, "ckks_modup ext"));
+    TRY(check_ptr(ws, "ckks_modup ws"));
+    KsSizes s = ks_sizes(ctx, level);
+    size_t eb = (size_t)s.beta * s.rows * s.N * 8, db = poly_bytes(ctx, level);
+    if (overlap(ext, eb, d, db) || overlap(ext, eb, ws, db) || overlap(d, db, ws, db))
+        return fail(CKKS_E_ARG, "ckks_modup: d, ext and ws must not overlap");
+    hipError_t e = modup_intt(ctx, d, 1, level, (uint64_t *)ws, S(stream));
+    if (e == hipSuccess) e = modup_from_coeffs(ctx, d, 1, level, (uint64_t *)ws, ext, S(stream));
+    return dev(e, "ckks_modup");
+}
+
+extern "C" ckks_status ckks_inner_product(ckks_ctx *ctx, const uint64_t *ext, uint32_t level, const ckks_key *key,
+                                          uint32_t galois, uint64_t *acc, void *stream)
+{
+    TRY(check_ctx(ctx));
+    TRY(check_level(ctx, level));
+    TRY(check_key(ctx, key));
+    TRY(check_ptr(ext, "ckks_inner_product ext"));
+    TRY(check_ptr(acc, "ckks_inner_product acc"));
+    if (galois % 2 == 0 || galois >= 2 * ctx->N) return fail(CKKS_E_ARG, "ckks_inner_product: galois must be odd < 2N");
+    KsSizes s = ks_sizes(ctx, level);
+    if (overlap(ext, (size_t)s.beta * s.rows * s.N * 8, acc, 2 * (size_t)s.rows * s.N * 8))
+        return fail(CKKS_E_ARG, "ckks_inner_product: acc overlaps ext");
+    return dev(inner_product(ctx, ext, level, key->data, galois, acc, S(stream)), "ckks_inner_product");
+}
+
+extern "C" ckks_status ckks_moddown(ckks_ctx *ctx, const uint64_t *x, uint32_t level, uint64_t *out, void *ws,
+                                    void *stream)
+{
+    TRY(check_ctx(ctx));
+    TRY(check_level(ctx, level));
+    TRY(check_ptr(x, "ckks_moddown x"));
+    TRY(check_ptr(out, "ckks_moddown out"));
+    TRY(check_ptr(ws, "ckks_moddown ws"));
+    KsSizes s = ks_sizes(ctx, level);
+    size_t xb = (size_t)s.rows * s.N * 8, ob = poly_bytes(ctx, level), wb = ckks_workspace_bytes(ctx, CKKS_OP_MODDOWN, level);
+    if (overlap(x, xb, out, ob) || overlap(x, xb, ws, wb) || overlap(out, ob, ws, wb))
+        return fail(CKKS_E_ARG, "ckks_moddown: x, out and ws must not overlap");
+    uint64_t *pc = (uint64_t *)ws, *conv = pc + (size_t)ctx->np * s.N;
+    uint64_t *outs[1] = {out};
+    return dev(moddown(ctx, x, 0, 1, level, outs, nullptr, 1, pc, conv, S(stream)), "ckks_moddown");
+}
+
+extern "C" ckks_status ckks_key_wrap(ckks_ctx *ctx, const uint64_t *dev_key, uint32_t galois, ckks_key **out)
+{
+    TRY(check_ctx(ctx));
+    if (!out) return fail(CKKS_E_ARG, "ckks_key_wrap: null output");
+    TRY(check_ptr(dev_key, "ckks_key_wrap key"));
+    if (galois != 0 && (galois % 2 == 0 || galois >= 2 * ctx->N || galois == 1))
+        return fail(CKKS_E_KEY, "ckks_key_wrap: galois must be 0 or odd in (1, 2N)");
+    ckks_key *k = new ckks_key();
+    k->data = dev_key;
+    k->galois = galois;
+    k->ctx = ctx;
+    *out = k;
+    return CKKS_OK;
+}
+
+extern "C" void ckks_key_release(ckks_key *key) { delete key; }
+
+extern "C" ckks_status ckks_keyswitch(ckks_ctx *ctx, const uint64_t *d, uint32_t level, const ckks_key *key,
+                                      uint64_t *out0, uint64_t *out1, void *ws, void *stream)
+{
+    TRY(check_ctx(ctx));
+    TRY(check_level(ctx, level));
+    TRY(check_key(ctx, key));
+    TRY(check_ptr(d, "ckks_keyswitch d"));
+    TRY(check_ptr(out0, "ckks_keyswitch out0"));
+    TRY(check_ptr(out1, "ckks_keyswitch out1"));
+    TRY(check_ptr(ws, "ckks_keyswitch ws"));
+    size_t pb = poly_bytes(ctx, level), wb = ckks_workspace_bytes(ctx, CKKS_OP_KEYSWITCH, level);
+    if (overlap(out0, pb, d, pb) || overlap(out1, pb, d, pb) || overlap(out0, pb, out1, pb) ||
+        overlap(ws, wb, d, pb) || overlap(ws, wb, out0, pb) || overlap(ws, wb, out1, pb))
+        return fail(CKKS_E_ARG, "ckks_keyswitch: d, out0, out1 and ws must not overlap");
+    return dev(keyswitch_core(ctx, d, 1, level, key->data, out0, out1, nullptr, nullptr, 1, ws, S(stream)),
+               "ckks_keyswitch");
+}
+
+extern "C" ckks_status ckks_hmult_relin(ckks_ctx *ctx, const ckks_ct *a, const ckks_ct *b, const ckks_key *rlk,
+                                        ckks_ct *out, void *ws, void *stream)
+{
+    TRY(check_ctx(ctx));
+    TRY(check_ct(ctx, a, "ckks_hmult_relin a"));
+    TRY(check_ct(ctx, b, "ckks_hmult_relin b"));
+    if (a->level != b->level) return fail(CKKS_E_LEVEL, "ckks_hmult_relin: operands at different levels");
+    TRY(check_key(ctx, rlk));
+    if (rlk->galois != 0) return fail(CKKS_E_KEY, "ckks_hmult_relin: key is not a relinearisation key");
+    if (!out) return fail(CKKS_E_ARG, "ckks_hmult_relin: null output");
+    uint32_t level = a->level;
+    ckks_ct o = *out;
+    o.level = level;
+    TRY(check_ct(ctx, &o, "ckks_hmult_relin out"));
+    TRY(check_ptr(ws, "ckks_hmult_relin ws"));
+    TRY(check_disjoint(ctx, &o, a, level, level, "ckks_hmult_relin"));
+    TRY(check_disjoint(ctx, &o, b, level, level, "ckks_hmult_relin"));
+    size_t wb = ckks_workspace_bytes(ctx, CKKS_OP_HMULT, level), pb = poly_bytes(ctx, level);
+    const void *all[6] = {a->c0, a->c1, b->c0, b->c1, o.c0, o.c1};
+    for (int i = 0; i < 6; ++i)
+        if (overlap(ws, wb, all[i], pb)) return fail(CKKS_E_ARG, "ckks_hmult_relin: workspace overlaps a polynomial");
+    const size_t N = ctx->N;
+    uint64_t *d2 = (uint64_t *)ws;
+    void *ks_ws = d2 + (size_t)(level + 1) * N;
+    hipError_t e = launch_tensor(a->c0, a->c1, b->c0, b->c1, o.c0, o.c1, d2, ctx->d_primes, level + 1, ctx->logn,
+                                 S(stream));
+    if (e == hipSuccess)
+        e = keyswitch_core(ctx, d2, 1, level, rlk->data, o.c0, o.c1, o.c0, o.c1, 1, ks_ws, S(stream));
+    TRY(dev(e, "ckks_hmult_relin"));
+    out->level = level;
+    out->scale = a->scale * b->scale;
+    return CKKS_OK;
+}
+
+extern "C" ckks_status ckks_rescale(ckks_ctx *ctx, const ckks_ct *in, ckks_ct *out, void *ws, void *stream)
+{
+    TRY(check_ctx(ctx));
+    TRY(check_ct(ctx, in, "ckks_rescale in"));
+    if (in->level < 1) return fail(CKKS_E_LEVEL, "ckks_rescale: level 0 cannot be rescaled");
+    if (!out) return fail(CKKS_E_ARG, "ckks_rescale: null output");
+    const uint32_t l = in->level;
+    ckks_ct o = *out;
+    o.level = l - 1;
+    TRY(check_ct(ctx, &o, "ckks_rescale out"));
+    TRY(check_ptr(ws, "ckks_rescale ws"));
+    const size_t N = ctx->N, ib = poly_bytes(ctx, l), ob = poly_bytes(ctx, l - 1);
+    // in place (same buffers) is allowed, any other overlap is not
+    const void *I[2] = {in->c0, in->c1}, *O[2] = {o.c0, o.c1};
+    for (int x = 0; x < 2; ++x)
+        for (int y = 0; y < 2; ++y)
+            if (overlap(O[x], ob, I[y], ib) && !(x == y && O[x] == I[y]))
+                return fail(CKKS_E_ARG, "ckks_rescale: output overlaps input other than exactly in place");
+    size_t wb = ckks_workspace_bytes(ctx, CKKS_OP_RESCALE, l);
+    for (int x = 0; x < 2; ++x)
+        if (overlap(ws, wb, I[x], ib) || overlap(ws, wb, O[x], ob))
+            return fail(CKKS_E_ARG, "ckks_rescale: workspace overlaps a polynomial");
+    uint64_t *v = (uint64_t *)ws, *mid = v + 2 * N;
+    NttArgs ia = base_args(ctx, true);
+    ia.src = in->c0 + (size_t)l * N;
+    ia.dst = v;
+    ia.map.rows = 1;
+    ia.map.prime0 = l;
+    ia.map.src_poly_stride = (int64_t)(in->c1 - in->c0);
+    ia.map.dst_poly_stride = (int64_t)N;
+    hipError_t e = launch_ntt_inv(ia, 2, PRO_PLAIN, S(stream), v, (int64_t)N);
+    if (e == hipSuccess) {
+        NttArgs a = base_args(ctx, false);
+        a.src = v;
+        a.dst = mid;
+        a.map.rows = l;
+        a.map.prime0 = 0;
+        a.map.src_poly_stride = 0;
+        a.map.dst_poly_stride = (int64_t)l * N;
+        a.rs_src[0] = v;
+        a.rs_src[1] = v + N;
+        a.rs_qlmod = ctx->d_rs_mod + (size_t)l * ctx->nq;
+        a.rs_ql = ctx->primes[l];
+        a.cst = ctx->d_rs_inv + (size_t)l * ctx->nq;
+        a.aux[0] = in->c0;
+        a.aux[1] = in->c1;
+        a.out[0] = o.c0;
+        a.out[1] = o.c1;
+        e = launch_ntt_fwd(a, 2 * l, PRO_RESCALE, EPI_RESCALE, S(stream), mid, (int64_t)l * N);
+    }
+    TRY(dev(e, "ckks_rescale"));
+    out->level = l - 1;
+    out->scale = in->scale / (double)ctx->primes[l];
+    return CKKS_OK;
+}
+
+extern "C" ckks_status ckks_apply_galois(ckks_ctx *ctx, const ckks_ct *in, uint32_t galois, const ckks_key *key,
+                                         ckks_ct *out, void *ws, void *stream)
+{
+    TRY(check_ctx(ctx));
+    TRY(check_ct(ctx, in, "ckks_apply_galois in"));
+    TRY(check_key(ctx, key));
+    if (galois % 2 == 0 || galois <= 1 || galois >= 2 * ctx->N)
+        return fail(CKKS_E_ARG, "ckks_apply_galois: galois must be odd in (1, 2N)");
+    if (key->galois != galois) return fail(CKKS_E_KEY, "ckks_apply_galois: key is for another Galois element");
+    if (!out) return fail(CKKS_E_ARG, "ckks_apply_galois: null output");
+    const uint32_t level = in->level;
+    ckks_ct o = *out;
+    o.level = level;
+    TRY(check_ct(ctx, &o, "ckks_apply_galois out"));
+    TRY(check_ptr(ws, "ckks_apply_galois ws"));
+    TRY(check_disjoint(ctx, &o, in, level, level, "ckks_apply_galois"));
+    size_t wb = ckks_workspace_bytes(ctx, CKKS_OP_ROTATE, level), pb = poly_bytes(ctx, level);
+    const void *all[4] = {in->c0, in->c1, o.c0, o.c1};
+    for (int i = 0; i < 4; ++i)
+        if (overlap(ws, wb, all[i], pb)) return fail(CKKS_E_ARG, "ckks_apply_galois: workspace overlaps a polynomial");
+    hipError_t e =
+        keyswitch_core(ctx, in->c1, galois, level, key->data, o.c0, o.c1, in->c0, nullptr, galois, ws, S(stream));
+    TRY(dev(e, "ckks_apply_galois"));
+    out->level = level;
+    out->scale = in->scale;
+    return CKKS_OK;
+}
+
+extern "C" ckks_status ckks_hrotate(ckks_ctx *ctx, const ckks_ct *in, int32_t k, const ckks_key *key, ckks_ct *out,
+                                    void *ws, void *stream)
+{
+    TRY(check_ctx(ctx));
+    uint32_t g = galois_of_rotation(ctx, k);
+    if (g == 1) return fail(CKKS_E_ARG, "ckks_hrotate: rotation by a multiple of N/2 is the identity");
+    return ckks_apply_galois(ctx, in, g, key, out, ws, stream);
+}
+
+extern "C" ckks_status ckks_conjugate(ckks_ctx *ctx, const ckks_ct *in, const ckks_key *key, ckks_ct *out, void *ws,
+                                      void *stream)
+{
+    TRY(check_ctx(ctx));
+    return ckks_apply_galois(ctx, in, 2 * ctx->N - 1, key, out, ws, stream);
+}
+
+extern "C" ckks_status ckks_hrotate_hoisted(ckks_ctx *ctx, const ckks_ct *in, uint32_t n, const int32_t *k,
+                                            const ckks_key *const *keys, ckks_ct *out, void *ws, void *stream)
+{
+    TRY(check_ctx(ctx));
+    TRY(check_ct(ctx, in, "ckks_hrotate_hoisted in"));
+    if (n == 0) return CKKS_OK;
+    if (!k || !keys || !out) return fail(CKKS_E_ARG, "ckks_hrotate_hoisted: null array");
+    TRY(check_ptr(ws, "ckks_hrotate_hoisted ws"));
+    const uint32_t level = in->level;
+    size_t wb = ckks_workspace_bytes(ctx, CKKS_OP_HOISTED, level), pb = poly_bytes(ctx, level);
+    std::vector<uint32_t> gs(n);
+    for (uint32_t i = 0; i < n; ++i) {
+        gs[i] = galois_of_rotation(ctx, k[i]);
+        if (gs[i] == 1) return fail(CKKS_E_ARG, "ckks_hrotate_hoisted: rotation by a multiple of N/2");
+        TRY(check_key(ctx, keys[i]));
+        if (keys[i]->galois != gs[i]) return fail(CKKS_E_KEY, "ckks_hrotate_hoisted: key " + std::to_string(i) +
+                                                                  " is for another Galois element");
+        ckks_ct o = out[i];
+        o.level = level;
+        TRY(check_ct(ctx, &o, "ckks_hrotate_hoisted out"));
+        TRY(check_disjoint(ctx, &o, in, level, level, "ckks_hrotate_hoisted"));
+        if (overlap(ws, wb, o.c0, pb) || overlap(ws, wb, o.c1, pb))
+            return fail(CKKS_E_ARG, "ckks_hrotate_hoisted: workspace overlaps an output");
+        for (uint32_t j = 0; j < i; ++j) {
+            ckks_ct p = out[j];
+            p.level = level;
+            TRY(check_disjoint(ctx, &o, &p, level, level, "ckks_hrotate_hoisted outputs"));
+        }
+    }
+    if (overlap(ws, wb, in->c0, pb) || overlap(ws, wb, in->c1, pb))
+        return fail(CKKS_E_ARG, "ckks_hrotate_hoisted: workspace overlaps the input");
+    KsSizes s = ks_sizes(ctx, level);
+    KsWs w = ks_ws(ctx, level, ws);
+    hipError_t e = modup_intt(ctx, in->c1, 1, level, w.dc, S(stream));
+    if (e == hipSuccess) e = modup_from_coeffs(ctx, in->c1, 1, level, w.dc, w.ext, S(stream));
+    for (uint32_t i = 0; i < n && e == hipSuccess; ++i) {
+        e = inner_product(ctx, w.ext, level, keys[i]->data, gs[i], w.acc, S(stream));
+        if (e != hipSuccess) break;
+        uint64_t *outs[2] = {out[i].c0, out[i].c1};
+        const uint64_t *adds[2] = {in->c0, nullptr};
+        e = moddown(ctx, w.acc, (int64_t)s.rows * s.N, 2, level, outs, adds, gs[i], w.pc, w.conv, S(stream));
+    }
+    TRY(dev(e, "ckks_hrotate_hoisted"));
+    for (uint32_t i = 0; i < n; ++i) {
+        out[i].level = level;
+        out[i].scale = in->scale;
+    }
+    return CKKS_OK;
+}
+
+static ckks_status elementwise(ckks_ctx *ctx, int op, const uint64_t *a, const uint64_t *b, const uint64_t *c,
+                               uint64_t *out, const uint64_t *host_scalars, uint32_t level, void *stream,
+                               const char *what)
+{
+    TRY(check_ctx(ctx));
+    TRY(check_level(ctx, level));
+    TRY(check_ptr(a, what));
+    TRY(check_ptr(out, what));
+    if (op <= 3) TRY(check_ptr(b, what));
+    if (op == 3) TRY(check_ptr(c, what));
+    if (op >= 4) {
+        if (!host_scalars) return fail(CKKS_E_ARG, std::string(what) + ": null scalars");
+        for (uint32_t i = 0; i <= level; ++i)
+            if (host_scalars[i] >= ctx->primes[i])
+                return fail(CKKS_E_ARG, std::string(what) + ": scalar not reduced modulo its prime");
+    }
+    size_t pb = poly_bytes(ctx, level);
+    const uint64_t *ins[3] = {a, op <= 3 ? b : nullptr, op == 3 ? c : nullptr};
+    for (int i = 0; i < 3; ++i)
+        if (ins[i] && ins[i] != out && overlap(ins[i], pb, out, pb))
+            return fail(CKKS_E_ARG, std::string(what) + ": output partially overlaps an input");
+    return dev(launch_elementwise(op, a, b, c, out, host_scalars, ctx->d_primes, level + 1, ctx->logn, S(stream)),
+               what);
+}
+
+extern "C" ckks_status ckks_poly_add(ckks_ctx *ctx, const uint64_t *a, const uint64_t *b, uint64_t *out,
+                                     uint32_t level, void *stream)
+{
+    return elementwise(ctx, 0, a, b, nullptr, out, nullptr, level, stream, "ckks_poly_add");
+}
+
+extern "C" ckks_status ckks_poly_sub(ckks_ctx *ctx, const uint64_t *a, const uint64_t *b, uint64_t *out,
+                                     uint32_t level, void *stream)
+{
+    return elementwise(ctx, 1, a, b, nullptr, out, nullptr, level, stream, "ckks_poly_sub");
+}
+
+extern "C" ckks_status ckks_poly_mul(ckks_ctx *ctx, const uint64_t *a, const uint64_t *b, uint64_t *out,
+                                     uint32_t level, void *stream)
+{
+    return elementwise(ctx, 2, a, b, nullptr, out, nullptr, level, stream, "ckks_poly_mul");
+}
+
+extern "C" ckks_status ckks_poly_mul_add(ckks_ctx *ctx, const uint64_t *a, const uint64_t *b, const uint64_t *c,
+                                         uint64_t *out, uint32_t level, void *stream)
+{
+    return elementwise(ctx, 3, a, b, c, out, nullptr, level, stream, "ckks_poly_mul_add");
+}
+
+extern "C" ckks_status ckks_poly_scalar_mul(ckks_ctx *ctx, const uint64_t *a, const uint64_t *s, uint64_t *out,
+                                            uint32_t level, void *stream)
+{
+    return elementwise(ctx, 4, a, nullptr, nullptr, out, s, level, stream, "ckks_poly_scalar_mul");
+}
+
+extern "C" ckks_status ckks_poly_scalar_add(ckks_ctx *ctx, const uint64_t *a, const uint64_t *s, uint64_t *out,
+                                            uint32_t level, void *stream)
+{
+    return elementwise(ctx, 5, a, nullptr, nullptr, out, s, level, stream, "ckks_poly_scalar_add");
+}
+
+extern "C" ckks_status ckks_automorph(ckks_ctx *ctx, const uint64_t *in, uint32_t galois, uint64_t *out,
+                                      uint32_t n_limbs, void *stream)
+{
+    TRY(check_ctx(ctx));
+    TRY(check_ptr(in, "ckks_automorph in"));
+    TRY(check_ptr(out, "ckks_automorph out"));
+    if (n_limbs == 0 || n_limbs > ctx->nq + ctx->np) return fail(CKKS_E_ARG, "ckks_automorph: bad limb count");
+    if (galois % 2 == 0 || galois >= 2 * ctx->N) return fail(CKKS_E_ARG, "ckks_automorph: galois must be odd < 2N");
+    size_t b = (size_t)n_limbs * ctx->N * 8;
+    if (overlap(in, b, out, b)) return fail(CKKS_E_ARG, "ckks_automorph: out overlaps in");
+    return dev(launch_automorph(in, out, n_limbs, ctx->logn, galois, S(stream)), "ckks_automorph");
+}

@@ -1,0 +1,158 @@
+// Internal declarations of the gfx950 CKKS library: the context with its
+// device tables, kernel argument blocks and kernel launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/ckks.h"
+#include "modarith.h"
+
+namespace ckks {
+
+constexpr int kMaxDigitPrimes = 16;  // primes per digit / in the special basis
+constexpr int kMaxDigits = 16;
+constexpr int kMaxPrimes = 64;
+constexpr uint32_t kAllPrimes = 0xFFFFFFFFu;
+
+// Row -> prime map of a launch over limbs.  Limb y of a launch is row
+// (y % rows) of polynomial (y / rows).  With level == kAllPrimes row r uses
+// prime prime0 + r; otherwise logical row lr = row0 + r uses q_lr for
+// lr <= level and p_{lr-level-1} (prime index nq + lr - level - 1) above.
+// skip_alpha > 0 skips, in polynomial j, the logical rows of digit j.
+struct LimbMap {
+    uint32_t rows;
+    uint32_t level;
+    uint32_t prime0;
+    uint32_t nq;
+    uint32_t row0;
+    uint32_t skip_alpha;
+    int64_t src_poly_stride;  // elements between polynomials of the input (may be negative)
+    int64_t dst_poly_stride;  // elements between polynomials of the output
+};
+
+__host__ __device__ inline uint32_t limb_prime(const LimbMap &m, uint32_t r)
+{
+    uint32_t lr = r + m.row0;
+    if (m.level == kAllPrimes) return m.prime0 + lr;
+    return lr <= m.level ? lr : m.nq + (lr - m.level - 1);
+}
+
+__host__ __device__ inline bool limb_skipped(const LimbMap &m, uint32_t poly, uint32_t r)
+{
+    if (m.skip_alpha == 0) return false;
+    uint32_t lr = r + m.row0;
+    uint32_t lo = poly * m.skip_alpha;
+    uint32_t hi = lo + m.skip_alpha < m.level + 1 ? lo + m.skip_alpha : m.level + 1;
+    return lr >= lo && lr < hi;
+}
+
+__device__ __forceinline__ uint32_t bitrev(uint32_t x, uint32_t logn) { return __brev(x) >> (32 - logn); }
+
+// Position whose value moves to position e under X -> X^g in the evaluation
+// domain: out[e] = in[br(((2 br(e) + 1) g mod 2N - 1) / 2)].
+__device__ __forceinline__ uint32_t galois_src(uint32_t e, uint32_t g, uint32_t logn)
+{
+    uint32_t i = bitrev(e, logn);
+    uint32_t x = ((2 * i + 1) * g) & ((2u << logn) - 1);  // wraps mod 2^32, exact mod 2N
+    return bitrev((x - 1) >> 1, logn);
+}
+
+// Prologue of the first forward pass / epilogue of the last forward pass.
+enum NttPro { PRO_PLAIN = 0, PRO_RESCALE = 1, PRO_GALOIS = 2 };
+enum NttEpi { EPI_PLAIN = 0, EPI_MODDOWN = 1, EPI_RESCALE = 2 };
+
+struct NttArgs {
+    uint64_t *dst;
+    const uint64_t *src;
+    LimbMap map;
+    const Prime *primes;
+    const ulonglong2 *tw;       // [n_primes][N] {w, floor(w 2^64 / q)}
+    uint32_t logn;
+    uint32_t galois;            // PRO_GALOIS gather / addend gather (1 = none)
+    // EPI_MODDOWN: out_p = Pinv (aux_p - x) + add_p ; EPI_RESCALE: out_p = qlinv (aux_p - x)
+    const uint64_t *aux[2];     // per polynomial (row r at aux[p] + r N)
+    const uint64_t *add[2];     // per polynomial, may be null
+    uint64_t *out[2];           // per polynomial
+    const ulonglong2 *cst;      // per prime index: Pinv or q_l^-1 pair
+    // PRO_RESCALE: input limb per polynomial (coefficients under q_l), q_l mod q_i per prime
+    const uint64_t *rs_src[2];
+    const uint64_t *rs_qlmod;
+    uint64_t rs_ql;
+};
+
+struct BconvJob {
+    const uint64_t *src;        // ns coefficient-domain limbs, stride N
+    uint64_t *dst;              // output rows at dst + r N
+    const uint64_t *copy_src;   // rows [lo, hi) copied from here to dst (may be null)
+    const ulonglong2 *hinv;     // ns pairs {[(B/b_i)^-1]_{b_i}, shoup}
+    const uint64_t *hmod;       // [n_primes][kMaxDigitPrimes]: [B/b_i]_c
+    uint32_t ns;
+    uint32_t src_prime0;
+    uint32_t lo, hi;            // output rows not converted
+};
+
+struct BconvArgs {
+    BconvJob job[kMaxDigits];
+    const Prime *primes;
+    uint32_t nrows;             // output rows 0..nrows-1
+    uint32_t level, nq;         // row -> prime map as in LimbMap
+    uint32_t N, logn;
+    uint32_t copy_galois;       // copied rows are gathered through X -> X^g (1 = plain copy)
+};
+
+struct IpArgs {
+    const uint64_t *ext;        // [beta][rows][N]
+    const uint64_t *key;        // [dnum][2][nq+np][N]
+    uint64_t *acc;              // [2][rows][N]
+    const Prime *primes;
+    uint32_t beta, rows, level, nq, np, logn, galois;
+};
+
+// Launchers (all asynchronous on `stream`).
+hipError_t launch_ntt_fwd(const NttArgs &a, uint32_t nlimbs, NttPro pro, NttEpi epi, hipStream_t stream,
+                          uint64_t *mid, int64_t mid_poly_stride);
+hipError_t launch_ntt_inv(const NttArgs &a, uint32_t nlimbs, NttPro pro, hipStream_t stream, uint64_t *mid,
+                          int64_t mid_poly_stride);
+hipError_t launch_bconv(const BconvArgs &a, uint32_t njobs, hipStream_t stream);
+hipError_t launch_inner_product(const IpArgs &a, hipStream_t stream);
+hipError_t launch_tensor(const uint64_t *a0, const uint64_t *a1, const uint64_t *b0, const uint64_t *b1,
+                         uint64_t *d0, uint64_t *d1, uint64_t *d2, const Prime *primes, uint32_t nlimbs,
+                         uint32_t logn, hipStream_t stream);
+// op: 0 add, 1 sub, 2 mul, 3 mul-add (a*b+c), 4 scalar mul (host_scalars[limb]), 5 scalar add
+hipError_t launch_elementwise(int op, const uint64_t *a, const uint64_t *b, const uint64_t *c, uint64_t *out,
+                              const uint64_t *host_scalars, const Prime *primes, uint32_t nlimbs, uint32_t logn,
+                              hipStream_t stream);
+hipError_t launch_automorph(const uint64_t *in, uint64_t *out, uint32_t nlimbs, uint32_t logn, uint32_t galois,
+                            hipStream_t stream);
+
+}  // namespace ckks
+
+// The opaque context of the C ABI.
+struct ckks_ctx {
+    int device = 0;
+    uint32_t logn = 0, N = 0, nq = 0, np = 0, dnum = 0, alpha = 0;
+    std::vector<uint64_t> primes;  // q_0..q_L, p_0..p_{K-1}
+    void *dev_block = nullptr;     // one allocation holding every table
+    ckks::Prime *d_primes = nullptr;
+    ulonglong2 *d_tw_fwd = nullptr;     // [n][N]
+    ulonglong2 *d_tw_inv = nullptr;     // [n][N]
+    // base-conversion sets: digit sets indexed (j * alpha + size - 1), then the P set
+    ulonglong2 *d_bc_hinv = nullptr;    // [nsets][kMaxDigitPrimes]
+    uint64_t *d_bc_hmod = nullptr;      // [nsets][n_primes][kMaxDigitPrimes]
+    ulonglong2 *d_pinv = nullptr;       // [n_primes] P^-1 mod q_i
+    ulonglong2 *d_rs_inv = nullptr;     // [nq][nq]: (level l, prime i) -> q_l^-1 mod q_i
+    uint64_t *d_rs_mod = nullptr;       // [nq][nq]: q_l mod q_i
+    uint32_t nsets = 0;
+
+    uint32_t set_index(uint32_t digit, uint32_t size) const { return digit * alpha + size - 1; }
+    uint32_t pset_index() const { return dnum * alpha; }
+};
+
+struct ckks_key {
+    const uint64_t *data;
+    uint32_t galois;
+    const ckks_ctx *ctx;
+};

@@ -1,0 +1,176 @@
+// Coefficient-wise kernels of the key-switching path for gfx950: the fast
+// base conversion (paper Eq. (1), Sec. III-F.3), the key inner product
+// (dot-product fusion of III-F.5), the HMult tensor and the limb-wise support
+// operations of Table I.  One thread per coefficient index, so every global
+// access is a fully coalesced 8-byte-per-lane row segment.
+#include "internal.h"
+
+namespace ckks {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ uint32_t row_prime(uint32_t r, uint32_t level, uint32_t nq)
+{
+    return r <= level ? r : nq + (r - level - 1);
+}
+
+// Conv_{B->C}: y_i = [x_i (B/b_i)^-1]_{b_i} (Shoup), then every output row c
+// gets [sum_i y_i [B/b_i]_c]_c, accumulated exactly in 128 bits and reduced
+// once (as the paper does).  blockIdx.y selects the job (digit or polynomial).
+__global__ __launch_bounds__(kThreads) void k_bconv(BconvArgs a)
+{
+    const BconvJob &J = a.job[blockIdx.y];
+    const uint32_t N = a.N;
+    const uint32_t n = blockIdx.x * kThreads + threadIdx.x;
+    uint64_t y[kMaxDigitPrimes];
+#pragma unroll
+    for (int i = 0; i < kMaxDigitPrimes; ++i) {
+        if (i < (int)J.ns) {
+            const uint64_t qi = a.primes[J.src_prime0 + i].q;
+            const ulonglong2 h = J.hinv[i];
+            y[i] = shoup(J.src[(size_t)i * N + n], h.x, h.y, qi);
+        } else {
+            y[i] = 0;
+        }
+    }
+    for (uint32_t r = 0; r < a.nrows; ++r) {
+        if (r >= J.lo && r < J.hi) {
+            if (J.copy_src)
+                J.dst[(size_t)r * N + n] =
+                    J.copy_src[(size_t)r * N + (a.copy_galois == 1 ? n : galois_src(n, a.copy_galois, a.logn))];
+            continue;
+        }
+        const uint32_t pi = row_prime(r, a.level, a.nq);
+        const uint64_t *h = J.hmod + (size_t)pi * kMaxDigitPrimes;
+        u128 acc = {0, 0};
+#pragma unroll
+        for (int i = 0; i < kMaxDigitPrimes; ++i)
+            if (i < (int)J.ns) acc = add128(acc, mul_wide(y[i], h[i]));
+        J.dst[(size_t)r * N + n] = reduce128(acc, a.primes[pi]);
+    }
+}
+
+// acc[t][r] = sum_j phi_g(ext_j)[r] * key[j][t][r] over the beta digits.
+__global__ __launch_bounds__(kThreads) void k_inner_product(IpArgs a)
+{
+    const uint32_t N = 1u << a.logn;
+    const uint32_t r = blockIdx.y;
+    const uint32_t n = blockIdx.x * kThreads + threadIdx.x;
+    const uint32_t pi = row_prime(r, a.level, a.nq);  // also the key row
+    const uint32_t sn = a.galois == 1 ? n : galois_src(n, a.galois, a.logn);
+    const size_t krows = a.nq + a.np;
+    u128 s0 = {0, 0}, s1 = {0, 0};
+    for (uint32_t j = 0; j < a.beta; ++j) {
+        const uint64_t x = a.ext[((size_t)j * a.rows + r) * N + sn];
+        const uint64_t k0 = a.key[(((size_t)j * 2 + 0) * krows + pi) * N + n];
+        const uint64_t k1 = a.key[(((size_t)j * 2 + 1) * krows + pi) * N + n];
+        s0 = add128(s0, mul_wide(x, k0));
+        s1 = add128(s1, mul_wide(x, k1));
+    }
+    const Prime P = a.primes[pi];
+    a.acc[(size_t)r * N + n] = reduce128(s0, P);
+    a.acc[((size_t)a.rows + r) * N + n] = reduce128(s1, P);
+}
+
+// d0 = a0 b0, d1 = a0 b1 + a1 b0, d2 = a1 b1 (limb l under q_l)
+__global__ __launch_bounds__(kThreads) void k_tensor(const uint64_t *__restrict__ a0, const uint64_t *__restrict__ a1,
+                                                     const uint64_t *__restrict__ b0, const uint64_t *__restrict__ b1,
+                                                     uint64_t *d0, uint64_t *d1, uint64_t *d2, const Prime *primes,
+                                                     uint32_t logn)
+{
+    const uint32_t l = blockIdx.y;
+    const size_t i = ((size_t)l << logn) + blockIdx.x * kThreads + threadIdx.x;
+    const Prime P = primes[l];
+    const uint64_t x0 = a0[i], x1 = a1[i], y0 = b0[i], y1 = b1[i];
+    d0[i] = reduce128(mul_wide(x0, y0), P);
+    d1[i] = reduce128(add128(mul_wide(x0, y1), mul_wide(x1, y0)), P);
+    d2[i] = reduce128(mul_wide(x1, y1), P);
+}
+
+struct Scalars {
+    uint64_t v[kMaxPrimes];
+};
+
+template <int OP>
+__global__ __launch_bounds__(kThreads) void k_elementwise(const uint64_t *a, const uint64_t *b, const uint64_t *c,
+                                                          uint64_t *out, Scalars scalars, const Prime *primes,
+                                                          uint32_t logn)
+{
+    const uint32_t l = blockIdx.y;
+    const size_t i = ((size_t)l << logn) + blockIdx.x * kThreads + threadIdx.x;
+    const Prime P = primes[l];
+    const uint64_t x = a[i];
+    uint64_t r;
+    if (OP == 0) r = addmod(x, b[i], P.q);
+    else if (OP == 1) r = submod(x, b[i], P.q);
+    else if (OP == 2) r = mulmod(x, b[i], P);
+    else if (OP == 3) r = reduce128(add128(mul_wide(x, b[i]), u128{c[i], 0}), P);
+    else if (OP == 4) r = mulmod(x, scalars.v[l], P);
+    else r = addmod(x, scalars.v[l], P.q);
+    out[i] = r;
+}
+
+__global__ __launch_bounds__(kThreads) void k_automorph(const uint64_t *__restrict__ in, uint64_t *__restrict__ out,
+                                                        uint32_t logn, uint32_t g)
+{
+    const uint32_t l = blockIdx.y;
+    const uint32_t e = blockIdx.x * kThreads + threadIdx.x;
+    const size_t base = (size_t)l << logn;
+    out[base + e] = in[base + galois_src(e, g, logn)];
+}
+
+}  // namespace
+
+hipError_t launch_bconv(const BconvArgs &a, uint32_t njobs, hipStream_t stream)
+{
+    if (njobs == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bconv, dim3(a.N / kThreads, njobs), dim3(kThreads), 0, stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_inner_product(const IpArgs &a, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_inner_product, dim3((1u << a.logn) / kThreads, a.rows), dim3(kThreads), 0, stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_tensor(const uint64_t *a0, const uint64_t *a1, const uint64_t *b0, const uint64_t *b1, uint64_t *d0,
+                         uint64_t *d1, uint64_t *d2, const Prime *primes, uint32_t nlimbs, uint32_t logn,
+                         hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_tensor, dim3((1u << logn) / kThreads, nlimbs), dim3(kThreads), 0, stream, a0, a1, b0, b1,
+                       d0, d1, d2, primes, logn);
+    return hipGetLastError();
+}
+
+hipError_t launch_elementwise(int op, const uint64_t *a, const uint64_t *b, const uint64_t *c, uint64_t *out,
+                              const uint64_t *host_scalars, const Prime *primes, uint32_t nlimbs, uint32_t logn,
+                              hipStream_t stream)
+{
+    dim3 grid((1u << logn) / kThreads, nlimbs), block(kThreads);
+    Scalars sc = {};
+    if (host_scalars)
+        for (uint32_t l = 0; l < nlimbs && l < (uint32_t)kMaxPrimes; ++l) sc.v[l] = host_scalars[l];
+    switch (op) {
+    case 0: hipLaunchKernelGGL((k_elementwise<0>), grid, block, 0, stream, a, b, c, out, sc, primes, logn); break;
+    case 1: hipLaunchKernelGGL((k_elementwise<1>), grid, block, 0, stream, a, b, c, out, sc, primes, logn); break;
+    case 2: hipLaunchKernelGGL((k_elementwise<2>), grid, block, 0, stream, a, b, c, out, sc, primes, logn); break;
+    case 3: hipLaunchKernelGGL((k_elementwise<3>), grid, block, 0, stream, a, b, c, out, sc, primes, logn); break;
+    case 4: hipLaunchKernelGGL((k_elementwise<4>), grid, block, 0, stream, a, b, c, out, sc, primes, logn); break;
+    case 5: hipLaunchKernelGGL((k_elementwise<5>), grid, block, 0, stream, a, b, c, out, sc, primes, logn); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_automorph(const uint64_t *in, uint64_t *out, uint32_t nlimbs, uint32_t logn, uint32_t galois,
+                            hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_automorph, dim3((1u << logn) / kThreads, nlimbs), dim3(kThreads), 0, stream, in, out, logn,
+                       galois);
+    return hipGetLastError();
+}
+
+}  // namespace ckks

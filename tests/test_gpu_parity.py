@@ -1,0 +1,210 @@
+"""Bit-exact parity of every C-ABI call with the CPU oracle on seeded inputs,
+at N = 2^12 (four limbs, dnum = 2) and N = 2^16 (31 limbs, dnum = 3, the
+paper-scale shape), at several levels including partial last digits."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_common import Setup, assert_equal, gpu_available
+from helpers import br
+from paper_2507_04775_amd import inputs
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+_setups = {}
+
+
+def setup(name):
+    if name not in _setups:
+        _setups[name] = Setup(name)
+    return _setups[name]
+
+
+LEVELS = {"small": [3, 2, 1, 0], "large": [30, 21, 12, 0]}
+
+
+@pytest.mark.parametrize("name", ["small", "large"])
+def test_twiddle_tables_match_oracle_roots(name):
+    s = setup(name)
+    for limb, m in enumerate(list(s.ps.q) + list(s.ps.p)):
+        tw = s.ctx.twiddles(limb)
+        psi = oracle.psi(m, s.ps.logn)
+        for k in [0, 1, 2, 3, 100, s.N // 2, s.N - 1]:
+            assert int(tw[k]) == pow(psi, br(k, s.ps.logn), m)
+
+
+@pytest.mark.parametrize("name", ["small", "large"])
+def test_ntt_intt_all_primes(name):
+    s = setup(name)
+    mods = list(s.ps.q) + list(s.ps.p)
+    a = inputs.uniform_residues(inputs.rng(1), mods, s.N)
+    t = s.dev(a)
+    s.ctx.ckks_ntt(t, 0, len(mods))
+    want = oracle.ntt(mods, a, s.ps.logn)
+    assert_equal(s.host(t), want, "ntt")
+    s.ctx.ckks_intt(t, 0, len(mods))
+    assert_equal(s.host(t), a, "intt(ntt)")
+    b = inputs.uniform_residues(inputs.rng(2), mods, s.N)
+    tb = s.dev(b)
+    s.ctx.ckks_intt(tb, 0, len(mods))
+    assert_equal(s.host(tb), oracle.intt(mods, b, s.ps.logn), "intt")
+
+
+@pytest.mark.parametrize("name", ["small", "large"])
+def test_ntt_edge_values(name):
+    s = setup(name)
+    mods = list(s.ps.q[:2]) + list(s.ps.p[:1])
+    a = np.zeros((3, s.N), dtype=np.uint64)
+    for i, m in enumerate(mods):
+        a[i, ::2] = m - 1          # maximal residues
+        a[i, 1::4] = 1
+    t = s.dev(a)
+    s.ctx.ckks_ntt(t, 0, 2)
+    s.ctx.ckks_ntt(t[2:], s.ps.L + 1, 1)
+    assert_equal(s.host(t), oracle.ntt(mods, a, s.ps.logn), "ntt edge")
+
+
+@pytest.mark.parametrize("name", ["small", "large"])
+def test_modup(name):
+    s = setup(name)
+    for level in LEVELS[name]:
+        d = inputs.random_poly(10 + level, s.ps, level)
+        ext = s.ctx.empty_poly(0).new_empty((s.ctx.beta(level), level + 1 + s.ps.K, s.N))
+        s.ctx.ckks_modup(s.dev(d), level, ext)
+        assert_equal(s.host(ext), oracle.modup(s.P, d, level), "modup level %d" % level)
+
+
+@pytest.mark.parametrize("name", ["small", "large"])
+def test_inner_product(name):
+    s = setup(name)
+    key, kh = s.key(5, 0)
+    for level in LEVELS[name][:2]:
+        beta, rows = s.ctx.beta(level), level + 1 + s.ps.K
+        mods = s.P.row_moduli(level)
+        ext = np.stack([inputs.uniform_residues(inputs.rng(20 + j), mods, s.N) for j in range(beta)])
+        te = s.dev(ext)
+        for g in [1, 5, 2 * s.N - 1]:
+            acc = te.new_empty((2, rows, s.N))
+            s.ctx.ckks_inner_product(te, level, kh, g, acc)
+            assert_equal(s.host(acc), oracle.inner_product(s.P, ext, key, level, g), "ip level %d g %d" % (level, g))
+
+
+@pytest.mark.parametrize("name", ["small", "large"])
+def test_moddown(name):
+    s = setup(name)
+    for level in LEVELS[name]:
+        x = inputs.uniform_residues(inputs.rng(30 + level), s.P.row_moduli(level), s.N)
+        out = s.ctx.empty_poly(level)
+        s.ctx.ckks_moddown(s.dev(x), level, out)
+        assert_equal(s.host(out), oracle.moddown(s.P, x, level), "moddown level %d" % level)
+
+
+@pytest.mark.parametrize("name", ["small", "large"])
+def test_keyswitch(name):
+    s = setup(name)
+    key, kh = s.key(6, 0)
+    for level in LEVELS[name]:
+        d = inputs.random_poly(40 + level, s.ps, level)
+        o0, o1 = s.ctx.empty_poly(level), s.ctx.empty_poly(level)
+        s.ctx.ckks_keyswitch(s.dev(d), level, kh, o0, o1)
+        w0, w1 = oracle.keyswitch(s.P, d, key, level)
+        assert_equal(s.host(o0), w0, "ks0 level %d" % level)
+        assert_equal(s.host(o1), w1, "ks1 level %d" % level)
+
+
+@pytest.mark.parametrize("name", ["small", "large"])
+def test_hmult_relin(name):
+    s = setup(name)
+    key, kh = s.key(7, 0)
+    for level in LEVELS[name][:3]:
+        a, ta = s.ct(50 + level, level)
+        b, tb = s.ct(60 + level, level)
+        out = s.ctx.empty_ct(level)
+        s.ctx.ckks_hmult_relin(ta, tb, kh, out)
+        w0, w1 = oracle.hmult_relin(s.P, a, b, key, level)
+        assert_equal(s.host(out.c0), w0, "hmult c0 level %d" % level)
+        assert_equal(s.host(out.c1), w1, "hmult c1 level %d" % level)
+
+
+@pytest.mark.parametrize("name", ["small", "large"])
+def test_rescale_out_of_place_and_in_place(name):
+    s = setup(name)
+    for level in [l for l in LEVELS[name] if l > 0] + [1]:
+        c, tc = s.ct(70 + level, level)
+        w0, w1 = oracle.rescale(s.P, c, level)
+        out = s.ctx.empty_ct(level - 1)
+        s.ctx.ckks_rescale(tc, out)
+        assert out.level == level - 1
+        assert_equal(s.host(out.c0), w0, "rescale c0 level %d" % level)
+        assert_equal(s.host(out.c1), w1, "rescale c1 level %d" % level)
+        # in place: the output views the first `level` limbs of the input buffers
+        inplace = s.ckks.Ciphertext(tc.c0[:level], tc.c1[:level], level - 1)
+        s.ctx.ckks_rescale(tc, inplace)
+        assert_equal(s.host(tc.c0[:level]), w0, "rescale in place c0")
+        assert_equal(s.host(tc.c1[:level]), w1, "rescale in place c1")
+
+
+@pytest.mark.parametrize("name", ["small", "large"])
+def test_hrotate_and_conjugate(name):
+    s = setup(name)
+    level = LEVELS[name][0]
+    c, tc = s.ct(80, level)
+    for k in [1, inputs.rotation_index(3, s.ps.logn), -1]:
+        g = oracle.galois_for_rotation(s.ps.logn, k)
+        key, kh = s.key(90 + g % 1000, g)
+        out = s.ctx.empty_ct(level)
+        s.ctx.ckks_hrotate(tc, k, kh, out)
+        w0, w1 = oracle.apply_galois(s.P, c, g, key, level)
+        assert_equal(s.host(out.c0), w0, "rotate %d c0" % k)
+        assert_equal(s.host(out.c1), w1, "rotate %d c1" % k)
+    g = 2 * s.N - 1
+    key, kh = s.key(99, g)
+    out = s.ctx.empty_ct(level)
+    s.ctx.ckks_conjugate(tc, kh, out)
+    w0, w1 = oracle.apply_galois(s.P, c, g, key, level)
+    assert_equal(s.host(out.c0), w0, "conjugate c0")
+    assert_equal(s.host(out.c1), w1, "conjugate c1")
+
+
+@pytest.mark.parametrize("name", ["small", "large"])
+def test_hoisted_rotations(name):
+    s = setup(name)
+    level = LEVELS[name][1]
+    c, tc = s.ct(81, level)
+    ks = [1, 2, 16, 5]
+    gs = [oracle.galois_for_rotation(s.ps.logn, k) for k in ks]
+    keys = [s.key(200 + i, g) for i, g in enumerate(gs)]
+    outs = [s.ctx.empty_ct(level) for _ in ks]
+    s.ctx.ckks_hrotate_hoisted(tc, ks, [k[1] for k in keys], outs)
+    w0, w1 = oracle.hoisted_rotate(s.P, c, gs, [k[0] for k in keys], level)
+    for i in range(len(ks)):
+        assert_equal(s.host(outs[i].c0), w0[i], "hoisted %d c0" % ks[i])
+        assert_equal(s.host(outs[i].c1), w1[i], "hoisted %d c1" % ks[i])
+
+
+@pytest.mark.parametrize("name", ["small", "large"])
+def test_elementwise_ops(name):
+    s = setup(name)
+    level = LEVELS[name][1]
+    mods = s.ps.q[: level + 1]
+    a, b, c = (inputs.random_poly(300 + i, s.ps, level) for i in range(3))
+    ta, tb, tc = s.dev(a), s.dev(b), s.dev(c)
+    out = s.ctx.empty_poly(level)
+    lg = s.ps.logn
+    s.ctx.ckks_poly_add(ta, tb, out, level)
+    assert_equal(s.host(out), oracle.vec(mods, a, b, "add", lg), "add")
+    s.ctx.ckks_poly_sub(ta, tb, out, level)
+    assert_equal(s.host(out), oracle.vec(mods, a, b, "sub", lg), "sub")
+    s.ctx.ckks_poly_mul(ta, tb, out, level)
+    assert_equal(s.host(out), oracle.vec(mods, a, b, "mul", lg), "mul")
+    s.ctx.ckks_poly_mul_add(ta, tb, tc, out, level)
+    assert_equal(s.host(out), oracle.vec(mods, oracle.vec(mods, a, b, "mul", lg), c, "add", lg), "mul_add")
+    sc = [int(m) - 1 - i for i, m in enumerate(mods)]
+    scal = np.array([[v] * s.N for v in sc], dtype=np.uint64)
+    s.ctx.ckks_poly_scalar_mul(ta, sc, out, level)
+    assert_equal(s.host(out), oracle.vec(mods, a, scal, "mul", lg), "scalar_mul")
+    s.ctx.ckks_poly_scalar_add(ta, sc, out, level)
+    assert_equal(s.host(out), oracle.vec(mods, a, scal, "add", lg), "scalar_add")
+    g = oracle.galois_for_rotation(lg, 7)
+    s.ctx.ckks_automorph(ta, g, out)
+    assert_equal(s.host(out), oracle.automorph_eval(lg, g, a), "automorph")
