@@ -1,0 +1,223 @@
+"""Benchmark of the CKKS key-switching hot path on one MI355X.
+
+Workload (N = 2^16, 31 ciphertext limbs (one 60-bit, thirty 50-bit primes),
+dnum = 3, four 60-bit special primes, top level l = 30): one step is one
+HMult+relinearisation, one Rescale of its result and one HRotate by a seeded
+slot index, on seeded uniform ciphertexts and keys (timing does not depend on
+the values).  Every step holds two key switches; `value` is key switches per
+second over the timed steps.
+
+Prints one JSON line.  Also reported: per-operation latencies (p50 / p99), a
+cold-pool rate (each step on a different ciphertext pair and key set, cycling
+through more than 1 GiB), the dominant kernel's roofline figures measured live
+with HIP events on the library's stream, and the CPU oracle timed on a bounded
+sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cold-sets", type=int, default=6)
+    return ap.parse_args()
+
+
+def percentile(xs, p):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    k = (len(xs) - 1) * p / 100.0
+    lo = int(k)
+    hi = min(lo + 1, len(xs) - 1)
+    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this library runs the key-switching path on a single MI355X; "
+              "--gpus %d is not supported" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2507_04775_amd import ckks, inputs
+
+    torch.cuda.set_device(0)
+    ps = inputs.params("large")
+    level = ps.L
+    ctx = ckks.Context(ps.logn, ps.q, ps.p, ps.dnum, device=0)
+    seed = inputs.BASE_SEED + 1
+    k_rot = inputs.rotation_index(seed, ps.logn)
+    g_rot = pow(5, k_rot, 2 * ps.N)
+
+    def make_set(s):
+        a = inputs.random_ct(s, ps, level)
+        b = inputs.random_ct(s + 1, ps, level)
+        ta = ckks.Ciphertext(ckks.to_device(a[0]), ckks.to_device(a[1]), level, 2.0 ** ps.log_scale)
+        tb = ckks.Ciphertext(ckks.to_device(b[0]), ckks.to_device(b[1]), level, 2.0 ** ps.log_scale)
+        rlk = ctx.key(ckks.to_device(inputs.random_key(s + 2, ps)), 0)
+        rk = ctx.key(ckks.to_device(inputs.random_key(s + 3, ps)), g_rot)
+        return ta, tb, rlk, rk
+
+    sets = [make_set(seed + 10 * i) for i in range(max(1, args.cold_sets))]
+    m = ctx.empty_ct(level)
+    r = ctx.empty_ct(level - 1)
+    rot = ctx.empty_ct(level)
+    ws_h = ctx.workspace(ckks.OP_HMULT, level)
+    ws_r = ctx.workspace(ckks.OP_RESCALE, level)
+    ws_k = ctx.workspace(ckks.OP_ROTATE, level)
+    stream = torch.cuda.current_stream()
+
+    def hmult(s):
+        ta, tb, rlk, _ = s
+        ctx.ckks_hmult_relin(ta, tb, rlk, m, ws_h)
+
+    def rescale(s):
+        ctx.ckks_rescale(m, r, ws_r)
+
+    def hrotate(s):
+        ta, _, _, rk = s
+        ctx.ckks_hrotate(ta, k_rot, rk, rot, ws_k)
+
+    def step(s):
+        hmult(s)
+        rescale(s)
+        hrotate(s)
+
+    # ---- warm-up, then the timed region (same buffers every step: warm)
+    for _ in range(args.warmup):
+        step(sets[0])
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for i in range(args.steps):
+        step(sets[0])
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)]
+    total_ms = ev[0].elapsed_time(ev[-1])
+    ms_per_step = total_ms / args.steps
+    ks_per_step = 2
+    value = ks_per_step * args.steps / (total_ms / 1e3)
+
+    # ---- cold pool: every step on another ciphertext pair and key set
+    cold = None
+    if len(sets) > 1:
+        for s in sets:
+            step(s)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        n_cold = max(len(sets), args.steps)
+        e0.record(stream)
+        for i in range(n_cold):
+            step(sets[i % len(sets)])
+        e1.record(stream)
+        torch.cuda.synchronize()
+        cold_ms = e0.elapsed_time(e1) / n_cold
+        pool_bytes = len(sets) * (4 * (level + 1) + 2 * ps.dnum * 2 * (ps.L + 1 + ps.K)) * ps.N * 8
+        cold = {"ms_per_step": round(cold_ms, 4), "key_switches_per_s": round(ks_per_step / (cold_ms / 1e3), 1),
+                "pool_bytes": pool_bytes, "sets": len(sets)}
+
+    # ---- per-operation latencies
+    def op_stats(fn, reps):
+        es = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+        es[0].record(stream)
+        for i in range(reps):
+            fn(sets[0])
+            es[i + 1].record(stream)
+        torch.cuda.synchronize()
+        xs = [es[i].elapsed_time(es[i + 1]) for i in range(reps)]
+        return {"p50_us": round(percentile(xs, 50) * 1e3, 2), "p99_us": round(percentile(xs, 99) * 1e3, 2),
+                "mean_us": round(sum(xs) / len(xs) * 1e3, 2)}
+
+    reps = max(20, args.steps)
+    ops = {"hmult_relin": op_stats(hmult, reps), "rescale": op_stats(rescale, reps), "hrotate": op_stats(hrotate, reps)}
+    ntt_poly = ctx.empty_poly(ps.L + ps.K)
+    ntt_poly.copy_(ckks.to_device(inputs.uniform_residues(inputs.rng(seed + 99), list(ps.q) + list(ps.p), ps.N)))
+    ops["ntt_35_limbs"] = op_stats(lambda s: ctx.ckks_ntt(ntt_poly), reps)
+    ops["intt_35_limbs"] = op_stats(lambda s: ctx.ckks_intt(ntt_poly), reps)
+
+    # ---- dominant kernel: the forward NTT over all 35 limbs (two passes, 16 x 35 workgroups each),
+    # timed on the library's stream; algorithmic bytes = read + write of every limb once.
+    ntt_ms = ops["ntt_35_limbs"]["mean_us"] / 1e3
+    ntt_bytes = (ps.L + 1 + ps.K) * ps.N * 8 * 2
+    achieved = ntt_bytes / (ntt_ms / 1e3) / 1e9
+    roofline = {"bound": "hbm", "kernel": "ntt16_fwd (column + row pass) over 35 limbs",
+                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "algorithmic_bytes_per_launch": ntt_bytes, "launch_us": round(ntt_ms * 1e3, 2)}
+
+    # ---- CPU oracle on a bounded sample of the same step
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        P = oracle.Params(ps.logn, ps.q, ps.p, ps.dnum)
+        a = inputs.random_ct(seed, ps, level)
+        b = inputs.random_ct(seed + 1, ps, level)
+        rlk = inputs.random_key(seed + 2, ps)
+        rk = inputs.random_key(seed + 3, ps)
+        oracle.lib()
+        n_steps, t_cpu = 0, 0.0
+        while t_cpu < args.cpu_seconds and n_steps < 50:
+            t1 = time.perf_counter()
+            mm = oracle.hmult_relin(P, a, b, rlk, level)
+            oracle.rescale(P, mm, level)
+            oracle.apply_galois(P, a, g_rot, rk, level)
+            t_cpu += time.perf_counter() - t1
+            n_steps += 1
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        cpu = {"value": round(ks_per_step * n_steps / t_cpu, 3), "unit": "key-switches/s", "cores": threads,
+               "kind": "oracle",
+               "sample": "%d steps (HMult+relin, Rescale, HRotate at l=30, N=2^16) in %.1f s" % (n_steps, t_cpu)}
+
+    out = {
+        "metric": "key-switches/s at logN=16 (1 GPU), plain per-op calls",
+        "value": round(value, 1),
+        "unit": "key-switches/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic (seeded uniform residues; timing is value-independent)",
+        "config": {"workload": "HMult+relin + Rescale + HRotate at level 30", "logN": ps.logn,
+                   "limbs": ps.L + 1, "special_primes": ps.K, "dnum": ps.dnum, "key_switches_per_step": ks_per_step,
+                   "parallelism": "single GPU"},
+        "step_p50_ms": round(percentile(step_ms, 50), 4),
+        "step_p99_ms": round(percentile(step_ms, 99), 4),
+        "wall_s": round(wall, 3),
+        "cold": cold,
+        "ops": ops,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
