@@ -19,7 +19,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 SOURCES = ["context.cpp", "api.cpp", "ntt.hip", "kernels.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-Wall", "-Wno-unused-result", "-Wno-unused-function"]
+         "-ffp-contract=off", "-Wall", "-Wno-unused-result", "-Wno-unused-function"]
 
 
 def build(verbose: bool = False) -> str:

@@ -91,6 +91,7 @@ NttArgs base_args(const ckks_ctx *c, bool inverse)
     memset(&a, 0, sizeof(a));
     a.primes = c->d_primes;
     a.tw = inverse ? c->d_tw_inv : c->d_tw_fwd;
+    a.twd = inverse ? c->d_twd_inv : c->d_twd_fwd;
     a.logn = c->logn;
     a.galois = 1;
     a.map.nq = c->nq;
@@ -98,7 +99,9 @@ NttArgs base_args(const ckks_ctx *c, bool inverse)
     return a;
 }
 
-// INTT of d (optionally gathered through X -> X^g) into dc.
+// INTT of d (optionally gathered through X -> X^g) into dc, leaving the
+// scaled base-conversion inputs y_i = [x_i (D_j/q_i)^-1]_{q_i} of each digit
+// (the scale and N^-1 are one constant of the last inverse pass).
 hipError_t modup_intt(const ckks_ctx *c, const uint64_t *d, uint32_t g, uint32_t level, uint64_t *dc, hipStream_t st)
 {
     NttArgs a = base_args(c, true);
@@ -107,14 +110,20 @@ hipError_t modup_intt(const ckks_ctx *c, const uint64_t *d, uint32_t g, uint32_t
     a.galois = g;
     a.map.rows = level + 1;
     a.map.prime0 = 0;
+    a.ys_mode = 1;
+    a.alpha = c->alpha;
+    a.nlev = level + 1;
+    a.ys = c->d_bc_ys;
+    a.ysd = c->d_bc_ysd;
     return launch_ntt_inv(a, level + 1, g == 1 ? PRO_PLAIN : PRO_GALOIS, st, dc, 0);
 }
 
-// ModUp from the coefficient-domain dc: base conversion of every digit into
-// ext, own rows copied (gathered through g) from the evaluation-domain d,
-// then the forward NTT of every converted row.
+// ModUp from the scaled coefficients dc: base conversion of every digit into
+// ext, then the forward NTT of every converted row.  With copy_own the digit's
+// own rows are copied (gathered through g) from the evaluation-domain d;
+// otherwise they are left unwritten and read from d by the inner product.
 hipError_t modup_from_coeffs(const ckks_ctx *c, const uint64_t *d, uint32_t g, uint32_t level, const uint64_t *dc,
-                             uint64_t *ext, hipStream_t st)
+                             uint64_t *ext, bool copy_own, hipStream_t st)
 {
     KsSizes s = ks_sizes(c, level);
     BconvArgs b;
@@ -126,7 +135,7 @@ hipError_t modup_from_coeffs(const ckks_ctx *c, const uint64_t *d, uint32_t g, u
         BconvJob &J = b.job[j];
         J.src = dc + (size_t)lo * s.N;
         J.dst = ext + (size_t)j * s.rows * s.N;
-        J.copy_src = d;
+        J.copy_src = copy_own ? d : nullptr;
         J.hinv = c->d_bc_hinv + (size_t)set * kMaxDigitPrimes;
         J.hmod = c->d_bc_hmod + (size_t)set * hm_stride;
         J.ns = hi - lo;
@@ -141,6 +150,7 @@ hipError_t modup_from_coeffs(const ckks_ctx *c, const uint64_t *d, uint32_t g, u
     b.N = c->N;
     b.logn = c->logn;
     b.copy_galois = g;
+    b.prescaled = 1;
     hipError_t e = launch_bconv(b, s.beta, st);
     if (e != hipSuccess) return e;
     NttArgs a = base_args(c, false);
@@ -154,7 +164,7 @@ hipError_t modup_from_coeffs(const ckks_ctx *c, const uint64_t *d, uint32_t g, u
 }
 
 hipError_t inner_product(const ckks_ctx *c, const uint64_t *ext, uint32_t level, const uint64_t *key, uint32_t g,
-                         uint64_t *acc, hipStream_t st)
+                         uint64_t *acc, hipStream_t st, const uint64_t *own = nullptr, uint32_t own_galois = 1)
 {
     KsSizes s = ks_sizes(c, level);
     IpArgs a;
@@ -168,12 +178,19 @@ hipError_t inner_product(const ckks_ctx *c, const uint64_t *ext, uint32_t level,
     a.nq = c->nq;
     a.np = c->np;
     a.logn = c->logn;
+    a.alpha = c->alpha;
     a.galois = g;
+    a.own = own;
+    a.own_galois = own_galois;
     return launch_inner_product(a, st);
 }
 
 // ModDown of npoly accumulators acc[t] (rows q_0..q_l, p_0..p_{K-1}, stride
-// acc_stride) into out[t] = P^-1 (acc_t - conv_t) + add_t (gathered through g).
+// acc_stride) into out[t] = P^-1 (acc_t - NTT(Conv_{P->q}(INTT(acc_t|P)))) + add_t
+// (add gathered through g).  The special rows' iNTT leaves the scaled
+// conversion inputs y_k = [a_k (P/p_k)^-1] (N^-1 folded into the same
+// constant); the forward NTT computes the conversion in its first pass and the
+// P^-1 (x - .) + add sequence in its last (III-F.5 ModDown fusion).
 hipError_t moddown(const ckks_ctx *c, const uint64_t *acc, int64_t acc_stride, uint32_t npoly, uint32_t level,
                    uint64_t *const *out, const uint64_t *const *add, uint32_t g, uint64_t *pc, uint64_t *conv,
                    hipStream_t st)
@@ -188,28 +205,11 @@ hipError_t moddown(const ckks_ctx *c, const uint64_t *acc, int64_t acc_stride, u
     ia.map.row0 = s.n;
     ia.map.src_poly_stride = acc_stride;
     ia.map.dst_poly_stride = kN;
+    ia.ys_mode = 2;
+    ia.pset = c->pset_index();
+    ia.ys = c->d_bc_ys;
+    ia.ysd = c->d_bc_ysd;
     hipError_t e = launch_ntt_inv(ia, npoly * c->np, PRO_PLAIN, st, pc, kN);
-    if (e != hipSuccess) return e;
-    BconvArgs b;
-    memset(&b, 0, sizeof(b));
-    const size_t hm_stride = (size_t)(c->nq + c->np) * kMaxDigitPrimes;
-    for (uint32_t t = 0; t < npoly; ++t) {
-        BconvJob &J = b.job[t];
-        J.src = pc + t * kN;
-        J.dst = conv + t * nN;
-        J.hinv = c->d_bc_hinv + (size_t)c->pset_index() * kMaxDigitPrimes;
-        J.hmod = c->d_bc_hmod + (size_t)c->pset_index() * hm_stride;
-        J.ns = c->np;
-        J.src_prime0 = c->nq;
-    }
-    b.primes = c->d_primes;
-    b.nrows = s.n;
-    b.level = level;
-    b.nq = c->nq;
-    b.N = c->N;
-    b.logn = c->logn;
-    b.copy_galois = 1;
-    e = launch_bconv(b, npoly, st);
     if (e != hipSuccess) return e;
     NttArgs a = base_args(c, false);
     a.src = conv;
@@ -219,16 +219,23 @@ hipError_t moddown(const ckks_ctx *c, const uint64_t *acc, int64_t acc_stride, u
     a.map.src_poly_stride = a.map.dst_poly_stride = nN;
     a.galois = g;
     a.cst = c->d_pinv;
+    a.bc_mode = 2;
+    a.bc_src = pc;
+    a.bc_poly_stride = kN;
+    a.pset = c->pset_index();
+    a.nprimes = c->nq + c->np;
+    a.hmod = c->d_bc_hmod;
     for (uint32_t t = 0; t < npoly; ++t) {
         a.aux[t] = acc + t * acc_stride;
         a.add[t] = add ? add[t] : nullptr;
         a.out[t] = out[t];
     }
-    return launch_ntt_fwd(a, npoly * s.n, PRO_PLAIN, EPI_MODDOWN, st, conv, nN);
+    return launch_ntt_fwd(a, npoly * s.n, PRO_BCONV, EPI_MODDOWN, st, conv, nN);
 }
 
 // Full key switch of d (gathered through g_in) with `key`; outputs
-// out_t = KS_t + add_t (add gathered through g_add).
+// out_t = KS_t + add_t (add gathered through g_add).  The digits' own rows are
+// never copied: the inner product reads them from d directly.
 hipError_t keyswitch_core(const ckks_ctx *c, const uint64_t *d, uint32_t g_in, uint32_t level, const uint64_t *key,
                           uint64_t *out0, uint64_t *out1, const uint64_t *add0, const uint64_t *add1, uint32_t g_add,
                           void *ws, hipStream_t st)
@@ -236,8 +243,8 @@ hipError_t keyswitch_core(const ckks_ctx *c, const uint64_t *d, uint32_t g_in, u
     KsSizes s = ks_sizes(c, level);
     KsWs w = ks_ws(c, level, ws);
     hipError_t e = modup_intt(c, d, g_in, level, w.dc, st);
-    if (e == hipSuccess) e = modup_from_coeffs(c, d, g_in, level, w.dc, w.ext, st);
-    if (e == hipSuccess) e = inner_product(c, w.ext, level, key, 1, w.acc, st);
+    if (e == hipSuccess) e = modup_from_coeffs(c, d, g_in, level, w.dc, w.ext, false, st);
+    if (e == hipSuccess) e = inner_product(c, w.ext, level, key, 1, w.acc, st, d, g_in);
     if (e != hipSuccess) return e;
     uint64_t *outs[2] = {out0, out1};
     const uint64_t *adds[2] = {add0, add1};
@@ -365,7 +372,7 @@ extern "C" ckks_status ckks_modup(ckks_ctx *ctx, const uint64_t *d, uint32_t lev
     if (overlap(ext, eb, d, db) || overlap(ext, eb, ws, db) || overlap(d, db, ws, db))
         return fail(CKKS_E_ARG, "ckks_modup: d, ext and ws must not overlap");
     hipError_t e = modup_intt(ctx, d, 1, level, (uint64_t *)ws, S(stream));
-    if (e == hipSuccess) e = modup_from_coeffs(ctx, d, 1, level, (uint64_t *)ws, ext, S(stream));
+    if (e == hipSuccess) e = modup_from_coeffs(ctx, d, 1, level, (uint64_t *)ws, ext, true, S(stream));
     return dev(e, "ckks_modup");
 }
 
@@ -604,9 +611,9 @@ extern "C" ckks_status ckks_hrotate_hoisted(ckks_ctx *ctx, const ckks_ct *in, ui
     KsSizes s = ks_sizes(ctx, level);
     KsWs w = ks_ws(ctx, level, ws);
     hipError_t e = modup_intt(ctx, in->c1, 1, level, w.dc, S(stream));
-    if (e == hipSuccess) e = modup_from_coeffs(ctx, in->c1, 1, level, w.dc, w.ext, S(stream));
+    if (e == hipSuccess) e = modup_from_coeffs(ctx, in->c1, 1, level, w.dc, w.ext, false, S(stream));
     for (uint32_t i = 0; i < n && e == hipSuccess; ++i) {
-        e = inner_product(ctx, w.ext, level, keys[i]->data, gs[i], w.acc, S(stream));
+        e = inner_product(ctx, w.ext, level, keys[i]->data, gs[i], w.acc, S(stream), in->c1, gs[i]);
         if (e != hipSuccess) break;
         uint64_t *outs[2] = {out[i].c0, out[i].c1};
         const uint64_t *adds[2] = {in->c0, nullptr};

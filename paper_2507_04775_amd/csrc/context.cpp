@@ -143,6 +143,7 @@ extern "C" ckks_status ckks_ctx_create(uint32_t log_n, const uint64_t *q, uint32
     // ---- host tables
     std::vector<Prime> hp(np_all);
     std::vector<ulonglong2> tw_f((size_t)np_all * N), tw_i((size_t)np_all * N);
+    std::vector<double> twd_f((size_t)np_all * N), twd_i((size_t)np_all * N);
     for (uint32_t i = 0; i < np_all; ++i) {
         uint64_t m = primes[i];
         Prime &P = hp[i];
@@ -153,13 +154,15 @@ extern "C" ckks_status ckks_ctx_create(uint32_t log_n, const uint64_t *q, uint32
         P.one_s = shoup_of(1, m);
         P.ninv = inv_mod(N % m, m);
         P.ninv_s = shoup_of(P.ninv, m);
-        P.pad = 0;
+        P.qinv = 1.0 / (double)m;
         uint64_t psi = smallest_2n_root(m, two_n), ipsi = inv_mod(psi, m);
         uint64_t f = 1, b = 1;
         for (uint32_t k = 0; k < N; ++k) {
             uint32_t pos = reverse_bits(k, log_n);
             tw_f[(size_t)i * N + pos] = pair(f, m);
             tw_i[(size_t)i * N + pos] = pair(b, m);
+            twd_f[(size_t)i * N + pos] = m < kFpMaxPrime ? (double)f : 0.0;
+            twd_i[(size_t)i * N + pos] = m < kFpMaxPrime ? (double)b : 0.0;
             f = mul_mod(f, psi, m);
             b = mul_mod(b, ipsi, m);
         }
@@ -169,12 +172,18 @@ extern "C" ckks_status ckks_ctx_create(uint32_t log_n, const uint64_t *q, uint32
     const size_t hm_stride = (size_t)np_all * kMaxDigitPrimes;
     std::vector<ulonglong2> bc_hinv((size_t)ctx->nsets * kMaxDigitPrimes);
     std::vector<uint64_t> bc_hmod((size_t)ctx->nsets * hm_stride, 0);
+    std::vector<ulonglong2> bc_ys((size_t)ctx->nsets * kMaxDigitPrimes);
+    std::vector<double> bc_ysd((size_t)ctx->nsets * kMaxDigitPrimes, 0.0);
     auto build_set = [&](uint32_t set, const uint64_t *src, uint32_t ns) {
         for (uint32_t i = 0; i < ns; ++i) {
             uint64_t prod = 1;
             for (uint32_t k = 0; k < ns; ++k)
                 if (k != i) prod = mul_mod(prod, src[k] % src[i], src[i]);
-            bc_hinv[(size_t)set * kMaxDigitPrimes + i] = pair(inv_mod(prod, src[i]), src[i]);
+            uint64_t hinv = inv_mod(prod, src[i]);
+            bc_hinv[(size_t)set * kMaxDigitPrimes + i] = pair(hinv, src[i]);
+            uint64_t ys = mul_mod(hinv, inv_mod(N % src[i], src[i]), src[i]);
+            bc_ys[(size_t)set * kMaxDigitPrimes + i] = pair(ys, src[i]);
+            bc_ysd[(size_t)set * kMaxDigitPrimes + i] = (double)ys;
             for (uint32_t c = 0; c < np_all; ++c) {
                 uint64_t v = 1;
                 for (uint32_t k = 0; k < ns; ++k)
@@ -208,9 +217,13 @@ extern "C" ckks_status ckks_ctx_create(uint32_t log_n, const uint64_t *q, uint32
     size_t off_primes = 0;
     size_t off_twf = align_up(off_primes + np_all * sizeof(Prime));
     size_t off_twi = align_up(off_twf + tw_f.size() * sizeof(ulonglong2));
-    size_t off_hinv = align_up(off_twi + tw_i.size() * sizeof(ulonglong2));
+    size_t off_twdf = align_up(off_twi + tw_i.size() * sizeof(ulonglong2));
+    size_t off_twdi = align_up(off_twdf + twd_f.size() * sizeof(double));
+    size_t off_hinv = align_up(off_twdi + twd_i.size() * sizeof(double));
     size_t off_hmod = align_up(off_hinv + bc_hinv.size() * sizeof(ulonglong2));
-    size_t off_pinv = align_up(off_hmod + bc_hmod.size() * sizeof(uint64_t));
+    size_t off_ys = align_up(off_hmod + bc_hmod.size() * sizeof(uint64_t));
+    size_t off_ysd = align_up(off_ys + bc_ys.size() * sizeof(ulonglong2));
+    size_t off_pinv = align_up(off_ysd + bc_ysd.size() * sizeof(double));
     size_t off_rsi = align_up(off_pinv + pinv.size() * sizeof(ulonglong2));
     size_t off_rsm = align_up(off_rsi + rs_inv.size() * sizeof(ulonglong2));
     size_t total = align_up(off_rsm + rs_mod.size() * sizeof(uint64_t));
@@ -223,8 +236,12 @@ extern "C" ckks_status ckks_ctx_create(uint32_t log_n, const uint64_t *q, uint32
     ctx->d_primes = (Prime *)(blk + off_primes);
     ctx->d_tw_fwd = (ulonglong2 *)(blk + off_twf);
     ctx->d_tw_inv = (ulonglong2 *)(blk + off_twi);
+    ctx->d_twd_fwd = (double *)(blk + off_twdf);
+    ctx->d_twd_inv = (double *)(blk + off_twdi);
     ctx->d_bc_hinv = (ulonglong2 *)(blk + off_hinv);
     ctx->d_bc_hmod = (uint64_t *)(blk + off_hmod);
+    ctx->d_bc_ys = (ulonglong2 *)(blk + off_ys);
+    ctx->d_bc_ysd = (double *)(blk + off_ysd);
     ctx->d_pinv = (ulonglong2 *)(blk + off_pinv);
     ctx->d_rs_inv = (ulonglong2 *)(blk + off_rsi);
     ctx->d_rs_mod = (uint64_t *)(blk + off_rsm);
@@ -233,9 +250,17 @@ extern "C" ckks_status ckks_ctx_create(uint32_t log_n, const uint64_t *q, uint32
                   hipSuccess &&
               hipMemcpy(ctx->d_tw_inv, tw_i.data(), tw_i.size() * sizeof(ulonglong2), hipMemcpyHostToDevice) ==
                   hipSuccess &&
+              hipMemcpy(ctx->d_twd_fwd, twd_f.data(), twd_f.size() * sizeof(double), hipMemcpyHostToDevice) ==
+                  hipSuccess &&
+              hipMemcpy(ctx->d_twd_inv, twd_i.data(), twd_i.size() * sizeof(double), hipMemcpyHostToDevice) ==
+                  hipSuccess &&
               hipMemcpy(ctx->d_bc_hinv, bc_hinv.data(), bc_hinv.size() * sizeof(ulonglong2),
                         hipMemcpyHostToDevice) == hipSuccess &&
               hipMemcpy(ctx->d_bc_hmod, bc_hmod.data(), bc_hmod.size() * sizeof(uint64_t), hipMemcpyHostToDevice) ==
+                  hipSuccess &&
+              hipMemcpy(ctx->d_bc_ys, bc_ys.data(), bc_ys.size() * sizeof(ulonglong2), hipMemcpyHostToDevice) ==
+                  hipSuccess &&
+              hipMemcpy(ctx->d_bc_ysd, bc_ysd.data(), bc_ysd.size() * sizeof(double), hipMemcpyHostToDevice) ==
                   hipSuccess &&
               hipMemcpy(ctx->d_pinv, pinv.data(), pinv.size() * sizeof(ulonglong2), hipMemcpyHostToDevice) ==
                   hipSuccess &&

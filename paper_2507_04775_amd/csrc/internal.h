@@ -61,7 +61,7 @@ __device__ __forceinline__ uint32_t galois_src(uint32_t e, uint32_t g, uint32_t 
 }
 
 // Prologue of the first forward pass / epilogue of the last forward pass.
-enum NttPro { PRO_PLAIN = 0, PRO_RESCALE = 1, PRO_GALOIS = 2 };
+enum NttPro { PRO_PLAIN = 0, PRO_RESCALE = 1, PRO_GALOIS = 2, PRO_BCONV = 3 };
 enum NttEpi { EPI_PLAIN = 0, EPI_MODDOWN = 1, EPI_RESCALE = 2 };
 
 struct NttArgs {
@@ -70,6 +70,7 @@ struct NttArgs {
     LimbMap map;
     const Prime *primes;
     const ulonglong2 *tw;       // [n_primes][N] {w, floor(w 2^64 / q)}
+    const double *twd;          // [n_primes][N] w as a double (primes below 2^50)
     uint32_t logn;
     uint32_t galois;            // PRO_GALOIS gather / addend gather (1 = none)
     // EPI_MODDOWN: out_p = Pinv (aux_p - x) + add_p ; EPI_RESCALE: out_p = qlinv (aux_p - x)
@@ -81,6 +82,36 @@ struct NttArgs {
     const uint64_t *rs_src[2];
     const uint64_t *rs_qlmod;
     uint64_t rs_ql;
+    // Last inverse pass: multiply by N^-1 (ys_mode 0), or by N^-1 [(B/b_i)^-1]_{b_i}, the scale
+    // that turns the row into the input of a fast base conversion from basis B: the ModUp digits
+    // of level nlev-1 (ys_mode 1, row i in digit i / alpha) or the special basis (ys_mode 2).
+    uint32_t ys_mode;
+    uint32_t alpha, nlev, nprimes, pset;
+    const ulonglong2 *ys;       // [nsets][kMaxDigitPrimes] Shoup pairs
+    const double *ysd;          // the same constants as doubles
+    // PRO_BCONV: the first forward pass computes its input as a fast base conversion of scaled
+    // rows (written by an inverse with ys_mode 1 or 2).  bc_mode 1: ModUp, polynomial j of the
+    // launch is digit j and its source rows are bc_src rows j alpha ..; bc_mode 2: ModDown,
+    // polynomial t reads the K rows at bc_src + t bc_poly_stride.
+    const uint64_t *bc_src;
+    int64_t bc_poly_stride;
+    uint32_t bc_mode;
+    const uint64_t *hmod;       // [nsets][n_primes][kMaxDigitPrimes]
+};
+
+// ModUp's last forward pass fused with the key inner product: row r of the
+// extended basis is transformed for every digit (or, for the digit's own rows,
+// taken from d) and multiplied into both key halves, summed over the digits.
+struct RowIpArgs {
+    const uint64_t *mid;        // [beta][rows][N] first-pass output
+    const uint64_t *d;          // [l+1][N] evaluation-domain input (own rows of each digit)
+    uint32_t d_galois;          // own rows gathered through X -> X^g (1 = none)
+    const uint64_t *key;        // [dnum][2][nq+np][N]
+    uint64_t *acc;              // [2][rows][N]
+    const Prime *primes;
+    const ulonglong2 *tw;
+    const double *twd;
+    uint32_t beta, rows, level, nq, np, alpha, logn;
 };
 
 struct BconvJob {
@@ -101,14 +132,20 @@ struct BconvArgs {
     uint32_t level, nq;         // row -> prime map as in LimbMap
     uint32_t N, logn;
     uint32_t copy_galois;       // copied rows are gathered through X -> X^g (1 = plain copy)
+    uint32_t prescaled;         // sources already hold y_i (the iNTT folded the scaling in)
 };
+
+constexpr uint32_t kBconvRowGroup = 8;  // output rows per workgroup (grid z splits the rows)
 
 struct IpArgs {
     const uint64_t *ext;        // [beta][rows][N]
     const uint64_t *key;        // [dnum][2][nq+np][N]
     uint64_t *acc;              // [2][rows][N]
     const Prime *primes;
-    uint32_t beta, rows, level, nq, np, logn, galois;
+    uint32_t beta, rows, level, nq, np, logn, alpha;
+    uint32_t galois;            // every digit row gathered through X -> X^g (hoisted rotation; 1 = none)
+    const uint64_t *own;        // non-null: digit j's own rows are read from own[r] (gathered through
+    uint32_t own_galois;        // own_galois), not from ext
 };
 
 // Launchers (all asynchronous on `stream`).
@@ -116,6 +153,7 @@ hipError_t launch_ntt_fwd(const NttArgs &a, uint32_t nlimbs, NttPro pro, NttEpi 
                           uint64_t *mid, int64_t mid_poly_stride);
 hipError_t launch_ntt_inv(const NttArgs &a, uint32_t nlimbs, NttPro pro, hipStream_t stream, uint64_t *mid,
                           int64_t mid_poly_stride);
+hipError_t launch_ntt_fwd_ip(const RowIpArgs &a, const NttArgs &col, hipStream_t stream);
 hipError_t launch_bconv(const BconvArgs &a, uint32_t njobs, hipStream_t stream);
 hipError_t launch_inner_product(const IpArgs &a, hipStream_t stream);
 hipError_t launch_tensor(const uint64_t *a0, const uint64_t *a1, const uint64_t *b0, const uint64_t *b1,
@@ -139,9 +177,13 @@ struct ckks_ctx {
     ckks::Prime *d_primes = nullptr;
     ulonglong2 *d_tw_fwd = nullptr;     // [n][N]
     ulonglong2 *d_tw_inv = nullptr;     // [n][N]
+    double *d_twd_fwd = nullptr;        // [n][N] same twiddles as doubles (primes below 2^50)
+    double *d_twd_inv = nullptr;
     // base-conversion sets: digit sets indexed (j * alpha + size - 1), then the P set
     ulonglong2 *d_bc_hinv = nullptr;    // [nsets][kMaxDigitPrimes]
     uint64_t *d_bc_hmod = nullptr;      // [nsets][n_primes][kMaxDigitPrimes]
+    ulonglong2 *d_bc_ys = nullptr;      // [nsets][kMaxDigitPrimes]: N^-1 [(B/b_i)^-1]_{b_i}
+    double *d_bc_ysd = nullptr;         // the same as doubles (primes below 2^50)
     ulonglong2 *d_pinv = nullptr;       // [n_primes] P^-1 mod q_i
     ulonglong2 *d_rs_inv = nullptr;     // [nq][nq]: (level l, prime i) -> q_l^-1 mod q_i
     uint64_t *d_rs_mod = nullptr;       // [nq][nq]: q_l mod q_i

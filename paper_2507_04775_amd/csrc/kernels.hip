@@ -16,39 +16,58 @@ __device__ __forceinline__ uint32_t row_prime(uint32_t r, uint32_t level, uint32
     return r <= level ? r : nq + (r - level - 1);
 }
 
-// Conv_{B->C}: y_i = [x_i (B/b_i)^-1]_{b_i} (Shoup), then every output row c
-// gets [sum_i y_i [B/b_i]_c]_c, accumulated exactly in 128 bits and reduced
-// once (as the paper does).  blockIdx.y selects the job (digit or polynomial).
+// Conv_{B->C}: y_i = [x_i (B/b_i)^-1]_{b_i} (Shoup; skipped when the inverse
+// NTT already produced y_i), then every output row c gets
+// [sum_i y_i [B/b_i]_c]_c, accumulated exactly in 128 bits and reduced once
+// (as the paper does).  blockIdx.y selects the job (digit or polynomial),
+// blockIdx.z a group of kBconvRowGroup output rows whose constants are staged
+// in LDS.
 __global__ __launch_bounds__(kThreads) void k_bconv(BconvArgs a)
 {
     const BconvJob &J = a.job[blockIdx.y];
     const uint32_t N = a.N;
     const uint32_t n = blockIdx.x * kThreads + threadIdx.x;
+    const uint32_t r0 = blockIdx.z * kBconvRowGroup;
+    const uint32_t r1 = min(r0 + kBconvRowGroup, a.nrows);
+    __shared__ uint64_t hm[kBconvRowGroup][kMaxDigitPrimes];
+    __shared__ Prime pr[kBconvRowGroup];
+    if (threadIdx.x < kBconvRowGroup * kMaxDigitPrimes) {
+        const uint32_t rr = threadIdx.x / kMaxDigitPrimes, i = threadIdx.x % kMaxDigitPrimes;
+        if (r0 + rr < r1) {
+            const uint32_t pi = row_prime(r0 + rr, a.level, a.nq);
+            hm[rr][i] = J.hmod[(size_t)pi * kMaxDigitPrimes + i];
+            if (i == 0) pr[rr] = a.primes[pi];
+        }
+    }
+    __syncthreads();
     uint64_t y[kMaxDigitPrimes];
 #pragma unroll
     for (int i = 0; i < kMaxDigitPrimes; ++i) {
         if (i < (int)J.ns) {
-            const uint64_t qi = a.primes[J.src_prime0 + i].q;
-            const ulonglong2 h = J.hinv[i];
-            y[i] = shoup(J.src[(size_t)i * N + n], h.x, h.y, qi);
+            const uint64_t x = J.src[(size_t)i * N + n];
+            if (a.prescaled) {
+                y[i] = x;
+            } else {
+                const ulonglong2 h = J.hinv[i];
+                y[i] = shoup(x, h.x, h.y, a.primes[J.src_prime0 + i].q);
+            }
         } else {
             y[i] = 0;
         }
     }
-    for (uint32_t r = 0; r < a.nrows; ++r) {
+    for (uint32_t r = r0; r < r1; ++r) {
         if (r >= J.lo && r < J.hi) {
             if (J.copy_src)
                 J.dst[(size_t)r * N + n] =
                     J.copy_src[(size_t)r * N + (a.copy_galois == 1 ? n : galois_src(n, a.copy_galois, a.logn))];
             continue;
         }
-        const uint32_t pi = row_prime(r, a.level, a.nq);
-        const uint64_t *h = J.hmod + (size_t)pi * kMaxDigitPrimes;
+        const uint64_t *h = hm[r - r0];
         u128 acc = {0, 0};
 #pragma unroll
         for (int i = 0; i < kMaxDigitPrimes; ++i)
             if (i < (int)J.ns) acc = add128(acc, mul_wide(y[i], h[i]));
-        J.dst[(size_t)r * N + n] = reduce128(acc, a.primes[pi]);
+        J.dst[(size_t)r * N + n] = reduce128(acc, pr[r - r0]);
     }
 }
 
@@ -63,7 +82,9 @@ __global__ __launch_bounds__(kThreads) void k_inner_product(IpArgs a)
     const size_t krows = a.nq + a.np;
     u128 s0 = {0, 0}, s1 = {0, 0};
     for (uint32_t j = 0; j < a.beta; ++j) {
-        const uint64_t x = a.ext[((size_t)j * a.rows + r) * N + sn];
+        const bool own = a.own && r >= j * a.alpha && r < min(j * a.alpha + a.alpha, a.level + 1);
+        const uint64_t x = own ? a.own[(size_t)r * N + (a.own_galois == 1 ? n : galois_src(n, a.own_galois, a.logn))]
+                               : a.ext[((size_t)j * a.rows + r) * N + sn];
         const uint64_t k0 = a.key[(((size_t)j * 2 + 0) * krows + pi) * N + n];
         const uint64_t k1 = a.key[(((size_t)j * 2 + 1) * krows + pi) * N + n];
         s0 = add128(s0, mul_wide(x, k0));
@@ -126,7 +147,8 @@ __global__ __launch_bounds__(kThreads) void k_automorph(const uint64_t *__restri
 hipError_t launch_bconv(const BconvArgs &a, uint32_t njobs, hipStream_t stream)
 {
     if (njobs == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_bconv, dim3(a.N / kThreads, njobs), dim3(kThreads), 0, stream, a);
+    hipLaunchKernelGGL(k_bconv, dim3(a.N / kThreads, njobs, (a.nrows + kBconvRowGroup - 1) / kBconvRowGroup),
+                       dim3(kThreads), 0, stream, a);
     return hipGetLastError();
 }
 

@@ -70,7 +70,7 @@ struct Prime {
     uint64_t r64, r64_s;  // 2^64 mod q and its Shoup companion
     uint64_t one_s;       // floor(2^64 / q): Shoup companion of 1
     uint64_t ninv, ninv_s;  // N^-1 mod q
-    uint64_t pad;
+    double qinv;            // 1/q rounded to double (FP64 path)
 };
 
 // Reduce an exact 128-bit value z (any z < 2^128) modulo q:
@@ -91,6 +91,47 @@ __device__ __forceinline__ uint64_t mulmod(uint64_t x, uint64_t y, const Prime &
 }
 
 __device__ __forceinline__ uint64_t addmod(uint64_t a, uint64_t b, uint64_t q) { return csub(a + b, q); }
+
+// ---------------------------------------------------------------- FP64 path
+// For primes below 2^50, residues are exact integers in doubles and a modular
+// product is exact through error-free transformations (full-rate FP64 FMA on
+// CDNA4).  With u = 2^-53 and |y| <= Y, w in [0, q):
+//   h = fl(y w), l = y w - h exactly (FMA), |l| <= u |y w|;
+//   k = rint(fl(h fl(1/q))) differs from y w / q by at most 1/2 + 3u |y w| / q;
+//   r = (h - k q) + l = y w - k q exactly, since every partial result is an
+//   integer of magnitude below 2^53.
+// Hence |r| <= (1/2 + 3u Y) q = (1/2 + 0.375 Y / 2^50) q for q < 2^50: the
+// result is a centred-ish representative, never canonical; callers keep every
+// intermediate below 2^53 in magnitude (see the NTT rounds).
+constexpr uint64_t kFpMaxPrime = 1ull << 50;
+
+struct FpMod {
+    double q, qinv;
+};
+
+__host__ __device__ __forceinline__ double fp_mulmod(double y, double w, FpMod m)
+{
+    double h = y * w;
+    double l = fma(y, w, -h);
+    double k = rint(h * m.qinv);
+    double r = fma(-k, m.q, h);
+    return r + l;
+}
+
+// centred reduction: |result| <= q/2 + 1 for |x| < 2^53
+__host__ __device__ __forceinline__ double fp_reduce(double x, FpMod m)
+{
+    double k = rint(x * m.qinv);
+    return fma(-k, m.q, x);
+}
+
+// canonical residue in [0, q) of an exact integer |x| < 2^53
+__host__ __device__ __forceinline__ uint64_t fp_canonical(double x, FpMod m)
+{
+    double r = fp_reduce(x, m);
+    r = r < 0.0 ? r + m.q : r;
+    return (uint64_t)r;
+}
 __device__ __forceinline__ uint64_t submod(uint64_t a, uint64_t b, uint64_t q) { return a >= b ? a - b : a + q - b; }
 
 }  // namespace ckks

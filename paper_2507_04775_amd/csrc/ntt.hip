@@ -2,9 +2,9 @@
 //
 // Forward: radix-2 Cooley-Tukey with the psi twist merged into the
 // butterflies, natural coefficients -> bit-reversed evaluations.  Inverse:
-// Gentleman-Sande butterflies, bit-reversed -> natural, times N^-1.  Twiddle
-// w for the butterfly of stage m at index j is psi^br(m + j div 2t), with its
-// Shoup companion (Table III), read from the context tables.
+// Gentleman-Sande butterflies, bit-reversed -> natural, times N^-1.  The
+// butterfly of stage m at index j uses w = psi^br(m + j div 2t) from the
+// context tables.
 //
 // Layout of the work: every thread owns 16 elements and runs four radix-2
 // stages on them in registers ("radix-16 rounds"); rounds exchange data
@@ -14,8 +14,16 @@
 // problem) and a row pass runs the last eight (each row of 256 contiguous
 // elements is independent, with its own twiddle subset).  Each pass reads and
 // writes every element once: four global accesses per element in total.
-// Values stay lazily reduced (Harvey butterflies: [0, 4q) forward, [0, 2q)
-// inverse) and are made canonical in the last pass.
+//
+// Two arithmetic paths, chosen per limb (uniform per workgroup):
+// - primes below 2^50: exact FP64 arithmetic (modarith.h).  Values are
+//   signed representatives; a centred reduction at the start of each round
+//   keeps |x| <= q/2 + 1, after which four forward stages stay below 5.3 q
+//   (7.1 q when a round starts from canonical input) and four inverse stages,
+//   with the sums of the third stage re-centred, below 4 q; all < 2^53.
+// - other primes (up to 2^61): 64-bit integers with Shoup twiddles and
+//   Harvey's lazy butterflies ([0, 4q) forward, [0, 2q) inverse).
+// Outputs of every transform are canonical.
 #include "internal.h"
 
 namespace ckks {
@@ -26,31 +34,97 @@ constexpr int kThreads = 256;
 
 __device__ __forceinline__ uint32_t pad(uint32_t x) { return x + (x >> 4); }
 
-// Harvey forward butterfly: x, y in [0, 4q) -> [0, 4q)
-__device__ __forceinline__ void ct_bfly(uint64_t &x, uint64_t &y, ulonglong2 w, uint64_t q, uint64_t q2)
-{
-    uint64_t a = x >= q2 ? x - q2 : x;
-    uint64_t t = shoup_lazy(y, w.x, w.y, q);
-    x = a + t;
-    y = a - t + q2;
-}
+// ----------------------------------------------------------- integer path
 
-// Harvey inverse butterfly: x, y in [0, 2q) -> [0, 2q)
-__device__ __forceinline__ void gs_bfly(uint64_t &x, uint64_t &y, ulonglong2 w, uint64_t q, uint64_t q2)
-{
-    uint64_t s = x + y;
-    s = s >= q2 ? s - q2 : s;
-    uint64_t d = x - y + q2;
-    x = s;
-    y = shoup_lazy(d, w.x, w.y, q);
-}
+struct IntArith {
+    typedef uint64_t V;
+    typedef ulonglong2 W;
+    const ulonglong2 *T;
+    uint64_t q, q2, fc, fc_s;  // fc: constant of the last inverse multiplication
+
+    __device__ __forceinline__ V from_u64(uint64_t x) const { return x; }
+    __device__ __forceinline__ V from_bits(uint64_t x) const { return x; }
+    __device__ __forceinline__ uint64_t to_bits(V x) const { return x; }
+    __device__ __forceinline__ W tw(uint32_t i) const { return T[i]; }
+    __device__ __forceinline__ void reduce_all(V (&)[16]) const {}
+    // Harvey forward butterfly: x, y in [0, 4q) -> [0, 4q)
+    __device__ __forceinline__ void ct(V &x, V &y, W w) const
+    {
+        uint64_t a = x >= q2 ? x - q2 : x;
+        uint64_t t = shoup_lazy(y, w.x, w.y, q);
+        x = a + t;
+        y = a - t + q2;
+    }
+    // Harvey inverse butterfly: x, y in [0, 2q) -> [0, 2q)
+    __device__ __forceinline__ void gs(V &x, V &y, W w, int) const
+    {
+        uint64_t s = x + y;
+        s = s >= q2 ? s - q2 : s;
+        uint64_t d = x - y + q2;
+        x = s;
+        y = shoup_lazy(d, w.x, w.y, q);
+    }
+    __device__ __forceinline__ uint64_t fwd_final(V x) const { return csub(csub(x, q2), q); }
+    __device__ __forceinline__ uint64_t inv_final(V x) const { return shoup(x, fc, fc_s, q); }
+    // key inner product on canonical values
+    __device__ __forceinline__ V mac_in(V x) const { return fwd_final(x); }
+    __device__ __forceinline__ V own(uint64_t x) const { return x; }
+    __device__ __forceinline__ void mac(V &acc, V v, uint64_t k, const Prime &P) const
+    {
+        acc = addmod(acc, mulmod(v, k, P), q);
+    }
+    __device__ __forceinline__ uint64_t acc_final(V acc) const { return acc; }
+};
+
+// ----------------------------------------------------------- FP64 path
+
+struct FpArith {
+    typedef double V;
+    typedef double W;
+    const double *T;
+    FpMod m;
+    double fc;  // constant of the last inverse multiplication
+
+    __device__ __forceinline__ V from_u64(uint64_t x) const { return (double)x; }
+    __device__ __forceinline__ V from_bits(uint64_t x) const { return __longlong_as_double((long long)x); }
+    __device__ __forceinline__ uint64_t to_bits(V x) const { return (uint64_t)__double_as_longlong(x); }
+    __device__ __forceinline__ W tw(uint32_t i) const { return T[i]; }
+    __device__ __forceinline__ void reduce_all(V (&v)[16]) const
+    {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) v[i] = fp_reduce(v[i], m);
+    }
+    __device__ __forceinline__ void ct(V &x, V &y, W w) const
+    {
+        double t = fp_mulmod(y, w, m);
+        double a = x;
+        x = a + t;
+        y = a - t;
+    }
+    // the sums of the third stage of a round (st == 2) are re-centred
+    __device__ __forceinline__ void gs(V &x, V &y, W w, int st) const
+    {
+        double s = x + y, d = x - y;
+        x = st == 2 ? fp_reduce(s, m) : s;
+        y = fp_mulmod(d, w, m);
+    }
+    __device__ __forceinline__ uint64_t fwd_final(V x) const { return fp_canonical(x, m); }
+    __device__ __forceinline__ uint64_t inv_final(V x) const { return fp_canonical(fp_mulmod(x, fc, m), m); }
+    // key inner product: |v| < 5.3 q from a forward round, the running sum re-centred each step
+    __device__ __forceinline__ V mac_in(V x) const { return x; }
+    __device__ __forceinline__ V own(uint64_t x) const { return (double)x; }
+    __device__ __forceinline__ void mac(V &acc, V v, uint64_t k, const Prime &) const
+    {
+        acc = fp_reduce(acc + fp_mulmod(v, (double)k, m), m);
+    }
+    __device__ __forceinline__ uint64_t acc_final(V acc) const { return fp_canonical(acc, m); }
+};
 
 // Four forward stages on v[i] = element base + STRIDE i of an NS-point
 // problem: t = 8 STRIDE, 4 STRIDE, 2 STRIDE, STRIDE.  base = a 16 STRIDE + s
 // with s < STRIDE.  Twiddles come from T[m B + j div 2t], m = NS / 2t.
-template <int NS, int STRIDE>
-__device__ __forceinline__ void fwd16(uint64_t (&v)[16], uint32_t base, const ulonglong2 *__restrict__ T, uint32_t B,
-                                      uint64_t q, uint64_t q2)
+template <int NS, int STRIDE, class A>
+__device__ __forceinline__ void fwd16(typename A::V (&v)[16], uint32_t base, const A &ar, uint32_t B)
 {
 #pragma unroll
     for (int st = 0; st < 4; ++st) {
@@ -60,17 +134,16 @@ __device__ __forceinline__ void fwd16(uint64_t (&v)[16], uint32_t base, const ul
         const uint32_t g0 = m * B + base / (2 * t);
 #pragma unroll
         for (int g = 0; g < (1 << st); ++g) {
-            const ulonglong2 w = T[g0 + g];
+            const typename A::W w = ar.tw(g0 + g);
 #pragma unroll
-            for (int k = 0; k < h; ++k) ct_bfly(v[g * 2 * h + k], v[g * 2 * h + k + h], w, q, q2);
+            for (int k = 0; k < h; ++k) ar.ct(v[g * 2 * h + k], v[g * 2 * h + k + h], w);
         }
     }
 }
 
 // Four inverse stages: t = STRIDE, 2 STRIDE, 4 STRIDE, 8 STRIDE.
-template <int NS, int STRIDE>
-__device__ __forceinline__ void inv16(uint64_t (&v)[16], uint32_t base, const ulonglong2 *__restrict__ T, uint32_t B,
-                                      uint64_t q, uint64_t q2)
+template <int NS, int STRIDE, class A>
+__device__ __forceinline__ void inv16(typename A::V (&v)[16], uint32_t base, const A &ar, uint32_t B)
 {
 #pragma unroll
     for (int st = 0; st < 4; ++st) {
@@ -80,9 +153,9 @@ __device__ __forceinline__ void inv16(uint64_t (&v)[16], uint32_t base, const ul
         const uint32_t g0 = m * B + base / (2 * t);
 #pragma unroll
         for (int g = 0; g < (8 >> st); ++g) {
-            const ulonglong2 w = T[g0 + g];
+            const typename A::W w = ar.tw(g0 + g);
 #pragma unroll
-            for (int k = 0; k < h; ++k) gs_bfly(v[g * 2 * h + k], v[g * 2 * h + k + h], w, q, q2);
+            for (int k = 0; k < h; ++k) ar.gs(v[g * 2 * h + k], v[g * 2 * h + k + h], w, st);
         }
     }
 }
@@ -139,7 +212,143 @@ __device__ __forceinline__ void store_fwd(const NttArgs &a, const LimbPos &lp, u
     }
 }
 
+__device__ __forceinline__ IntArith int_arith(const ulonglong2 *tw, const Prime &P, uint32_t prime, uint32_t N)
+{
+    IntArith r;
+    r.T = tw + (size_t)prime * N;
+    r.q = P.q;
+    r.q2 = P.two_q;
+    r.fc = P.ninv;
+    r.fc_s = P.ninv_s;
+    return r;
+}
+
+__device__ __forceinline__ FpArith fp_arith(const double *twd, const Prime &P, uint32_t prime, uint32_t N)
+{
+    FpArith r;
+    r.T = twd + (size_t)prime * N;
+    r.m.q = (double)P.q;
+    r.m.qinv = P.qinv;
+    r.fc = (double)P.ninv;
+    return r;
+}
+
+__device__ __forceinline__ IntArith int_arith(const NttArgs &a, const Prime &P, uint32_t prime, uint32_t N)
+{
+    return int_arith(a.tw, P, prime, N);
+}
+
+__device__ __forceinline__ FpArith fp_arith(const NttArgs &a, const Prime &P, uint32_t prime, uint32_t N)
+{
+    return fp_arith(a.twd, P, prime, N);
+}
+
+// Constant of the last inverse multiplication of a limb: N^-1, or the
+// base-conversion input scale N^-1 [(B/b_i)^-1]_{b_i} (ys_mode 1 / 2).
+__device__ __forceinline__ uint32_t ys_index(const NttArgs &a, const LimbPos &lp)
+{
+    if (a.ys_mode == 1) {
+        const uint32_t r = lp.row + a.map.row0, j = r / a.alpha, lo = j * a.alpha;
+        const uint32_t ns = min(a.alpha, a.nlev - lo);
+        return (j * a.alpha + ns - 1) * kMaxDigitPrimes + (r - lo);
+    }
+    return a.pset * kMaxDigitPrimes + lp.row;
+}
+
+__device__ __forceinline__ IntArith inv_int_arith(const NttArgs &a, const LimbPos &lp, const Prime &P, uint32_t N)
+{
+    IntArith r = int_arith(a, P, lp.prime, N);
+    if (a.ys_mode) {
+        const ulonglong2 c = a.ys[ys_index(a, lp)];
+        r.fc = c.x;
+        r.fc_s = c.y;
+    }
+    return r;
+}
+
+__device__ __forceinline__ FpArith inv_fp_arith(const NttArgs &a, const LimbPos &lp, const Prime &P, uint32_t N)
+{
+    FpArith r = fp_arith(a, P, lp.prime, N);
+    if (a.ys_mode) r.fc = a.ysd[ys_index(a, lp)];
+    return r;
+}
+
+// Source of a base conversion computed in the first forward pass (PRO_BCONV).
+struct BcSrc {
+    const uint64_t *y;   // ns scaled source rows, stride N
+    const uint64_t *hm;  // [B/b_i] mod the target prime, i < ns
+    uint32_t ns;
+};
+
+__device__ __forceinline__ BcSrc bc_source(const NttArgs &a, uint32_t poly, uint32_t prime, size_t N)
+{
+    BcSrc b;
+    uint32_t set;
+    if (a.bc_mode == 1) {
+        const uint32_t lo = poly * a.alpha;
+        b.ns = min(a.alpha, a.nlev - lo);
+        set = poly * a.alpha + b.ns - 1;
+        b.y = a.bc_src + (size_t)lo * N;
+    } else {
+        b.ns = a.nprimes - a.map.nq;
+        set = a.pset;
+        b.y = a.bc_src + (int64_t)poly * a.bc_poly_stride;
+    }
+    b.hm = a.hmod + ((size_t)set * a.nprimes + prime) * kMaxDigitPrimes;
+    return b;
+}
+
+// v[i] = Conv(y)[pos(i)]: sum_k y_k[pos] [B/b_k]_q accumulated exactly, reduced
+// once; two halves of eight elements keep the 128-bit sums in few registers.
+template <class A, class Pos>
+__device__ __forceinline__ void bconv_load16(typename A::V (&v)[16], const A &ar, const BcSrc &b, const Prime &P,
+                                             size_t N, Pos pos)
+{
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+        u128 acc[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) acc[i] = u128{0, 0};
+        for (uint32_t k = 0; k < b.ns; ++k) {
+            const uint64_t h = b.hm[k];
+            const uint64_t *yk = b.y + (size_t)k * N;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) acc[i] = add128(acc[i], mul_wide(yk[pos(8 * half + i)], h));
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[8 * half + i] = ar.from_u64(reduce128(acc[i], P));
+    }
+}
+
 // ------------------------------------------------------------------ N = 2^16
+
+template <int PRO, class A>
+__device__ __forceinline__ void fwd_col_body(const NttArgs &a, const LimbPos &lp, const Prime &P, const A &ar,
+                                             uint64_t *lds, uint64_t *mid, int64_t mid_stride)
+{
+    const uint32_t col = threadIdx.x & 15, s = threadIdx.x >> 4, c = blockIdx.x * 16 + col;
+    const uint64_t *src = a.src + (int64_t)lp.poly * a.map.src_poly_stride + (size_t)lp.row * 65536;
+    typename A::V v[16];
+    if (PRO == PRO_BCONV) {
+        bconv_load16(v, ar, bc_source(a, lp.poly, lp.prime, 65536), P, 65536,
+                     [&](int i) { return (s + 16 * i) * 256 + c; });
+    } else {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) v[i] = ar.from_u64(load_fwd<PRO>(a, lp, src, (s + 16 * i) * 256 + c, P));
+    }
+    fwd16<256, 16>(v, s, ar, 1);
+    uint64_t *L = lds + col * 272;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) L[pad(s + 16 * i)] = ar.to_bits(v[i]);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = ar.from_bits(L[pad(16 * s + i)]);
+    ar.reduce_all(v);
+    fwd16<256, 1>(v, 16 * s, ar, 1);
+    uint64_t *m = mid + (int64_t)lp.poly * mid_stride + (size_t)lp.row * 65536;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) m[(16 * s + i) * 256 + c] = ar.to_bits(v[i]);
+}
 
 template <int PRO>
 __global__ __launch_bounds__(kThreads) void k_ntt16_fwd_col(NttArgs a, uint64_t *mid, int64_t mid_stride)
@@ -148,24 +357,37 @@ __global__ __launch_bounds__(kThreads) void k_ntt16_fwd_col(NttArgs a, uint64_t 
     const LimbPos lp = limb_pos(a.map);
     if (lp.skip) return;
     const Prime P = a.primes[lp.prime];
-    const uint64_t q = P.q, q2 = P.two_q;
-    const ulonglong2 *T = a.tw + (size_t)lp.prime * 65536;
-    const uint32_t col = threadIdx.x & 15, s = threadIdx.x >> 4, c = blockIdx.x * 16 + col;
-    const uint64_t *src = a.src + (int64_t)lp.poly * a.map.src_poly_stride + (size_t)lp.row * 65536;
-    uint64_t v[16];
+    if (P.q < kFpMaxPrime)
+        fwd_col_body<PRO>(a, lp, P, fp_arith(a, P, lp.prime, 65536), lds, mid, mid_stride);
+    else
+        fwd_col_body<PRO>(a, lp, P, int_arith(a, P, lp.prime, 65536), lds, mid, mid_stride);
+}
+
+template <int EPI, class A>
+__device__ __forceinline__ void fwd_row_body(const NttArgs &a, const LimbPos &lp, const Prime &P, const A &ar,
+                                             uint64_t *lds, const uint64_t *mid, int64_t mid_stride)
+{
+    const uint32_t blk = threadIdx.x >> 4, s = threadIdx.x & 15, b = blockIdx.x * 16 + blk;
+    const uint64_t *m = mid + (int64_t)lp.poly * mid_stride + (size_t)lp.row * 65536 + b * 256;
+    typename A::V v[16];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) v[i] = load_fwd<PRO>(a, lp, src, (s + 16 * i) * 256 + c, P);
-    fwd16<256, 16>(v, s, T, 1, q, q2);
-    uint64_t *L = lds + col * 272;
+    for (int i = 0; i < 16; ++i) v[i] = ar.from_bits(m[s + 16 * i]);
+    ar.reduce_all(v);
+    fwd16<256, 16>(v, s, ar, 256 + b);
+    uint64_t *L = lds + blk * 272;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) L[pad(s + 16 * i)] = v[i];
+    for (int i = 0; i < 16; ++i) L[pad(s + 16 * i)] = ar.to_bits(v[i]);
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < 16; ++i) v[i] = L[pad(16 * s + i)];
-    fwd16<256, 1>(v, 16 * s, T, 1, q, q2);
-    uint64_t *m = mid + (int64_t)lp.poly * mid_stride + (size_t)lp.row * 65536;
+    for (int i = 0; i < 16; ++i) v[i] = ar.from_bits(L[pad(16 * s + i)]);
+    ar.reduce_all(v);
+    fwd16<256, 1>(v, 16 * s, ar, 256 + b);
 #pragma unroll
-    for (int i = 0; i < 16; ++i) m[(16 * s + i) * 256 + c] = v[i];
+    for (int i = 0; i < 16; ++i) L[pad(16 * s + i)] = ar.fwd_final(v[i]);
+    __syncthreads();
+    uint64_t *dst = a.dst + (int64_t)lp.poly * a.map.dst_poly_stride + (size_t)lp.row * 65536;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) store_fwd<EPI>(a, lp, dst, b * 256 + s + 16 * i, L[pad(s + 16 * i)], P, 65536);
 }
 
 template <int EPI>
@@ -175,43 +397,16 @@ __global__ __launch_bounds__(kThreads) void k_ntt16_fwd_row(NttArgs a, const uin
     const LimbPos lp = limb_pos(a.map);
     if (lp.skip) return;
     const Prime P = a.primes[lp.prime];
-    const uint64_t q = P.q, q2 = P.two_q;
-    const ulonglong2 *T = a.tw + (size_t)lp.prime * 65536;
-    const uint32_t blk = threadIdx.x >> 4, s = threadIdx.x & 15, b = blockIdx.x * 16 + blk;
-    const uint64_t *m = mid + (int64_t)lp.poly * mid_stride + (size_t)lp.row * 65536 + b * 256;
-    uint64_t v[16];
-#pragma unroll
-    for (int i = 0; i < 16; ++i) v[i] = m[s + 16 * i];
-    fwd16<256, 16>(v, s, T, 256 + b, q, q2);
-    uint64_t *L = lds + blk * 272;
-#pragma unroll
-    for (int i = 0; i < 16; ++i) L[pad(s + 16 * i)] = v[i];
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < 16; ++i) v[i] = L[pad(16 * s + i)];
-    fwd16<256, 1>(v, 16 * s, T, 256 + b, q, q2);
-#pragma unroll
-    for (int i = 0; i < 16; ++i) L[pad(16 * s + i)] = v[i];
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < 16; ++i) v[i] = L[pad(s + 16 * i)];
-    uint64_t *dst = a.dst + (int64_t)lp.poly * a.map.dst_poly_stride + (size_t)lp.row * 65536;
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        uint64_t x = csub(csub(v[i], q2), q);
-        store_fwd<EPI>(a, lp, dst, b * 256 + s + 16 * i, x, P, 65536);
-    }
+    if (P.q < kFpMaxPrime)
+        fwd_row_body<EPI>(a, lp, P, fp_arith(a, P, lp.prime, 65536), lds, mid, mid_stride);
+    else
+        fwd_row_body<EPI>(a, lp, P, int_arith(a, P, lp.prime, 65536), lds, mid, mid_stride);
 }
 
-template <int PRO>
-__global__ __launch_bounds__(kThreads) void k_ntt16_inv_row(NttArgs a, uint64_t *mid, int64_t mid_stride)
+template <int PRO, class A>
+__device__ __forceinline__ void inv_row_body(const NttArgs &a, const LimbPos &lp, const A &ar, uint64_t *lds,
+                                             uint64_t *mid, int64_t mid_stride)
 {
-    __shared__ uint64_t lds[16 * 272];
-    const LimbPos lp = limb_pos(a.map);
-    if (lp.skip) return;
-    const Prime P = a.primes[lp.prime];
-    const uint64_t q = P.q, q2 = P.two_q;
-    const ulonglong2 *T = a.tw + (size_t)lp.prime * 65536;
     const uint32_t blk = threadIdx.x >> 4, s = threadIdx.x & 15, b = blockIdx.x * 16 + blk;
     const uint64_t *src = a.src + (int64_t)lp.poly * a.map.src_poly_stride + (size_t)lp.row * 65536;
     uint64_t *L = lds + blk * 272;
@@ -221,19 +416,58 @@ __global__ __launch_bounds__(kThreads) void k_ntt16_inv_row(NttArgs a, uint64_t 
         L[pad(s + 16 * i)] = src[PRO == PRO_GALOIS ? galois_src(e, a.galois, 16) : e];
     }
     __syncthreads();
-    uint64_t v[16];
+    typename A::V v[16];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) v[i] = L[pad(16 * s + i)];
-    inv16<256, 1>(v, 16 * s, T, 256 + b, q, q2);
+    for (int i = 0; i < 16; ++i) v[i] = ar.from_u64(L[pad(16 * s + i)]);
+    ar.reduce_all(v);
+    inv16<256, 1>(v, 16 * s, ar, 256 + b);
 #pragma unroll
-    for (int i = 0; i < 16; ++i) L[pad(16 * s + i)] = v[i];
+    for (int i = 0; i < 16; ++i) L[pad(16 * s + i)] = ar.to_bits(v[i]);
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < 16; ++i) v[i] = L[pad(s + 16 * i)];
-    inv16<256, 16>(v, s, T, 256 + b, q, q2);
+    for (int i = 0; i < 16; ++i) v[i] = ar.from_bits(L[pad(s + 16 * i)]);
+    ar.reduce_all(v);
+    inv16<256, 16>(v, s, ar, 256 + b);
     uint64_t *m = mid + (int64_t)lp.poly * mid_stride + (size_t)lp.row * 65536 + b * 256;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) m[s + 16 * i] = v[i];
+    for (int i = 0; i < 16; ++i) m[s + 16 * i] = ar.to_bits(v[i]);
+}
+
+template <int PRO>
+__global__ __launch_bounds__(kThreads) void k_ntt16_inv_row(NttArgs a, uint64_t *mid, int64_t mid_stride)
+{
+    __shared__ uint64_t lds[16 * 272];
+    const LimbPos lp = limb_pos(a.map);
+    if (lp.skip) return;
+    const Prime P = a.primes[lp.prime];
+    if (P.q < kFpMaxPrime)
+        inv_row_body<PRO>(a, lp, fp_arith(a, P, lp.prime, 65536), lds, mid, mid_stride);
+    else
+        inv_row_body<PRO>(a, lp, int_arith(a, P, lp.prime, 65536), lds, mid, mid_stride);
+}
+
+template <class A>
+__device__ __forceinline__ void inv_col_body(const NttArgs &a, const LimbPos &lp, const A &ar, uint64_t *lds,
+                                             const uint64_t *mid, int64_t mid_stride)
+{
+    const uint32_t col = threadIdx.x & 15, s = threadIdx.x >> 4, c = blockIdx.x * 16 + col;
+    const uint64_t *m = mid + (int64_t)lp.poly * mid_stride + (size_t)lp.row * 65536;
+    typename A::V v[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = ar.from_bits(m[(16 * s + i) * 256 + c]);
+    ar.reduce_all(v);
+    inv16<256, 1>(v, 16 * s, ar, 1);
+    uint64_t *L = lds + col * 272;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) L[pad(16 * s + i)] = ar.to_bits(v[i]);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = ar.from_bits(L[pad(s + 16 * i)]);
+    ar.reduce_all(v);
+    inv16<256, 16>(v, s, ar, 1);
+    uint64_t *dst = a.dst + (int64_t)lp.poly * a.map.dst_poly_stride + (size_t)lp.row * 65536;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) dst[(s + 16 * i) * 256 + c] = ar.inv_final(v[i]);
 }
 
 __global__ __launch_bounds__(kThreads) void k_ntt16_inv_col(NttArgs a, const uint64_t *mid, int64_t mid_stride)
@@ -242,27 +476,49 @@ __global__ __launch_bounds__(kThreads) void k_ntt16_inv_col(NttArgs a, const uin
     const LimbPos lp = limb_pos(a.map);
     if (lp.skip) return;
     const Prime P = a.primes[lp.prime];
-    const uint64_t q = P.q, q2 = P.two_q;
-    const ulonglong2 *T = a.tw + (size_t)lp.prime * 65536;
-    const uint32_t col = threadIdx.x & 15, s = threadIdx.x >> 4, c = blockIdx.x * 16 + col;
-    const uint64_t *m = mid + (int64_t)lp.poly * mid_stride + (size_t)lp.row * 65536;
-    uint64_t v[16];
-#pragma unroll
-    for (int i = 0; i < 16; ++i) v[i] = m[(16 * s + i) * 256 + c];
-    inv16<256, 1>(v, 16 * s, T, 1, q, q2);
-    uint64_t *L = lds + col * 272;
-#pragma unroll
-    for (int i = 0; i < 16; ++i) L[pad(16 * s + i)] = v[i];
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < 16; ++i) v[i] = L[pad(s + 16 * i)];
-    inv16<256, 16>(v, s, T, 1, q, q2);
-    uint64_t *dst = a.dst + (int64_t)lp.poly * a.map.dst_poly_stride + (size_t)lp.row * 65536;
-#pragma unroll
-    for (int i = 0; i < 16; ++i) dst[(s + 16 * i) * 256 + c] = shoup(v[i], P.ninv, P.ninv_s, q);
+    if (P.q < kFpMaxPrime)
+        inv_col_body(a, lp, inv_fp_arith(a, lp, P, 65536), lds, mid, mid_stride);
+    else
+        inv_col_body(a, lp, inv_int_arith(a, lp, P, 65536), lds, mid, mid_stride);
 }
 
 // ------------------------------------------------------------------ N = 2^12
+
+template <int PRO, int EPI, class A>
+__device__ __forceinline__ void fwd12_body(const NttArgs &a, const LimbPos &lp, const Prime &P, const A &ar,
+                                           uint64_t *lds)
+{
+    const uint32_t t = threadIdx.x, base2 = (t >> 4) * 256 + (t & 15);
+    const uint64_t *src = a.src + (int64_t)lp.poly * a.map.src_poly_stride + (size_t)lp.row * 4096;
+    typename A::V v[16];
+    if (PRO == PRO_BCONV) {
+        bconv_load16(v, ar, bc_source(a, lp.poly, lp.prime, 4096), P, 4096, [&](int i) { return t + 256 * i; });
+    } else {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) v[i] = ar.from_u64(load_fwd<PRO>(a, lp, src, t + 256 * i, P));
+    }
+    fwd16<4096, 256>(v, t, ar, 1);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) lds[pad(t + 256 * i)] = ar.to_bits(v[i]);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = ar.from_bits(lds[pad(base2 + 16 * i)]);
+    ar.reduce_all(v);
+    fwd16<4096, 16>(v, base2, ar, 1);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) lds[pad(base2 + 16 * i)] = ar.to_bits(v[i]);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = ar.from_bits(lds[pad(16 * t + i)]);
+    ar.reduce_all(v);
+    fwd16<4096, 1>(v, 16 * t, ar, 1);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) lds[pad(16 * t + i)] = ar.fwd_final(v[i]);
+    __syncthreads();
+    uint64_t *dst = a.dst + (int64_t)lp.poly * a.map.dst_poly_stride + (size_t)lp.row * 4096;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) store_fwd<EPI>(a, lp, dst, t + 256 * i, lds[pad(t + 256 * i)], P, 4096);
+}
 
 template <int PRO, int EPI>
 __global__ __launch_bounds__(kThreads) void k_ntt12_fwd(NttArgs a)
@@ -271,35 +527,45 @@ __global__ __launch_bounds__(kThreads) void k_ntt12_fwd(NttArgs a)
     const LimbPos lp = limb_pos(a.map);
     if (lp.skip) return;
     const Prime P = a.primes[lp.prime];
-    const uint64_t q = P.q, q2 = P.two_q;
-    const ulonglong2 *T = a.tw + (size_t)lp.prime * 4096;
+    if (P.q < kFpMaxPrime)
+        fwd12_body<PRO, EPI>(a, lp, P, fp_arith(a, P, lp.prime, 4096), lds);
+    else
+        fwd12_body<PRO, EPI>(a, lp, P, int_arith(a, P, lp.prime, 4096), lds);
+}
+
+template <int PRO, class A>
+__device__ __forceinline__ void inv12_body(const NttArgs &a, const LimbPos &lp, const A &ar, uint64_t *lds)
+{
     const uint32_t t = threadIdx.x, base2 = (t >> 4) * 256 + (t & 15);
     const uint64_t *src = a.src + (int64_t)lp.poly * a.map.src_poly_stride + (size_t)lp.row * 4096;
-    uint64_t v[16];
-#pragma unroll
-    for (int i = 0; i < 16; ++i) v[i] = load_fwd<PRO>(a, lp, src, t + 256 * i, P);
-    fwd16<4096, 256>(v, t, T, 1, q, q2);
-#pragma unroll
-    for (int i = 0; i < 16; ++i) lds[pad(t + 256 * i)] = v[i];
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < 16; ++i) v[i] = lds[pad(base2 + 16 * i)];
-    fwd16<4096, 16>(v, base2, T, 1, q, q2);
-#pragma unroll
-    for (int i = 0; i < 16; ++i) lds[pad(base2 + 16 * i)] = v[i];
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < 16; ++i) v[i] = lds[pad(16 * t + i)];
-    fwd16<4096, 1>(v, 16 * t, T, 1, q, q2);
-#pragma unroll
-    for (int i = 0; i < 16; ++i) lds[pad(16 * t + i)] = v[i];
-    __syncthreads();
-    uint64_t *dst = a.dst + (int64_t)lp.poly * a.map.dst_poly_stride + (size_t)lp.row * 4096;
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
-        uint64_t x = csub(csub(lds[pad(t + 256 * i)], q2), q);
-        store_fwd<EPI>(a, lp, dst, t + 256 * i, x, P, 4096);
+        uint32_t e = t + 256 * i;
+        lds[pad(e)] = src[PRO == PRO_GALOIS ? galois_src(e, a.galois, 12) : e];
     }
+    __syncthreads();
+    typename A::V v[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = ar.from_u64(lds[pad(16 * t + i)]);
+    ar.reduce_all(v);
+    inv16<4096, 1>(v, 16 * t, ar, 1);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) lds[pad(16 * t + i)] = ar.to_bits(v[i]);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = ar.from_bits(lds[pad(base2 + 16 * i)]);
+    ar.reduce_all(v);
+    inv16<4096, 16>(v, base2, ar, 1);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) lds[pad(base2 + 16 * i)] = ar.to_bits(v[i]);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = ar.from_bits(lds[pad(t + 256 * i)]);
+    ar.reduce_all(v);
+    inv16<4096, 256>(v, t, ar, 1);
+    uint64_t *dst = a.dst + (int64_t)lp.poly * a.map.dst_poly_stride + (size_t)lp.row * 4096;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) dst[t + 256 * i] = ar.inv_final(v[i]);
 }
 
 template <int PRO>
@@ -309,35 +575,165 @@ __global__ __launch_bounds__(kThreads) void k_ntt12_inv(NttArgs a)
     const LimbPos lp = limb_pos(a.map);
     if (lp.skip) return;
     const Prime P = a.primes[lp.prime];
-    const uint64_t q = P.q, q2 = P.two_q;
-    const ulonglong2 *T = a.tw + (size_t)lp.prime * 4096;
-    const uint32_t t = threadIdx.x, base2 = (t >> 4) * 256 + (t & 15);
-    const uint64_t *src = a.src + (int64_t)lp.poly * a.map.src_poly_stride + (size_t)lp.row * 4096;
+    if (P.q < kFpMaxPrime)
+        inv12_body<PRO>(a, lp, inv_fp_arith(a, lp, P, 4096), lds);
+    else
+        inv12_body<PRO>(a, lp, inv_int_arith(a, lp, P, 4096), lds);
+}
+
+// ------------------------------------------- ModUp last pass + key inner product
+
+__device__ __forceinline__ uint32_t ext_row_prime(uint32_t r, uint32_t level, uint32_t nq)
+{
+    return r <= level ? r : nq + (r - level - 1);
+}
+
+// One workgroup per (16 blocks of one extended row r): for each digit the row
+// pass of NTT(Conv(digit)) runs (or, for the digit's own rows, the input is
+// read), and both key halves are multiplied in and summed over the digits.
+template <class A>
+__device__ __forceinline__ void row_ip16_body(const RowIpArgs &a, const A &ar, const Prime &P, uint32_t r,
+                                              uint32_t pi, uint64_t *lds)
+{
+    const size_t N = 65536, krows = a.nq + a.np;
+    const uint32_t blk = threadIdx.x >> 4, s = threadIdx.x & 15, b = blockIdx.x * 16 + blk;
+    uint64_t *L = lds + blk * 272;
+    typename A::V acc0[16], acc1[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc0[i] = acc1[i] = (typename A::V)0;
+    for (uint32_t j = 0; j < a.beta; ++j) {
+        const uint32_t lo = j * a.alpha, hi = min(lo + a.alpha, a.level + 1);
+        typename A::V v[16];
+        if (r >= lo && r < hi) {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const uint32_t e = b * 256 + s + 16 * i;
+                v[i] = ar.own(a.d[(size_t)r * N + (a.d_galois == 1 ? e : galois_src(e, a.d_galois, 16))]);
+            }
+        } else {
+            const uint64_t *m = a.mid + ((size_t)j * a.rows + r) * N + b * 256;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) v[i] = ar.from_bits(m[s + 16 * i]);
+            ar.reduce_all(v);
+            fwd16<256, 16>(v, s, ar, 256 + b);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) L[pad(s + 16 * i)] = ar.to_bits(v[i]);
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < 16; ++i) v[i] = ar.from_bits(L[pad(16 * s + i)]);
+            ar.reduce_all(v);
+            fwd16<256, 1>(v, 16 * s, ar, 256 + b);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) L[pad(16 * s + i)] = ar.to_bits(ar.mac_in(v[i]));
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < 16; ++i) v[i] = ar.from_bits(L[pad(s + 16 * i)]);
+            __syncthreads();
+        }
+        const uint64_t *k0 = a.key + ((size_t)(2 * j) * krows + pi) * N + b * 256;
+        const uint64_t *k1 = a.key + ((size_t)(2 * j + 1) * krows + pi) * N + b * 256;
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+            uint64_t kk0[8], kk1[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                kk0[i] = k0[s + 16 * (8 * half + i)];
+                kk1[i] = k1[s + 16 * (8 * half + i)];
+            }
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                ar.mac(acc0[8 * half + i], v[8 * half + i], kk0[i], P);
+                ar.mac(acc1[8 * half + i], v[8 * half + i], kk1[i], P);
+            }
+        }
+    }
+    uint64_t *o0 = a.acc + (size_t)r * N + b * 256, *o1 = a.acc + ((size_t)a.rows + r) * N + b * 256;
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
-        uint32_t e = t + 256 * i;
-        lds[pad(e)] = src[PRO == PRO_GALOIS ? galois_src(e, a.galois, 12) : e];
+        o0[s + 16 * i] = ar.acc_final(acc0[i]);
+        o1[s + 16 * i] = ar.acc_final(acc1[i]);
     }
-    __syncthreads();
-    uint64_t v[16];
+}
+
+__global__ __launch_bounds__(kThreads) void k_ntt16_fwd_row_ip(RowIpArgs a)
+{
+    __shared__ uint64_t lds[16 * 272];
+    const uint32_t r = blockIdx.y, pi = ext_row_prime(r, a.level, a.nq);
+    const Prime P = a.primes[pi];
+    if (P.q < kFpMaxPrime)
+        row_ip16_body(a, fp_arith(a.twd, P, pi, 65536), P, r, pi, lds);
+    else
+        row_ip16_body(a, int_arith(a.tw, P, pi, 65536), P, r, pi, lds);
+}
+
+// N = 2^12: one workgroup per extended row does, per digit, the base
+// conversion, the whole transform and the key products.
+template <class A>
+__device__ __forceinline__ void ip12_body(const RowIpArgs &a, const NttArgs &c, const A &ar, const Prime &P,
+                                          uint32_t r, uint32_t pi, uint64_t *lds)
+{
+    const size_t N = 4096, krows = a.nq + a.np;
+    const uint32_t t = threadIdx.x, base2 = (t >> 4) * 256 + (t & 15);
+    typename A::V acc0[16], acc1[16];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) v[i] = lds[pad(16 * t + i)];
-    inv16<4096, 1>(v, 16 * t, T, 1, q, q2);
+    for (int i = 0; i < 16; ++i) acc0[i] = acc1[i] = (typename A::V)0;
+    for (uint32_t j = 0; j < a.beta; ++j) {
+        const uint32_t lo = j * a.alpha, hi = min(lo + a.alpha, a.level + 1);
+        typename A::V v[16];
+        if (r >= lo && r < hi) {
 #pragma unroll
-    for (int i = 0; i < 16; ++i) lds[pad(16 * t + i)] = v[i];
-    __syncthreads();
+            for (int i = 0; i < 16; ++i) {
+                const uint32_t e = t + 256 * i;
+                v[i] = ar.own(a.d[(size_t)r * N + (a.d_galois == 1 ? e : galois_src(e, a.d_galois, 12))]);
+            }
+        } else {
+            bconv_load16(v, ar, bc_source(c, j, pi, N), P, N, [&](int i) { return t + 256 * i; });
+            fwd16<4096, 256>(v, t, ar, 1);
 #pragma unroll
-    for (int i = 0; i < 16; ++i) v[i] = lds[pad(base2 + 16 * i)];
-    inv16<4096, 16>(v, base2, T, 1, q, q2);
+            for (int i = 0; i < 16; ++i) lds[pad(t + 256 * i)] = ar.to_bits(v[i]);
+            __syncthreads();
 #pragma unroll
-    for (int i = 0; i < 16; ++i) lds[pad(base2 + 16 * i)] = v[i];
-    __syncthreads();
+            for (int i = 0; i < 16; ++i) v[i] = ar.from_bits(lds[pad(base2 + 16 * i)]);
+            ar.reduce_all(v);
+            fwd16<4096, 16>(v, base2, ar, 1);
 #pragma unroll
-    for (int i = 0; i < 16; ++i) v[i] = lds[pad(t + 256 * i)];
-    inv16<4096, 256>(v, t, T, 1, q, q2);
-    uint64_t *dst = a.dst + (int64_t)lp.poly * a.map.dst_poly_stride + (size_t)lp.row * 4096;
+            for (int i = 0; i < 16; ++i) lds[pad(base2 + 16 * i)] = ar.to_bits(v[i]);
+            __syncthreads();
 #pragma unroll
-    for (int i = 0; i < 16; ++i) dst[t + 256 * i] = shoup(v[i], P.ninv, P.ninv_s, q);
+            for (int i = 0; i < 16; ++i) v[i] = ar.from_bits(lds[pad(16 * t + i)]);
+            ar.reduce_all(v);
+            fwd16<4096, 1>(v, 16 * t, ar, 1);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) lds[pad(16 * t + i)] = ar.to_bits(ar.mac_in(v[i]));
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < 16; ++i) v[i] = ar.from_bits(lds[pad(t + 256 * i)]);
+            __syncthreads();
+        }
+        const uint64_t *k0 = a.key + ((size_t)(2 * j) * krows + pi) * N;
+        const uint64_t *k1 = a.key + ((size_t)(2 * j + 1) * krows + pi) * N;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            ar.mac(acc0[i], v[i], k0[t + 256 * i], P);
+            ar.mac(acc1[i], v[i], k1[t + 256 * i], P);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        a.acc[(size_t)r * N + t + 256 * i] = ar.acc_final(acc0[i]);
+        a.acc[((size_t)a.rows + r) * N + t + 256 * i] = ar.acc_final(acc1[i]);
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_ntt12_fwd_ip(RowIpArgs a, NttArgs c)
+{
+    __shared__ uint64_t lds[4352];
+    const uint32_t r = blockIdx.y, pi = ext_row_prime(r, a.level, a.nq);
+    const Prime P = a.primes[pi];
+    if (P.q < kFpMaxPrime)
+        ip12_body(a, c, fp_arith(a.twd, P, pi, 4096), P, r, pi, lds);
+    else
+        ip12_body(a, c, int_arith(a.tw, P, pi, 4096), P, r, pi, lds);
 }
 
 }  // namespace
@@ -357,6 +753,7 @@ hipError_t launch_ntt_fwd(const NttArgs &a, uint32_t nlimbs, NttPro pro, NttEpi 
         K12(PRO_PLAIN, EPI_PLAIN)
         K12(PRO_PLAIN, EPI_MODDOWN)
         K12(PRO_RESCALE, EPI_RESCALE)
+        K12(PRO_BCONV, EPI_MODDOWN)
 #undef K12
         return hipErrorInvalidValue;
     }
@@ -365,6 +762,8 @@ hipError_t launch_ntt_fwd(const NttArgs &a, uint32_t nlimbs, NttPro pro, NttEpi 
         hipLaunchKernelGGL((k_ntt16_fwd_col<PRO_PLAIN>), grid, block, 0, stream, a, mid, mid_poly_stride);
     else if (pro == PRO_RESCALE)
         hipLaunchKernelGGL((k_ntt16_fwd_col<PRO_RESCALE>), grid, block, 0, stream, a, mid, mid_poly_stride);
+    else if (pro == PRO_BCONV)
+        hipLaunchKernelGGL((k_ntt16_fwd_col<PRO_BCONV>), grid, block, 0, stream, a, mid, mid_poly_stride);
     else
         return hipErrorInvalidValue;
     if (epi == EPI_PLAIN)
@@ -373,6 +772,19 @@ hipError_t launch_ntt_fwd(const NttArgs &a, uint32_t nlimbs, NttPro pro, NttEpi 
         hipLaunchKernelGGL((k_ntt16_fwd_row<EPI_MODDOWN>), grid, block, 0, stream, a, mid, mid_poly_stride);
     else
         hipLaunchKernelGGL((k_ntt16_fwd_row<EPI_RESCALE>), grid, block, 0, stream, a, mid, mid_poly_stride);
+    return hipGetLastError();
+}
+
+hipError_t launch_ntt_fwd_ip(const RowIpArgs &a, const NttArgs &col, hipStream_t stream)
+{
+    dim3 block(kThreads);
+    if (a.logn == 12) {
+        hipLaunchKernelGGL(k_ntt12_fwd_ip, dim3(1, a.rows), block, 0, stream, a, col);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL((k_ntt16_fwd_col<PRO_BCONV>), dim3(16, a.beta * a.rows), block, 0, stream, col,
+                       (uint64_t *)a.mid, (int64_t)a.rows * 65536);
+    hipLaunchKernelGGL(k_ntt16_fwd_row_ip, dim3(16, a.rows), block, 0, stream, a);
     return hipGetLastError();
 }
 
