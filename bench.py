@@ -36,6 +36,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--cold-sets", type=int, default=6)
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-items", type=int, default=128)
+    ap.add_argument("--batch-reps", type=int, default=5)
     return ap.parse_args()
 
 
@@ -47,6 +50,92 @@ def percentile(xs, p):
     lo = int(k)
     hi = min(lo + 1, len(xs) - 1)
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+def run_batch(ctx, ps, seed, args):
+    """C3-style batch: one graph replay of the persistent stage kernels vs the same
+    items issued as plain per-operation calls on one stream."""
+    import torch
+
+    from paper_2507_04775_amd import ckks, inputs
+
+    plan = inputs.batch_plan(seed + 500, args.batch_items, ps.logn, ps.L)
+    allm = list(ps.q) + list(ps.p)
+
+    def dev_key(s):
+        k = torch.empty((ps.dnum, 2, len(allm), ps.N), dtype=torch.uint64, device="cuda")
+        for j in range(ps.dnum):
+            for t in range(2):
+                k[j, t] = inputs.device_residues(s + 7 * j + t, allm, ps.N)
+        return k
+
+    rlk = ctx.key(dev_key(seed + 600), 0)
+    rkeys = {}
+    for k in inputs.batch_rotation_set(ps.logn):
+        rkeys[k] = ctx.key(dev_key(seed + 700 + k), pow(5, k, 2 * ps.N))
+
+    def dev_ct(s, level):
+        return ckks.Ciphertext(inputs.device_residues(s, ps.q[: level + 1], ps.N),
+                               inputs.device_residues(s + 1, ps.q[: level + 1], ps.N), level)
+
+    items = []
+    for i, (kind, level, ks) in enumerate(plan):
+        a = dev_ct(seed + 1000 + 4 * i, level)
+        if kind == "hmult":
+            items.append((kind, a, dev_ct(seed + 1002 + 4 * i, level), ctx.empty_ct(level)))
+        else:
+            items.append((kind, a, ks, [ctx.empty_ct(level) for _ in ks]))
+    batch = ckks.Batch(ctx)
+    for kind, a, x, out in items:
+        if kind == "hmult":
+            batch.hmult(a, x, rlk, out)
+        else:
+            batch.hoisted(a, x, [rkeys[k] for k in x], out)
+    batch.build()
+    st = torch.cuda.Stream()
+    n_ks = batch.keyswitches
+    with torch.cuda.stream(st):
+        batch.tune(st)
+        batch.capture(st)
+        batch.replay(st)
+        st.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = []
+        for _ in range(args.batch_reps):
+            e0.record(st)
+            batch.replay(st)
+            e1.record(st)
+            st.synchronize()
+            reps.append(e0.elapsed_time(e1))
+        ws_h = ctx.workspace(ckks.OP_HMULT, ps.L)
+        ws_o = ctx.workspace(ckks.OP_HOISTED, ps.L)
+
+        def plain():
+            for kind, a, x, out in items:
+                if kind == "hmult":
+                    ctx.ckks_hmult_relin(a, x, rlk, out, ws_h, st)
+                else:
+                    ctx.ckks_hrotate_hoisted(a, x, [rkeys[k] for k in x], out, ws_o, st)
+
+        plain()
+        st.synchronize()
+        preps = []
+        for _ in range(max(2, args.batch_reps // 2)):
+            e0.record(st)
+            plain()
+            e1.record(st)
+            st.synchronize()
+            preps.append(e0.elapsed_time(e1))
+    bt, pt = min(reps), min(preps)
+    res = {"workload": "%d ciphertexts, levels 4..%d, half HMult+relin, half hoisted 8-way rotations" % (
+               len(plan), ps.L),
+           "key_switches": n_ks, "batched_ms": round(bt, 3), "plain_ms": round(pt, 3),
+           "batched_key_switches_per_s": round(n_ks / (bt / 1e3), 1),
+           "plain_key_switches_per_s": round(n_ks / (pt / 1e3), 1),
+           "speedup": round(pt / bt, 3), "workspace_bytes": int(batch.ws.numel() * 8),
+           "tuned_grid_wg_per_cu": [batch.grid(i) for i in range(12)]}
+    batch.close()
+    return res
 
 
 def main():
@@ -169,6 +258,11 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                 "algorithmic_bytes_per_launch": ntt_bytes, "launch_us": round(ntt_ms * 1e3, 2)}
 
+    # ---- batched: 128 ciphertexts at levels 4..30, half HMult+relin, half hoisted 8-way rotations
+    batched = None
+    if not args.no_batch:
+        batched = run_batch(ctx, ps, seed, args)
+
     # ---- CPU oracle on a bounded sample of the same step
     cpu = None
     if not args.no_cpu_baseline:
@@ -212,6 +306,7 @@ def main():
         "step_p99_ms": round(percentile(step_ms, 99), 4),
         "wall_s": round(wall, 3),
         "cold": cold,
+        "batched": batched,
         "ops": ops,
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -227,6 +227,57 @@ ckks_status ckks_poly_scalar_add(ckks_ctx *ctx, const uint64_t *a, const uint64_
 ckks_status ckks_automorph(ckks_ctx *ctx, const uint64_t *in, uint32_t galois, uint64_t *out, uint32_t n_limbs,
                            void *stream);
 
+/*
+ * Batched key switching (limb batching, Sec. III-F.1).  A batch is a list of
+ * independent work items at any levels:
+ *   CKKS_WORK_HMULT_RELIN : out[0] = HMult+relin(a, b) with key (galois 0)
+ *   CKKS_WORK_KEYSWITCH   : (out[0].c0, out[0].c1) = KeySwitch(a.c0 at a.level, key)
+ *   CKKS_WORK_ROTATE      : out[0] = apply_galois(a, galois, key)
+ *   CKKS_WORK_HOISTED     : out[i] = HRotate(a, rot[i], rot_keys[i]) for i < n_rot, one ModUp
+ * Each item's result is bit-identical to the corresponding single-operation
+ * call.  ckks_batch_create validates every item, binds the caller-owned
+ * workspace `ws` (ckks_batch_workspace_bytes bytes, kept for the batch's
+ * life) and uploads the batch's launch tables (the one allocation, freed by
+ * ckks_batch_destroy).  ckks_batch_run executes every step of every item as
+ * one persistent work-queue launch per step on `stream`; ckks_batch_capture
+ * records that launch sequence into a HIP graph that ckks_batch_replay
+ * relaunches (a non-default stream is required to capture).  ckks_batch_tune
+ * runs the batch with several persistent grid sizes and keeps, per step, the
+ * fastest (it runs the batch, overwriting the outputs with the same values).
+ * Items must not share outputs, and no output may overlap another item's
+ * input or workspace; inputs and keys must stay valid while the batch is used.
+ */
+enum {
+    CKKS_WORK_HMULT_RELIN = 1,
+    CKKS_WORK_KEYSWITCH = 2,
+    CKKS_WORK_ROTATE = 3,
+    CKKS_WORK_HOISTED = 4
+};
+
+typedef struct {
+    uint32_t kind;
+    ckks_ct a;                       /* input ciphertext (KEYSWITCH: a.c0 is the polynomial) */
+    ckks_ct b;                       /* second HMult operand */
+    const ckks_key *key;             /* HMULT / KEYSWITCH / ROTATE key */
+    uint32_t galois;                 /* ROTATE: Galois element (the key's) */
+    uint32_t n_rot;                  /* HOISTED: number of rotations */
+    const int32_t *rot;              /* HOISTED: slot rotations (host array) */
+    const ckks_key *const *rot_keys; /* HOISTED: one key per rotation (host array) */
+    ckks_ct *out;                    /* outputs (n_rot for HOISTED, else 1); levels are set */
+} ckks_work;
+
+typedef struct ckks_batch ckks_batch;
+
+size_t ckks_batch_workspace_bytes(const ckks_ctx *ctx, const ckks_work *items, uint32_t n);
+ckks_status ckks_batch_create(ckks_ctx *ctx, const ckks_work *items, uint32_t n, void *ws, ckks_batch **out);
+ckks_status ckks_batch_run(ckks_batch *batch, void *stream);
+ckks_status ckks_batch_tune(ckks_batch *batch, void *stream);
+ckks_status ckks_batch_capture(ckks_batch *batch, void *stream);
+ckks_status ckks_batch_replay(ckks_batch *batch, void *stream);
+uint32_t ckks_batch_keyswitches(const ckks_batch *batch); /* key switches performed per run */
+uint32_t ckks_batch_grid(const ckks_batch *batch, uint32_t step); /* persistent grid, in workgroups per CU */
+void ckks_batch_destroy(ckks_batch *batch);
+
 #ifdef __cplusplus
 }
 #endif

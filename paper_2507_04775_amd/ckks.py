@@ -33,6 +33,12 @@ class _Ct(ctypes.Structure):
 
 
 OP_MODUP, OP_MODDOWN, OP_KEYSWITCH, OP_HMULT, OP_RESCALE, OP_ROTATE, OP_HOISTED = 1, 2, 3, 4, 5, 6, 7
+WORK_HMULT_RELIN, WORK_KEYSWITCH, WORK_ROTATE, WORK_HOISTED = 1, 2, 3, 4
+
+
+class _Work(ctypes.Structure):
+    _fields_ = [("kind", _u32), ("a", _Ct), ("b", _Ct), ("key", _vp), ("galois", _u32), ("n_rot", _u32),
+                ("rot", ctypes.POINTER(_i32)), ("rot_keys", ctypes.POINTER(_vp)), ("out", ctypes.POINTER(_Ct))]
 
 _sigs = {
     "ckks_ctx_create": (ctypes.c_int, [_u32, _u64p, _u32, _u64p, _u32, _u32, ctypes.c_int, ctypes.POINTER(_vp)]),
@@ -63,6 +69,15 @@ _sigs = {
     "ckks_poly_scalar_mul": (ctypes.c_int, [_vp, _vp, _u64p, _vp, _u32, _vp]),
     "ckks_poly_scalar_add": (ctypes.c_int, [_vp, _vp, _u64p, _vp, _u32, _vp]),
     "ckks_automorph": (ctypes.c_int, [_vp, _vp, _u32, _vp, _u32, _vp]),
+    "ckks_batch_workspace_bytes": (ctypes.c_size_t, [_vp, ctypes.POINTER(_Work), _u32]),
+    "ckks_batch_create": (ctypes.c_int, [_vp, ctypes.POINTER(_Work), _u32, _vp, ctypes.POINTER(_vp)]),
+    "ckks_batch_run": (ctypes.c_int, [_vp, _vp]),
+    "ckks_batch_tune": (ctypes.c_int, [_vp, _vp]),
+    "ckks_batch_capture": (ctypes.c_int, [_vp, _vp]),
+    "ckks_batch_replay": (ctypes.c_int, [_vp, _vp]),
+    "ckks_batch_keyswitches": (_u32, [_vp]),
+    "ckks_batch_grid": (_u32, [_vp, _u32]),
+    "ckks_batch_destroy": (None, [_vp]),
 }
 for _name, (_res, _args) in _sigs.items():
     _f = getattr(_lib, _name)
@@ -289,6 +304,102 @@ class Context:
         n_limbs = inp.shape[0] if n_limbs is None else n_limbs
         _check(_lib.ckks_automorph(self.handle, _ptr(inp), galois, _ptr(out), n_limbs, _stream(stream)),
                "ckks_automorph")
+
+
+class Batch:
+    """A batch of independent key-switching work items run by persistent
+    work-queue kernels, one launch per step (ckks_batch_* in include/ckks.h).
+
+    Add items with hmult/keyswitch/rotate/hoisted, then call build() once; the
+    workspace is allocated here with torch and bound to the batch."""
+
+    def __init__(self, ctx: "Context"):
+        self.ctx = ctx
+        self._items = []
+        self._keep = []
+        self.handle = None
+        self.ws = None
+
+    def hmult(self, a: Ciphertext, b: Ciphertext, rlk: Key, out: Ciphertext):
+        out.level = a.level
+        self._items.append((WORK_HMULT_RELIN, a, b, rlk, 0, None, None, [out]))
+
+    def keyswitch(self, d: torch.Tensor, level: int, key: Key, out0: torch.Tensor, out1: torch.Tensor):
+        a = Ciphertext(d, d, level)
+        self._items.append((WORK_KEYSWITCH, a, None, key, 0, None, None, [Ciphertext(out0, out1, level)]))
+
+    def rotate(self, a: Ciphertext, galois: int, key: Key, out: Ciphertext):
+        out.level, out.scale = a.level, a.scale
+        self._items.append((WORK_ROTATE, a, None, key, galois, None, None, [out]))
+
+    def hoisted(self, a: Ciphertext, ks: Sequence[int], keys: Sequence[Key], outs: Sequence[Ciphertext]):
+        for o in outs:
+            o.level, o.scale = a.level, a.scale
+        self._items.append((WORK_HOISTED, a, None, None, 0, list(ks), list(keys), list(outs)))
+
+    def _works(self):
+        n = len(self._items)
+        arr = (_Work * n)()
+        keep = []
+        for i, (kind, a, b, key, g, ks, keys, outs) in enumerate(self._items):
+            w = arr[i]
+            w.kind = kind
+            w.a = a._c()
+            if b is not None:
+                w.b = b._c()
+            w.key = key.handle if key is not None else None
+            w.galois = g
+            outs_c = (_Ct * len(outs))(*[o._c() for o in outs])
+            keep.append(outs_c)
+            w.out = outs_c
+            if kind == WORK_HOISTED:
+                rot = (_i32 * len(ks))(*ks)
+                rk = (_vp * len(keys))(*[k.handle for k in keys])
+                keep += [rot, rk]
+                w.n_rot = len(ks)
+                w.rot = rot
+                w.rot_keys = rk
+        return arr, keep
+
+    def build(self):
+        arr, keep = self._works()
+        nbytes = int(_lib.ckks_batch_workspace_bytes(self.ctx.handle, arr, len(self._items)))
+        if nbytes == 0:
+            raise CkksError(-1, "ckks_batch_workspace_bytes")
+        self.ws = torch.empty((nbytes + 7) // 8, dtype=torch.uint64, device=self.ctx.device)
+        h = _vp()
+        _check(_lib.ckks_batch_create(self.ctx.handle, arr, len(self._items), self.ws.data_ptr(), ctypes.byref(h)),
+               "ckks_batch_create")
+        self.handle = h
+        self._keep = keep
+        return self
+
+    @property
+    def keyswitches(self) -> int:
+        return int(_lib.ckks_batch_keyswitches(self.handle))
+
+    def grid(self, step: int) -> int:
+        return int(_lib.ckks_batch_grid(self.handle, step))
+
+    def run(self, stream=None):
+        _check(_lib.ckks_batch_run(self.handle, _stream(stream)), "ckks_batch_run")
+
+    def tune(self, stream=None):
+        _check(_lib.ckks_batch_tune(self.handle, _stream(stream)), "ckks_batch_tune")
+
+    def capture(self, stream):
+        _check(_lib.ckks_batch_capture(self.handle, _stream(stream)), "ckks_batch_capture")
+
+    def replay(self, stream=None):
+        _check(_lib.ckks_batch_replay(self.handle, _stream(stream)), "ckks_batch_replay")
+
+    def close(self, _destroy=_lib.ckks_batch_destroy):
+        if getattr(self, "handle", None):
+            _destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        self.close()
 
 
 def to_device(a, device="cuda") -> torch.Tensor:

@@ -9,6 +9,7 @@
 #include <string>
 
 #include "internal.h"
+#include "ks_args.h"
 
 namespace ckks {
 ckks_status fail(ckks_status s, const std::string &msg);
@@ -47,142 +48,25 @@ ckks_status check_ptr(const void *p, const char *what)
         if (_s != CKKS_OK) return _s;       \
     } while (0)
 
-struct KsSizes {
-    uint32_t n, rows, beta;
-    size_t N;
-};
-
-KsSizes ks_sizes(const ckks_ctx *c, uint32_t level)
-{
-    KsSizes s;
-    s.n = level + 1;
-    s.rows = s.n + c->np;
-    s.beta = (s.n + c->alpha - 1) / c->alpha;
-    s.N = c->N;
-    return s;
-}
-
-// workspace layout of the key-switching core (elements)
-struct KsWs {
-    uint64_t *dc, *ext, *acc, *pc, *conv;
-};
-
-size_t ks_ws_elems(const ckks_ctx *c, uint32_t level)
-{
-    KsSizes s = ks_sizes(c, level);
-    return ((size_t)s.n + (size_t)s.beta * s.rows + 2 * (size_t)s.rows + 2 * (size_t)c->np + 2 * (size_t)s.n) * s.N;
-}
-
-KsWs ks_ws(const ckks_ctx *c, uint32_t level, void *ws)
-{
-    KsSizes s = ks_sizes(c, level);
-    KsWs w;
-    w.dc = (uint64_t *)ws;
-    w.ext = w.dc + (size_t)s.n * s.N;
-    w.acc = w.ext + (size_t)s.beta * s.rows * s.N;
-    w.pc = w.acc + 2 * (size_t)s.rows * s.N;
-    w.conv = w.pc + 2 * (size_t)c->np * s.N;
-    return w;
-}
-
-NttArgs base_args(const ckks_ctx *c, bool inverse)
-{
-    NttArgs a;
-    memset(&a, 0, sizeof(a));
-    a.primes = c->d_primes;
-    a.tw = inverse ? c->d_tw_inv : c->d_tw_fwd;
-    a.twd = inverse ? c->d_twd_inv : c->d_twd_fwd;
-    a.logn = c->logn;
-    a.galois = 1;
-    a.map.nq = c->nq;
-    a.map.level = kAllPrimes;
-    return a;
-}
-
-// INTT of d (optionally gathered through X -> X^g) into dc, leaving the
-// scaled base-conversion inputs y_i = [x_i (D_j/q_i)^-1]_{q_i} of each digit
-// (the scale and N^-1 are one constant of the last inverse pass).
 hipError_t modup_intt(const ckks_ctx *c, const uint64_t *d, uint32_t g, uint32_t level, uint64_t *dc, hipStream_t st)
 {
-    NttArgs a = base_args(c, true);
-    a.src = d;
-    a.dst = dc;
-    a.galois = g;
-    a.map.rows = level + 1;
-    a.map.prime0 = 0;
-    a.ys_mode = 1;
-    a.alpha = c->alpha;
-    a.nlev = level + 1;
-    a.ys = c->d_bc_ys;
-    a.ysd = c->d_bc_ysd;
-    return launch_ntt_inv(a, level + 1, g == 1 ? PRO_PLAIN : PRO_GALOIS, st, dc, 0);
+    return launch_ntt_stage(g == 1 ? STAGE_INV_PLAIN : STAGE_INV_GALOIS, args_modup_intt(c, d, g, level, dc), level + 1,
+                            st);
 }
 
-// ModUp from the scaled coefficients dc: base conversion of every digit into
-// ext, then the forward NTT of every converted row.  With copy_own the digit's
-// own rows are copied (gathered through g) from the evaluation-domain d;
-// otherwise they are left unwritten and read from d by the inner product.
 hipError_t modup_from_coeffs(const ckks_ctx *c, const uint64_t *d, uint32_t g, uint32_t level, const uint64_t *dc,
                              uint64_t *ext, bool copy_own, hipStream_t st)
 {
     KsSizes s = ks_sizes(c, level);
-    BconvArgs b;
-    memset(&b, 0, sizeof(b));
-    const size_t hm_stride = (size_t)(c->nq + c->np) * kMaxDigitPrimes;
-    for (uint32_t j = 0; j < s.beta; ++j) {
-        uint32_t lo = j * c->alpha, hi = lo + c->alpha < s.n ? lo + c->alpha : s.n;
-        uint32_t set = c->set_index(j, hi - lo);
-        BconvJob &J = b.job[j];
-        J.src = dc + (size_t)lo * s.N;
-        J.dst = ext + (size_t)j * s.rows * s.N;
-        J.copy_src = copy_own ? d : nullptr;
-        J.hinv = c->d_bc_hinv + (size_t)set * kMaxDigitPrimes;
-        J.hmod = c->d_bc_hmod + (size_t)set * hm_stride;
-        J.ns = hi - lo;
-        J.src_prime0 = lo;
-        J.lo = lo;
-        J.hi = hi;
-    }
-    b.primes = c->d_primes;
-    b.nrows = s.rows;
-    b.level = level;
-    b.nq = c->nq;
-    b.N = c->N;
-    b.logn = c->logn;
-    b.copy_galois = g;
-    b.prescaled = 1;
-    hipError_t e = launch_bconv(b, s.beta, st);
+    hipError_t e = launch_bconv(args_modup_bconv(c, d, g, level, dc, ext, copy_own), s.beta, st);
     if (e != hipSuccess) return e;
-    NttArgs a = base_args(c, false);
-    a.src = ext;
-    a.dst = ext;
-    a.map.rows = s.rows;
-    a.map.level = level;
-    a.map.skip_alpha = c->alpha;
-    a.map.src_poly_stride = a.map.dst_poly_stride = (int64_t)s.rows * s.N;
-    return launch_ntt_fwd(a, s.beta * s.rows, PRO_PLAIN, EPI_PLAIN, st, ext, (int64_t)s.rows * s.N);
+    return launch_ntt_stage(STAGE_FWD_PLAIN, args_modup_ntt(c, level, ext), s.beta * s.rows, st);
 }
 
 hipError_t inner_product(const ckks_ctx *c, const uint64_t *ext, uint32_t level, const uint64_t *key, uint32_t g,
                          uint64_t *acc, hipStream_t st, const uint64_t *own = nullptr, uint32_t own_galois = 1)
 {
-    KsSizes s = ks_sizes(c, level);
-    IpArgs a;
-    a.ext = ext;
-    a.key = key;
-    a.acc = acc;
-    a.primes = c->d_primes;
-    a.beta = s.beta;
-    a.rows = s.rows;
-    a.level = level;
-    a.nq = c->nq;
-    a.np = c->np;
-    a.logn = c->logn;
-    a.alpha = c->alpha;
-    a.galois = g;
-    a.own = own;
-    a.own_galois = own_galois;
-    return launch_inner_product(a, st);
+    return launch_inner_product(args_ip(c, ext, level, key, g, acc, own, own_galois), st);
 }
 
 // ModDown of npoly accumulators acc[t] (rows q_0..q_l, p_0..p_{K-1}, stride
@@ -196,41 +80,10 @@ hipError_t moddown(const ckks_ctx *c, const uint64_t *acc, int64_t acc_stride, u
                    hipStream_t st)
 {
     KsSizes s = ks_sizes(c, level);
-    const int64_t kN = (int64_t)c->np * s.N, nN = (int64_t)s.n * s.N;
-    NttArgs ia = base_args(c, true);
-    ia.src = acc + nN;
-    ia.dst = pc;
-    ia.map.rows = c->np;
-    ia.map.level = level;
-    ia.map.row0 = s.n;
-    ia.map.src_poly_stride = acc_stride;
-    ia.map.dst_poly_stride = kN;
-    ia.ys_mode = 2;
-    ia.pset = c->pset_index();
-    ia.ys = c->d_bc_ys;
-    ia.ysd = c->d_bc_ysd;
-    hipError_t e = launch_ntt_inv(ia, npoly * c->np, PRO_PLAIN, st, pc, kN);
+    hipError_t e = launch_ntt_stage(STAGE_INV_PLAIN, args_moddown_intt(c, acc, acc_stride, level, pc), npoly * c->np, st);
     if (e != hipSuccess) return e;
-    NttArgs a = base_args(c, false);
-    a.src = conv;
-    a.dst = conv;
-    a.map.rows = s.n;
-    a.map.level = level;
-    a.map.src_poly_stride = a.map.dst_poly_stride = nN;
-    a.galois = g;
-    a.cst = c->d_pinv;
-    a.bc_mode = 2;
-    a.bc_src = pc;
-    a.bc_poly_stride = kN;
-    a.pset = c->pset_index();
-    a.nprimes = c->nq + c->np;
-    a.hmod = c->d_bc_hmod;
-    for (uint32_t t = 0; t < npoly; ++t) {
-        a.aux[t] = acc + t * acc_stride;
-        a.add[t] = add ? add[t] : nullptr;
-        a.out[t] = out[t];
-    }
-    return launch_ntt_fwd(a, npoly * s.n, PRO_BCONV, EPI_MODDOWN, st, conv, nN);
+    return launch_ntt_stage(STAGE_FWD_BCONV_MODDOWN,
+                            args_moddown_ntt(c, acc, acc_stride, npoly, level, out, add, g, pc, conv), npoly * s.n, st);
 }
 
 // Full key switch of d (gathered through g_in) with `key`; outputs

@@ -67,6 +67,8 @@ enum NttEpi { EPI_PLAIN = 0, EPI_MODDOWN = 1, EPI_RESCALE = 2 };
 struct NttArgs {
     uint64_t *dst;
     const uint64_t *src;
+    uint64_t *mid;              // output of the first pass / input of the second (N = 2^16)
+    int64_t mid_stride;         // elements between polynomials in mid
     LimbMap map;
     const Prime *primes;
     const ulonglong2 *tw;       // [n_primes][N] {w, floor(w 2^64 / q)}
@@ -99,19 +101,58 @@ struct NttArgs {
     const uint64_t *hmod;       // [nsets][n_primes][kMaxDigitPrimes]
 };
 
-// ModUp's last forward pass fused with the key inner product: row r of the
-// extended basis is transformed for every digit (or, for the digit's own rows,
-// taken from d) and multiplied into both key halves, summed over the digits.
-struct RowIpArgs {
-    const uint64_t *mid;        // [beta][rows][N] first-pass output
-    const uint64_t *d;          // [l+1][N] evaluation-domain input (own rows of each digit)
-    uint32_t d_galois;          // own rows gathered through X -> X^g (1 = none)
-    const uint64_t *key;        // [dnum][2][nq+np][N]
-    uint64_t *acc;              // [2][rows][N]
-    const Prime *primes;
-    const ulonglong2 *tw;
-    const double *twd;
-    uint32_t beta, rows, level, nq, np, alpha, logn;
+// A unit of work of a persistent stage kernel is one tile of limb `limb` of
+// instance `inst` (an NttArgs / BconvArgs / IpArgs of the batch); units are
+// claimed in order from `counter`, which must be zero when the stage starts.
+struct UnitRec {
+    uint32_t inst, limb;
+};
+
+struct WorkQueue {
+    const UnitRec *recs;
+    uint32_t nrecs;
+    uint32_t tiles;             // units per record
+    uint32_t *counter;
+};
+
+// Persistent work-queue loop shared by every stage kernel: units are claimed
+// from q.counter (the next claim is issued while the current unit runs), the
+// unit's argument block is copied into LDS (`sa`) whenever the instance
+// changes, and body(sa, limb, tile) processes the unit with the whole block.
+template <class Args, class Body>
+__device__ __forceinline__ void run_work_queue(const Args *insts, const WorkQueue &q, Args &sa, uint32_t *claim,
+                                               Body body)
+{
+    static_assert(sizeof(Args) % 8 == 0, "argument blocks are copied as 8-byte words");
+    const uint32_t total = q.nrecs * q.tiles;
+    if (threadIdx.x == 0) *claim = atomicAdd(q.counter, 1u);
+    __syncthreads();
+    uint32_t u = *claim;
+    uint32_t have = 0xFFFFFFFFu;
+    while (u < total) {
+        const UnitRec rec = q.recs[u / q.tiles];
+        __syncthreads();  // every thread has read *claim and is done with sa and the unit's LDS
+        if (threadIdx.x == 0) *claim = atomicAdd(q.counter, 1u);
+        if (rec.inst != have) {
+            const uint64_t *src = (const uint64_t *)(insts + rec.inst);
+            uint64_t *dst = (uint64_t *)&sa;
+            for (uint32_t i = threadIdx.x; i < sizeof(Args) / 8; i += blockDim.x) dst[i] = src[i];
+            have = rec.inst;
+        }
+        __syncthreads();
+        body(sa, rec.limb, u % q.tiles);
+        __syncthreads();
+        u = *claim;
+    }
+}
+
+enum NttStage {
+    STAGE_FWD_PLAIN = 0,
+    STAGE_FWD_MODDOWN,
+    STAGE_FWD_RESCALE,
+    STAGE_FWD_BCONV_MODDOWN,
+    STAGE_INV_PLAIN,
+    STAGE_INV_GALOIS
 };
 
 struct BconvJob {
@@ -136,6 +177,7 @@ struct BconvArgs {
 };
 
 constexpr uint32_t kBconvRowGroup = 8;  // output rows per workgroup (grid z splits the rows)
+constexpr uint32_t kQueueBlocks = 16;   // 256-coefficient blocks per unit of the persistent coefficient-wise kernels
 
 struct IpArgs {
     const uint64_t *ext;        // [beta][rows][N]
@@ -148,13 +190,28 @@ struct IpArgs {
     uint32_t own_galois;        // own_galois), not from ext
 };
 
+struct TensorArgs {
+    const uint64_t *a0, *a1, *b0, *b1;
+    uint64_t *d0, *d1, *d2;
+    const Prime *primes;
+    uint32_t logn, pad;
+};
+
 // Launchers (all asynchronous on `stream`).
 hipError_t launch_ntt_fwd(const NttArgs &a, uint32_t nlimbs, NttPro pro, NttEpi epi, hipStream_t stream,
                           uint64_t *mid, int64_t mid_poly_stride);
 hipError_t launch_ntt_inv(const NttArgs &a, uint32_t nlimbs, NttPro pro, hipStream_t stream, uint64_t *mid,
                           int64_t mid_poly_stride);
-hipError_t launch_ntt_fwd_ip(const RowIpArgs &a, const NttArgs &col, hipStream_t stream);
+uint32_t ntt_passes(uint32_t logn);
+uint32_t ntt_tiles(uint32_t logn);
+hipError_t launch_ntt_stage(NttStage st, const NttArgs &a, uint32_t nlimbs, hipStream_t stream);
+hipError_t launch_ntt_stage_queue(NttStage st, uint32_t logn, uint32_t pass, const NttArgs *insts,
+                                  const WorkQueue &q, uint32_t grid, hipStream_t stream);
 hipError_t launch_bconv(const BconvArgs &a, uint32_t njobs, hipStream_t stream);
+hipError_t launch_bconv_queue(const BconvArgs *insts, const WorkQueue &q, uint32_t grid, hipStream_t stream);
+hipError_t launch_inner_product_queue(const IpArgs *insts, const WorkQueue &q, uint32_t grid, hipStream_t stream);
+hipError_t launch_tensor_queue(const TensorArgs *insts, const WorkQueue &q, uint32_t grid, hipStream_t stream);
+hipError_t launch_zero_u32(uint32_t *p, uint32_t n, hipStream_t stream);
 hipError_t launch_inner_product(const IpArgs &a, hipStream_t stream);
 hipError_t launch_tensor(const uint64_t *a0, const uint64_t *a1, const uint64_t *b0, const uint64_t *b1,
                          uint64_t *d0, uint64_t *d1, uint64_t *d2, const Prime *primes, uint32_t nlimbs,

@@ -22,15 +22,21 @@ __device__ __forceinline__ uint32_t row_prime(uint32_t r, uint32_t level, uint32
 // (as the paper does).  blockIdx.y selects the job (digit or polynomial),
 // blockIdx.z a group of kBconvRowGroup output rows whose constants are staged
 // in LDS.
-__global__ __launch_bounds__(kThreads) void k_bconv(BconvArgs a)
+struct BconvLds {
+    uint64_t hm[kBconvRowGroup][kMaxDigitPrimes];
+    Prime pr[kBconvRowGroup];
+};
+
+__device__ __forceinline__ void bconv_unit(const BconvArgs &a, uint32_t job, uint32_t bx, uint32_t bz, BconvLds &S)
 {
-    const BconvJob &J = a.job[blockIdx.y];
+    const BconvJob &J = a.job[job];
     const uint32_t N = a.N;
-    const uint32_t n = blockIdx.x * kThreads + threadIdx.x;
-    const uint32_t r0 = blockIdx.z * kBconvRowGroup;
+    const uint32_t n = bx * kThreads + threadIdx.x;
+    const uint32_t r0 = bz * kBconvRowGroup;
+    if (r0 >= a.nrows) return;
     const uint32_t r1 = min(r0 + kBconvRowGroup, a.nrows);
-    __shared__ uint64_t hm[kBconvRowGroup][kMaxDigitPrimes];
-    __shared__ Prime pr[kBconvRowGroup];
+    uint64_t (&hm)[kBconvRowGroup][kMaxDigitPrimes] = S.hm;
+    Prime (&pr)[kBconvRowGroup] = S.pr;
     if (threadIdx.x < kBconvRowGroup * kMaxDigitPrimes) {
         const uint32_t rr = threadIdx.x / kMaxDigitPrimes, i = threadIdx.x % kMaxDigitPrimes;
         if (r0 + rr < r1) {
@@ -71,20 +77,55 @@ __global__ __launch_bounds__(kThreads) void k_bconv(BconvArgs a)
     }
 }
 
+__global__ __launch_bounds__(kThreads) void k_bconv(BconvArgs a)
+{
+    __shared__ BconvLds S;
+    bconv_unit(a, blockIdx.y, blockIdx.x, blockIdx.z, S);
+}
+
+// persistent: tile t of record (inst, job) covers kQueueBlocks coefficient blocks
+// ((t % (N / (256 kQueueBlocks))) kQueueBlocks ..) of row group t / (N / (256 kQueueBlocks))
+__global__ __launch_bounds__(kThreads) void q_bconv(const BconvArgs *insts, WorkQueue q)
+{
+    __shared__ BconvLds S;
+    __shared__ BconvArgs sa;
+    __shared__ uint32_t claim;
+    run_work_queue(insts, q, sa, &claim, [&](const BconvArgs &a, uint32_t job, uint32_t t) {
+        const uint32_t nb = a.N / (kThreads * kQueueBlocks);
+        for (uint32_t i = 0; i < kQueueBlocks; ++i) {
+            if (i) __syncthreads();  // the row-group constants in S are rewritten
+            bconv_unit(a, job, (t % nb) * kQueueBlocks + i, t / nb, S);
+        }
+    });
+}
+
 // acc[t][r] = sum_j phi_g(ext_j)[r] * key[j][t][r] over the beta digits.
-__global__ __launch_bounds__(kThreads) void k_inner_product(IpArgs a)
+// Under X -> X^g the 256 positions of a block all come from one source block
+// (the low bits of the natural index are fixed inside a block of bit-reversed
+// positions), so a gathered row is read as one coalesced block into LDS and
+// permuted there.
+__device__ __forceinline__ uint64_t ip_read(const uint64_t *row, uint32_t n, uint32_t bx, uint32_t g, uint32_t logn,
+                                            uint64_t *stage)
+{
+    if (g == 1) return row[n];
+    const uint32_t sb = galois_src(bx * kThreads, g, logn) & ~(uint32_t)(kThreads - 1);
+    __syncthreads();
+    stage[threadIdx.x] = row[sb + threadIdx.x];
+    __syncthreads();
+    return stage[galois_src(n, g, logn) - sb];
+}
+
+__device__ __forceinline__ void ip_unit(const IpArgs &a, uint32_t r, uint32_t bx, uint64_t *stage)
 {
     const uint32_t N = 1u << a.logn;
-    const uint32_t r = blockIdx.y;
-    const uint32_t n = blockIdx.x * kThreads + threadIdx.x;
+    const uint32_t n = bx * kThreads + threadIdx.x;
     const uint32_t pi = row_prime(r, a.level, a.nq);  // also the key row
-    const uint32_t sn = a.galois == 1 ? n : galois_src(n, a.galois, a.logn);
     const size_t krows = a.nq + a.np;
     u128 s0 = {0, 0}, s1 = {0, 0};
     for (uint32_t j = 0; j < a.beta; ++j) {
         const bool own = a.own && r >= j * a.alpha && r < min(j * a.alpha + a.alpha, a.level + 1);
-        const uint64_t x = own ? a.own[(size_t)r * N + (a.own_galois == 1 ? n : galois_src(n, a.own_galois, a.logn))]
-                               : a.ext[((size_t)j * a.rows + r) * N + sn];
+        const uint64_t x = own ? ip_read(a.own + (size_t)r * N, n, bx, a.own_galois, a.logn, stage)
+                               : ip_read(a.ext + ((size_t)j * a.rows + r) * N, n, bx, a.galois, a.logn, stage);
         const uint64_t k0 = a.key[(((size_t)j * 2 + 0) * krows + pi) * N + n];
         const uint64_t k1 = a.key[(((size_t)j * 2 + 1) * krows + pi) * N + n];
         s0 = add128(s0, mul_wide(x, k0));
@@ -95,19 +136,49 @@ __global__ __launch_bounds__(kThreads) void k_inner_product(IpArgs a)
     a.acc[((size_t)a.rows + r) * N + n] = reduce128(s1, P);
 }
 
-// d0 = a0 b0, d1 = a0 b1 + a1 b0, d2 = a1 b1 (limb l under q_l)
-__global__ __launch_bounds__(kThreads) void k_tensor(const uint64_t *__restrict__ a0, const uint64_t *__restrict__ a1,
-                                                     const uint64_t *__restrict__ b0, const uint64_t *__restrict__ b1,
-                                                     uint64_t *d0, uint64_t *d1, uint64_t *d2, const Prime *primes,
-                                                     uint32_t logn)
+__global__ __launch_bounds__(kThreads) void k_inner_product(IpArgs a)
 {
-    const uint32_t l = blockIdx.y;
-    const size_t i = ((size_t)l << logn) + blockIdx.x * kThreads + threadIdx.x;
-    const Prime P = primes[l];
-    const uint64_t x0 = a0[i], x1 = a1[i], y0 = b0[i], y1 = b1[i];
-    d0[i] = reduce128(mul_wide(x0, y0), P);
-    d1[i] = reduce128(add128(mul_wide(x0, y1), mul_wide(x1, y0)), P);
-    d2[i] = reduce128(mul_wide(x1, y1), P);
+    __shared__ uint64_t stage[kThreads];
+    ip_unit(a, blockIdx.y, blockIdx.x, stage);
+}
+
+__global__ __launch_bounds__(kThreads) void q_inner_product(const IpArgs *insts, WorkQueue q)
+{
+    __shared__ uint64_t stage[kThreads];
+    __shared__ IpArgs sa;
+    __shared__ uint32_t claim;
+    run_work_queue(insts, q, sa, &claim, [&](const IpArgs &a, uint32_t row, uint32_t t) {
+        for (uint32_t i = 0; i < kQueueBlocks; ++i) ip_unit(a, row, t * kQueueBlocks + i, stage);
+    });
+}
+
+// d0 = a0 b0, d1 = a0 b1 + a1 b0, d2 = a1 b1 (limb l under q_l)
+__device__ __forceinline__ void tensor_unit(const TensorArgs &a, uint32_t l, uint32_t bx)
+{
+    const size_t i = ((size_t)l << a.logn) + bx * kThreads + threadIdx.x;
+    const Prime P = a.primes[l];
+    const uint64_t x0 = a.a0[i], x1 = a.a1[i], y0 = a.b0[i], y1 = a.b1[i];
+    a.d0[i] = reduce128(mul_wide(x0, y0), P);
+    a.d1[i] = reduce128(add128(mul_wide(x0, y1), mul_wide(x1, y0)), P);
+    a.d2[i] = reduce128(mul_wide(x1, y1), P);
+}
+
+__global__ __launch_bounds__(kThreads) void k_tensor(TensorArgs a) { tensor_unit(a, blockIdx.y, blockIdx.x); }
+
+__global__ __launch_bounds__(kThreads) void q_tensor(const TensorArgs *insts, WorkQueue q)
+{
+    __shared__ TensorArgs sa;
+    __shared__ uint32_t claim;
+    run_work_queue(insts, q, sa, &claim, [&](const TensorArgs &a, uint32_t limb, uint32_t t) {
+        for (uint32_t i = 0; i < kQueueBlocks; ++i) tensor_unit(a, limb, t * kQueueBlocks + i);
+    });
+}
+
+// zeroes n counters (a fill kernel: safe inside captured graphs)
+__global__ void k_zero_u32(uint32_t *p, uint32_t n)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
 }
 
 struct Scalars {
@@ -162,8 +233,33 @@ hipError_t launch_tensor(const uint64_t *a0, const uint64_t *a1, const uint64_t 
                          uint64_t *d1, uint64_t *d2, const Prime *primes, uint32_t nlimbs, uint32_t logn,
                          hipStream_t stream)
 {
-    hipLaunchKernelGGL(k_tensor, dim3((1u << logn) / kThreads, nlimbs), dim3(kThreads), 0, stream, a0, a1, b0, b1,
-                       d0, d1, d2, primes, logn);
+    TensorArgs a = {a0, a1, b0, b1, d0, d1, d2, primes, logn, 0};
+    hipLaunchKernelGGL(k_tensor, dim3((1u << logn) / kThreads, nlimbs), dim3(kThreads), 0, stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_bconv_queue(const BconvArgs *insts, const WorkQueue &q, uint32_t grid, hipStream_t stream)
+{
+    hipLaunchKernelGGL(q_bconv, dim3(grid), dim3(kThreads), 0, stream, insts, q);
+    return hipGetLastError();
+}
+
+hipError_t launch_inner_product_queue(const IpArgs *insts, const WorkQueue &q, uint32_t grid, hipStream_t stream)
+{
+    hipLaunchKernelGGL(q_inner_product, dim3(grid), dim3(kThreads), 0, stream, insts, q);
+    return hipGetLastError();
+}
+
+hipError_t launch_tensor_queue(const TensorArgs *insts, const WorkQueue &q, uint32_t grid, hipStream_t stream)
+{
+    hipLaunchKernelGGL(q_tensor, dim3(grid), dim3(kThreads), 0, stream, insts, q);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_u32(uint32_t *p, uint32_t n, hipStream_t stream)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_u32, dim3((n + 255) / 256), dim3(256), 0, stream, p, n);
     return hipGetLastError();
 }
 

@@ -165,11 +165,11 @@ struct LimbPos {
     bool skip;
 };
 
-__device__ __forceinline__ LimbPos limb_pos(const LimbMap &m)
+__device__ __forceinline__ LimbPos limb_pos(const LimbMap &m, uint32_t limb)
 {
     LimbPos p;
-    p.poly = blockIdx.y / m.rows;
-    p.row = blockIdx.y - p.poly * m.rows;
+    p.poly = limb / m.rows;
+    p.row = limb - p.poly * m.rows;
     p.skip = limb_skipped(m, p.poly, p.row);
     p.prime = limb_prime(m, p.row);
     return p;
@@ -193,10 +193,11 @@ __device__ __forceinline__ uint64_t load_fwd(const NttArgs &a, const LimbPos &lp
     }
 }
 
-// Final forward value x (canonical) at element e of the limb.
+// Final forward value x (canonical) at element e of the limb; `addv` is the
+// addend of the ModDown epilogue (already gathered, 0 without addend).
 template <int EPI>
 __device__ __forceinline__ void store_fwd(const NttArgs &a, const LimbPos &lp, uint64_t *dst, uint32_t e, uint64_t x,
-                                          const Prime &P, size_t N)
+                                          uint64_t addv, const Prime &P, size_t N)
 {
     if (EPI == EPI_PLAIN) {
         dst[e] = x;
@@ -204,10 +205,7 @@ __device__ __forceinline__ void store_fwd(const NttArgs &a, const LimbPos &lp, u
         const size_t off = (size_t)lp.row * N;
         const ulonglong2 c = a.cst[lp.prime];
         uint64_t r = shoup(submod(a.aux[lp.poly][off + e], x, P.q), c.x, c.y, P.q);
-        if (EPI == EPI_MODDOWN) {
-            const uint64_t *add = a.add[lp.poly];
-            if (add) r = addmod(r, add[off + (a.galois == 1 ? e : galois_src(e, a.galois, a.logn))], P.q);
-        }
+        if (EPI == EPI_MODDOWN) r = addmod(r, addv, P.q);
         a.out[lp.poly][off + e] = r;
     }
 }
@@ -321,12 +319,16 @@ __device__ __forceinline__ void bconv_load16(typename A::V (&v)[16], const A &ar
 }
 
 // ------------------------------------------------------------------ N = 2^16
+// Every kernel body processes one "unit": tile `tile` (16 columns or 16 rows
+// of the 256 x 256 view) of limb `limb` of a launch described by NttArgs.
+// Grid kernels take (tile, limb) from (blockIdx.x, blockIdx.y); persistent
+// kernels claim units from a work queue (see the end of this file).
 
 template <int PRO, class A>
 __device__ __forceinline__ void fwd_col_body(const NttArgs &a, const LimbPos &lp, const Prime &P, const A &ar,
-                                             uint64_t *lds, uint64_t *mid, int64_t mid_stride)
+                                             uint64_t *lds, uint32_t tile)
 {
-    const uint32_t col = threadIdx.x & 15, s = threadIdx.x >> 4, c = blockIdx.x * 16 + col;
+    const uint32_t col = threadIdx.x & 15, s = threadIdx.x >> 4, c = tile * 16 + col;
     const uint64_t *src = a.src + (int64_t)lp.poly * a.map.src_poly_stride + (size_t)lp.row * 65536;
     typename A::V v[16];
     if (PRO == PRO_BCONV) {
@@ -345,30 +347,29 @@ __device__ __forceinline__ void fwd_col_body(const NttArgs &a, const LimbPos &lp
     for (int i = 0; i < 16; ++i) v[i] = ar.from_bits(L[pad(16 * s + i)]);
     ar.reduce_all(v);
     fwd16<256, 1>(v, 16 * s, ar, 1);
-    uint64_t *m = mid + (int64_t)lp.poly * mid_stride + (size_t)lp.row * 65536;
+    uint64_t *m = a.mid + (int64_t)lp.poly * a.mid_stride + (size_t)lp.row * 65536;
 #pragma unroll
     for (int i = 0; i < 16; ++i) m[(16 * s + i) * 256 + c] = ar.to_bits(v[i]);
 }
 
 template <int PRO>
-__global__ __launch_bounds__(kThreads) void k_ntt16_fwd_col(NttArgs a, uint64_t *mid, int64_t mid_stride)
+__device__ __forceinline__ void fwd_col_unit(const NttArgs &a, uint32_t limb, uint32_t tile, uint64_t *lds)
 {
-    __shared__ uint64_t lds[16 * 272];
-    const LimbPos lp = limb_pos(a.map);
+    const LimbPos lp = limb_pos(a.map, limb);
     if (lp.skip) return;
     const Prime P = a.primes[lp.prime];
     if (P.q < kFpMaxPrime)
-        fwd_col_body<PRO>(a, lp, P, fp_arith(a, P, lp.prime, 65536), lds, mid, mid_stride);
+        fwd_col_body<PRO>(a, lp, P, fp_arith(a, P, lp.prime, 65536), lds, tile);
     else
-        fwd_col_body<PRO>(a, lp, P, int_arith(a, P, lp.prime, 65536), lds, mid, mid_stride);
+        fwd_col_body<PRO>(a, lp, P, int_arith(a, P, lp.prime, 65536), lds, tile);
 }
 
 template <int EPI, class A>
 __device__ __forceinline__ void fwd_row_body(const NttArgs &a, const LimbPos &lp, const Prime &P, const A &ar,
-                                             uint64_t *lds, const uint64_t *mid, int64_t mid_stride)
+                                             uint64_t *lds, uint32_t tile)
 {
-    const uint32_t blk = threadIdx.x >> 4, s = threadIdx.x & 15, b = blockIdx.x * 16 + blk;
-    const uint64_t *m = mid + (int64_t)lp.poly * mid_stride + (size_t)lp.row * 65536 + b * 256;
+    const uint32_t blk = threadIdx.x >> 4, s = threadIdx.x & 15, b = tile * 16 + blk;
+    const uint64_t *m = a.mid + (int64_t)lp.poly * a.mid_stride + (size_t)lp.row * 65536 + b * 256;
     typename A::V v[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) v[i] = ar.from_bits(m[s + 16 * i]);
@@ -385,29 +386,50 @@ __device__ __forceinline__ void fwd_row_body(const NttArgs &a, const LimbPos &lp
 #pragma unroll
     for (int i = 0; i < 16; ++i) L[pad(16 * s + i)] = ar.fwd_final(v[i]);
     __syncthreads();
+    uint64_t x[16], addv[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        x[i] = L[pad(s + 16 * i)];
+        addv[i] = 0;
+    }
+    const uint64_t *add = EPI == EPI_MODDOWN ? a.add[lp.poly] : nullptr;
+    if (add) {
+        add += (size_t)lp.row * 65536;
+        if (a.galois == 1) {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) addv[i] = add[b * 256 + s + 16 * i];
+        } else {  // block b's addend comes from one block sb: stage it through LDS
+            const uint32_t sb = galois_src(b * 256, a.galois, 16) & ~255u;
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < 16; ++i) L[pad(s + 16 * i)] = add[sb + s + 16 * i];
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < 16; ++i) addv[i] = L[pad(galois_src(b * 256 + s + 16 * i, a.galois, 16) - sb)];
+        }
+    }
     uint64_t *dst = a.dst + (int64_t)lp.poly * a.map.dst_poly_stride + (size_t)lp.row * 65536;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) store_fwd<EPI>(a, lp, dst, b * 256 + s + 16 * i, L[pad(s + 16 * i)], P, 65536);
+    for (int i = 0; i < 16; ++i) store_fwd<EPI>(a, lp, dst, b * 256 + s + 16 * i, x[i], addv[i], P, 65536);
 }
 
 template <int EPI>
-__global__ __launch_bounds__(kThreads) void k_ntt16_fwd_row(NttArgs a, const uint64_t *mid, int64_t mid_stride)
+__device__ __forceinline__ void fwd_row_unit(const NttArgs &a, uint32_t limb, uint32_t tile, uint64_t *lds)
 {
-    __shared__ uint64_t lds[16 * 272];
-    const LimbPos lp = limb_pos(a.map);
+    const LimbPos lp = limb_pos(a.map, limb);
     if (lp.skip) return;
     const Prime P = a.primes[lp.prime];
     if (P.q < kFpMaxPrime)
-        fwd_row_body<EPI>(a, lp, P, fp_arith(a, P, lp.prime, 65536), lds, mid, mid_stride);
+        fwd_row_body<EPI>(a, lp, P, fp_arith(a, P, lp.prime, 65536), lds, tile);
     else
-        fwd_row_body<EPI>(a, lp, P, int_arith(a, P, lp.prime, 65536), lds, mid, mid_stride);
+        fwd_row_body<EPI>(a, lp, P, int_arith(a, P, lp.prime, 65536), lds, tile);
 }
 
 template <int PRO, class A>
 __device__ __forceinline__ void inv_row_body(const NttArgs &a, const LimbPos &lp, const A &ar, uint64_t *lds,
-                                             uint64_t *mid, int64_t mid_stride)
+                                             uint32_t tile)
 {
-    const uint32_t blk = threadIdx.x >> 4, s = threadIdx.x & 15, b = blockIdx.x * 16 + blk;
+    const uint32_t blk = threadIdx.x >> 4, s = threadIdx.x & 15, b = tile * 16 + blk;
     const uint64_t *src = a.src + (int64_t)lp.poly * a.map.src_poly_stride + (size_t)lp.row * 65536;
     uint64_t *L = lds + blk * 272;
 #pragma unroll
@@ -428,30 +450,29 @@ __device__ __forceinline__ void inv_row_body(const NttArgs &a, const LimbPos &lp
     for (int i = 0; i < 16; ++i) v[i] = ar.from_bits(L[pad(s + 16 * i)]);
     ar.reduce_all(v);
     inv16<256, 16>(v, s, ar, 256 + b);
-    uint64_t *m = mid + (int64_t)lp.poly * mid_stride + (size_t)lp.row * 65536 + b * 256;
+    uint64_t *m = a.mid + (int64_t)lp.poly * a.mid_stride + (size_t)lp.row * 65536 + b * 256;
 #pragma unroll
     for (int i = 0; i < 16; ++i) m[s + 16 * i] = ar.to_bits(v[i]);
 }
 
 template <int PRO>
-__global__ __launch_bounds__(kThreads) void k_ntt16_inv_row(NttArgs a, uint64_t *mid, int64_t mid_stride)
+__device__ __forceinline__ void inv_row_unit(const NttArgs &a, uint32_t limb, uint32_t tile, uint64_t *lds)
 {
-    __shared__ uint64_t lds[16 * 272];
-    const LimbPos lp = limb_pos(a.map);
+    const LimbPos lp = limb_pos(a.map, limb);
     if (lp.skip) return;
     const Prime P = a.primes[lp.prime];
     if (P.q < kFpMaxPrime)
-        inv_row_body<PRO>(a, lp, fp_arith(a, P, lp.prime, 65536), lds, mid, mid_stride);
+        inv_row_body<PRO>(a, lp, fp_arith(a, P, lp.prime, 65536), lds, tile);
     else
-        inv_row_body<PRO>(a, lp, int_arith(a, P, lp.prime, 65536), lds, mid, mid_stride);
+        inv_row_body<PRO>(a, lp, int_arith(a, P, lp.prime, 65536), lds, tile);
 }
 
 template <class A>
 __device__ __forceinline__ void inv_col_body(const NttArgs &a, const LimbPos &lp, const A &ar, uint64_t *lds,
-                                             const uint64_t *mid, int64_t mid_stride)
+                                             uint32_t tile)
 {
-    const uint32_t col = threadIdx.x & 15, s = threadIdx.x >> 4, c = blockIdx.x * 16 + col;
-    const uint64_t *m = mid + (int64_t)lp.poly * mid_stride + (size_t)lp.row * 65536;
+    const uint32_t col = threadIdx.x & 15, s = threadIdx.x >> 4, c = tile * 16 + col;
+    const uint64_t *m = a.mid + (int64_t)lp.poly * a.mid_stride + (size_t)lp.row * 65536;
     typename A::V v[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) v[i] = ar.from_bits(m[(16 * s + i) * 256 + c]);
@@ -470,16 +491,15 @@ __device__ __forceinline__ void inv_col_body(const NttArgs &a, const LimbPos &lp
     for (int i = 0; i < 16; ++i) dst[(s + 16 * i) * 256 + c] = ar.inv_final(v[i]);
 }
 
-__global__ __launch_bounds__(kThreads) void k_ntt16_inv_col(NttArgs a, const uint64_t *mid, int64_t mid_stride)
+__device__ __forceinline__ void inv_col_unit(const NttArgs &a, uint32_t limb, uint32_t tile, uint64_t *lds)
 {
-    __shared__ uint64_t lds[16 * 272];
-    const LimbPos lp = limb_pos(a.map);
+    const LimbPos lp = limb_pos(a.map, limb);
     if (lp.skip) return;
     const Prime P = a.primes[lp.prime];
     if (P.q < kFpMaxPrime)
-        inv_col_body(a, lp, inv_fp_arith(a, lp, P, 65536), lds, mid, mid_stride);
+        inv_col_body(a, lp, inv_fp_arith(a, lp, P, 65536), lds, tile);
     else
-        inv_col_body(a, lp, inv_int_arith(a, lp, P, 65536), lds, mid, mid_stride);
+        inv_col_body(a, lp, inv_int_arith(a, lp, P, 65536), lds, tile);
 }
 
 // ------------------------------------------------------------------ N = 2^12
@@ -515,16 +535,36 @@ __device__ __forceinline__ void fwd12_body(const NttArgs &a, const LimbPos &lp, 
 #pragma unroll
     for (int i = 0; i < 16; ++i) lds[pad(16 * t + i)] = ar.fwd_final(v[i]);
     __syncthreads();
+    uint64_t x[16], addv[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        x[i] = lds[pad(t + 256 * i)];
+        addv[i] = 0;
+    }
+    const uint64_t *add = EPI == EPI_MODDOWN ? a.add[lp.poly] : nullptr;
+    if (add) {
+        add += (size_t)lp.row * 4096;
+        if (a.galois == 1) {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) addv[i] = add[t + 256 * i];
+        } else {  // the whole limb's addend through LDS, then permuted
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < 16; ++i) lds[pad(t + 256 * i)] = add[t + 256 * i];
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < 16; ++i) addv[i] = lds[pad(galois_src(t + 256 * i, a.galois, 12))];
+        }
+    }
     uint64_t *dst = a.dst + (int64_t)lp.poly * a.map.dst_poly_stride + (size_t)lp.row * 4096;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) store_fwd<EPI>(a, lp, dst, t + 256 * i, lds[pad(t + 256 * i)], P, 4096);
+    for (int i = 0; i < 16; ++i) store_fwd<EPI>(a, lp, dst, t + 256 * i, x[i], addv[i], P, 4096);
 }
 
 template <int PRO, int EPI>
-__global__ __launch_bounds__(kThreads) void k_ntt12_fwd(NttArgs a)
+__device__ __forceinline__ void fwd12_unit(const NttArgs &a, uint32_t limb, uint32_t, uint64_t *lds)
 {
-    __shared__ uint64_t lds[4352];
-    const LimbPos lp = limb_pos(a.map);
+    const LimbPos lp = limb_pos(a.map, limb);
     if (lp.skip) return;
     const Prime P = a.primes[lp.prime];
     if (P.q < kFpMaxPrime)
@@ -569,10 +609,9 @@ __device__ __forceinline__ void inv12_body(const NttArgs &a, const LimbPos &lp, 
 }
 
 template <int PRO>
-__global__ __launch_bounds__(kThreads) void k_ntt12_inv(NttArgs a)
+__device__ __forceinline__ void inv12_unit(const NttArgs &a, uint32_t limb, uint32_t, uint64_t *lds)
 {
-    __shared__ uint64_t lds[4352];
-    const LimbPos lp = limb_pos(a.map);
+    const LimbPos lp = limb_pos(a.map, limb);
     if (lp.skip) return;
     const Prime P = a.primes[lp.prime];
     if (P.q < kFpMaxPrime)
@@ -581,233 +620,147 @@ __global__ __launch_bounds__(kThreads) void k_ntt12_inv(NttArgs a)
         inv12_body<PRO>(a, lp, inv_int_arith(a, lp, P, 4096), lds);
 }
 
-// ------------------------------------------- ModUp last pass + key inner product
+// ---------------------------------------------------- kernels: grid and queue
+// Every NTT stage exists as a grid kernel (one launch = one NttArgs, unit =
+// (blockIdx.x, blockIdx.y)) and as a persistent kernel that claims units
+// (instance, limb, tile) of many launches from a work queue, so a whole batch
+// of ciphertexts at different levels goes through one launch per stage.
 
-__device__ __forceinline__ uint32_t ext_row_prime(uint32_t r, uint32_t level, uint32_t nq)
-{
-    return r <= level ? r : nq + (r - level - 1);
-}
+constexpr int kLds16 = 16 * 272, kLds12 = 4352;
 
-// One workgroup per (16 blocks of one extended row r): for each digit the row
-// pass of NTT(Conv(digit)) runs (or, for the digit's own rows, the input is
-// read), and both key halves are multiplied in and summed over the digits.
-template <class A>
-__device__ __forceinline__ void row_ip16_body(const RowIpArgs &a, const A &ar, const Prime &P, uint32_t r,
-                                              uint32_t pi, uint64_t *lds)
-{
-    const size_t N = 65536, krows = a.nq + a.np;
-    const uint32_t blk = threadIdx.x >> 4, s = threadIdx.x & 15, b = blockIdx.x * 16 + blk;
-    uint64_t *L = lds + blk * 272;
-    typename A::V acc0[16], acc1[16];
-#pragma unroll
-    for (int i = 0; i < 16; ++i) acc0[i] = acc1[i] = (typename A::V)0;
-    for (uint32_t j = 0; j < a.beta; ++j) {
-        const uint32_t lo = j * a.alpha, hi = min(lo + a.alpha, a.level + 1);
-        typename A::V v[16];
-        if (r >= lo && r < hi) {
-#pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                const uint32_t e = b * 256 + s + 16 * i;
-                v[i] = ar.own(a.d[(size_t)r * N + (a.d_galois == 1 ? e : galois_src(e, a.d_galois, 16))]);
-            }
-        } else {
-            const uint64_t *m = a.mid + ((size_t)j * a.rows + r) * N + b * 256;
-#pragma unroll
-            for (int i = 0; i < 16; ++i) v[i] = ar.from_bits(m[s + 16 * i]);
-            ar.reduce_all(v);
-            fwd16<256, 16>(v, s, ar, 256 + b);
-#pragma unroll
-            for (int i = 0; i < 16; ++i) L[pad(s + 16 * i)] = ar.to_bits(v[i]);
-            __syncthreads();
-#pragma unroll
-            for (int i = 0; i < 16; ++i) v[i] = ar.from_bits(L[pad(16 * s + i)]);
-            ar.reduce_all(v);
-            fwd16<256, 1>(v, 16 * s, ar, 256 + b);
-#pragma unroll
-            for (int i = 0; i < 16; ++i) L[pad(16 * s + i)] = ar.to_bits(ar.mac_in(v[i]));
-            __syncthreads();
-#pragma unroll
-            for (int i = 0; i < 16; ++i) v[i] = ar.from_bits(L[pad(s + 16 * i)]);
-            __syncthreads();
-        }
-        const uint64_t *k0 = a.key + ((size_t)(2 * j) * krows + pi) * N + b * 256;
-        const uint64_t *k1 = a.key + ((size_t)(2 * j + 1) * krows + pi) * N + b * 256;
-#pragma unroll
-        for (int half = 0; half < 2; ++half) {
-            uint64_t kk0[8], kk1[8];
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                kk0[i] = k0[s + 16 * (8 * half + i)];
-                kk1[i] = k1[s + 16 * (8 * half + i)];
-            }
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                ar.mac(acc0[8 * half + i], v[8 * half + i], kk0[i], P);
-                ar.mac(acc1[8 * half + i], v[8 * half + i], kk1[i], P);
-            }
-        }
+#define NTT_KERNELS(NAME, LDS, UNIT)                                                              \
+    __global__ __launch_bounds__(kThreads) void k_##NAME(NttArgs a)                              \
+    {                                                                                             \
+        __shared__ uint64_t lds[LDS];                                                             \
+        UNIT(a, blockIdx.y, blockIdx.x, lds);                                                     \
+    }                                                                                             \
+    __global__ __launch_bounds__(kThreads) void q_##NAME(const NttArgs *insts, WorkQueue q)       \
+    {                                                                                             \
+        __shared__ uint64_t lds[LDS];                                                             \
+        __shared__ NttArgs sa;                                                                    \
+        __shared__ uint32_t claim;                                                                \
+        run_work_queue(insts, q, sa, &claim,                                                      \
+                       [&](const NttArgs &a, uint32_t limb, uint32_t tile) { UNIT(a, limb, tile, lds); }); \
     }
-    uint64_t *o0 = a.acc + (size_t)r * N + b * 256, *o1 = a.acc + ((size_t)a.rows + r) * N + b * 256;
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        o0[s + 16 * i] = ar.acc_final(acc0[i]);
-        o1[s + 16 * i] = ar.acc_final(acc1[i]);
-    }
-}
 
-__global__ __launch_bounds__(kThreads) void k_ntt16_fwd_row_ip(RowIpArgs a)
-{
-    __shared__ uint64_t lds[16 * 272];
-    const uint32_t r = blockIdx.y, pi = ext_row_prime(r, a.level, a.nq);
-    const Prime P = a.primes[pi];
-    if (P.q < kFpMaxPrime)
-        row_ip16_body(a, fp_arith(a.twd, P, pi, 65536), P, r, pi, lds);
-    else
-        row_ip16_body(a, int_arith(a.tw, P, pi, 65536), P, r, pi, lds);
-}
+NTT_KERNELS(fwd_col_plain, kLds16, fwd_col_unit<PRO_PLAIN>)
+NTT_KERNELS(fwd_col_rescale, kLds16, fwd_col_unit<PRO_RESCALE>)
+NTT_KERNELS(fwd_col_bconv, kLds16, fwd_col_unit<PRO_BCONV>)
+NTT_KERNELS(fwd_row_plain, kLds16, fwd_row_unit<EPI_PLAIN>)
+NTT_KERNELS(fwd_row_moddown, kLds16, fwd_row_unit<EPI_MODDOWN>)
+NTT_KERNELS(fwd_row_rescale, kLds16, fwd_row_unit<EPI_RESCALE>)
+NTT_KERNELS(inv_row_plain, kLds16, inv_row_unit<PRO_PLAIN>)
+NTT_KERNELS(inv_row_galois, kLds16, inv_row_unit<PRO_GALOIS>)
+NTT_KERNELS(inv_col, kLds16, inv_col_unit)
+#define FWD12_PP fwd12_unit<PRO_PLAIN, EPI_PLAIN>
+#define FWD12_PM fwd12_unit<PRO_PLAIN, EPI_MODDOWN>
+#define FWD12_RR fwd12_unit<PRO_RESCALE, EPI_RESCALE>
+#define FWD12_BM fwd12_unit<PRO_BCONV, EPI_MODDOWN>
+NTT_KERNELS(fwd12_plain, kLds12, FWD12_PP)
+NTT_KERNELS(fwd12_moddown, kLds12, FWD12_PM)
+NTT_KERNELS(fwd12_rescale, kLds12, FWD12_RR)
+NTT_KERNELS(fwd12_bconv_moddown, kLds12, FWD12_BM)
+NTT_KERNELS(inv12_plain, kLds12, inv12_unit<PRO_PLAIN>)
+NTT_KERNELS(inv12_galois, kLds12, inv12_unit<PRO_GALOIS>)
+#undef FWD12_PP
+#undef FWD12_PM
+#undef FWD12_RR
+#undef FWD12_BM
+#undef NTT_KERNELS
 
-// N = 2^12: one workgroup per extended row does, per digit, the base
-// conversion, the whole transform and the key products.
-template <class A>
-__device__ __forceinline__ void ip12_body(const RowIpArgs &a, const NttArgs &c, const A &ar, const Prime &P,
-                                          uint32_t r, uint32_t pi, uint64_t *lds)
+typedef void (*GridKernel)(NttArgs);
+typedef void (*QueueKernel)(const NttArgs *, WorkQueue);
+
+struct StageKernels {
+    GridKernel grid;
+    QueueKernel queue;
+};
+
+// The kernel that runs one pass of a stage (pass 0 = first, 1 = second at N = 2^16).
+bool stage_kernels(NttStage st, uint32_t logn, int pass, StageKernels &k)
 {
-    const size_t N = 4096, krows = a.nq + a.np;
-    const uint32_t t = threadIdx.x, base2 = (t >> 4) * 256 + (t & 15);
-    typename A::V acc0[16], acc1[16];
-#pragma unroll
-    for (int i = 0; i < 16; ++i) acc0[i] = acc1[i] = (typename A::V)0;
-    for (uint32_t j = 0; j < a.beta; ++j) {
-        const uint32_t lo = j * a.alpha, hi = min(lo + a.alpha, a.level + 1);
-        typename A::V v[16];
-        if (r >= lo && r < hi) {
-#pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                const uint32_t e = t + 256 * i;
-                v[i] = ar.own(a.d[(size_t)r * N + (a.d_galois == 1 ? e : galois_src(e, a.d_galois, 12))]);
-            }
-        } else {
-            bconv_load16(v, ar, bc_source(c, j, pi, N), P, N, [&](int i) { return t + 256 * i; });
-            fwd16<4096, 256>(v, t, ar, 1);
-#pragma unroll
-            for (int i = 0; i < 16; ++i) lds[pad(t + 256 * i)] = ar.to_bits(v[i]);
-            __syncthreads();
-#pragma unroll
-            for (int i = 0; i < 16; ++i) v[i] = ar.from_bits(lds[pad(base2 + 16 * i)]);
-            ar.reduce_all(v);
-            fwd16<4096, 16>(v, base2, ar, 1);
-#pragma unroll
-            for (int i = 0; i < 16; ++i) lds[pad(base2 + 16 * i)] = ar.to_bits(v[i]);
-            __syncthreads();
-#pragma unroll
-            for (int i = 0; i < 16; ++i) v[i] = ar.from_bits(lds[pad(16 * t + i)]);
-            ar.reduce_all(v);
-            fwd16<4096, 1>(v, 16 * t, ar, 1);
-#pragma unroll
-            for (int i = 0; i < 16; ++i) lds[pad(16 * t + i)] = ar.to_bits(ar.mac_in(v[i]));
-            __syncthreads();
-#pragma unroll
-            for (int i = 0; i < 16; ++i) v[i] = ar.from_bits(lds[pad(t + 256 * i)]);
-            __syncthreads();
-        }
-        const uint64_t *k0 = a.key + ((size_t)(2 * j) * krows + pi) * N;
-        const uint64_t *k1 = a.key + ((size_t)(2 * j + 1) * krows + pi) * N;
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            ar.mac(acc0[i], v[i], k0[t + 256 * i], P);
-            ar.mac(acc1[i], v[i], k1[t + 256 * i], P);
+#define SK(G) \
+    k.grid = k_##G; \
+    k.queue = q_##G; \
+    return true;
+    if (logn == 12) {
+        if (pass != 0) return false;
+        switch (st) {
+        case STAGE_FWD_PLAIN: SK(fwd12_plain)
+        case STAGE_FWD_MODDOWN: SK(fwd12_moddown)
+        case STAGE_FWD_RESCALE: SK(fwd12_rescale)
+        case STAGE_FWD_BCONV_MODDOWN: SK(fwd12_bconv_moddown)
+        case STAGE_INV_PLAIN: SK(inv12_plain)
+        case STAGE_INV_GALOIS: SK(inv12_galois)
+        default: return false;
         }
     }
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        a.acc[(size_t)r * N + t + 256 * i] = ar.acc_final(acc0[i]);
-        a.acc[((size_t)a.rows + r) * N + t + 256 * i] = ar.acc_final(acc1[i]);
+    switch (st) {
+    case STAGE_FWD_PLAIN:
+        if (pass == 0) { SK(fwd_col_plain) } else { SK(fwd_row_plain) }
+    case STAGE_FWD_MODDOWN:
+        if (pass == 0) { SK(fwd_col_plain) } else { SK(fwd_row_moddown) }
+    case STAGE_FWD_RESCALE:
+        if (pass == 0) { SK(fwd_col_rescale) } else { SK(fwd_row_rescale) }
+    case STAGE_FWD_BCONV_MODDOWN:
+        if (pass == 0) { SK(fwd_col_bconv) } else { SK(fwd_row_moddown) }
+    case STAGE_INV_PLAIN:
+        if (pass == 0) { SK(inv_row_plain) } else { SK(inv_col) }
+    case STAGE_INV_GALOIS:
+        if (pass == 0) { SK(inv_row_galois) } else { SK(inv_col) }
+    default: return false;
     }
-}
-
-__global__ __launch_bounds__(kThreads) void k_ntt12_fwd_ip(RowIpArgs a, NttArgs c)
-{
-    __shared__ uint64_t lds[4352];
-    const uint32_t r = blockIdx.y, pi = ext_row_prime(r, a.level, a.nq);
-    const Prime P = a.primes[pi];
-    if (P.q < kFpMaxPrime)
-        ip12_body(a, c, fp_arith(a.twd, P, pi, 4096), P, r, pi, lds);
-    else
-        ip12_body(a, c, int_arith(a.tw, P, pi, 4096), P, r, pi, lds);
+#undef SK
 }
 
 }  // namespace
 
-hipError_t launch_ntt_fwd(const NttArgs &a, uint32_t nlimbs, NttPro pro, NttEpi epi, hipStream_t stream,
+uint32_t ntt_passes(uint32_t logn) { return logn == 12 ? 1 : 2; }
+uint32_t ntt_tiles(uint32_t logn) { return logn == 12 ? 1 : 16; }
+
+hipError_t launch_ntt_stage(NttStage st, const NttArgs &a, uint32_t nlimbs, hipStream_t stream)
+{
+    if (nlimbs == 0) return hipSuccess;
+    for (uint32_t pass = 0; pass < ntt_passes(a.logn); ++pass) {
+        StageKernels k;
+        if (!stage_kernels(st, a.logn, pass, k)) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k.grid, dim3(ntt_tiles(a.logn), nlimbs), dim3(kThreads), 0, stream, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_ntt_stage_queue(NttStage st, uint32_t logn, uint32_t pass, const NttArgs *insts,
+                                  const WorkQueue &q, uint32_t grid, hipStream_t stream)
+{
+    StageKernels k;
+    if (!stage_kernels(st, logn, pass, k)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k.queue, dim3(grid), dim3(kThreads), 0, stream, insts, q);
+    return hipGetLastError();
+}
+
+// Compatibility wrappers used by the single-operation paths.
+hipError_t launch_ntt_fwd(const NttArgs &a0, uint32_t nlimbs, NttPro pro, NttEpi epi, hipStream_t stream,
                           uint64_t *mid, int64_t mid_poly_stride)
 {
-    if (nlimbs == 0) return hipSuccess;
-    dim3 block(kThreads);
-    if (a.logn == 12) {
-        dim3 grid(1, nlimbs);
-#define K12(P, E)                                                                            \
-    if (pro == P && epi == E) {                                                              \
-        hipLaunchKernelGGL((k_ntt12_fwd<P, E>), grid, block, 0, stream, a);                 \
-        return hipGetLastError();                                                            \
-    }
-        K12(PRO_PLAIN, EPI_PLAIN)
-        K12(PRO_PLAIN, EPI_MODDOWN)
-        K12(PRO_RESCALE, EPI_RESCALE)
-        K12(PRO_BCONV, EPI_MODDOWN)
-#undef K12
-        return hipErrorInvalidValue;
-    }
-    dim3 grid(16, nlimbs);
-    if (pro == PRO_PLAIN)
-        hipLaunchKernelGGL((k_ntt16_fwd_col<PRO_PLAIN>), grid, block, 0, stream, a, mid, mid_poly_stride);
-    else if (pro == PRO_RESCALE)
-        hipLaunchKernelGGL((k_ntt16_fwd_col<PRO_RESCALE>), grid, block, 0, stream, a, mid, mid_poly_stride);
-    else if (pro == PRO_BCONV)
-        hipLaunchKernelGGL((k_ntt16_fwd_col<PRO_BCONV>), grid, block, 0, stream, a, mid, mid_poly_stride);
-    else
-        return hipErrorInvalidValue;
-    if (epi == EPI_PLAIN)
-        hipLaunchKernelGGL((k_ntt16_fwd_row<EPI_PLAIN>), grid, block, 0, stream, a, mid, mid_poly_stride);
-    else if (epi == EPI_MODDOWN)
-        hipLaunchKernelGGL((k_ntt16_fwd_row<EPI_MODDOWN>), grid, block, 0, stream, a, mid, mid_poly_stride);
-    else
-        hipLaunchKernelGGL((k_ntt16_fwd_row<EPI_RESCALE>), grid, block, 0, stream, a, mid, mid_poly_stride);
-    return hipGetLastError();
+    NttArgs a = a0;
+    a.mid = mid;
+    a.mid_stride = mid_poly_stride;
+    NttStage st;
+    if (pro == PRO_PLAIN && epi == EPI_PLAIN) st = STAGE_FWD_PLAIN;
+    else if (pro == PRO_PLAIN && epi == EPI_MODDOWN) st = STAGE_FWD_MODDOWN;
+    else if (pro == PRO_RESCALE && epi == EPI_RESCALE) st = STAGE_FWD_RESCALE;
+    else if (pro == PRO_BCONV && epi == EPI_MODDOWN) st = STAGE_FWD_BCONV_MODDOWN;
+    else return hipErrorInvalidValue;
+    return launch_ntt_stage(st, a, nlimbs, stream);
 }
 
-hipError_t launch_ntt_fwd_ip(const RowIpArgs &a, const NttArgs &col, hipStream_t stream)
-{
-    dim3 block(kThreads);
-    if (a.logn == 12) {
-        hipLaunchKernelGGL(k_ntt12_fwd_ip, dim3(1, a.rows), block, 0, stream, a, col);
-        return hipGetLastError();
-    }
-    hipLaunchKernelGGL((k_ntt16_fwd_col<PRO_BCONV>), dim3(16, a.beta * a.rows), block, 0, stream, col,
-                       (uint64_t *)a.mid, (int64_t)a.rows * 65536);
-    hipLaunchKernelGGL(k_ntt16_fwd_row_ip, dim3(16, a.rows), block, 0, stream, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_ntt_inv(const NttArgs &a, uint32_t nlimbs, NttPro pro, hipStream_t stream, uint64_t *mid,
+hipError_t launch_ntt_inv(const NttArgs &a0, uint32_t nlimbs, NttPro pro, hipStream_t stream, uint64_t *mid,
                           int64_t mid_poly_stride)
 {
-    if (nlimbs == 0) return hipSuccess;
-    dim3 block(kThreads);
-    if (a.logn == 12) {
-        dim3 grid(1, nlimbs);
-        if (pro == PRO_GALOIS)
-            hipLaunchKernelGGL((k_ntt12_inv<PRO_GALOIS>), grid, block, 0, stream, a);
-        else
-            hipLaunchKernelGGL((k_ntt12_inv<PRO_PLAIN>), grid, block, 0, stream, a);
-        return hipGetLastError();
-    }
-    dim3 grid(16, nlimbs);
-    if (pro == PRO_GALOIS)
-        hipLaunchKernelGGL((k_ntt16_inv_row<PRO_GALOIS>), grid, block, 0, stream, a, mid, mid_poly_stride);
-    else
-        hipLaunchKernelGGL((k_ntt16_inv_row<PRO_PLAIN>), grid, block, 0, stream, a, mid, mid_poly_stride);
-    hipLaunchKernelGGL(k_ntt16_inv_col, grid, block, 0, stream, a, mid, mid_poly_stride);
-    return hipGetLastError();
+    NttArgs a = a0;
+    a.mid = mid;
+    a.mid_stride = mid_poly_stride;
+    return launch_ntt_stage(pro == PRO_GALOIS ? STAGE_INV_GALOIS : STAGE_INV_PLAIN, a, nlimbs, stream);
 }
 
 }  // namespace ckks

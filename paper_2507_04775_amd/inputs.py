@@ -156,6 +156,20 @@ def random_key(seed: int, ps: ParamSet) -> np.ndarray:
     return key
 
 
+def device_residues(seed: int, moduli, N: int, device="cuda"):
+    """Uniform residues generated directly in device memory (torch's Philox
+    generator, seeded): rows of a [len(moduli)][N] uint64 tensor, row i in
+    [0, moduli[i]).  Used where the inputs are too large to draw on the host
+    quickly (batched and served workloads); run time does not depend on values."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    out = torch.empty((len(moduli), N), dtype=torch.int64, device=device)
+    for i, m in enumerate(moduli):
+        out[i] = torch.randint(0, int(m), (N,), generator=gen, dtype=torch.int64, device=device)
+    return out.view(torch.uint64)
+
+
 def ternary(g: np.random.Generator, N: int) -> np.ndarray:
     """Secret coefficients iid uniform in {-1, 0, 1}."""
     return g.integers(-1, 2, size=N).astype(np.int64)
@@ -175,3 +189,23 @@ def complex_slots(g: np.random.Generator, n: int) -> np.ndarray:
 
 def rotation_index(seed: int, logn: int) -> int:
     return int(rng(seed).integers(1, 1 << (logn - 1)))
+
+
+# Rotation indices of the batched workload: 1..16 and the powers of two up to N/4.
+def batch_rotation_set(logn: int) -> list[int]:
+    return list(range(1, 17)) + [1 << k for k in range(5, logn - 1)]
+
+
+def batch_plan(seed: int, n_items: int, logn: int, max_level: int, min_level: int = 4, n_rot: int = 8):
+    """The mixed batch: half HMult+relin items, half hoisted-rotation items,
+    levels uniform in [min_level, max_level], n_rot distinct rotations each."""
+    g = rng(seed)
+    rs = batch_rotation_set(logn)
+    plan = []
+    for i in range(n_items):
+        level = int(g.integers(min_level, max_level + 1))
+        if i % 2 == 0:
+            plan.append(("hmult", level, None))
+        else:
+            plan.append(("hoisted", level, [int(x) for x in g.choice(rs, size=n_rot, replace=False)]))
+    return plan
