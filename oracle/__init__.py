@@ -68,6 +68,7 @@ def lib():
                                        u64p, u64p]
         L.orc_hoisted_rotate.argtypes = [u32, u64p, u32, u64p, u32, u32, u32, u64p, u64p, u32, u64p,
                                          ctypes.POINTER(u64p), u64p, u64p]
+        L.orc_reduce_f64.argtypes = [u64p, u32, u32, ctypes.POINTER(ctypes.c_double), u64p]
         _lib = L
     return _lib
 
@@ -238,6 +239,16 @@ def hoisted_rotate(P: Params, ct, gs, keys, level: int):
     o1 = np.zeros_like(o0)
     lib().orc_hoisted_rotate(*P._args(), P.dnum, level, _p(c0), _p(c1), n, _p(gs_a), kp, _p(o0), _p(o1))
     return o0, o1
+
+
+def reduce_f64(mods, x: np.ndarray) -> np.ndarray:
+    """Exact residues [len(mods)][len(x)] of integer-valued doubles."""
+    mods = _u64(mods)
+    x = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+    assert np.all(np.floor(x) == x), "plaintext coefficients must be integers"
+    out = np.zeros((len(mods), len(x)), dtype=np.uint64)
+    lib().orc_reduce_f64(_p(mods), len(mods), len(x), x.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _p(out))
+    return out
 
 
 def galois_for_rotation(logn: int, k: int) -> int:

@@ -485,3 +485,29 @@ void orc_hoisted_rotate(uint32_t logn, const uint64_t *q, uint32_t nq, const uin
     }
     free(ext); free(acc); free(r0); free(k0);
 }
+
+/* --------------------------------------------------------- plaintext encoding
+ * Residues of integer-valued doubles (the bootstrap planner's plaintext
+ * coefficients).  A double v = M 2^e with |M| < 2^53 an integer is reduced as
+ * [M]_m [2^e]_m when e > 0, else directly; out[i][k] for modulus mods[i].   */
+void orc_reduce_f64(const uint64_t *mods, uint32_t nmods, uint32_t count, const double *x, uint64_t *out)
+{
+#pragma omp parallel for
+    for (uint32_t i = 0; i < nmods; i++) {
+        uint64_t m = mods[i];
+        for (uint32_t k = 0; k < count; k++) {
+            double v = x[k];
+            int neg = v < 0;
+            double a = neg ? -v : v;
+            int e = 0;
+            uint64_t r;
+            if (a < 9007199254740992.0) {               /* 2^53: an exact integer */
+                r = (uint64_t)a % m;
+            } else {
+                while (a >= 9007199254740992.0) { a *= 0.5; e++; }   /* exact halvings */
+                r = mulm((uint64_t)a % m, powm(2, (uint64_t)e, m), m);
+            }
+            out[(size_t)i * count + k] = neg && r ? m - r : r;
+        }
+    }
+}

@@ -14,6 +14,8 @@ this library is measured on):
                  largest digit, so decryptions after key switching are meaningful).
 * ``large``    : N = 2^16, q = 1 x 60-bit + 30 x 50-bit, dnum = 3, K = 4.
 * ``large-nv`` : as ``large`` with K = 10.
+* ``boot-small``: N = 2^12, q = 1 x 60-bit + 20 x 50-bit, dnum = 3, K = 7: the
+                 smallest set with room for a full-slot bootstrap (18 levels).
 """
 from __future__ import annotations
 
@@ -117,6 +119,8 @@ def params(name: str) -> ParamSet:
         return make_params(16, 50, 30, 4, 3, 50, name)
     if name == "large-nv":
         return make_params(16, 50, 30, 10, 3, 50, name)
+    if name == "boot-small":
+        return make_params(12, 50, 20, 7, 3, 50, name)
     if name == "tiny":  # N = 2^6, for brute-force pins
         return make_params(6, 30, 3, 2, 2, 20, name)
     raise KeyError(name)

@@ -1,0 +1,166 @@
+"""Pins of the oracle's bootstrapping (Sec. III-F.7): the homomorphic DFT
+factors against the brute-force canonical embedding, the baby-step/giant-step
+evaluation against the dense map, and each homomorphic phase (ModRaise,
+CoeffToSlot, EvalMod, the whole bootstrap) through decryption against what it
+must compute on the plaintext."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import bootstrap as B
+from oracle import client
+from helpers import ClientSetup, br, max_err_bits
+from paper_2507_04775_amd import inputs
+
+
+def _dense_embedding(logn):
+    """U[j][k] = zeta^(5^j k), j, k < n: z = U (t_lo + i t_hi) for the slots z of t."""
+    N, n = 1 << logn, 1 << (logn - 1)
+    e = client.slot_exponents(logn)
+    return np.exp(1j * np.pi * np.outer(e, np.arange(n)) / N)
+
+
+def _apply(mp, v):
+    return sum(d * np.roll(v, -o) for o, d in mp.items())
+
+
+@pytest.mark.parametrize("logn", [5, 6, 7])
+def test_stages_compose_to_the_embedding(logn):
+    n = 1 << (logn - 1)
+    w = inputs.complex_slots(inputs.rng(logn), n)
+    perm = np.array([br(x, logn - 1) for x in range(n)])
+    U = _dense_embedding(logn)
+    v = w[perm]
+    for h in [1 << i for i in range(logn - 1)]:
+        v = _apply(B.special_fft_stage(n, logn, h, False), v)
+    assert np.max(np.abs(v - U @ w)) < 1e-10
+    v = U @ w
+    for h in [1 << i for i in range(logn - 1)][::-1]:
+        v = _apply(B.special_fft_stage(n, logn, h, True), v)
+    assert np.max(np.abs(v - w[perm])) < 1e-12
+
+
+@pytest.mark.parametrize("logn,radix", [(6, [2, 2, 1]), (6, [5]), (7, [3, 3]), (7, [1, 4, 1])])
+def test_groups_by_bsgs_equal_the_dense_transform(logn, radix):
+    """Merged groups evaluated as sum_g rot(sum_b d'_(g,b) rot(v, b h0), G_g)
+    reproduce the inverse and forward special FFT."""
+    n = 1 << (logn - 1)
+    w = inputs.complex_slots(inputs.rng(10 + logn), n)
+    perm = np.array([br(x, logn - 1) for x in range(n)])
+    U = _dense_embedding(logn)
+
+    def bsgs(v, halves, inverse):
+        m_lo, count, baby, giants, h0 = B.group_layout(n, halves)
+        pds = B.group_diagonals(n, logn, halves, inverse)
+        G = B.giant_offsets(n, halves)
+        babies = [np.roll(v, -b * h0) for b in range(baby)]
+        out = 0
+        for g in range(giants):
+            part = sum(pds[i] * babies[i - g * baby] for i in range(g * baby, min(count, (g + 1) * baby)))
+            out = out + np.roll(part, -G[g])
+        return out
+
+    v = U @ w
+    for halves in B.stage_groups(logn, radix, False):
+        v = bsgs(v, halves, True)
+    assert np.max(np.abs(v - w[perm])) < 1e-12
+    v = w[perm]
+    for halves in B.stage_groups(logn, radix[::-1], True):
+        v = bsgs(v, halves, False)
+    assert np.max(np.abs(v - U @ w)) < 1e-10
+
+
+def test_layout_counts_and_rotations():
+    # 2^11 slots, CoeffToSlot groups of 4, 4, 3 stages
+    n = 2048
+    g0, g1, g2 = B.stage_groups(12, [4, 4, 3], False)
+    assert g0 == [1024, 512, 256, 128] and g2 == [4, 2, 1]
+    assert B.group_layout(n, g0) == (0, 16, 4, 4, 128)        # holds n/2: offsets wrap
+    assert B.group_layout(n, g1) == (-15, 31, 8, 4, 8)
+    assert B.giant_offsets(n, g1) == [-120, -56, 8, 72]
+    assert B.baby_offsets(n, g2) == [1, 2, 3]
+
+
+def test_scale_chain():
+    ps = inputs.params("boot-small")
+    q = ps.q
+    sc = B.level_scales(q, ps.L, 2.0 ** 50)
+    for l in range(1, ps.L + 1):
+        assert abs(sc[l] * sc[l] / q[l] / sc[l - 1] - 1) < 1e-15
+        assert abs(B.pt_scale(sc, q, l, 1) * sc[l] / q[l] / sc[l - 1] - 1) < 1e-15
+        assert B.pt_scale(sc, q, l, 1) == B.const_factor(sc, q, l, l - 1)
+    assert abs(B.pt_scale(sc, q, 20, 2) * sc[20] / (q[20] * q[19]) / sc[18] - 1) < 1e-15
+    assert B.round_half_away(2.5) == 3 and B.round_half_away(-2.5) == -3 and B.round_half_away(-0.4) == 0
+
+
+def test_reduce_f64_is_exact():
+    mods = inputs.params("boot-small").q[:3]
+    x = np.array([0.0, -1.0, 2.0 ** 53 + 2, -(2.0 ** 77) - 2.0 ** 30, 123456789012345.0, 3.0 * 2 ** 61])
+    r = oracle.reduce_f64(mods, x)
+    for i, m in enumerate(mods):
+        assert [int(v) for v in r[i]] == [int(v) % m for v in x]
+
+
+BP_SMALL = dict(logn=12, cts_radix_logs=[4, 4, 3], stc_radix_logs=[3, 4, 4], cheb_degree=63,
+                double_angles=5, k_range=128.0, top_scale=2.0 ** 50, in_scale=2.0 ** 50)
+
+
+@pytest.fixture(scope="module")
+def boot_small():
+    ps = inputs.params("boot-small")
+    cs = ClientSetup(ps, seed=31)
+    bp = B.BootParams(**BP_SMALL)
+    pl = B.plan(cs.P, bp)
+    rk = {k: cs.galois_key(oracle.galois_for_rotation(ps.logn, k)) for k in B.rotations_needed(bp)}
+    ex = B.Executor(cs.P, pl, cs.relin_key(), cs.galois_key(oracle.galois_conjugate(ps.logn)), rk)
+    z = inputs.complex_slots(inputs.rng(32), ps.N // 2)
+    c0, c1 = cs.encrypt(z, 0, bp.in_scale)
+    return cs, ex, z, (c0, c1, 0)
+
+
+def _raised_coefficients(cs, ct):
+    P = cs.P
+    pt = client.decrypt(P, cs.sk, (ct[0], ct[1]), ct[2])
+    return np.array(client.crt_centred(oracle.intt(P.q[: ct[2] + 1], pt, P.logn), P.q[: ct[2] + 1]), dtype=object)
+
+
+def test_modraise_keeps_the_message_mod_q0(boot_small):
+    cs, ex, z, ct = boot_small
+    r = ex.modraise(ct)
+    assert r[2] == cs.ps.L
+    t = _raised_coefficients(cs, r)
+    q0 = cs.ps.q[0]
+    m = _raised_coefficients(cs, ct)   # the level-0 plaintext, centred mod q0
+    assert all((int(a) - int(b)) % q0 == 0 for a, b in zip(t, m))
+    assert max(abs(int(a) - int(b)) // q0 for a, b in zip(t, m)) < ex.bp.k_range
+
+
+def test_coeff_to_slot_moves_coefficients_into_slots(boot_small):
+    cs, ex, z, ct = boot_small
+    r = ex.modraise(ct)
+    t = _raised_coefficients(cs, r)
+    n, q0, K = cs.ps.N // 2, cs.ps.q[0], ex.bp.k_range
+    c = ex.coeff_to_slot(r)
+    assert c[2] == cs.ps.L - 4
+    perm = np.array([br(x, cs.ps.logn - 1) for x in range(n)])
+    want = (t[:n].astype(float) + 1j * t[n:].astype(float))[perm] / (2 * q0 * K)
+    assert max_err_bits(cs.decrypt((c[0], c[1]), c[2], ex.sc[c[2]]), want) < -30
+
+
+def test_eval_mod_computes_the_scaled_sine(boot_small):
+    cs, ex, z, ct = boot_small
+    n = cs.ps.N // 2
+    y = inputs.rng(33).uniform(-0.5, 0.5, size=n)
+    yc = cs.encrypt(y, ex.L - 4, ex.sc[ex.L - 4])
+    out = ex.eval_mod((yc[0], yc[1], ex.L - 4))
+    assert out[2] == ex.L - 4 - B.levels_used(ex.bp)["evalmod"]
+    got = cs.decrypt((out[0], out[1]), out[2], ex.sc[out[2]])
+    assert max_err_bits(got, np.sin(2 * np.pi * ex.bp.k_range * y)) < -18
+
+
+def test_bootstrap_recovers_the_input(boot_small):
+    cs, ex, z, ct = boot_small
+    out = ex.bootstrap(ct)
+    assert out[2] == B.output_level(cs.P, ex.bp) == 1
+    err = max_err_bits(cs.decrypt((out[0], out[1]), out[2], ex.sc[out[2]]), z)
+    assert err < -11, err
