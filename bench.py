@@ -39,6 +39,12 @@ def parse():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-items", type=int, default=128)
     ap.add_argument("--batch-reps", type=int, default=5)
+    ap.add_argument("--no-boot", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=48)
+    ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-mem-gib", type=int, default=16)
+    ap.add_argument("--boot-reps", type=int, default=10)
     return ap.parse_args()
 
 
@@ -136,6 +142,130 @@ def run_batch(ctx, ps, seed, args):
            "tuned_grid_wg_per_cu": [batch.grid(i) for i in range(12)]}
     batch.close()
     return res
+
+
+def run_bootstrap(seed, args):
+    """Full-slot bootstrap at N = 2^16 (L = 30, dnum = 3, ten special primes so
+    that key switching keeps the message): keys and plaintexts made by the
+    client helpers, one eager bootstrap per step and the captured HIP graph
+    replayed; the decrypted error against the input slots is reported."""
+    import numpy as np
+    import torch
+
+    from paper_2507_04775_amd import bootplan, ckks, inputs
+    from paper_2507_04775_amd.client import Client
+
+    ps = inputs.params("large-nv")
+    ctx = ckks.Context(ps.logn, ps.q, ps.p, ps.dnum, device=0)
+    scale = 2.0 ** ps.log_scale
+    cfg = bootplan.default_config(ps.logn, scale)
+    t0 = time.perf_counter()
+    pl = bootplan.plan(ps.q, cfg)
+    t_plan = time.perf_counter() - t0
+    cl = Client(ctx, ps, seed)
+    t0 = time.perf_counter()
+    rot = {k: cl.rotation_key(k) for k in pl.rotations}
+    relin, conj = cl.relin_key(), cl.conjugation_key()
+    torch.cuda.synchronize()
+    t_keys = time.perf_counter() - t0
+    boot = ckks.Boot(ctx, cfg.cts_radix_logs, cfg.stc_radix_logs, pl.cts, pl.stc, pl.cheb, cfg.double_angles,
+                     cfg.top_scale, relin, conj, rot)
+    z = inputs.complex_slots(inputs.rng(seed + 5), ps.N // 2)
+    ct = cl.encrypt(z, 0, scale)
+    out = ctx.empty_ct(boot.output_level)
+    stream = torch.cuda.current_stream()
+    boot.ckks_bootstrap(ct, out)
+    torch.cuda.synchronize()
+    err = float(np.log2(np.max(np.abs(cl.decrypt(out) - z))))
+    reps = max(3, args.boot_reps)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    ev[0].record(stream)
+    for i in range(reps):
+        boot.ckks_bootstrap(ct, out)
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    eager = [ev[i].elapsed_time(ev[i + 1]) for i in range(reps)]
+    gs = torch.cuda.Stream()
+    out_g = ctx.empty_ct(boot.output_level)
+    boot.capture(ct, out_g, gs)
+    boot.replay(gs)
+    gs.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    ev[0].record(gs)
+    for i in range(reps):
+        boot.replay(gs)
+        ev[i + 1].record(gs)
+    gs.synchronize()
+    graph = [ev[i].elapsed_time(ev[i + 1]) for i in range(reps)]
+    same = bool(torch.equal(out_g.c0, out.c0) and torch.equal(out_g.c1, out.c1))
+    g50 = percentile(graph, 50)
+    res = {"bootstraps_per_s": round(1e3 / g50, 2), "graph_p50_ms": round(g50, 3),
+           "graph_p99_ms": round(percentile(graph, 99), 3), "eager_p50_ms": round(percentile(eager, 50), 3),
+           "eager_p99_ms": round(percentile(eager, 99), 3), "reps": reps, "graph_equals_eager": same,
+           "key_switches": boot.keyswitches, "levels_left": boot.output_level, "slots": ps.N // 2,
+           "decrypted_error_bits": round(err, 2), "device_bytes": boot.device_bytes,
+           "rotation_keys": len(rot), "plan_s": round(t_plan, 2), "keygen_s": round(t_keys, 2),
+           "config": {"logN": ps.logn, "limbs": ps.L + 1, "special_primes": ps.K, "dnum": ps.dnum,
+                      "cts_groups": cfg.cts_radix_logs, "stc_groups": cfg.stc_radix_logs,
+                      "cheb_degree": cfg.cheb_degree, "double_angles": cfg.double_angles, "k_range": cfg.k_range,
+                      "scale_log2": ps.log_scale}}
+    boot.close()
+    del rot, relin, conj
+    ctx.close()
+    return res
+
+
+def run_serving(ctx, ps, seed, args):
+    """Served requests (op chains at levels 10..30, 10 % ending in a bootstrap)
+    through the continuous-batching server: saturation throughput with every
+    request queued at t = 0, the same requests run one at a time (plain), and
+    Poisson arrivals at fractions of saturation with p50 / p99 latency."""
+    import torch
+
+    from paper_2507_04775_amd import bootplan, ckks, inputs
+    from paper_2507_04775_amd.serve import Server
+
+    def rkey(sd, g):
+        mods = (list(ps.q) + list(ps.p)) * (2 * ps.dnum)
+        d = inputs.device_residues(sd, mods, ps.N).reshape(ps.dnum, 2, -1, ps.N).contiguous()
+        return ctx.key(d, g)
+
+    rs = inputs.batch_rotation_set(ps.logn)
+    rot = {k: rkey(seed + 100 + k, pow(5, k, 2 * ps.N)) for k in rs}
+    relin = rkey(seed + 1, 0)
+    pts = [inputs.device_residues(seed + 7 + i, ps.q, ps.N) for i in range(4)]
+    cfg = bootplan.default_config(ps.logn, 2.0 ** ps.log_scale)
+    pl = bootplan.plan(ps.q, cfg)
+    bkeys = {k: rkey(seed + 5000 + k, pow(5, k, 2 * ps.N)) for k in pl.rotations}
+    boot = ckks.Boot(ctx, cfg.cts_radix_logs, cfg.stc_radix_logs, pl.cts, pl.stc, pl.cheb, cfg.double_angles,
+                     cfg.top_scale, relin, rkey(seed + 2, 2 * ps.N - 1), bkeys)
+    srv = Server(ctx, relin, rot, pts, boot, slots=args.serve_slots, mem_budget=args.serve_mem_gib << 30)
+    n = args.serve_requests
+    gen = lambda rate, sd: inputs.serving_requests(sd, n, ps.logn, rate)
+    srv.run(gen(None, seed + 900)[: max(2, n // 8)])  # warm-up
+
+    def summarise(done, reqs):
+        lat = [d.latency * 1e3 for d in done]
+        span = max(d.finish for d in done) - min(r.arrival for r in reqs)
+        ks = sum(d.keyswitches for d in done)
+        return {"requests_per_s": round(len(done) / span, 2), "key_switches_per_s": round(ks / span, 1),
+                "p50_ms": round(percentile(lat, 50), 3), "p99_ms": round(percentile(lat, 99), 3),
+                "makespan_s": round(span, 4)}
+
+    reqs = gen(None, seed + 901)
+    sat = summarise(srv.run(reqs), reqs)
+    plain = summarise(srv.run(reqs, concurrent=False), reqs)
+    sweep = []
+    for f in (0.5, 0.9, 1.1):
+        rate = f * sat["requests_per_s"]
+        rq = gen(rate, seed + 902 + int(f * 100))
+        r = summarise(srv.run(rq), rq)
+        r.update({"load": f, "offered_rps": round(rate, 2)})
+        sweep.append(r)
+    boot.close()
+    return {"requests": n, "slots": args.serve_slots, "mem_budget_gib": args.serve_mem_gib,
+            "boot_fraction": 0.1, "saturation": sat, "plain_sequential": plain, "poisson": sweep,
+            "served_vs_plain": round(sat["requests_per_s"] / plain["requests_per_s"], 3)}
 
 
 def main():
@@ -263,6 +393,16 @@ def main():
     if not args.no_batch:
         batched = run_batch(ctx, ps, seed, args)
 
+    # ---- full-slot bootstrapping (its own context: ten special primes)
+    boot = None
+    if not args.no_boot:
+        boot = run_bootstrap(seed + 500, args)
+
+    # ---- served request chains with continuous batching
+    serving = None
+    if not args.no_serve:
+        serving = run_serving(ctx, ps, seed + 700, args)
+
     # ---- CPU oracle on a bounded sample of the same step
     cpu = None
     if not args.no_cpu_baseline:
@@ -287,7 +427,7 @@ def main():
                "sample": "%d steps (HMult+relin, Rescale, HRotate at l=30, N=2^16) in %.1f s" % (n_steps, t_cpu)}
 
     out = {
-        "metric": "key-switches/s at logN=16 (1 GPU), plain per-op calls",
+        "metric": "key-switches/s and bootstraps/s at logN=16 (1 GPU), batched vs plain; p99 latency",
         "value": round(value, 1),
         "unit": "key-switches/s",
         "n_gpus": 1,
@@ -307,6 +447,8 @@ def main():
         "wall_s": round(wall, 3),
         "cold": cold,
         "batched": batched,
+        "bootstrap": boot,
+        "serving": serving,
         "ops": ops,
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -204,7 +204,9 @@ ckks_status ckks_hrotate_hoisted(ckks_ctx *ctx, const ckks_ct *in, uint32_t n, c
 
 /*
  * Limb-wise support operations of Table I on evaluation-domain data; all
- * operands at `level` (l+1 limbs), out may alias an input exactly.
+ * operands at `level` (l+1 limbs), out may alias an input exactly.  Row i
+ * uses the i-th prime of q_0..q_L, p_0..p_{K-1}, so l may reach n_q+n_p-1
+ * for extended polynomials (key generation); CKKS_E_LEVEL beyond that.
  *   ckks_poly_add/sub/mul : out = a (+,-,*) b              (HAdd, PtAdd, PtMult per polynomial)
  *   ckks_poly_mul_add     : out = a * b + c                (PtMulAdd per polynomial)
  *   ckks_poly_scalar_mul  : out = a * s[i] on limb i       (ScalarMult; s: host array [l+1], s[i] < q_i)
@@ -277,6 +279,81 @@ ckks_status ckks_batch_replay(ckks_batch *batch, void *stream);
 uint32_t ckks_batch_keyswitches(const ckks_batch *batch); /* key switches performed per run */
 uint32_t ckks_batch_grid(const ckks_batch *batch, uint32_t step); /* persistent grid, in workgroups per CU */
 void ckks_batch_destroy(ckks_batch *batch);
+
+/*
+ * Bootstrapping (Sec. III-F.7): ModRaise, CoeffToSlot, EvalMod, SlotToCoeff
+ * for a fully packed ciphertext (N/2 slots).
+ *
+ * Schedule, derived by the library from the descriptor:
+ * - ModRaise: the level-0 input's coefficients are lifted centred from q_0 to
+ *   q_0..q_L (L = n_q - 1) and returned to the evaluation domain.
+ * - CoeffToSlot: the inverse special-FFT stages (butterflies pairing slots x
+ *   and x + h, half-sizes n/2 down to 1, n = N/2) are merged into groups of
+ *   cts_radix_logs[g] stages in that order; SlotToCoeff merges the forward
+ *   stages (half-sizes 1 up to n/2) into groups of stc_radix_logs[g].  A
+ *   group of r stages with smallest half-size h0 has R = 2^r and diagonals at
+ *   slot offsets m h0 for m in [m_lo, m_lo + count): m_lo = 0, count = R when
+ *   R h0 = n, else m_lo = -(R-1), count = 2R-1.  Diagonal i = g B + b (B the
+ *   smallest power of two with B^2 >= count) is applied as
+ *   sum_g rot(sum_b pt_i * rot(ct, b h0), G_g), G_g = (g B + m_lo) h0, with
+ *   the baby rotations b = 1..B-1 hoisted.  Each group ends with a rescale;
+ *   the first CoeffToSlot group rescales twice.
+ * - Between them: ct_re = ct + conj(ct), ct_im = (conj(ct) - ct) X^(N/2);
+ *   each goes through EvalMod; then ct = ct_re + ct_im X^(N/2).
+ * - EvalMod: T_1 = y, T_2m = 2 T_m^2 - 1, T_2m+1 = 2 T_m T_m+1 - T_1 up to
+ *   T_d (d = cheb_degree), then sum_k c_k T_k taken to the level one below
+ *   the lowest T_k plus c_0, then double_angles steps y <- 2 y^2 - 1.
+ *
+ * Scales: level L has top_scale, level l-1 has (D_l * D_l) / q_l (double
+ * arithmetic).  Taking a level-l ciphertext times a real c to level t < l
+ * drops its limbs above t+1, multiplies by round(c (D_t q_(t+1)) / D_l) and
+ * rescales; a constant c added at level l is round(c D_l); rounding is half
+ * away from zero.  Multiplications are HMult+relin followed by a rescale.
+ *
+ * Descriptor: cts_diags[g] / stc_diags[g] point to count_g host vectors of N
+ * integer-valued doubles (the plaintext coefficients of group g's diagonals,
+ * already multiplied by their scale, in index order i); cheb[0..d] are the
+ * Chebyshev coefficients; relin (galois 0), conj (galois 2N-1) and one key
+ * per slot rotation of the schedule (rot_steps[i] taken mod N/2, key galois
+ * 5^rot_steps[i] mod 2N) must stay valid while the handle lives.
+ *
+ * ckks_boot_create validates the descriptor (CKKS_E_KEY when a rotation of
+ * the schedule has no key, CKKS_E_UNSUPPORTED when a group needs more than
+ * 16 baby steps or the levels run out), uploads and transforms the plaintexts
+ * and allocates its buffers: one device allocation, freed by
+ * ckks_boot_destroy.  ckks_bootstrap runs the whole pipeline on `stream`:
+ * in->level must be 0, out receives level ckks_boot_output_level() (out's
+ * buffers hold that many limbs + 1) and scale D_out.  Calls on one handle
+ * must not overlap in time (they share its buffers).  ckks_boot_capture
+ * records the launch sequence for (in, out) into a HIP graph on a
+ * non-default stream; ckks_boot_replay relaunches it (same in and out).
+ */
+typedef struct ckks_boot ckks_boot;
+
+typedef struct {
+    uint32_t n_cts, n_stc;               /* numbers of CoeffToSlot / SlotToCoeff groups */
+    const uint32_t *cts_radix_logs;      /* stages per group, application order */
+    const uint32_t *stc_radix_logs;
+    const double *const *cts_diags;      /* [n_cts] host pointers to [count_g][N] doubles */
+    const double *const *stc_diags;
+    uint32_t cheb_degree;
+    const double *cheb;                  /* cheb_degree + 1 coefficients */
+    uint32_t double_angles;
+    double top_scale;                    /* scale of level L */
+    const ckks_key *relin, *conj;
+    uint32_t n_rot;
+    const int32_t *rot_steps;
+    const ckks_key *const *rot_keys;
+} ckks_boot_desc;
+
+ckks_status ckks_boot_create(ckks_ctx *ctx, const ckks_boot_desc *desc, ckks_boot **out);
+uint32_t ckks_boot_output_level(const ckks_boot *boot);
+uint32_t ckks_boot_keyswitches(const ckks_boot *boot);  /* key switches per bootstrap */
+size_t ckks_boot_device_bytes(const ckks_boot *boot);   /* plaintexts, buffers and workspace */
+ckks_status ckks_bootstrap(ckks_boot *boot, const ckks_ct *in, ckks_ct *out, void *stream);
+ckks_status ckks_boot_capture(ckks_boot *boot, const ckks_ct *in, ckks_ct *out, void *stream);
+ckks_status ckks_boot_replay(ckks_boot *boot, void *stream);
+void ckks_boot_destroy(ckks_boot *boot);
 
 #ifdef __cplusplus
 }

@@ -40,6 +40,14 @@ class _Work(ctypes.Structure):
     _fields_ = [("kind", _u32), ("a", _Ct), ("b", _Ct), ("key", _vp), ("galois", _u32), ("n_rot", _u32),
                 ("rot", ctypes.POINTER(_i32)), ("rot_keys", ctypes.POINTER(_vp)), ("out", ctypes.POINTER(_Ct))]
 
+class _BootDesc(ctypes.Structure):
+    _fields_ = [("n_cts", _u32), ("n_stc", _u32), ("cts_radix_logs", ctypes.POINTER(_u32)),
+                ("stc_radix_logs", ctypes.POINTER(_u32)), ("cts_diags", ctypes.POINTER(_vp)),
+                ("stc_diags", ctypes.POINTER(_vp)), ("cheb_degree", _u32), ("cheb", ctypes.POINTER(ctypes.c_double)),
+                ("double_angles", _u32), ("top_scale", ctypes.c_double), ("relin", _vp), ("conj", _vp),
+                ("n_rot", _u32), ("rot_steps", ctypes.POINTER(_i32)), ("rot_keys", ctypes.POINTER(_vp))]
+
+
 _sigs = {
     "ckks_ctx_create": (ctypes.c_int, [_u32, _u64p, _u32, _u64p, _u32, _u32, ctypes.c_int, ctypes.POINTER(_vp)]),
     "ckks_ctx_destroy": (None, [_vp]),
@@ -78,6 +86,14 @@ _sigs = {
     "ckks_batch_keyswitches": (_u32, [_vp]),
     "ckks_batch_grid": (_u32, [_vp, _u32]),
     "ckks_batch_destroy": (None, [_vp]),
+    "ckks_boot_create": (ctypes.c_int, [_vp, ctypes.POINTER(_BootDesc), ctypes.POINTER(_vp)]),
+    "ckks_boot_output_level": (_u32, [_vp]),
+    "ckks_boot_keyswitches": (_u32, [_vp]),
+    "ckks_boot_device_bytes": (ctypes.c_size_t, [_vp]),
+    "ckks_bootstrap": (ctypes.c_int, [_vp, ctypes.POINTER(_Ct), ctypes.POINTER(_Ct), _vp]),
+    "ckks_boot_capture": (ctypes.c_int, [_vp, ctypes.POINTER(_Ct), ctypes.POINTER(_Ct), _vp]),
+    "ckks_boot_replay": (ctypes.c_int, [_vp, _vp]),
+    "ckks_boot_destroy": (None, [_vp]),
 }
 for _name, (_res, _args) in _sigs.items():
     _f = getattr(_lib, _name)
@@ -394,6 +410,77 @@ class Batch:
         _check(_lib.ckks_batch_replay(self.handle, _stream(stream)), "ckks_batch_replay")
 
     def close(self, _destroy=_lib.ckks_batch_destroy):
+        if getattr(self, "handle", None):
+            _destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        self.close()
+
+
+class Boot:
+    """A bootstrapping handle (ckks_boot_* in include/ckks.h): the schedule is
+    derived by the library from the group sizes, the Chebyshev degree and the
+    number of double-angle steps; the planned constants (plaintext diagonals as
+    integer-valued float64 arrays [count][N], Chebyshev coefficients) and the
+    keys are passed in."""
+
+    def __init__(self, ctx: "Context", cts_radix_logs, stc_radix_logs, cts_diags, stc_diags, cheb,
+                 double_angles: int, top_scale: float, relin: Key, conj: Key, rot_keys: dict):
+        import numpy as np
+        self.ctx = ctx
+        self._keys = [relin, conj] + list(rot_keys.values())
+        d = _BootDesc()
+        d.n_cts, d.n_stc = len(cts_radix_logs), len(stc_radix_logs)
+        cr = (_u32 * d.n_cts)(*cts_radix_logs)
+        sr = (_u32 * d.n_stc)(*stc_radix_logs)
+        arrs = [np.ascontiguousarray(x, dtype=np.float64) for x in list(cts_diags) + list(stc_diags)]
+        cd = (_vp * d.n_cts)(*[a.ctypes.data for a in arrs[: d.n_cts]])
+        sd = (_vp * d.n_stc)(*[a.ctypes.data for a in arrs[d.n_cts:]])
+        ch = np.ascontiguousarray(cheb, dtype=np.float64)
+        steps = sorted(rot_keys)
+        rs = (_i32 * max(1, len(steps)))(*steps)
+        rk = (_vp * max(1, len(steps)))(*[rot_keys[k].handle for k in steps])
+        d.cts_radix_logs, d.stc_radix_logs, d.cts_diags, d.stc_diags = cr, sr, cd, sd
+        d.cheb_degree = len(ch) - 1
+        d.cheb = ch.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        d.double_angles = double_angles
+        d.top_scale = top_scale
+        d.relin, d.conj = relin.handle, conj.handle
+        d.n_rot, d.rot_steps, d.rot_keys = len(steps), rs, rk
+        h = _vp()
+        _check(_lib.ckks_boot_create(ctx.handle, ctypes.byref(d), ctypes.byref(h)), "ckks_boot_create")
+        self.handle = h
+        self._captured = None
+
+    @property
+    def output_level(self) -> int:
+        return int(_lib.ckks_boot_output_level(self.handle))
+
+    @property
+    def keyswitches(self) -> int:
+        return int(_lib.ckks_boot_keyswitches(self.handle))
+
+    @property
+    def device_bytes(self) -> int:
+        return int(_lib.ckks_boot_device_bytes(self.handle))
+
+    def ckks_bootstrap(self, inp: Ciphertext, out: Ciphertext, stream=None):
+        i, o = inp._c(), out._c()
+        _check(_lib.ckks_bootstrap(self.handle, ctypes.byref(i), ctypes.byref(o), _stream(stream)), "ckks_bootstrap")
+        out.level, out.scale = o.level, o.scale
+
+    def capture(self, inp: Ciphertext, out: Ciphertext, stream):
+        i, o = inp._c(), out._c()
+        _check(_lib.ckks_boot_capture(self.handle, ctypes.byref(i), ctypes.byref(o), _stream(stream)),
+               "ckks_boot_capture")
+        out.level, out.scale = o.level, o.scale
+        self._captured = (inp, out)
+
+    def replay(self, stream=None):
+        _check(_lib.ckks_boot_replay(self.handle, _stream(stream)), "ckks_boot_replay")
+
+    def close(self, _destroy=_lib.ckks_boot_destroy):
         if getattr(self, "handle", None):
             _destroy(self.handle)
             self.handle = None

@@ -485,7 +485,7 @@ static ckks_status elementwise(ckks_ctx *ctx, int op, const uint64_t *a, const u
                                const char *what)
 {
     TRY(check_ctx(ctx));
-    TRY(check_level(ctx, level));
+    if (level >= ctx->nq + ctx->np) return fail(CKKS_E_LEVEL, std::string(what) + ": more rows than primes");
     TRY(check_ptr(a, what));
     TRY(check_ptr(out, what));
     if (op <= 3) TRY(check_ptr(b, what));

@@ -1,0 +1,636 @@
+// Bootstrapping executor (paper Sec. III-F.7): ModRaise, CoeffToSlot as
+// merged special-FFT stages evaluated with baby-step/giant-step over hoisted
+// rotations, EvalMod as a Chebyshev product tree plus double-angle steps, and
+// SlotToCoeff.  The schedule (levels, layouts, rotations, constants) is
+// derived here from the descriptor; the plaintext diagonals arrive as
+// integer-valued doubles and are reduced and transformed on the device once,
+// at creation.  A run is a fixed host-side sequence of library operations on
+// one stream, so it can be captured into a HIP graph.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+#include "ks_args.h"
+
+namespace ckks {
+ckks_status fail(ckks_status s, const std::string &msg);
+}
+
+using namespace ckks;
+
+namespace {
+
+#define TRY(x)                              \
+    do {                                    \
+        ckks_status _s = (x);               \
+        if (_s != CKKS_OK) return _s;       \
+    } while (0)
+
+hipStream_t S(void *stream) { return (hipStream_t)stream; }
+
+ckks_status dev(hipError_t e, const char *what)
+{
+    if (e == hipSuccess) return CKKS_OK;
+    return fail(CKKS_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+struct Layout {
+    int32_t m_lo;
+    uint32_t count, baby, giants, h0;
+};
+
+// Diagonals of a group of r stages with smallest half-size h0 sit at offsets
+// m h0, m in [m_lo, m_lo + count); index i = m - m_lo = g baby + b.
+Layout group_layout(uint32_t n, uint32_t r, uint32_t h0)
+{
+    Layout L;
+    const uint32_t R = 1u << r;
+    L.h0 = h0;
+    if ((uint64_t)R * h0 == n) {
+        L.m_lo = 0;
+        L.count = R;
+    } else {
+        L.m_lo = -(int32_t)(R - 1);
+        L.count = 2 * R - 1;
+    }
+    L.baby = 1;
+    while (L.baby * L.baby < L.count) L.baby *= 2;
+    L.giants = (L.count + L.baby - 1) / L.baby;
+    return L;
+}
+
+double round_half_away(double v)
+{
+    const double a = floor(fabs(v) + 0.5);
+    return v >= 0 ? a : -a;
+}
+
+struct Group {
+    Layout lay;
+    uint32_t level;      // input level
+    uint32_t rescales;
+    std::vector<int32_t> giant;   // G_g
+    std::vector<int32_t> baby_k;  // b h0, b = 1..min(baby, count)-1
+    uint64_t *pt = nullptr;       // [count][level+1][N], evaluation domain
+};
+
+// A ciphertext held in one of the executor's buffers (or the caller's output).
+struct Ct {
+    uint64_t *c0, *c1;
+    uint32_t level;
+};
+
+}  // namespace
+
+struct ckks_boot {
+    ckks_ctx *ctx = nullptr;
+    uint32_t L = 0, n = 0, N = 0;
+    std::vector<Group> cts, stc;
+    uint32_t degree = 0, double_angles = 0, evalmod_in = 0, out_level = 0, keyswitches = 0;
+    std::vector<double> cheb, sc;  // Chebyshev coefficients; level scales
+    std::vector<uint32_t> cheb_depth;
+    const ckks_key *relin = nullptr, *conj = nullptr;
+    std::map<uint32_t, const ckks_key *> rot;  // slot rotation mod n -> key
+    void *dev = nullptr;
+    size_t bytes = 0;
+    uint64_t *mono = nullptr;   // [L+1][N]: X^(N/2) in the evaluation domain
+    uint64_t *slots = nullptr;  // nslots buffers of 2 (L+1) N words
+    size_t slot_words = 0;
+    uint32_t nslots = 0, max_baby = 1;
+    void *ws = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+
+    // buffer indices
+    uint32_t s_babies() const { return 0; }  // max_baby - 1 buffers
+    uint32_t s_p() const { return max_baby - 1; }
+    uint32_t s_r() const { return max_baby; }
+    uint32_t s_acc(uint32_t i) const { return max_baby + 1 + i; }  // i = 0, 1
+    uint32_t s_x() const { return max_baby + 3; }
+    uint32_t s_cj() const { return max_baby + 4; }
+    uint32_t s_re(uint32_t i) const { return max_baby + 5 + i; }
+    uint32_t s_im(uint32_t i) const { return max_baby + 7 + i; }
+    uint32_t s_d(uint32_t i) const { return max_baby + 9 + i; }  // level-down temporaries 0..2
+    uint32_t s_t(uint32_t k) const { return max_baby + 12 + (k - 2); }  // T_k, k = 2..degree
+    uint32_t slot_count() const { return max_baby + 12 + (degree >= 2 ? degree - 1 : 0); }
+
+    Ct slot(uint32_t i, uint32_t level) const
+    {
+        uint64_t *b = slots + (size_t)i * slot_words;
+        return Ct{b, b + (size_t)(L + 1) * N, level};
+    }
+};
+
+namespace {
+
+ckks_ct as_ct(const Ct &c) { return ckks_ct{c.c0, c.c1, c.level, 1.0}; }
+
+struct Runner {
+    ckks_boot *b;
+    hipStream_t st;
+    std::vector<uint64_t> res;
+
+    ckks_ctx *ctx() const { return b->ctx; }
+
+    const uint64_t *residues(int64_t C, uint32_t level)
+    {
+        res.resize(level + 1);
+        for (uint32_t i = 0; i <= level; ++i) {
+            const int64_t q = (int64_t)ctx()->primes[i];
+            int64_t r = C % q;
+            res[i] = (uint64_t)(r < 0 ? r + q : r);
+        }
+        return res.data();
+    }
+
+    ckks_status rescale(Ct &c, const Ct *dst = nullptr)
+    {
+        ckks_ct in = as_ct(c), out = dst ? as_ct(*dst) : in;
+        TRY(ckks_rescale(ctx(), &in, &out, b->ws, st));
+        c = Ct{out.c0, out.c1, c.level - 1};
+        return CKKS_OK;
+    }
+
+    ckks_status scalar_mul(const Ct &src, const Ct &dst, int64_t C)
+    {
+        const uint64_t *r = residues(C, src.level);
+        TRY(ckks_poly_scalar_mul(ctx(), src.c0, r, dst.c0, src.level, st));
+        return ckks_poly_scalar_mul(ctx(), src.c1, r, dst.c1, src.level, st);
+    }
+
+    ckks_status scalar_add(const Ct &c, double v)
+    {
+        return ckks_poly_scalar_add(ctx(), c.c0, residues((int64_t)round_half_away(v * b->sc[c.level]), c.level),
+                                    c.c0, c.level, st);
+    }
+
+    ckks_status add(const Ct &x, const Ct &y, const Ct &out, bool sub = false)
+    {
+        auto f = sub ? ckks_poly_sub : ckks_poly_add;
+        TRY(f(ctx(), x.c0, y.c0, out.c0, x.level, st));
+        return f(ctx(), x.c1, y.c1, out.c1, x.level, st);
+    }
+
+    // src times the real c, taken to level t < src.level, written to dst
+    ckks_status mult_const_to(const Ct &src, double c, uint32_t t, const Ct &dst_buf, Ct &out)
+    {
+        const double X = (b->sc[t] * (double)ctx()->primes[t + 1]) / b->sc[src.level];
+        Ct d{dst_buf.c0, dst_buf.c1, t + 1};
+        TRY(scalar_mul(Ct{src.c0, src.c1, t + 1}, d, (int64_t)round_half_away(c * X)));
+        TRY(rescale(d));
+        out = d;
+        return CKKS_OK;
+    }
+
+    ckks_status level_down(const Ct &src, uint32_t t, const Ct &buf, Ct &out)
+    {
+        if (src.level == t) {
+            out = src;
+            return CKKS_OK;
+        }
+        return mult_const_to(src, 1.0, t, buf, out);
+    }
+
+    // dst = rescale(relin(x y)) at the lower of the two levels
+    ckks_status mul(const Ct &x, const Ct &y, const Ct &dst_buf, Ct &out)
+    {
+        const uint32_t l = std::min(x.level, y.level);
+        Ct a, c;
+        TRY(level_down(x, l, b->slot(b->s_d(0), 0), a));
+        if (y.c0 == x.c0) {
+            c = a;
+        } else {
+            TRY(level_down(y, l, b->slot(b->s_d(1), 0), c));
+        }
+        ckks_ct A = as_ct(a), B = as_ct(c), O = as_ct(Ct{dst_buf.c0, dst_buf.c1, l});
+        TRY(ckks_hmult_relin(ctx(), &A, &B, b->relin, &O, b->ws, st));
+        out = Ct{dst_buf.c0, dst_buf.c1, l};
+        return rescale(out);
+    }
+
+    ckks_status linear_transform(const Group &g, const Ct &in, uint32_t acc_slot, const Ct *final_out, Ct &out)
+    {
+        const uint32_t lvl = in.level;
+        if (lvl != g.level) return fail(CKKS_E_LEVEL, "ckks_bootstrap: schedule level mismatch");
+        const size_t N = b->N, limb = (size_t)(lvl + 1) * N;
+        std::vector<Ct> src(1, in);
+        if (!g.baby_k.empty()) {
+            std::vector<const ckks_key *> keys;
+            std::vector<ckks_ct> outs;
+            for (size_t i = 0; i < g.baby_k.size(); ++i) {
+                keys.push_back(b->rot.at((uint32_t)g.baby_k[i] % b->n));
+                Ct o = b->slot(b->s_babies() + (uint32_t)i, lvl);
+                src.push_back(o);
+                outs.push_back(as_ct(o));
+            }
+            ckks_ct I = as_ct(in);
+            TRY(ckks_hrotate_hoisted(ctx(), &I, (uint32_t)g.baby_k.size(), g.baby_k.data(), keys.data(), outs.data(),
+                                     b->ws, st));
+        }
+        const Ct acc = b->slot(acc_slot, lvl), P = b->slot(b->s_p(), lvl), R = b->slot(b->s_r(), lvl);
+        for (uint32_t gi = 0; gi < g.lay.giants; ++gi) {
+            const uint32_t i0 = gi * g.lay.baby, nb = std::min(g.lay.baby, g.lay.count - i0);
+            const uint32_t G = (uint32_t)(((int64_t)g.giant[gi] % b->n + b->n) % b->n);
+            LincombArgs la;
+            memset(&la, 0, sizeof(la));
+            for (uint32_t j = 0; j < nb; ++j) {
+                la.a0[j] = src[j].c0;
+                la.a1[j] = src[j].c1;
+                la.pt[j] = g.pt + (size_t)(i0 + j) * limb;
+            }
+            const Ct &target = (G == 0 && gi == 0) ? acc : P;
+            la.out0 = target.c0;
+            la.out1 = target.c1;
+            la.primes = ctx()->d_primes;
+            la.n = nb;
+            la.logn = ctx()->logn;
+            TRY(dev(launch_lincomb(la, lvl + 1, st), "ckks_bootstrap lincomb"));
+            Ct part = P;
+            if (G != 0) {
+                part = gi == 0 ? acc : R;
+                ckks_ct I = as_ct(P), O = as_ct(part);
+                TRY(ckks_hrotate(ctx(), &I, (int32_t)G, b->rot.at(G), &O, b->ws, st));
+            }
+            if (gi > 0) TRY(add(acc, part, acc));
+        }
+        Ct c = acc;
+        for (uint32_t r = 0; r < g.rescales; ++r) TRY(rescale(c, (r + 1 == g.rescales) ? final_out : nullptr));
+        out = c;
+        return CKKS_OK;
+    }
+
+    // EvalMod of the ciphertext in buffer s0 (s1 is its partner); result in s0 or s1
+    ckks_status eval_mod(uint32_t s0, uint32_t s1, Ct &out)
+    {
+        const uint32_t d = b->degree;
+        std::vector<Ct> T(d + 1);
+        T[1] = b->slot(s0, b->evalmod_in);
+        Ct tmp;
+        for (uint32_t k = 2; k <= d; ++k) {
+            const Ct buf = b->slot(b->s_t(k), 0);
+            if (k % 2 == 0) {
+                TRY(mul(T[k / 2], T[k / 2], buf, T[k]));
+                TRY(scalar_mul(T[k], T[k], 2));
+                TRY(scalar_add(T[k], -1.0));
+            } else {
+                TRY(mul(T[(k - 1) / 2], T[(k + 1) / 2], buf, T[k]));
+                TRY(scalar_mul(T[k], T[k], 2));
+                TRY(level_down(T[1], T[k].level, b->slot(b->s_d(2), 0), tmp));
+                TRY(add(T[k], tmp, T[k], true));
+            }
+        }
+        uint32_t lowest = T[1].level;
+        for (uint32_t k = 2; k <= d; ++k) lowest = std::min(lowest, T[k].level);
+        const uint32_t t = lowest - 1;
+        Ct acc;
+        TRY(mult_const_to(T[1], b->cheb[1], t, b->slot(s1, 0), acc));
+        for (uint32_t k = 2; k <= d; ++k) {
+            TRY(mult_const_to(T[k], b->cheb[k], t, b->slot(b->s_d(2), 0), tmp));
+            TRY(add(acc, tmp, acc));
+        }
+        TRY(scalar_add(acc, b->cheb[0]));
+        uint32_t cur = s1, other = s0;
+        for (uint32_t r = 0; r < b->double_angles; ++r) {
+            Ct y;
+            TRY(mul(acc, acc, b->slot(other, 0), y));
+            TRY(scalar_mul(y, y, 2));
+            TRY(scalar_add(y, -1.0));
+            acc = y;
+            std::swap(cur, other);
+        }
+        out = acc;
+        return CKKS_OK;
+    }
+
+    ckks_status modraise(const ckks_ct &in, const Ct &x)
+    {
+        const ckks_ctx *c = ctx();
+        const size_t N = c->N;
+        uint64_t *v = (uint64_t *)b->ws;
+        NttArgs ia = base_args(c, true);
+        ia.src = in.c0;
+        ia.dst = v;
+        ia.map.rows = 1;
+        ia.map.prime0 = 0;
+        ia.map.src_poly_stride = (int64_t)(in.c1 - in.c0);
+        ia.map.dst_poly_stride = (int64_t)N;
+        TRY(dev(launch_ntt_inv(ia, 2, PRO_PLAIN, st, v, (int64_t)N), "ckks_bootstrap modraise"));
+        NttArgs a = base_args(c, false);
+        a.src = v;
+        a.dst = x.c0;
+        a.map.rows = b->L + 1;
+        a.map.prime0 = 0;
+        a.map.src_poly_stride = 0;
+        a.map.dst_poly_stride = (int64_t)(x.c1 - x.c0);
+        a.rs_src[0] = v;
+        a.rs_src[1] = v + N;
+        a.rs_qlmod = c->d_rs_mod;  // row 0: q_0 mod q_i
+        a.rs_ql = c->primes[0];
+        return dev(launch_ntt_fwd(a, 2 * (b->L + 1), PRO_RESCALE, EPI_PLAIN, st, x.c0, (int64_t)(x.c1 - x.c0)),
+                   "ckks_bootstrap modraise");
+    }
+
+    ckks_status run(const ckks_ct &in, const ckks_ct &out)
+    {
+        Ct x = b->slot(b->s_x(), b->L);
+        TRY(modraise(in, x));
+        uint32_t ai = 0;
+        for (const Group &g : b->cts) {
+            TRY(linear_transform(g, x, b->s_acc(ai), nullptr, x));
+            ai ^= 1;
+        }
+        // split: re = x + conj(x), im = (conj(x) - x) X^(N/2)
+        const uint32_t l = x.level;
+        const Ct cj = b->slot(b->s_cj(), l), re = b->slot(b->s_re(0), l), im = b->slot(b->s_im(0), l);
+        ckks_ct X = as_ct(x), CJ = as_ct(cj);
+        TRY(ckks_conjugate(ctx(), &X, b->conj, &CJ, b->ws, st));
+        TRY(add(x, cj, re));
+        TRY(add(cj, x, im, true));
+        TRY(ckks_poly_mul(ctx(), im.c0, b->mono, im.c0, l, st));
+        TRY(ckks_poly_mul(ctx(), im.c1, b->mono, im.c1, l, st));
+        Ct yr, yi;
+        TRY(eval_mod(b->s_re(0), b->s_re(1), yr));
+        TRY(eval_mod(b->s_im(0), b->s_im(1), yi));
+        TRY(ckks_poly_mul(ctx(), yi.c0, b->mono, yi.c0, yi.level, st));
+        TRY(ckks_poly_mul(ctx(), yi.c1, b->mono, yi.c1, yi.level, st));
+        TRY(add(yr, yi, yi));
+        x = yi;
+        const Ct fin{out.c0, out.c1, b->out_level};
+        for (size_t i = 0; i < b->stc.size(); ++i) {
+            TRY(linear_transform(b->stc[i], x, b->s_acc(ai), i + 1 == b->stc.size() ? &fin : nullptr, x));
+            ai ^= 1;
+        }
+        return CKKS_OK;
+    }
+};
+
+uint32_t keyswitches_of(const ckks_boot &b)
+{
+    uint32_t ks = 1;  // conjugation
+    for (const auto *gs : {&b.cts, &b.stc})
+        for (const Group &g : *gs) {
+            ks += (uint32_t)g.baby_k.size();
+            for (int32_t G : g.giant) ks += (((int64_t)G % b.n + b.n) % b.n) != 0;
+        }
+    ks += 2 * (b.degree - 1 + b.double_angles);  // relinearisations of both halves
+    return ks;
+}
+
+}  // namespace
+
+extern "C" ckks_status ckks_boot_create(ckks_ctx *ctx, const ckks_boot_desc *desc, ckks_boot **out)
+{
+    if (!ctx || !desc || !out) return fail(CKKS_E_ARG, "ckks_boot_create: null argument");
+    *out = nullptr;
+    const uint32_t logn = ctx->logn, N = ctx->N, n = N / 2, L = ctx->nq - 1;
+    if (desc->n_cts == 0 || desc->n_stc == 0 || !desc->cts_radix_logs || !desc->stc_radix_logs || !desc->cts_diags ||
+        !desc->stc_diags || !desc->cheb || desc->cheb_degree < 1 || !(desc->top_scale > 0))
+        return fail(CKKS_E_ARG, "ckks_boot_create: incomplete descriptor");
+    if (!desc->relin || desc->relin->galois != 0 || desc->relin->ctx != ctx)
+        return fail(CKKS_E_KEY, "ckks_boot_create: missing relinearisation key");
+    if (!desc->conj || desc->conj->galois != 2 * N - 1 || desc->conj->ctx != ctx)
+        return fail(CKKS_E_KEY, "ckks_boot_create: missing conjugation key");
+    if (desc->n_rot && (!desc->rot_steps || !desc->rot_keys))
+        return fail(CKKS_E_ARG, "ckks_boot_create: null rotation arrays");
+
+    ckks_boot *b = new ckks_boot();
+    b->ctx = ctx;
+    b->L = L;
+    b->n = n;
+    b->N = N;
+    b->degree = desc->cheb_degree;
+    b->double_angles = desc->double_angles;
+    b->cheb.assign(desc->cheb, desc->cheb + desc->cheb_degree + 1);
+    b->relin = desc->relin;
+    b->conj = desc->conj;
+    auto bail = [&](ckks_status s, const std::string &m) {
+        ckks_boot_destroy(b);
+        return fail(s, "ckks_boot_create: " + m);
+    };
+    for (uint32_t i = 0; i < desc->n_rot; ++i) {
+        const ckks_key *k = desc->rot_keys[i];
+        const uint32_t r = (uint32_t)(((int64_t)desc->rot_steps[i] % n + n) % n);
+        uint64_t g = 1, p = 5;
+        for (uint32_t e = r; e; e >>= 1, p = p * p % (2ull * N))
+            if (e & 1) g = g * p % (2ull * N);
+        if (!k || k->ctx != ctx || k->galois != g) return bail(CKKS_E_KEY, "rotation key " + std::to_string(i) +
+                                                                             " does not match its step");
+        b->rot[r] = k;
+    }
+
+    // level scales and the Chebyshev tree depths (same recurrences as the documented schedule)
+    b->sc.assign(L + 1, 0.0);
+    b->sc[L] = desc->top_scale;
+    for (uint32_t l = L; l >= 1; --l) b->sc[l - 1] = (b->sc[l] * b->sc[l]) / (double)ctx->primes[l];
+    b->cheb_depth.assign(b->degree + 1, 0);
+    uint32_t depth = 0;
+    for (uint32_t k = 2; k <= b->degree; ++k) {
+        b->cheb_depth[k] = k % 2 == 0 ? b->cheb_depth[k / 2] + 1
+                                      : std::max(b->cheb_depth[(k - 1) / 2], b->cheb_depth[(k + 1) / 2]) + 1;
+        depth = std::max(depth, b->cheb_depth[k]);
+    }
+
+    // groups and levels
+    uint32_t sum_c = 0, sum_s = 0;
+    for (uint32_t i = 0; i < desc->n_cts; ++i) sum_c += desc->cts_radix_logs[i];
+    for (uint32_t i = 0; i < desc->n_stc; ++i) sum_s += desc->stc_radix_logs[i];
+    if (sum_c != logn - 1 || sum_s != logn - 1) return bail(CKKS_E_ARG, "radix logs must cover log2(N/2) stages");
+    int64_t lvl = L;
+    auto make_group = [&](uint32_t r, uint32_t h0, uint32_t rescales) {
+        Group g;
+        g.lay = group_layout(n, r, h0);
+        g.level = (uint32_t)std::max<int64_t>(lvl, 0);
+        g.rescales = rescales;
+        for (uint32_t gi = 0; gi < g.lay.giants; ++gi) g.giant.push_back(((int32_t)(gi * g.lay.baby) + g.lay.m_lo) * (int32_t)h0);
+        for (uint32_t k = 1; k < std::min(g.lay.baby, g.lay.count); ++k) g.baby_k.push_back((int32_t)(k * h0));
+        lvl -= rescales;
+        return g;
+    };
+    uint32_t stage = 0;
+    for (uint32_t i = 0; i < desc->n_cts; ++i) {
+        const uint32_t r = desc->cts_radix_logs[i];
+        b->cts.push_back(make_group(r, n >> (stage + r), i == 0 ? 2 : 1));
+        stage += r;
+    }
+    b->evalmod_in = (uint32_t)std::max<int64_t>(lvl, 0);
+    lvl -= depth + 1 + b->double_angles;
+    stage = 0;
+    for (uint32_t i = 0; i < desc->n_stc; ++i) {
+        const uint32_t r = desc->stc_radix_logs[i];
+        b->stc.push_back(make_group(r, 1u << stage, 1));
+        stage += r;
+    }
+    if (lvl < 0) return bail(CKKS_E_UNSUPPORTED, "the schedule needs more levels than the context has");
+    b->out_level = (uint32_t)lvl;
+    for (const auto *gs : {&b->cts, &b->stc})
+        for (const Group &g : *gs) {
+            if (g.lay.baby > kMaxLincomb) return bail(CKKS_E_UNSUPPORTED, "more than 16 baby steps in a group");
+            b->max_baby = std::max(b->max_baby, g.lay.baby);
+            for (int32_t k : g.baby_k)
+                if (!b->rot.count((uint32_t)k % n)) return bail(CKKS_E_KEY, "no key for rotation " + std::to_string(k));
+            for (int32_t G : g.giant) {
+                const uint32_t r = (uint32_t)(((int64_t)G % n + n) % n);
+                if (r && !b->rot.count(r)) return bail(CKKS_E_KEY, "no key for rotation " + std::to_string(r));
+            }
+        }
+    b->keyswitches = keyswitches_of(*b);
+
+    // one device allocation: plaintexts, X^(N/2), buffers, workspace
+    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    size_t pt_words = 0;
+    for (const auto *gs : {&b->cts, &b->stc})
+        for (const Group &g : *gs) pt_words += (size_t)g.lay.count * (g.level + 1) * N;
+    b->slot_words = 2 * (size_t)(L + 1) * N;
+    b->nslots = b->slot_count();
+    size_t wsb = 0;
+    for (uint32_t op : {CKKS_OP_HMULT, CKKS_OP_ROTATE, CKKS_OP_HOISTED, CKKS_OP_RESCALE})
+        wsb = std::max(wsb, ckks_workspace_bytes(ctx, op, L));
+    wsb = std::max(wsb, 2 * (size_t)N * 8);
+    const size_t off_mono = up(pt_words * 8), off_slots = off_mono + up((size_t)(L + 1) * N * 8);
+    const size_t off_ws = off_slots + up(b->nslots * b->slot_words * 8);
+    b->bytes = off_ws + up(wsb);
+    if (hipSetDevice(ctx->device) != hipSuccess || hipMalloc(&b->dev, b->bytes) != hipSuccess) {
+        b->dev = nullptr;
+        return bail(CKKS_E_NOMEM, "device allocation of " + std::to_string(b->bytes) + " bytes failed");
+    }
+    uint8_t *base = (uint8_t *)b->dev;
+    b->mono = (uint64_t *)(base + off_mono);
+    b->slots = (uint64_t *)(base + off_slots);
+    b->ws = base + off_ws;
+
+    // plaintexts: integer-valued doubles -> residues -> evaluation domain
+    size_t max_count = 0;
+    for (const auto *gs : {&b->cts, &b->stc})
+        for (const Group &g : *gs) max_count = std::max(max_count, (size_t)g.lay.count);
+    double *stage_buf = nullptr;
+    if (hipMalloc(&stage_buf, max_count * N * sizeof(double)) != hipSuccess)
+        return bail(CKKS_E_NOMEM, "staging allocation failed");
+    uint64_t *pt = (uint64_t *)base;
+    hipError_t e = hipSuccess;
+    std::vector<double> host;
+    for (int side = 0; side < 2 && e == hipSuccess; ++side) {
+        std::vector<Group> &gs = side == 0 ? b->cts : b->stc;
+        const double *const *diags = side == 0 ? desc->cts_diags : desc->stc_diags;
+        for (size_t i = 0; i < gs.size() && e == hipSuccess; ++i) {
+            Group &g = gs[i];
+            if (!diags[i]) {
+                e = hipErrorInvalidValue;
+                break;
+            }
+            const size_t words = (size_t)g.lay.count * N;
+            host.assign(diags[i], diags[i] + words);
+            for (double v : host)
+                if (!(v == floor(v)) || fabs(v) > 1e300) {
+                    (void)hipFree(stage_buf);
+                    return bail(CKKS_E_ARG, "plaintext coefficients must be finite integers");
+                }
+            g.pt = pt;
+            e = hipMemcpy(stage_buf, host.data(), words * sizeof(double), hipMemcpyHostToDevice);
+            if (e == hipSuccess) e = launch_reduce_f64(stage_buf, g.pt, ctx->d_primes, g.lay.count, g.level + 1, logn, 0);
+            if (e == hipSuccess) {
+                NttArgs a = base_args(ctx, false);
+                a.src = g.pt;
+                a.dst = g.pt;
+                a.map.rows = g.level + 1;
+                a.map.prime0 = 0;
+                a.map.src_poly_stride = a.map.dst_poly_stride = (int64_t)(g.level + 1) * N;
+                e = launch_ntt_fwd(a, g.lay.count * (g.level + 1), PRO_PLAIN, EPI_PLAIN, 0, g.pt,
+                                   (int64_t)(g.level + 1) * N);
+            }
+            if (e == hipSuccess) e = hipStreamSynchronize(0);  // the staging buffer is reused
+            pt += (size_t)g.lay.count * (g.level + 1) * N;
+        }
+    }
+    (void)hipFree(stage_buf);
+    if (e == hipSuccess) e = launch_half_monomial(b->mono, L + 1, logn, 0);
+    if (e == hipSuccess) {
+        NttArgs a = base_args(ctx, false);
+        a.src = a.dst = b->mono;
+        a.map.rows = L + 1;
+        a.map.prime0 = 0;
+        a.map.src_poly_stride = a.map.dst_poly_stride = 0;
+        e = launch_ntt_fwd(a, L + 1, PRO_PLAIN, EPI_PLAIN, 0, b->mono, 0);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(0);
+    if (e != hipSuccess) return bail(CKKS_E_DEVICE, std::string("plaintext upload: ") + hipGetErrorString(e));
+    *out = b;
+    return CKKS_OK;
+}
+
+extern "C" uint32_t ckks_boot_output_level(const ckks_boot *b) { return b ? b->out_level : 0; }
+extern "C" uint32_t ckks_boot_keyswitches(const ckks_boot *b) { return b ? b->keyswitches : 0; }
+extern "C" size_t ckks_boot_device_bytes(const ckks_boot *b) { return b ? b->bytes : 0; }
+
+static ckks_status check_io(const ckks_boot *b, const ckks_ct *in, const ckks_ct *out, const char *what)
+{
+    if (!b || !in || !out) return fail(CKKS_E_ARG, std::string(what) + ": null argument");
+    if (in->level != 0) return fail(CKKS_E_LEVEL, std::string(what) + ": the input must be at level 0");
+    const void *p[4] = {in->c0, in->c1, out->c0, out->c1};
+    for (const void *x : p)
+        if (!x || ((uintptr_t)x & 7)) return fail(CKKS_E_ARG, std::string(what) + ": null or misaligned polynomial");
+    const size_t N = b->N, ob = (size_t)(b->out_level + 1) * N * 8, ib = N * 8;
+    auto ov = [](const void *a, size_t an, const void *c, size_t cn) {
+        return (uintptr_t)a < (uintptr_t)c + cn && (uintptr_t)c < (uintptr_t)a + an;
+    };
+    if (ov(out->c0, ob, out->c1, ob) || ov(out->c0, ob, in->c0, ib) || ov(out->c0, ob, in->c1, ib) ||
+        ov(out->c1, ob, in->c0, ib) || ov(out->c1, ob, in->c1, ib))
+        return fail(CKKS_E_ARG, std::string(what) + ": output overlaps the input or itself");
+    for (const void *x : p)
+        if (ov(x, 8, b->dev, b->bytes)) return fail(CKKS_E_ARG, std::string(what) + ": operand inside the handle's buffers");
+    return CKKS_OK;
+}
+
+extern "C" ckks_status ckks_bootstrap(ckks_boot *b, const ckks_ct *in, ckks_ct *out, void *stream)
+{
+    TRY(check_io(b, in, out, "ckks_bootstrap"));
+    Runner r{b, S(stream), {}};
+    TRY(r.run(*in, *out));
+    out->level = b->out_level;
+    out->scale = b->sc[b->out_level];
+    return CKKS_OK;
+}
+
+extern "C" ckks_status ckks_boot_capture(ckks_boot *b, const ckks_ct *in, ckks_ct *out, void *stream)
+{
+    TRY(check_io(b, in, out, "ckks_boot_capture"));
+    hipStream_t st = S(stream);
+    if (!st) return fail(CKKS_E_ARG, "ckks_boot_capture: the default stream cannot be captured");
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return fail(CKKS_E_DEVICE, "ckks_boot_capture: begin capture failed");
+    Runner r{b, st, {}};
+    ckks_status s = r.run(*in, *out);
+    hipError_t e = hipStreamEndCapture(st, &b->graph);
+    if (s != CKKS_OK) return s;
+    if (e != hipSuccess) return fail(CKKS_E_DEVICE, "ckks_boot_capture: capture failed");
+    if (hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess)
+        return fail(CKKS_E_DEVICE, "ckks_boot_capture: instantiate failed");
+    out->level = b->out_level;
+    out->scale = b->sc[b->out_level];
+    return CKKS_OK;
+}
+
+extern "C" ckks_status ckks_boot_replay(ckks_boot *b, void *stream)
+{
+    if (!b || !b->exec) return fail(CKKS_E_ARG, "ckks_boot_replay: nothing captured");
+    hipError_t e = hipGraphLaunch(b->exec, S(stream));
+    if (e != hipSuccess) return fail(CKKS_E_DEVICE, std::string("ckks_boot_replay: ") + hipGetErrorString(e));
+    return CKKS_OK;
+}
+
+extern "C" void ckks_boot_destroy(ckks_boot *b)
+{
+    if (!b) return;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->dev) (void)hipFree(b->dev);
+    delete b;
+}

@@ -152,7 +152,8 @@ enum NttStage {
     STAGE_FWD_RESCALE,
     STAGE_FWD_BCONV_MODDOWN,
     STAGE_INV_PLAIN,
-    STAGE_INV_GALOIS
+    STAGE_INV_GALOIS,
+    STAGE_FWD_LIFT              // centred lift of one source limb into every row, then forward NTT
 };
 
 struct BconvJob {
@@ -197,6 +198,17 @@ struct TensorArgs {
     uint32_t logn, pad;
 };
 
+// Linear combination of ciphertexts with plaintexts (the baby-step sums of
+// the bootstrap's linear transforms): out_t = sum_b a_t[b] * pt[b], t = 0, 1.
+constexpr uint32_t kMaxLincomb = 16;
+
+struct LincombArgs {
+    const uint64_t *a0[kMaxLincomb], *a1[kMaxLincomb], *pt[kMaxLincomb];
+    uint64_t *out0, *out1;
+    const Prime *primes;
+    uint32_t n, logn;
+};
+
 // Launchers (all asynchronous on `stream`).
 hipError_t launch_ntt_fwd(const NttArgs &a, uint32_t nlimbs, NttPro pro, NttEpi epi, hipStream_t stream,
                           uint64_t *mid, int64_t mid_poly_stride);
@@ -222,6 +234,12 @@ hipError_t launch_elementwise(int op, const uint64_t *a, const uint64_t *b, cons
                               hipStream_t stream);
 hipError_t launch_automorph(const uint64_t *in, uint64_t *out, uint32_t nlimbs, uint32_t logn, uint32_t galois,
                             hipStream_t stream);
+hipError_t launch_lincomb(const LincombArgs &a, uint32_t nlimbs, hipStream_t stream);
+// x: [ndiag][N] integer-valued doubles -> out: [ndiag][nlimbs][N] residues modulo primes 0..nlimbs-1
+hipError_t launch_reduce_f64(const double *x, uint64_t *out, const Prime *primes, uint32_t ndiag, uint32_t nlimbs,
+                             uint32_t logn, hipStream_t stream);
+// out[l][N/2] = 1 on every limb l < nlimbs, zeros elsewhere (coefficient domain X^(N/2))
+hipError_t launch_half_monomial(uint64_t *out, uint32_t nlimbs, uint32_t logn, hipStream_t stream);
 
 }  // namespace ckks
 

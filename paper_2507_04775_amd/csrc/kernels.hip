@@ -213,7 +213,84 @@ __global__ __launch_bounds__(kThreads) void k_automorph(const uint64_t *__restri
     out[base + e] = in[base + galois_src(e, g, logn)];
 }
 
+// out_t = sum_b a_t[b] pt[b] on every coefficient of every limb: the products
+// are summed exactly in 128 bits (n <= 16 products below 2^122 each) and
+// reduced once.
+__global__ __launch_bounds__(kThreads) void k_lincomb(LincombArgs a)
+{
+    const uint32_t l = blockIdx.y;
+    const size_t i = ((size_t)l << a.logn) + blockIdx.x * kThreads + threadIdx.x;
+    const Prime P = a.primes[l];
+    u128 s0 = {0, 0}, s1 = {0, 0};
+    for (uint32_t b = 0; b < a.n; ++b) {
+        const uint64_t w = a.pt[b][i];
+        s0 = add128(s0, mul_wide(a.a0[b][i], w));
+        s1 = add128(s1, mul_wide(a.a1[b][i], w));
+    }
+    a.out0[i] = reduce128(s0, P);
+    a.out1[i] = reduce128(s1, P);
+}
+
+__device__ uint64_t pow2_mod(uint32_t e, const Prime &P)
+{
+    uint64_t r = 1, b = 2 % P.q;
+    for (; e; e >>= 1) {
+        if (e & 1) r = mulmod(r, b, P);
+        b = mulmod(b, b, P);
+    }
+    return r;
+}
+
+// Residue of an integer-valued double v = +-m 2^e (m < 2^53 from its bit
+// fields): m >> -e when e <= 0, else [m]_q [2^e]_q.
+__global__ __launch_bounds__(kThreads) void k_reduce_f64(const double *__restrict__ x, uint64_t *__restrict__ out,
+                                                         const Prime *primes, uint32_t nlimbs, uint32_t logn)
+{
+    const uint32_t l = blockIdx.y, d = blockIdx.z;
+    const uint32_t k = blockIdx.x * kThreads + threadIdx.x;
+    const Prime P = primes[l];
+    const uint64_t bits = (uint64_t)__double_as_longlong(x[((size_t)d << logn) + k]);
+    const uint32_t ex = (uint32_t)(bits >> 52) & 0x7ff;
+    uint64_t r = 0;
+    if (ex != 0) {  // zero has ex = 0; an integer-valued double is never subnormal
+        const uint64_t m = (bits & ((1ull << 52) - 1)) | (1ull << 52);
+        const int e = (int)ex - 1075;
+        r = e <= 0 ? (m >> (uint32_t)(-e)) % P.q : mulmod(m % P.q, pow2_mod((uint32_t)e, P), P);
+    }
+    if ((bits >> 63) && r) r = P.q - r;
+    out[(((size_t)d * nlimbs + l) << logn) + k] = r;
+}
+
+__global__ __launch_bounds__(kThreads) void k_half_monomial(uint64_t *out, uint32_t logn)
+{
+    const size_t i = ((size_t)blockIdx.y << logn) + blockIdx.x * kThreads + threadIdx.x;
+    const uint32_t k = blockIdx.x * kThreads + threadIdx.x;
+    out[i] = k == (1u << (logn - 1)) ? 1 : 0;
+}
+
 }  // namespace
+
+hipError_t launch_lincomb(const LincombArgs &a, uint32_t nlimbs, hipStream_t stream)
+{
+    if (a.n == 0 || a.n > kMaxLincomb) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_lincomb, dim3((1u << a.logn) / kThreads, nlimbs), dim3(kThreads), 0, stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_f64(const double *x, uint64_t *out, const Prime *primes, uint32_t ndiag, uint32_t nlimbs,
+                             uint32_t logn, hipStream_t stream)
+{
+    if (ndiag == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reduce_f64, dim3((1u << logn) / kThreads, nlimbs, ndiag), dim3(kThreads), 0, stream, x,
+                       out, primes, nlimbs, logn);
+    return hipGetLastError();
+}
+
+hipError_t launch_half_monomial(uint64_t *out, uint32_t nlimbs, uint32_t logn, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_half_monomial, dim3((1u << logn) / kThreads, nlimbs), dim3(kThreads), 0, stream, out, logn);
+    return hipGetLastError();
+}
 
 hipError_t launch_bconv(const BconvArgs &a, uint32_t njobs, hipStream_t stream)
 {

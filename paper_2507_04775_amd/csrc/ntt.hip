@@ -655,16 +655,19 @@ NTT_KERNELS(inv_col, kLds16, inv_col_unit)
 #define FWD12_PP fwd12_unit<PRO_PLAIN, EPI_PLAIN>
 #define FWD12_PM fwd12_unit<PRO_PLAIN, EPI_MODDOWN>
 #define FWD12_RR fwd12_unit<PRO_RESCALE, EPI_RESCALE>
+#define FWD12_RP fwd12_unit<PRO_RESCALE, EPI_PLAIN>
 #define FWD12_BM fwd12_unit<PRO_BCONV, EPI_MODDOWN>
 NTT_KERNELS(fwd12_plain, kLds12, FWD12_PP)
 NTT_KERNELS(fwd12_moddown, kLds12, FWD12_PM)
 NTT_KERNELS(fwd12_rescale, kLds12, FWD12_RR)
+NTT_KERNELS(fwd12_lift, kLds12, FWD12_RP)
 NTT_KERNELS(fwd12_bconv_moddown, kLds12, FWD12_BM)
 NTT_KERNELS(inv12_plain, kLds12, inv12_unit<PRO_PLAIN>)
 NTT_KERNELS(inv12_galois, kLds12, inv12_unit<PRO_GALOIS>)
 #undef FWD12_PP
 #undef FWD12_PM
 #undef FWD12_RR
+#undef FWD12_RP
 #undef FWD12_BM
 #undef NTT_KERNELS
 
@@ -689,6 +692,7 @@ bool stage_kernels(NttStage st, uint32_t logn, int pass, StageKernels &k)
         case STAGE_FWD_PLAIN: SK(fwd12_plain)
         case STAGE_FWD_MODDOWN: SK(fwd12_moddown)
         case STAGE_FWD_RESCALE: SK(fwd12_rescale)
+        case STAGE_FWD_LIFT: SK(fwd12_lift)
         case STAGE_FWD_BCONV_MODDOWN: SK(fwd12_bconv_moddown)
         case STAGE_INV_PLAIN: SK(inv12_plain)
         case STAGE_INV_GALOIS: SK(inv12_galois)
@@ -702,6 +706,8 @@ bool stage_kernels(NttStage st, uint32_t logn, int pass, StageKernels &k)
         if (pass == 0) { SK(fwd_col_plain) } else { SK(fwd_row_moddown) }
     case STAGE_FWD_RESCALE:
         if (pass == 0) { SK(fwd_col_rescale) } else { SK(fwd_row_rescale) }
+    case STAGE_FWD_LIFT:
+        if (pass == 0) { SK(fwd_col_rescale) } else { SK(fwd_row_plain) }
     case STAGE_FWD_BCONV_MODDOWN:
         if (pass == 0) { SK(fwd_col_bconv) } else { SK(fwd_row_moddown) }
     case STAGE_INV_PLAIN:
@@ -749,6 +755,7 @@ hipError_t launch_ntt_fwd(const NttArgs &a0, uint32_t nlimbs, NttPro pro, NttEpi
     if (pro == PRO_PLAIN && epi == EPI_PLAIN) st = STAGE_FWD_PLAIN;
     else if (pro == PRO_PLAIN && epi == EPI_MODDOWN) st = STAGE_FWD_MODDOWN;
     else if (pro == PRO_RESCALE && epi == EPI_RESCALE) st = STAGE_FWD_RESCALE;
+    else if (pro == PRO_RESCALE && epi == EPI_PLAIN) st = STAGE_FWD_LIFT;
     else if (pro == PRO_BCONV && epi == EPI_MODDOWN) st = STAGE_FWD_BCONV_MODDOWN;
     else return hipErrorInvalidValue;
     return launch_ntt_stage(st, a, nlimbs, stream);

@@ -213,3 +213,43 @@ def batch_plan(seed: int, n_items: int, logn: int, max_level: int, min_level: in
         else:
             plan.append(("hoisted", level, [int(x) for x in g.choice(rs, size=n_rot, replace=False)]))
     return plan
+
+
+@dataclass
+class Request:
+    """One served request: an op chain on two fresh ciphertexts (A, B) at
+    `level`.  ops: ("hmult",) A <- rescale(A * B), ("ptmuladd",) A <-
+    rescale(A * pt + B), ("rotate", k) A <- rot(A, k); with `boot`, A is then
+    truncated to level 0 and bootstrapped."""
+    rid: int
+    arrival: float
+    level: int
+    ops: list
+    boot: bool
+    seed: int
+
+
+def serving_requests(seed: int, n: int, logn: int, rate: float | None, min_level: int = 10, max_level: int = 30,
+                     min_ops: int = 4, max_ops: int = 40, boot_frac: float = 0.1) -> list:
+    """Poisson arrivals at `rate` requests/s (all at t = 0 when rate is None);
+    start levels uniform in [min_level, max_level]; chains of uniform length
+    mixing the three ops, never leaving level 1 before the last op."""
+    g = rng(seed)
+    rs = batch_rotation_set(logn)
+    t, out = 0.0, []
+    for i in range(n):
+        if rate is not None:
+            t += float(g.exponential(1.0 / rate))
+        level = int(g.integers(min_level, max_level + 1))
+        length = int(g.integers(min_ops, max_ops + 1))
+        ops, lv = [], level
+        for _ in range(length):
+            kind = int(g.integers(0, 3))
+            if kind < 2 and lv >= 2:
+                ops.append(("hmult",) if kind == 0 else ("ptmuladd",))
+                lv -= 1
+            else:
+                ops.append(("rotate", int(g.choice(rs))))
+        out.append(Request(rid=i, arrival=t, level=level, ops=ops, boot=bool(g.random() < boot_frac),
+                           seed=int(g.integers(1, 2 ** 31))))
+    return out

@@ -1,0 +1,57 @@
+"""The library's bootstrap planner against the oracle's: both derive the
+homomorphic DFT diagonals (by different routes: probe vectors pushed through
+the butterflies here, composition of per-stage diagonals there) and the
+Chebyshev coefficients independently; they must agree to floating-point
+rounding, and so must the schedule quantities (rotations, output level)."""
+import numpy as np
+import pytest
+
+from oracle import bootstrap as OB
+from helpers import oracle_params
+from paper_2507_04775_amd import bootplan as PB
+from paper_2507_04775_amd import inputs
+
+
+def _oracle_params(cfg):
+    return OB.BootParams(logn=cfg.logn, cts_radix_logs=cfg.cts_radix_logs, stc_radix_logs=cfg.stc_radix_logs,
+                         cheb_degree=cfg.cheb_degree, double_angles=cfg.double_angles, k_range=cfg.k_range,
+                         top_scale=cfg.top_scale, in_scale=cfg.in_scale)
+
+
+@pytest.mark.parametrize("logn,radix", [(6, [2, 2, 1]), (7, [1, 4, 1]), (8, [7])])
+def test_group_diagonals_match(logn, radix):
+    n = 1 << (logn - 1)
+    for inverse in (True, False):
+        for halves in OB.stage_groups(logn, radix, not inverse):
+            mine = PB.group_diagonals(logn, halves, inverse)
+            theirs = OB.group_map(n, logn, halves, inverse)
+            m_lo, count, baby, giants, h0 = OB.group_layout(n, halves)
+            for m in range(m_lo, m_lo + count):
+                a = mine.get(m, np.zeros(n))
+                b = theirs.get((m * h0) % n, np.zeros(n))
+                assert np.max(np.abs(a - b)) < 1e-12, (halves, m)
+
+
+def test_coefficients_of_slots_invert_the_embedding():
+    logn = 7
+    N = 1 << logn
+    z = inputs.complex_slots(inputs.rng(5), N // 2)
+    m = PB.coeffs_of_slots(z, logn)
+    zeta = np.exp(1j * np.pi / N)
+    for j in (0, 1, 17, N // 2 - 1):
+        assert abs(np.polyval(m[::-1], zeta ** pow(5, j, 2 * N)) - z[j]) < 1e-12
+
+
+def test_plan_matches_the_oracle_planner():
+    ps = inputs.params("boot-small")
+    cfg = PB.default_config(12, 2.0 ** 50)
+    mine = PB.plan(ps.q, cfg)
+    P = oracle_params(ps)
+    bp = _oracle_params(cfg)
+    theirs = OB.plan(P, bp)
+    assert mine.rotations == OB.rotations_needed(bp)
+    assert mine.output_level == OB.output_level(P, bp)
+    for a, b in zip(mine.cts + mine.stc, theirs.cts + theirs.stc):
+        assert a.shape == b.shape
+        assert np.all(np.abs(a - b) <= 1 + 1e-14 * np.max(np.abs(b)))
+    assert np.max(np.abs(mine.cheb - theirs.cheb)) < 1e-13

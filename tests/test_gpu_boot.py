@@ -1,0 +1,111 @@
+"""Bootstrapping on the GPU (ckks_boot_* through the C ABI) against the
+oracle's executor, bit for bit on every limb of the output: at N = 2^12 with
+the full schedule (valid keys, so the decrypted error is reported too) and at
+N = 2^16 with the three-group CoeffToSlot / SlotToCoeff of the full-slot
+workload and a short EvalMod.  HIP-graph replays must match the eager run."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import bootstrap as B
+from gpu_common import Setup, assert_equal, gpu_available
+from helpers import ClientSetup, max_err_bits
+from paper_2507_04775_amd import inputs
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _boot_handle(s, bp, pl, relin, conj, rot):
+    return s.ckks.Boot(s.ctx, bp.cts_radix_logs, bp.stc_radix_logs, pl.cts, pl.stc, pl.cheb, bp.double_angles,
+                       bp.top_scale, relin, conj, rot)
+
+
+def _check_ct(s, got, want, what):
+    assert got.level == want[2], (what, got.level, want[2])
+    assert_equal(s.host(got.c0)[: want[2] + 1], want[0], what + " c0")
+    assert_equal(s.host(got.c1)[: want[2] + 1], want[1], what + " c1")
+
+
+def test_bootstrap_small_full_schedule():
+    _say("bootstrap boot-small: keys and plan")
+    s = Setup("boot-small")
+    cs = ClientSetup(s.ps, seed=31)
+    bp = B.BootParams(logn=12, cts_radix_logs=[4, 4, 3], stc_radix_logs=[3, 4, 4], cheb_degree=63,
+                      double_angles=5, k_range=128.0, top_scale=2.0 ** 50, in_scale=2.0 ** 50)
+    pl = B.plan(s.P, bp)
+    rot_np = {k: cs.galois_key(oracle.galois_for_rotation(12, k)) for k in B.rotations_needed(bp)}
+    conj_np = cs.galois_key(oracle.galois_conjugate(12))
+    rlk_np = cs.relin_key()
+    z = inputs.complex_slots(inputs.rng(32), s.N // 2)
+    c0, c1 = cs.encrypt(z, 0, bp.in_scale)
+    want = B.Executor(s.P, pl, rlk_np, conj_np, rot_np).bootstrap((c0, c1, 0))
+
+    _say("bootstrap boot-small: GPU")
+    rot = {k: s.ctx.key(s.dev(v), oracle.galois_for_rotation(12, k)) for k, v in rot_np.items()}
+    boot = _boot_handle(s, bp, pl, s.ctx.key(s.dev(rlk_np), 0), s.ctx.key(s.dev(conj_np), 2 * s.N - 1), rot)
+    assert boot.output_level == B.output_level(s.P, bp)
+    inp = s.ckks.Ciphertext(s.dev(c0), s.dev(c1), 0, bp.in_scale)
+    out = s.ctx.empty_ct(boot.output_level)
+    boot.ckks_bootstrap(inp, out)
+    _check_ct(s, out, want, "bootstrap")
+    err = max_err_bits(cs.decrypt((s.host(out.c0), s.host(out.c1)), out.level, out.scale), z)
+    _say("bootstrap boot-small: decrypted error 2^%.2f, %d key switches" % (err, boot.keyswitches))
+    assert err < -11
+
+
+def _random_key(s, seed, galois):
+    from paper_2507_04775_amd.inputs import device_residues
+    mods = (list(s.ps.q) + list(s.ps.p)) * (2 * s.ps.dnum)
+    d = device_residues(seed, mods, s.N).reshape(s.ps.dnum, 2, len(s.ps.q) + len(s.ps.p), s.N).contiguous()
+    return d, s.ctx.key(d, galois)
+
+
+def test_bootstrap_large_graph_replay():
+    import torch
+    _say("bootstrap large: plan and keys")
+    s = Setup("large")
+    bp = B.BootParams(logn=16, cts_radix_logs=[5, 5, 5], stc_radix_logs=[5, 5, 5], cheb_degree=7,
+                      double_angles=1, k_range=512.0, top_scale=2.0 ** 50, in_scale=2.0 ** 50)
+    pl = B.plan(s.P, bp)
+    rot = {}
+    for k in B.rotations_needed(bp):
+        rot[k] = _random_key(s, 1000 + k, oracle.galois_for_rotation(16, k))
+    rlk = _random_key(s, 1, 0)
+    conj = _random_key(s, 2, 2 * s.N - 1)
+    boot = _boot_handle(s, bp, pl, rlk[1], conj[1], {k: v[1] for k, v in rot.items()})
+    c0, c1 = inputs.random_ct(5, s.ps, 0)
+    inp = s.ckks.Ciphertext(s.dev(c0), s.dev(c1), 0, bp.in_scale)
+    out = s.ctx.empty_ct(boot.output_level)
+    _say("bootstrap large: GPU eager")
+    boot.ckks_bootstrap(inp, out)
+    eager = (s.host(out.c0).copy(), s.host(out.c1).copy())
+
+    _say("bootstrap large: oracle")
+    host = lambda t: t.cpu().numpy()
+    want = B.Executor(s.P, pl, host(rlk[0]), host(conj[0]), {k: host(v[0]) for k, v in rot.items()}).bootstrap(
+        (c0, c1, 0))
+    _check_ct(s, out, want, "bootstrap")
+
+    _say("bootstrap large: graph replays")
+    st = torch.cuda.Stream()
+    out2 = s.ctx.empty_ct(boot.output_level)
+    with torch.cuda.stream(st):
+        boot.capture(inp, out2, st)
+    for rep in range(3):
+        out2.c0.fill_(0)
+        out2.c1.fill_(0)
+        torch.cuda.synchronize()
+        boot.replay(st)
+        st.synchronize()
+        assert_equal(s.host(out2.c0), eager[0], "replay %d c0" % rep)
+        assert_equal(s.host(out2.c1), eager[1], "replay %d c1" % rep)
+        boot.ckks_bootstrap(inp, out)  # eager work between replays
+        torch.cuda.synchronize()
+    assert_equal(s.host(out.c0), eager[0], "eager after replays")

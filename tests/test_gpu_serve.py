@@ -1,0 +1,85 @@
+"""The continuous-batching server: every request's result is the same when it
+runs alone and when it runs in the concurrent mix (bit for bit), chains
+without bootstrap match the oracle applying the same ops, and every request
+completes after it arrived."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_common import Setup, assert_equal, gpu_available
+from paper_2507_04775_amd import inputs
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+
+def _server(s, slots, budget):
+    import torch
+    from paper_2507_04775_amd import bootplan, ckks
+    from paper_2507_04775_amd.serve import Server
+
+    def rkey(seed, g):
+        mods = (list(s.ps.q) + list(s.ps.p)) * (2 * s.ps.dnum)
+        d = inputs.device_residues(seed, mods, s.N).reshape(s.ps.dnum, 2, -1, s.N).contiguous()
+        return d, s.ctx.key(d, g)
+
+    rs = inputs.batch_rotation_set(s.ps.logn)
+    rot = {k: rkey(100 + k, pow(5, k, 2 * s.N)) for k in rs}
+    relin = rkey(1, 0)
+    pts = [inputs.device_residues(7 + i, s.ps.q, s.N) for i in range(3)]
+    cfg = bootplan.default_config(s.ps.logn, 2.0 ** s.ps.log_scale)
+    pl = bootplan.plan(s.ps.q, cfg)
+    bkeys = {k: rkey(5000 + k, pow(5, k, 2 * s.N))[1] for k in pl.rotations}
+    boot = ckks.Boot(s.ctx, cfg.cts_radix_logs, cfg.stc_radix_logs, pl.cts, pl.stc, pl.cheb, cfg.double_angles,
+                     cfg.top_scale, relin[1], rkey(2, 2 * s.N - 1)[1], bkeys)
+    srv = Server(s.ctx, relin[1], {k: v[1] for k, v in rot.items()}, pts, boot, slots=slots, mem_budget=budget)
+    return srv, relin[0], {k: v[0] for k, v in rot.items()}, pts
+
+
+def _oracle_chain(s, r, rlk, rot, pts):
+    host = lambda t: t.cpu().numpy()
+    mods = s.ps.q[: r.level + 1]
+    cts = [host(inputs.device_residues(r.seed * 4 + i, mods, s.N)) for i in range(4)]
+    A, B = (cts[0], cts[1]), (cts[2], cts[3])
+    l = r.level
+    for op in r.ops:
+        if op[0] == "hmult":
+            m = oracle.hmult_relin(s.P, A, (B[0][: l + 1], B[1][: l + 1]), host(rlk), l)
+            A = oracle.rescale(s.P, m, l)
+            l -= 1
+        elif op[0] == "ptmuladd":
+            pt = host(pts[r.rid % len(pts)][: l + 1])
+            q = s.ps.q[: l + 1]
+            m = tuple(oracle.vec(q, oracle.vec(q, A[t], pt, "mul", s.ps.logn), B[t][: l + 1], "add", s.ps.logn)
+                      for t in range(2))
+            A = oracle.rescale(s.P, m, l)
+            l -= 1
+        else:
+            g = oracle.galois_for_rotation(s.ps.logn, op[1])
+            A = oracle.apply_galois(s.P, A, g, host(rot[op[1]]), l)
+    return A, l
+
+
+def test_results_alone_equal_results_in_the_mix():
+    s = Setup("boot-small")
+    srv, rlk, rot, pts = _server(s, slots=4, budget=64 << 20)
+    reqs = inputs.serving_requests(inputs.BASE_SEED + 5, 14, s.ps.logn, rate=4000.0, min_level=4, max_level=20,
+                                   min_ops=3, max_ops=12, boot_frac=0.25)
+    assert any(r.boot for r in reqs) and not all(r.boot for r in reqs)
+    mix = srv.run(reqs, keep_outputs=True, concurrent=True)
+    alone = srv.run(reqs, keep_outputs=True, concurrent=False)
+    assert [d.rid for d in mix] == [r.rid for r in reqs] == [d.rid for d in alone]
+    for d, a in zip(mix, alone):
+        assert d.output[2] == a.output[2]
+        assert_equal(d.output[0], a.output[0], "request %d c0" % d.rid)
+        assert_equal(d.output[1], a.output[1], "request %d c1" % d.rid)
+        assert d.finish >= d.arrival - 1e-3
+    checked = 0
+    for r, d in zip(reqs, mix):
+        if r.boot or checked == 2:
+            continue
+        (w0, w1), lw = _oracle_chain(s, r, rlk, rot, pts)
+        assert d.output[2] == lw
+        assert_equal(d.output[0], w0, "oracle chain %d c0" % r.rid)
+        assert_equal(d.output[1], w1, "oracle chain %d c1" % r.rid)
+        checked += 1
+    assert checked == 2
