@@ -300,9 +300,16 @@ void ckks_batch_destroy(ckks_batch *batch);
  *   the first CoeffToSlot group rescales twice.
  * - Between them: ct_re = ct + conj(ct), ct_im = (conj(ct) - ct) X^(N/2);
  *   each goes through EvalMod; then ct = ct_re + ct_im X^(N/2).
- * - EvalMod: T_1 = y, T_2m = 2 T_m^2 - 1, T_2m+1 = 2 T_m T_m+1 - T_1 up to
- *   T_d (d = cheb_degree), then sum_k c_k T_k taken to the level one below
- *   the lowest T_k plus c_0, then double_angles steps y <- 2 y^2 - 1.
+ * - EvalMod: the babies T_1..T_min(b,d) (d = cheb_degree, b = cheb_baby)
+ *   from T_1 = y, T_2m = 2 T_m^2 - 1, T_2m+1 = 2 T_m T_m+1 - T_1, the giants
+ *   T_2b, T_4b, .. up to d by squaring.  A series of degree D >= b is split
+ *   at the largest giant G <= D as q T_G + r (q_0 = c_G, q_i = 2 c_(G+i),
+ *   r_(G-i) = c_(G-i) - c_(G+i), double arithmetic), r evaluated first, then
+ *   q (a constant q_0 is multiplied in as a real constant); q T_G and r are
+ *   brought to the lower of their levels and added.  Below degree b a leaf is
+ *   sum_k round(c_k (D_t q_(t+1)) / D_level(T_k)) T_k on the limbs 0..t+1,
+ *   rescaled once, plus c_0, with t one below the lowest of T_1..T_(b-1).
+ *   Then double_angles steps y <- 2 y^2 - 1.
  *
  * Scales: level L has top_scale, level l-1 has (D_l * D_l) / q_l (double
  * arithmetic).  Taking a level-l ciphertext times a real c to level t < l
@@ -338,6 +345,7 @@ typedef struct {
     const double *const *stc_diags;
     uint32_t cheb_degree;
     const double *cheb;                  /* cheb_degree + 1 coefficients */
+    uint32_t cheb_baby;                  /* baby-step size, a power of two >= 2; 0: smallest b with b^2 > d */
     uint32_t double_angles;
     double top_scale;                    /* scale of level L */
     const ckks_key *relin, *conj;

@@ -32,10 +32,17 @@ Schedule (n = N/2 slots, full packing):
    group, so the slots of both hold t_k / (q_0 K) for the coefficients t_k of
    the raised plaintext (slot x of ct_re holds t at position br(x), of ct_im
    at br(x) + n).
-4. EvalMod on each: p(y) = sum_k c_k T_k(y) with T_1 = y, T_2m = 2 T_m^2 - 1,
-   T_2m+1 = 2 T_m T_m+1 - T_1, the terms c_k T_k all taken to the level one
-   below the lowest T_k, then c_0 added; then r double-angle steps
-   y <- 2 y^2 - 1.  With p interpolating cos(2 pi (K y - 1/4) / 2^r) on
+4. EvalMod on each: p(y) = sum_k c_k T_k(y) by baby-step/giant-step.  The
+   babies T_1..T_min(b,d) (b a power of two, by default the smallest with
+   b^2 > d) come from
+   T_2m = 2 T_m^2 - 1 and T_2m+1 = 2 T_m T_m+1 - T_1, the giants T_2b, T_4b, ..
+   (up to d) by squaring.  A polynomial of degree D >= b is split at the
+   largest giant G <= D as p = q T_G + r (Chebyshev division: q_0 = c_G,
+   q_i = 2 c_(G+i), r_(G-i) = c_(G-i) - c_(G+i)), q and r evaluated the same
+   way and combined by one multiplication; below degree b a leaf
+   c_0 + sum_k c_k T_k is one integer combination of the babies at the level
+   one above the lowest baby T_1..T_(b-1), rescaled once.  Then r double-angle
+   steps y <- 2 y^2 - 1.  With p interpolating cos(2 pi (K y - 1/4) / 2^r) on
    [-1, 1] this yields sin(2 pi t_k / q_0).
 5. Recombine: ct = ct_re + ct_im * X^(N/2).
 6. SlotToCoeff: the forward special-FFT stages merged into groups, the
@@ -70,6 +77,11 @@ class BootParams:
     k_range: float                # |t_k / q_0| is assumed below k_range
     top_scale: float              # Delta_L
     in_scale: float               # scale of the level-0 input
+    cheb_baby: int = 0            # baby-step size of the Chebyshev evaluation (0: smallest b with b^2 > d)
+
+    @property
+    def baby(self) -> int:
+        return self.cheb_baby or baby_size(self.cheb_degree)
 
     @property
     def n(self) -> int:
@@ -153,21 +165,53 @@ def baby_offsets(n: int, halves):
     return [b * h0 for b in range(1, min(baby, count))]
 
 
-def cheb_levels(d: int) -> dict:
-    """Depth of T_k (k = 1..d) in the product tree (T_1 at depth 0)."""
-    depth = {1: 0}
-    for k in range(2, d + 1):
-        if k % 2 == 0:
-            depth[k] = depth[k // 2] + 1
-        else:
-            depth[k] = max(depth[(k - 1) // 2], depth[(k + 1) // 2]) + 1
-    return depth
+def baby_size(d: int) -> int:
+    b = 2
+    while b * b <= d:
+        b *= 2
+    return b
+
+
+def cheb_split(c, G: int):
+    """p = q T_G + r for Chebyshev coefficients c of degree D with G <= D < 2G."""
+    D = len(c) - 1
+    q = [0.0] * (D - G + 1)
+    r = list(c[:G])
+    q[0] = c[G]
+    for i in range(1, D - G + 1):
+        q[i] = 2.0 * c[G + i]
+        r[G - i] = r[G - i] - c[G + i]
+    return q, r
+
+
+def cheb_schedule_depth(d: int, b: int) -> int:
+    """Levels the baby-step/giant-step evaluation of degree d with baby size b
+    consumes (a dry run of Executor.chebyshev on levels alone)."""
+    lv = {1: 0}
+    for k in range(2, min(b, d) + 1):
+        lv[k] = lv[k // 2] - 1 if k % 2 == 0 else min(lv[k // 2], lv[k // 2 + 1]) - 1
+    G = b
+    while 2 * G <= d:
+        lv[2 * G] = lv[G] - 1
+        G *= 2
+    t_leaf = min(lv[k] for k in range(1, min(b - 1, d) + 1)) - 1
+
+    def poly(D):
+        if D < b:
+            return t_leaf
+        G = b
+        while 2 * G <= D:
+            G *= 2
+        r = poly(G - 1)
+        p = lv[G] - 1 if D == G else min(poly(D - G), lv[G]) - 1
+        return min(p, r)
+    return -poly(d)
 
 
 def levels_used(bp: BootParams) -> dict:
     """Levels consumed by each phase."""
     return {"cts": len(bp.cts_radix_logs) + 1,
-            "evalmod": max(cheb_levels(bp.cheb_degree).values()) + 1 + bp.double_angles,
+            "evalmod": cheb_schedule_depth(bp.cheb_degree, bp.baby) + bp.double_angles,
             "stc": len(bp.stc_radix_logs)}
 
 
@@ -411,22 +455,50 @@ class Executor:
         return total
 
     def chebyshev(self, y):
-        c = self.pl.cheb
+        c = [float(x) for x in self.pl.cheb]
         d = len(c) - 1
+        b = self.bp.baby
         T = {1: y}
-        for k in range(2, d + 1):
+        for k in range(2, min(b, d) + 1):
             if k % 2 == 0:
                 p = self.scalar_mul_int(self.mul(T[k // 2], T[k // 2]), 2)
                 T[k] = self.scalar_add(p, -1.0)
             else:
-                p = self.scalar_mul_int(self.mul(T[(k - 1) // 2], T[(k + 1) // 2]), 2)
+                p = self.scalar_mul_int(self.mul(T[k // 2], T[k // 2 + 1]), 2)
                 T[k] = self.add(p, self.level_down(T[1], p[2]), "sub")
-        t = min(T[k][2] for k in T) - 1
+        G = b
+        while 2 * G <= d:
+            p = self.scalar_mul_int(self.mul(T[G], T[G]), 2)
+            T[2 * G] = self.scalar_add(p, -1.0)
+            G *= 2
+        t_leaf = min(T[k][2] for k in range(1, min(b - 1, d) + 1)) - 1
+        return self._poly(c, T, b, t_leaf)
+
+    def _leaf(self, c, T, t: int):
+        """c_0 + sum_k c_k T_k: the babies truncated to level t + 1, times
+        round(c_k (Delta_t q_(t+1)) / Delta_level(T_k)), summed, rescaled once."""
         acc = None
-        for k in range(1, d + 1):
-            u = self.mult_const_to(T[k], float(c[k]), t)
+        for k in range(1, len(c)):
+            C = round_half_away(c[k] * const_factor(self.sc, self.q, T[k][2], t))
+            u = self.scalar_mul_int(self.drop(T[k], t + 1), C)
             acc = u if acc is None else self.add(acc, u)
-        return self.scalar_add(acc, float(c[0]))
+        return self.scalar_add(self.rescale(acc), c[0])
+
+    def _poly(self, c, T, b: int, t_leaf: int):
+        D = len(c) - 1
+        if D < b:
+            return self._leaf(c, T, t_leaf)
+        G = b
+        while 2 * G <= D:
+            G *= 2
+        q, r = cheb_split(c, G)
+        R = self._poly(r, T, b, t_leaf)
+        if len(q) == 1:
+            P = self.mult_const_to(T[G], q[0], T[G][2] - 1)
+        else:
+            P = self.mul(self._poly(q, T, b, t_leaf), T[G])
+        l = min(P[2], R[2])
+        return self.add(self.level_down(P, l), self.level_down(R, l))
 
     def eval_mod(self, y):
         y = self.chebyshev(y)

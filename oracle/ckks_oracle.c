@@ -285,10 +285,58 @@ void orc_inner_product(uint32_t logn, const uint64_t *q, uint32_t nq, const uint
 }
 
 /*
+ * Centred fast base conversion from the special basis: the same sum as
+ * orc_bconv, with every y_k taken as its representative in
+ * [-(p_k-1)/2, (p_k-1)/2].  The value it represents is v = sum_k y_k P/p_k,
+ * congruent to x mod P with |v| < K P / 2 and no bias in sign.
+ */
+static void bconv_centred(const uint64_t *src, uint32_t ns, const uint64_t *dst, uint32_t nd, uint32_t logn,
+                          const uint64_t *x, uint64_t *out)
+{
+    uint64_t N = 1ull << logn;
+    uint64_t *hat_inv = (uint64_t *)malloc(ns * sizeof(uint64_t));
+    uint64_t *hat_mod = (uint64_t *)malloc((size_t)ns * nd * sizeof(uint64_t));
+    for (uint32_t i = 0; i < ns; i++) {
+        uint64_t prod = 1;
+        for (uint32_t k = 0; k < ns; k++)
+            if (k != i) prod = mulm(prod, src[k] % src[i], src[i]);
+        hat_inv[i] = invm(prod, src[i]);
+        for (uint32_t c = 0; c < nd; c++) {
+            uint64_t pc = 1;
+            for (uint32_t k = 0; k < ns; k++)
+                if (k != i) pc = mulm(pc, src[k] % dst[c], dst[c]);
+            hat_mod[(size_t)c * ns + i] = pc;
+        }
+    }
+#pragma omp parallel for schedule(static)
+    for (int64_t n = 0; n < (int64_t)N; n++) {
+        for (uint32_t c = 0; c < nd; c++) {
+            uint64_t m = dst[c], s = 0;
+            for (uint32_t i = 0; i < ns; i++) {
+                uint64_t y = mulm(x[(uint64_t)i * N + n], hat_inv[i], src[i]);
+                uint64_t t = mulm(y % m, hat_mod[(size_t)c * ns + i], m);      /* y * [B/b_i]_c */
+                if (y > (src[i] - 1) / 2) {                                     /* y - b_i instead of y */
+                    uint64_t bmod = mulm(src[i] % m, hat_mod[(size_t)c * ns + i], m);
+                    t = subm(t, bmod, m);
+                }
+                s = addm(s, t, m);
+            }
+            out[(uint64_t)c * N + n] = s;
+        }
+    }
+    free(hat_inv);
+    free(hat_mod);
+}
+
+/*
  * ModDown: x has rows q_0..q_l, p_0..p_{K-1} (eval domain).  The P rows are
- * brought to coefficients, converted to Q_l with Conv_{P->Q_l}, brought back,
- * and out_i = [P^-1]_{q_i} * (x_i - NTT(conv_i)) (the ModDown fusion sequence
- * of III-F.5; floor division by P, no rounding offset).  out is [l+1][N].
+ * brought to coefficients, converted to Q_l with the centred conversion above,
+ * brought back, and out_i = [P^-1]_{q_i} * (x_i - NTT(conv_i)) (the ModDown
+ * fusion sequence of III-F.5).  The result is (x - v) / P with v = x mod P up
+ * to a multiple u P, |v| < K P / 2: x / P rounded with an error of zero mean
+ * (a floor division, or a canonical conversion whose overshoot u lies in
+ * [0, K), would leave a bias of about K / 2 in every coefficient).  out is
+ * [l+1][N].
  */
 void orc_moddown(uint32_t logn, const uint64_t *q, uint32_t nq, const uint64_t *p, uint32_t np,
                  uint32_t level, const uint64_t *x, uint64_t *out)
@@ -300,7 +348,7 @@ void orc_moddown(uint32_t logn, const uint64_t *q, uint32_t nq, const uint64_t *
     memcpy(a, x + (size_t)n * N, (size_t)np * N * sizeof(uint64_t));
     orc_ntt(p, np, logn, a, 1);
     uint64_t *conv = (uint64_t *)malloc((size_t)n * N * sizeof(uint64_t));
-    orc_bconv(p, np, q, n, logn, a, conv);
+    bconv_centred(p, np, q, n, logn, a, conv);
     orc_ntt(q, n, logn, conv, 0);
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < (int64_t)n; i++) {

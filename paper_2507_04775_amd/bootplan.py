@@ -42,10 +42,20 @@ class BootConfig:
     k_range: float
     top_scale: float
     in_scale: float
+    cheb_baby: int = 0   # baby-step size of the Chebyshev evaluation (0: smallest power of two b with b^2 > d)
 
     @property
     def n(self) -> int:
         return 1 << (self.logn - 1)
+
+    @property
+    def baby(self) -> int:
+        if self.cheb_baby:
+            return self.cheb_baby
+        b = 2
+        while b * b <= self.cheb_degree:
+            b *= 2
+        return b
 
 
 # The schedule used for the full-slot workloads: three merged groups each way.
@@ -175,11 +185,30 @@ def chebyshev(cfg: BootConfig) -> np.ndarray:
     return c
 
 
-def cheb_depth(d: int) -> int:
-    dep = [0, 0]
-    for k in range(2, d + 1):
-        dep.append(dep[k // 2] + 1 if k % 2 == 0 else max(dep[k // 2], dep[k // 2 + 1]) + 1)
-    return max(dep)
+def cheb_depth(d: int, b: int) -> int:
+    """Levels of the baby-step/giant-step Chebyshev evaluation: babies T_k at
+    depth 0 (k = 1), one more per product; giants T_2b, T_4b, .. by squaring;
+    leaves one level below the deepest of T_1..T_(b-1); a split q T_G + r one
+    below the deeper of q and T_G (of T_G alone for a constant q), and no
+    higher than r."""
+    dep = {1: 0}
+    for k in range(2, min(b, d) + 1):
+        dep[k] = 1 + (dep[k // 2] if k % 2 == 0 else max(dep[k // 2], dep[k // 2 + 1]))
+    G = b
+    while 2 * G <= d:
+        dep[2 * G] = dep[G] + 1
+        G *= 2
+    leaf = 1 + max(dep[k] for k in range(1, min(b - 1, d) + 1))
+
+    def node(D):
+        if D < b:
+            return leaf
+        G = b
+        while 2 * G <= D:
+            G *= 2
+        prod = dep[G] + 1 if D == G else max(node(D - G), dep[G]) + 1
+        return max(prod, node(G - 1))
+    return node(d)
 
 
 def rotations(cfg: BootConfig) -> list:
@@ -215,7 +244,7 @@ def plan(q, cfg: BootConfig) -> BootPlan:
         f = d[L] / (2.0 * q[0] * cfg.k_range) if i == 0 else 1.0
         p.cts.append(encode_group(cfg, halves, True, f, _pt_scale(d, q, lv, k)))
         lv -= k
-    lv -= cheb_depth(cfg.cheb_degree) + 1 + cfg.double_angles
+    lv -= cheb_depth(cfg.cheb_degree, cfg.baby) + cfg.double_angles
     for i, halves in enumerate(_halves(cfg.logn, cfg.stc_radix_logs, True)):
         f = q[0] / (2.0 * np.pi * cfg.in_scale) if i == 0 else 1.0
         p.stc.append(encode_group(cfg, halves, False, f, _pt_scale(d, q, lv, 1)))

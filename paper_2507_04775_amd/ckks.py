@@ -44,7 +44,7 @@ class _BootDesc(ctypes.Structure):
     _fields_ = [("n_cts", _u32), ("n_stc", _u32), ("cts_radix_logs", ctypes.POINTER(_u32)),
                 ("stc_radix_logs", ctypes.POINTER(_u32)), ("cts_diags", ctypes.POINTER(_vp)),
                 ("stc_diags", ctypes.POINTER(_vp)), ("cheb_degree", _u32), ("cheb", ctypes.POINTER(ctypes.c_double)),
-                ("double_angles", _u32), ("top_scale", ctypes.c_double), ("relin", _vp), ("conj", _vp),
+                ("cheb_baby", _u32), ("double_angles", _u32), ("top_scale", ctypes.c_double), ("relin", _vp), ("conj", _vp),
                 ("n_rot", _u32), ("rot_steps", ctypes.POINTER(_i32)), ("rot_keys", ctypes.POINTER(_vp))]
 
 
@@ -426,7 +426,7 @@ class Boot:
     keys are passed in."""
 
     def __init__(self, ctx: "Context", cts_radix_logs, stc_radix_logs, cts_diags, stc_diags, cheb,
-                 double_angles: int, top_scale: float, relin: Key, conj: Key, rot_keys: dict):
+                 double_angles: int, top_scale: float, relin: Key, conj: Key, rot_keys: dict, cheb_baby: int = 0):
         import numpy as np
         self.ctx = ctx
         self._keys = [relin, conj] + list(rot_keys.values())
@@ -445,6 +445,7 @@ class Boot:
         d.cheb_degree = len(ch) - 1
         d.cheb = ch.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         d.double_angles = double_angles
+        d.cheb_baby = cheb_baby
         d.top_scale = top_scale
         d.relin, d.conj = relin.handle, conj.handle
         d.n_rot, d.rot_steps, d.rot_keys = len(steps), rs, rk

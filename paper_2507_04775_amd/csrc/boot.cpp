@@ -1,7 +1,9 @@
 // Bootstrapping executor (paper Sec. III-F.7): ModRaise, CoeffToSlot as
 // merged special-FFT stages evaluated with baby-step/giant-step over hoisted
 // rotations, EvalMod as a Chebyshev product tree plus double-angle steps, and
-// SlotToCoeff.  The schedule (levels, layouts, rotations, constants) is
+// SlotToCoeff.  EvalMod evaluates the Chebyshev series by baby-step/giant-step
+// (a tree of Chebyshev divisions p = q T_G + r over power-of-two giants, with
+// integer combinations of the babies at the leaves).  The schedule (levels, layouts, rotations, constants) is
 // derived here from the descriptor; the plaintext diagonals arrive as
 // integer-valued doubles and are reduced and transformed on the device once,
 // at creation.  A run is a fixed host-side sequence of library operations on
@@ -10,6 +12,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <functional>
 #include <map>
 #include <string>
 #include <vector>
@@ -79,6 +82,32 @@ struct Group {
     uint64_t *pt = nullptr;       // [count][level+1][N], evaluation domain
 };
 
+// One node of the baby-step/giant-step Chebyshev evaluation: a leaf
+// c_0 + sum_k c_k T_k below the baby size, or a split p = q T_G + r.
+struct ChebNode {
+    bool leaf = false;
+    std::vector<double> c;  // leaf coefficients c_0..c_D
+    size_t cst = 0;         // leaf: offset of its [D][t+2] constant residues in the device table
+    uint32_t G = 0;
+    int q = -1, r = -1;     // children; q = -1 when the quotient is the constant q0
+    double q0 = 0;
+    int level = 0;          // level of the result relative to the EvalMod input
+};
+
+// p = q T_G + r for Chebyshev coefficients c of degree D, G <= D < 2G:
+// q_0 = c_G, q_i = 2 c_(G+i), r_(G-i) = c_(G-i) - c_(G+i).
+void cheb_split(const std::vector<double> &c, uint32_t G, std::vector<double> &q, std::vector<double> &r)
+{
+    const uint32_t D = (uint32_t)c.size() - 1;
+    q.assign(D - G + 1, 0.0);
+    r.assign(c.begin(), c.begin() + G);
+    q[0] = c[G];
+    for (uint32_t i = 1; i <= D - G; ++i) {
+        q[i] = 2.0 * c[G + i];
+        r[G - i] = r[G - i] - c[G + i];
+    }
+}
+
 // A ciphertext held in one of the executor's buffers (or the caller's output).
 struct Ct {
     uint64_t *c0, *c1;
@@ -93,7 +122,14 @@ struct ckks_boot {
     std::vector<Group> cts, stc;
     uint32_t degree = 0, double_angles = 0, evalmod_in = 0, out_level = 0, keyswitches = 0;
     std::vector<double> cheb, sc;  // Chebyshev coefficients; level scales
-    std::vector<uint32_t> cheb_depth;
+    // baby-step/giant-step evaluation: baby size, giants (2b, 4b, ..), levels of T_k relative
+    // to the EvalMod input, leaf level, the node tree (root last) and the leaf constants
+    uint32_t baby = 0, nbaby = 0;
+    std::vector<uint32_t> giants;
+    std::map<uint32_t, int> lvT;
+    int t_leaf = 0;
+    std::vector<ChebNode> nodes;
+    uint64_t *leaf_cst = nullptr;
     const ckks_key *relin = nullptr, *conj = nullptr;
     std::map<uint32_t, const ckks_key *> rot;  // slot rotation mod n -> key
     void *dev = nullptr;
@@ -116,8 +152,11 @@ struct ckks_boot {
     uint32_t s_re(uint32_t i) const { return max_baby + 5 + i; }
     uint32_t s_im(uint32_t i) const { return max_baby + 7 + i; }
     uint32_t s_d(uint32_t i) const { return max_baby + 9 + i; }  // level-down temporaries 0..2
-    uint32_t s_t(uint32_t k) const { return max_baby + 12 + (k - 2); }  // T_k, k = 2..degree
-    uint32_t slot_count() const { return max_baby + 12 + (degree >= 2 ? degree - 1 : 0); }
+    uint32_t s_t(uint32_t k) const { return max_baby + 12 + (k - 2); }  // babies T_k, k = 2..nbaby
+    uint32_t s_g(uint32_t j) const { return max_baby + 12 + (nbaby - 1) + j; }  // giants
+    uint32_t pool0() const { return s_g((uint32_t)giants.size()); }
+    uint32_t pool_size() const { return 2 * (uint32_t)giants.size() + 6; }
+    uint32_t slot_count() const { return pool0() + pool_size(); }
 
     Ct slot(uint32_t i, uint32_t level) const
     {
@@ -264,44 +303,122 @@ struct Runner {
         return CKKS_OK;
     }
 
+    // buffers of the Chebyshev evaluation
+    std::vector<uint32_t> pool;
+    std::map<uint32_t, Ct> T;
+
+    ckks_status take(uint32_t &s)
+    {
+        if (pool.empty()) return fail(CKKS_E_UNSUPPORTED, "ckks_bootstrap: Chebyshev buffer pool exhausted");
+        s = pool.back();
+        pool.pop_back();
+        return CKKS_OK;
+    }
+
+    ckks_status poly(int ni, Ct &out, uint32_t &slot)
+    {
+        const ChebNode &nd = b->nodes[ni];
+        if (nd.leaf) {
+            // sum_k C_k T_k on the limbs 0..t+1, rescaled once, plus c_0
+            const uint32_t t = (uint32_t)((int)b->evalmod_in + nd.level), D = (uint32_t)nd.c.size() - 1;
+            TRY(take(slot));
+            const Ct dst = b->slot(slot, t + 1);
+            for (uint32_t k0 = 1; k0 <= D; k0 += kMaxLincomb) {
+                ScalarLincombArgs la;
+                memset(&la, 0, sizeof(la));
+                la.n = std::min<uint32_t>(kMaxLincomb, D - k0 + 1);
+                for (uint32_t j = 0; j < la.n; ++j) {
+                    la.a0[j] = T.at(k0 + j).c0;
+                    la.a1[j] = T.at(k0 + j).c1;
+                }
+                la.cst = b->leaf_cst + nd.cst + (size_t)(k0 - 1) * (t + 2);
+                la.cst_stride = t + 2;
+                la.acc0 = k0 > 1 ? dst.c0 : nullptr;
+                la.acc1 = k0 > 1 ? dst.c1 : nullptr;
+                la.out0 = dst.c0;
+                la.out1 = dst.c1;
+                la.primes = ctx()->d_primes;
+                la.logn = ctx()->logn;
+                TRY(dev(launch_scalar_lincomb(la, t + 2, st), "ckks_bootstrap leaf"));
+            }
+            out = dst;
+            TRY(rescale(out));
+            return scalar_add(out, nd.c[0]);
+        }
+        Ct R, P;
+        uint32_t sr, sp;
+        TRY(poly(nd.r, R, sr));
+        const Ct &TG = T.at(nd.G);
+        TRY(take(sp));
+        if (nd.q < 0) {
+            TRY(mult_const_to(TG, nd.q0, TG.level - 1, b->slot(sp, 0), P));
+        } else {
+            Ct Q;
+            uint32_t sq;
+            TRY(poly(nd.q, Q, sq));
+            TRY(mul(Q, TG, b->slot(sp, 0), P));
+            pool.push_back(sq);
+        }
+        const uint32_t l = std::min(P.level, R.level);
+        TRY(level_down(P, l, P, P));
+        TRY(level_down(R, l, R, R));
+        TRY(add(P, R, P));
+        pool.push_back(sr);
+        out = P;
+        slot = sp;
+        return CKKS_OK;
+    }
+
     // EvalMod of the ciphertext in buffer s0 (s1 is its partner); result in s0 or s1
     ckks_status eval_mod(uint32_t s0, uint32_t s1, Ct &out)
     {
-        const uint32_t d = b->degree;
-        std::vector<Ct> T(d + 1);
+        T.clear();
+        pool.clear();
+        for (uint32_t i = 0; i < b->pool_size(); ++i) pool.push_back(b->pool0() + i);
         T[1] = b->slot(s0, b->evalmod_in);
         Ct tmp;
-        for (uint32_t k = 2; k <= d; ++k) {
+        for (uint32_t k = 2; k <= b->nbaby; ++k) {
             const Ct buf = b->slot(b->s_t(k), 0);
+            Ct v;
             if (k % 2 == 0) {
-                TRY(mul(T[k / 2], T[k / 2], buf, T[k]));
-                TRY(scalar_mul(T[k], T[k], 2));
-                TRY(scalar_add(T[k], -1.0));
+                TRY(mul(T.at(k / 2), T.at(k / 2), buf, v));
+                TRY(scalar_mul(v, v, 2));
+                TRY(scalar_add(v, -1.0));
             } else {
-                TRY(mul(T[(k - 1) / 2], T[(k + 1) / 2], buf, T[k]));
-                TRY(scalar_mul(T[k], T[k], 2));
-                TRY(level_down(T[1], T[k].level, b->slot(b->s_d(2), 0), tmp));
-                TRY(add(T[k], tmp, T[k], true));
+                TRY(mul(T.at(k / 2), T.at(k / 2 + 1), buf, v));
+                TRY(scalar_mul(v, v, 2));
+                TRY(level_down(T.at(1), v.level, b->slot(b->s_d(2), 0), tmp));
+                TRY(add(v, tmp, v, true));
             }
+            T[k] = v;
         }
-        uint32_t lowest = T[1].level;
-        for (uint32_t k = 2; k <= d; ++k) lowest = std::min(lowest, T[k].level);
-        const uint32_t t = lowest - 1;
+        for (size_t j = 0; j < b->giants.size(); ++j) {
+            const uint32_t G = b->giants[j];
+            Ct v;
+            TRY(mul(T.at(G / 2), T.at(G / 2), b->slot(b->s_g((uint32_t)j), 0), v));
+            TRY(scalar_mul(v, v, 2));
+            TRY(scalar_add(v, -1.0));
+            T[G] = v;
+        }
         Ct acc;
-        TRY(mult_const_to(T[1], b->cheb[1], t, b->slot(s1, 0), acc));
-        for (uint32_t k = 2; k <= d; ++k) {
-            TRY(mult_const_to(T[k], b->cheb[k], t, b->slot(b->s_d(2), 0), tmp));
-            TRY(add(acc, tmp, acc));
-        }
-        TRY(scalar_add(acc, b->cheb[0]));
-        uint32_t cur = s1, other = s0;
+        uint32_t sa;
+        TRY(poly((int)b->nodes.size() - 1, acc, sa));
+        // double angles y <- 2 y^2 - 1, alternating between s1 and s0 (T_1 is no longer read)
+        uint32_t other = s1;
         for (uint32_t r = 0; r < b->double_angles; ++r) {
             Ct y;
             TRY(mul(acc, acc, b->slot(other, 0), y));
             TRY(scalar_mul(y, y, 2));
             TRY(scalar_add(y, -1.0));
             acc = y;
-            std::swap(cur, other);
+            other = other == s1 ? s0 : s1;
+        }
+        if (b->double_angles == 0) {  // the result must leave the shared pool
+            const Ct dst = b->slot(s1, acc.level);
+            const size_t bytes = (size_t)(acc.level + 1) * b->N * 8;
+            TRY(dev(hipMemcpyAsync(dst.c0, acc.c0, bytes, hipMemcpyDeviceToDevice, st), "ckks_bootstrap copy"));
+            TRY(dev(hipMemcpyAsync(dst.c1, acc.c1, bytes, hipMemcpyDeviceToDevice, st), "ckks_bootstrap copy"));
+            acc = dst;
         }
         out = acc;
         return CKKS_OK;
@@ -377,7 +494,9 @@ uint32_t keyswitches_of(const ckks_boot &b)
             ks += (uint32_t)g.baby_k.size();
             for (int32_t G : g.giant) ks += (((int64_t)G % b.n + b.n) % b.n) != 0;
         }
-    ks += 2 * (b.degree - 1 + b.double_angles);  // relinearisations of both halves
+    uint32_t products = 0;
+    for (const ChebNode &nd : b.nodes) products += !nd.leaf && nd.q >= 0;
+    ks += 2 * ((b.nbaby - 1) + (uint32_t)b.giants.size() + products + b.double_angles);  // both halves
     return ks;
 }
 
@@ -404,6 +523,10 @@ extern "C" ckks_status ckks_boot_create(ckks_ctx *ctx, const ckks_boot_desc *des
     b->n = n;
     b->N = N;
     b->degree = desc->cheb_degree;
+    if (b->degree < 2) {
+        delete b;
+        return fail(CKKS_E_ARG, "ckks_boot_create: cheb_degree must be at least 2");
+    }
     b->double_angles = desc->double_angles;
     b->cheb.assign(desc->cheb, desc->cheb + desc->cheb_degree + 1);
     b->relin = desc->relin;
@@ -427,13 +550,48 @@ extern "C" ckks_status ckks_boot_create(ckks_ctx *ctx, const ckks_boot_desc *des
     b->sc.assign(L + 1, 0.0);
     b->sc[L] = desc->top_scale;
     for (uint32_t l = L; l >= 1; --l) b->sc[l - 1] = (b->sc[l] * b->sc[l]) / (double)ctx->primes[l];
-    b->cheb_depth.assign(b->degree + 1, 0);
-    uint32_t depth = 0;
-    for (uint32_t k = 2; k <= b->degree; ++k) {
-        b->cheb_depth[k] = k % 2 == 0 ? b->cheb_depth[k / 2] + 1
-                                      : std::max(b->cheb_depth[(k - 1) / 2], b->cheb_depth[(k + 1) / 2]) + 1;
-        depth = std::max(depth, b->cheb_depth[k]);
+    // baby-step/giant-step plan: levels of T_k relative to the EvalMod input, then the node tree
+    b->baby = desc->cheb_baby;
+    if (b->baby == 0) {
+        b->baby = 2;
+        while (b->baby * b->baby <= b->degree) b->baby *= 2;
     }
+    if (b->baby < 2 || (b->baby & (b->baby - 1))) return bail(CKKS_E_ARG, "cheb_baby must be a power of two >= 2");
+    b->nbaby = std::min(b->baby, b->degree);
+    b->lvT[1] = 0;
+    for (uint32_t k = 2; k <= b->nbaby; ++k)
+        b->lvT[k] = k % 2 == 0 ? b->lvT[k / 2] - 1 : std::min(b->lvT[k / 2], b->lvT[k / 2 + 1]) - 1;
+    for (uint32_t G = b->baby; 2 * G <= b->degree; G *= 2) {
+        b->giants.push_back(2 * G);
+        b->lvT[2 * G] = b->lvT[G] - 1;
+    }
+    b->t_leaf = 0;
+    for (uint32_t k = 1; k <= std::min(b->baby - 1, b->degree); ++k) b->t_leaf = std::min(b->t_leaf, b->lvT[k]);
+    b->t_leaf -= 1;
+    std::function<int(const std::vector<double> &)> build = [&](const std::vector<double> &c) -> int {
+        const uint32_t D = (uint32_t)c.size() - 1;
+        ChebNode nd;
+        if (D < b->baby) {
+            nd.leaf = true;
+            nd.c = c;
+            nd.level = b->t_leaf;
+        } else {
+            uint32_t G = b->baby;
+            while (2 * G <= D) G *= 2;
+            std::vector<double> q, r;
+            cheb_split(c, G, q, r);
+            nd.G = G;
+            nd.r = build(r);
+            nd.q0 = q[0];
+            if (q.size() > 1) nd.q = build(q);
+            const int p = nd.q < 0 ? b->lvT[G] - 1 : std::min(b->nodes[nd.q].level, b->lvT[G]) - 1;
+            nd.level = std::min(p, b->nodes[nd.r].level);
+        }
+        b->nodes.push_back(nd);
+        return (int)b->nodes.size() - 1;
+    };
+    build(b->cheb);
+    const uint32_t depth = (uint32_t)(-b->nodes.back().level);
 
     // groups and levels
     uint32_t sum_c = 0, sum_s = 0;
@@ -458,7 +616,9 @@ extern "C" ckks_status ckks_boot_create(ckks_ctx *ctx, const ckks_boot_desc *des
         stage += r;
     }
     b->evalmod_in = (uint32_t)std::max<int64_t>(lvl, 0);
-    lvl -= depth + 1 + b->double_angles;
+    lvl -= depth + b->double_angles;
+    if ((int64_t)b->evalmod_in + b->t_leaf < 0 || lvl < 0)
+        return bail(CKKS_E_UNSUPPORTED, "the schedule needs more levels than the context has");
     stage = 0;
     for (uint32_t i = 0; i < desc->n_stc; ++i) {
         const uint32_t r = desc->stc_radix_logs[i];
@@ -491,7 +651,27 @@ extern "C" ckks_status ckks_boot_create(ckks_ctx *ctx, const ckks_boot_desc *des
     for (uint32_t op : {CKKS_OP_HMULT, CKKS_OP_ROTATE, CKKS_OP_HOISTED, CKKS_OP_RESCALE})
         wsb = std::max(wsb, ckks_workspace_bytes(ctx, op, L));
     wsb = std::max(wsb, 2 * (size_t)N * 8);
-    const size_t off_mono = up(pt_words * 8), off_slots = off_mono + up((size_t)(L + 1) * N * 8);
+    // leaf constants: for each leaf, C_k = round(c_k (D_t q_(t+1)) / D_level(T_k)) mod q_0..q_(t+1)
+    std::vector<uint64_t> cst;
+    {
+        const uint32_t t = (uint32_t)((int)b->evalmod_in + b->t_leaf);
+        for (ChebNode &nd : b->nodes) {
+            if (!nd.leaf) continue;
+            nd.cst = cst.size();
+            for (uint32_t k = 1; k < nd.c.size(); ++k) {
+                const double X = (b->sc[t] * (double)ctx->primes[t + 1]) / b->sc[b->evalmod_in + b->lvT[k]];
+                const int64_t C = (int64_t)round_half_away(nd.c[k] * X);
+                for (uint32_t i = 0; i <= t + 1; ++i) {
+                    const int64_t qi = (int64_t)ctx->primes[i];
+                    const int64_t m = C % qi;
+                    cst.push_back((uint64_t)(m < 0 ? m + qi : m));
+                }
+            }
+        }
+    }
+    const size_t off_cst = up(pt_words * 8);
+    const size_t off_mono = off_cst + up(std::max<size_t>(cst.size(), 1) * 8),
+                 off_slots = off_mono + up((size_t)(L + 1) * N * 8);
     const size_t off_ws = off_slots + up(b->nslots * b->slot_words * 8);
     b->bytes = off_ws + up(wsb);
     if (hipSetDevice(ctx->device) != hipSuccess || hipMalloc(&b->dev, b->bytes) != hipSuccess) {
@@ -500,6 +680,7 @@ extern "C" ckks_status ckks_boot_create(ckks_ctx *ctx, const ckks_boot_desc *des
     }
     uint8_t *base = (uint8_t *)b->dev;
     b->mono = (uint64_t *)(base + off_mono);
+    b->leaf_cst = (uint64_t *)(base + off_cst);
     b->slots = (uint64_t *)(base + off_slots);
     b->ws = base + off_ws;
 
@@ -547,6 +728,8 @@ extern "C" ckks_status ckks_boot_create(ckks_ctx *ctx, const ckks_boot_desc *des
         }
     }
     (void)hipFree(stage_buf);
+    if (e == hipSuccess && !cst.empty())
+        e = hipMemcpy(b->leaf_cst, cst.data(), cst.size() * 8, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = launch_half_monomial(b->mono, L + 1, logn, 0);
     if (e == hipSuccess) {
         NttArgs a = base_args(ctx, false);

@@ -199,10 +199,12 @@ extern "C" ckks_status ckks_ctx_create(uint32_t log_n, const uint64_t *q, uint32
         }
     build_set(ctx->pset_index(), &primes[n_q], n_p);
     std::vector<ulonglong2> pinv(np_all);
+    std::vector<uint64_t> pmod(np_all, 0);
     for (uint32_t i = 0; i < np_all; ++i) {
         uint64_t P = 1;
         for (uint32_t k = 0; k < n_p; ++k) P = mul_mod(P, p[k] % primes[i], primes[i]);
         pinv[i] = i < n_q ? pair(inv_mod(P, primes[i]), primes[i]) : pair(0, primes[i]);
+        pmod[i] = i < n_q ? P : 0;
     }
     std::vector<ulonglong2> rs_inv((size_t)n_q * n_q);
     std::vector<uint64_t> rs_mod((size_t)n_q * n_q, 0);
@@ -226,7 +228,8 @@ extern "C" ckks_status ckks_ctx_create(uint32_t log_n, const uint64_t *q, uint32
     size_t off_pinv = align_up(off_ysd + bc_ysd.size() * sizeof(double));
     size_t off_rsi = align_up(off_pinv + pinv.size() * sizeof(ulonglong2));
     size_t off_rsm = align_up(off_rsi + rs_inv.size() * sizeof(ulonglong2));
-    size_t total = align_up(off_rsm + rs_mod.size() * sizeof(uint64_t));
+    size_t off_pmod = align_up(off_rsm + rs_mod.size() * sizeof(uint64_t));
+    size_t total = align_up(off_pmod + pmod.size() * sizeof(uint64_t));
     char *blk = nullptr;
     if (hipMalloc((void **)&blk, total) != hipSuccess) {
         delete ctx;
@@ -245,6 +248,7 @@ extern "C" ckks_status ckks_ctx_create(uint32_t log_n, const uint64_t *q, uint32
     ctx->d_pinv = (ulonglong2 *)(blk + off_pinv);
     ctx->d_rs_inv = (ulonglong2 *)(blk + off_rsi);
     ctx->d_rs_mod = (uint64_t *)(blk + off_rsm);
+    ctx->d_pmod = (uint64_t *)(blk + off_pmod);
     bool ok = hipMemcpy(ctx->d_primes, hp.data(), hp.size() * sizeof(Prime), hipMemcpyHostToDevice) == hipSuccess &&
               hipMemcpy(ctx->d_tw_fwd, tw_f.data(), tw_f.size() * sizeof(ulonglong2), hipMemcpyHostToDevice) ==
                   hipSuccess &&
@@ -267,7 +271,8 @@ extern "C" ckks_status ckks_ctx_create(uint32_t log_n, const uint64_t *q, uint32
               hipMemcpy(ctx->d_rs_inv, rs_inv.data(), rs_inv.size() * sizeof(ulonglong2), hipMemcpyHostToDevice) ==
                   hipSuccess &&
               hipMemcpy(ctx->d_rs_mod, rs_mod.data(), rs_mod.size() * sizeof(uint64_t), hipMemcpyHostToDevice) ==
-                  hipSuccess;
+                  hipSuccess &&
+              hipMemcpy(ctx->d_pmod, pmod.data(), pmod.size() * sizeof(uint64_t), hipMemcpyHostToDevice) == hipSuccess;
     if (!ok) {
         (void)hipFree(blk);
         delete ctx;

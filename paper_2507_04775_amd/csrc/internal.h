@@ -99,6 +99,9 @@ struct NttArgs {
     int64_t bc_poly_stride;
     uint32_t bc_mode;
     const uint64_t *hmod;       // [nsets][n_primes][kMaxDigitPrimes]
+    // bc_mode 2 converts with centred inputs y_k in [-(p_k-1)/2, (p_k-1)/2]: every y_k above
+    // (p_k-1)/2 subtracts [P]_q once, read from pmod[prime]
+    const uint64_t *pmod;
 };
 
 // A unit of work of a persistent stage kernel is one tile of limb `limb` of
@@ -209,6 +212,18 @@ struct LincombArgs {
     uint32_t n, logn;
 };
 
+// out_t = acc_t + sum_b a_t[b] * c[b][limb] with per-limb scalar residues
+// c[b][limb] = cst[b * cst_stride + limb] (integer combination of ciphertexts).
+struct ScalarLincombArgs {
+    const uint64_t *a0[kMaxLincomb], *a1[kMaxLincomb];
+    const uint64_t *cst;
+    uint32_t cst_stride;
+    const uint64_t *acc0, *acc1;  // may be null; may equal out
+    uint64_t *out0, *out1;
+    const Prime *primes;
+    uint32_t n, logn;
+};
+
 // Launchers (all asynchronous on `stream`).
 hipError_t launch_ntt_fwd(const NttArgs &a, uint32_t nlimbs, NttPro pro, NttEpi epi, hipStream_t stream,
                           uint64_t *mid, int64_t mid_poly_stride);
@@ -235,6 +250,7 @@ hipError_t launch_elementwise(int op, const uint64_t *a, const uint64_t *b, cons
 hipError_t launch_automorph(const uint64_t *in, uint64_t *out, uint32_t nlimbs, uint32_t logn, uint32_t galois,
                             hipStream_t stream);
 hipError_t launch_lincomb(const LincombArgs &a, uint32_t nlimbs, hipStream_t stream);
+hipError_t launch_scalar_lincomb(const ScalarLincombArgs &a, uint32_t nlimbs, hipStream_t stream);
 // x: [ndiag][N] integer-valued doubles -> out: [ndiag][nlimbs][N] residues modulo primes 0..nlimbs-1
 hipError_t launch_reduce_f64(const double *x, uint64_t *out, const Prime *primes, uint32_t ndiag, uint32_t nlimbs,
                              uint32_t logn, hipStream_t stream);
@@ -260,6 +276,7 @@ struct ckks_ctx {
     ulonglong2 *d_bc_ys = nullptr;      // [nsets][kMaxDigitPrimes]: N^-1 [(B/b_i)^-1]_{b_i}
     double *d_bc_ysd = nullptr;         // the same as doubles (primes below 2^50)
     ulonglong2 *d_pinv = nullptr;       // [n_primes] P^-1 mod q_i
+    uint64_t *d_pmod = nullptr;         // [n_primes] P mod q_i (0 on the special primes)
     ulonglong2 *d_rs_inv = nullptr;     // [nq][nq]: (level l, prime i) -> q_l^-1 mod q_i
     uint64_t *d_rs_mod = nullptr;       // [nq][nq]: q_l mod q_i
     uint32_t nsets = 0;

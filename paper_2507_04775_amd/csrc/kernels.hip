@@ -231,6 +231,23 @@ __global__ __launch_bounds__(kThreads) void k_lincomb(LincombArgs a)
     a.out1[i] = reduce128(s1, P);
 }
 
+// out_t = acc_t + sum_b a_t[b] c_b (c_b a residue per limb), summed exactly in
+// 128 bits and reduced once; acc may be the output itself (read first).
+__global__ __launch_bounds__(kThreads) void k_scalar_lincomb(ScalarLincombArgs a)
+{
+    const uint32_t l = blockIdx.y;
+    const size_t i = ((size_t)l << a.logn) + blockIdx.x * kThreads + threadIdx.x;
+    const Prime P = a.primes[l];
+    u128 s0 = {a.acc0 ? a.acc0[i] : 0, 0}, s1 = {a.acc1 ? a.acc1[i] : 0, 0};
+    for (uint32_t b = 0; b < a.n; ++b) {
+        const uint64_t w = a.cst[(size_t)b * a.cst_stride + l];
+        s0 = add128(s0, mul_wide(a.a0[b][i], w));
+        s1 = add128(s1, mul_wide(a.a1[b][i], w));
+    }
+    a.out0[i] = reduce128(s0, P);
+    a.out1[i] = reduce128(s1, P);
+}
+
 __device__ uint64_t pow2_mod(uint32_t e, const Prime &P)
 {
     uint64_t r = 1, b = 2 % P.q;
@@ -274,6 +291,13 @@ hipError_t launch_lincomb(const LincombArgs &a, uint32_t nlimbs, hipStream_t str
 {
     if (a.n == 0 || a.n > kMaxLincomb) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_lincomb, dim3((1u << a.logn) / kThreads, nlimbs), dim3(kThreads), 0, stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_scalar_lincomb(const ScalarLincombArgs &a, uint32_t nlimbs, hipStream_t stream)
+{
+    if (a.n == 0 || a.n > kMaxLincomb || nlimbs > a.cst_stride) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_scalar_lincomb, dim3((1u << a.logn) / kThreads, nlimbs), dim3(kThreads), 0, stream, a);
     return hipGetLastError();
 }
 

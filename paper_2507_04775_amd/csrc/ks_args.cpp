@@ -178,6 +178,7 @@ NttArgs args_moddown_ntt(const ckks_ctx *c, const uint64_t *acc, int64_t acc_str
     a.pset = c->pset_index();
     a.nprimes = c->nq + c->np;
     a.hmod = c->d_bc_hmod;
+    a.pmod = c->d_pmod;
     for (uint32_t t = 0; t < npoly; ++t) {
         a.aux[t] = acc + t * acc_stride;
         a.add[t] = add ? add[t] : nullptr;

@@ -276,6 +276,8 @@ struct BcSrc {
     const uint64_t *y;   // ns scaled source rows, stride N
     const uint64_t *hm;  // [B/b_i] mod the target prime, i < ns
     uint32_t ns;
+    const Prime *src;    // centred conversion (ModDown): the source primes, else null
+    uint64_t bq;         // [B]_q of the target prime (centred conversion)
 };
 
 __device__ __forceinline__ BcSrc bc_source(const NttArgs &a, uint32_t poly, uint32_t prime, size_t N)
@@ -287,10 +289,14 @@ __device__ __forceinline__ BcSrc bc_source(const NttArgs &a, uint32_t poly, uint
         b.ns = min(a.alpha, a.nlev - lo);
         set = poly * a.alpha + b.ns - 1;
         b.y = a.bc_src + (size_t)lo * N;
+        b.src = nullptr;
+        b.bq = 0;
     } else {
         b.ns = a.nprimes - a.map.nq;
         set = a.pset;
         b.y = a.bc_src + (int64_t)poly * a.bc_poly_stride;
+        b.src = a.primes + a.map.nq;
+        b.bq = a.pmod[prime];
     }
     b.hm = a.hmod + ((size_t)set * a.nprimes + prime) * kMaxDigitPrimes;
     return b;
@@ -305,16 +311,29 @@ __device__ __forceinline__ void bconv_load16(typename A::V (&v)[16], const A &ar
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
         u128 acc[8];
+        uint32_t high[8];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) acc[i] = u128{0, 0};
+        for (int i = 0; i < 8; ++i) {
+            acc[i] = u128{0, 0};
+            high[i] = 0;
+        }
         for (uint32_t k = 0; k < b.ns; ++k) {
             const uint64_t h = b.hm[k];
             const uint64_t *yk = b.y + (size_t)k * N;
+            const uint64_t half_k = b.src ? (b.src[k].q - 1) >> 1 : ~0ull;
 #pragma unroll
-            for (int i = 0; i < 8; ++i) acc[i] = add128(acc[i], mul_wide(yk[pos(8 * half + i)], h));
+            for (int i = 0; i < 8; ++i) {
+                const uint64_t y = yk[pos(8 * half + i)];
+                acc[i] = add128(acc[i], mul_wide(y, h));
+                high[i] += y > half_k;
+            }
         }
 #pragma unroll
-        for (int i = 0; i < 8; ++i) v[8 * half + i] = ar.from_u64(reduce128(acc[i], P));
+        for (int i = 0; i < 8; ++i) {
+            uint64_t r = reduce128(acc[i], P);
+            if (b.src) r = submod(r, mulmod(high[i], b.bq, P), P.q);  // y_k - p_k for the high inputs
+            v[8 * half + i] = ar.from_u64(r);
+        }
     }
 }
 

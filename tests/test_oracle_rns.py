@@ -87,8 +87,10 @@ def _moddown_case(ps, level, seed):
     return P, rows, x, out
 
 
-@pytest.mark.parametrize("name,level", [("tiny", 3), ("tiny", 0), ("small", 2)])
-def test_moddown_is_floor_division_up_to_conversion_error(name, level):
+@pytest.mark.parametrize("name,level", [("tiny", 3), ("tiny", 0), ("small", 2), ("small-nv", 1)])
+def test_moddown_is_centred_division(name, level):
+    """out = (X - v) / P exactly, with v = X mod P and |v| < K P / 2 (X the
+    integer the rows represent); for K = 1 that is X / P rounded."""
     ps = inputs.params(name)
     P, rows, x, out = _moddown_case(ps, level, 31 + level)
     xc = oracle.intt(rows, x, ps.logn)
@@ -99,8 +101,33 @@ def test_moddown_is_floor_division_up_to_conversion_error(name, level):
     for n in coeffs:
         A = _crt(xc[:, n], rows)
         o = _crt(oc[:, n], ps.q[: level + 1])
-        u = (A // Pp - o) % Ql
-        assert 0 <= u < ps.K
+        v = (A - o * Pp) % (Ql * Pp)
+        if v > Ql * Pp // 2:
+            v -= Ql * Pp
+        assert 2 * abs(v) < ps.K * Pp
+        if ps.K == 1:
+            assert 2 * abs(v) < Pp
+
+
+@pytest.mark.parametrize("name", ["small", "small-nv"])
+def test_moddown_error_has_zero_mean(name):
+    """The rounding error v / P of ModDown averages to zero over a polynomial
+    (a canonical conversion would average about -K/2)."""
+    ps = inputs.params(name)
+    level = 2
+    P, rows, x, out = _moddown_case(ps, level, 77)
+    xc = oracle.intt(rows, x, ps.logn)
+    oc = oracle.intt(ps.q[: level + 1], out, ps.logn)
+    Pp, Ql = _prod(ps.p), _prod(ps.q[: level + 1])
+    errs = []
+    for n in range(0, ps.N, 4):
+        A = _crt(xc[:, n], rows)
+        o = _crt(oc[:, n], ps.q[: level + 1])
+        v = (A - o * Pp) % (Ql * Pp)
+        if v > Ql * Pp // 2:
+            v -= Ql * Pp
+        errs.append(v / Pp)
+    assert abs(np.mean(errs)) < 0.05 * ps.K
 
 
 @pytest.mark.parametrize("name,level", [("tiny", 3), ("small", 3), ("small", 0)])
