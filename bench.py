@@ -40,6 +40,9 @@ def parse():
     ap.add_argument("--batch-items", type=int, default=128)
     ap.add_argument("--batch-reps", type=int, default=5)
     ap.add_argument("--no-boot", action="store_true")
+    ap.add_argument("--no-uniform-boot", action="store_true", help="skip the uniform-secret bootstrap variant")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain 256 MiB device copy (the reference kernel for HBM counter scaling)")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=48)
     ap.add_argument("--serve-slots", type=int, default=8)
@@ -144,11 +147,14 @@ def run_batch(ctx, ps, seed, args):
     return res
 
 
-def run_bootstrap(seed, args):
+def run_bootstrap(seed, args, sparse=True):
     """Full-slot bootstrap at N = 2^16 (L = 30, dnum = 3, ten special primes so
     that key switching keeps the message): keys and plaintexts made by the
     client helpers, one eager bootstrap per step and the captured HIP graph
-    replayed; the decrypted error against the input slots is reported."""
+    replayed; the decrypted error against the input slots is reported.  With
+    `sparse`, the input is encapsulated under a sparse secret around ModRaise
+    (degree 31, 3 double angles); without, EvalMod covers the uniform secret's
+    range (degree 119, 6 double angles)."""
     import numpy as np
     import torch
 
@@ -158,7 +164,7 @@ def run_bootstrap(seed, args):
     ps = inputs.params("large-nv")
     ctx = ckks.Context(ps.logn, ps.q, ps.p, ps.dnum, device=0)
     scale = 2.0 ** ps.log_scale
-    cfg = bootplan.default_config(ps.logn, scale)
+    cfg = bootplan.default_config(ps.logn, scale, sparse=sparse)
     t0 = time.perf_counter()
     pl = bootplan.plan(ps.q, cfg)
     t_plan = time.perf_counter() - t0
@@ -166,10 +172,11 @@ def run_bootstrap(seed, args):
     t0 = time.perf_counter()
     rot = {k: cl.rotation_key(k) for k in pl.rotations}
     relin, conj = cl.relin_key(), cl.conjugation_key()
+    sp = cl.sparse_keys(bootplan.SPARSE_H) if sparse else None
     torch.cuda.synchronize()
     t_keys = time.perf_counter() - t0
     boot = ckks.Boot(ctx, cfg.cts_radix_logs, cfg.stc_radix_logs, pl.cts, pl.stc, pl.cheb, cfg.double_angles,
-                     cfg.top_scale, relin, conj, rot)
+                     cfg.top_scale, relin, conj, rot, sparse=sp)
     z = inputs.complex_slots(inputs.rng(seed + 5), ps.N // 2)
     ct = cl.encrypt(z, 0, scale)
     out = ctx.empty_ct(boot.output_level)
@@ -207,10 +214,11 @@ def run_bootstrap(seed, args):
            "rotation_keys": len(rot), "plan_s": round(t_plan, 2), "keygen_s": round(t_keys, 2),
            "config": {"logN": ps.logn, "limbs": ps.L + 1, "special_primes": ps.K, "dnum": ps.dnum,
                       "cts_groups": cfg.cts_radix_logs, "stc_groups": cfg.stc_radix_logs,
-                      "cheb_degree": cfg.cheb_degree, "double_angles": cfg.double_angles, "k_range": cfg.k_range,
-                      "scale_log2": ps.log_scale}}
+                      "cheb_degree": cfg.cheb_degree, "cheb_baby": cfg.baby, "double_angles": cfg.double_angles,
+                      "k_range": cfg.k_range, "sparse_secret_encapsulation": sparse,
+                      "sparse_h": bootplan.SPARSE_H if sparse else None, "scale_log2": ps.log_scale}}
     boot.close()
-    del rot, relin, conj
+    del rot, relin, conj, sp
     ctx.close()
     return res
 
@@ -238,7 +246,8 @@ def run_serving(ctx, ps, seed, args):
     pl = bootplan.plan(ps.q, cfg)
     bkeys = {k: rkey(seed + 5000 + k, pow(5, k, 2 * ps.N)) for k in pl.rotations}
     boot = ckks.Boot(ctx, cfg.cts_radix_logs, cfg.stc_radix_logs, pl.cts, pl.stc, pl.cheb, cfg.double_angles,
-                     cfg.top_scale, relin, rkey(seed + 2, 2 * ps.N - 1), bkeys)
+                     cfg.top_scale, relin, rkey(seed + 2, 2 * ps.N - 1), bkeys,
+                     sparse=(rkey(seed + 3, 0), rkey(seed + 4, 0)))
     srv = Server(ctx, relin, rot, pts, boot, slots=args.serve_slots, mem_budget=args.serve_mem_gib << 30)
     n = args.serve_requests
     gen = lambda rate, sd: inputs.serving_requests(sd, n, ps.logn, rate)
@@ -378,6 +387,14 @@ def main():
     ops["ntt_35_limbs"] = op_stats(lambda s: ctx.ckks_ntt(ntt_poly), reps)
     ops["intt_35_limbs"] = op_stats(lambda s: ctx.ckks_intt(ntt_poly), reps)
 
+    if args.copy_calibration:
+        src = torch.empty(32 << 20, dtype=torch.int64, device="cuda").fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     # ---- dominant kernel: the forward NTT over all 35 limbs (two passes, 16 x 35 workgroups each),
     # timed on the library's stream; algorithmic bytes = read + write of every limb once.
     ntt_ms = ops["ntt_35_limbs"]["mean_us"] / 1e3
@@ -394,9 +411,11 @@ def main():
         batched = run_batch(ctx, ps, seed, args)
 
     # ---- full-slot bootstrapping (its own context: ten special primes)
-    boot = None
+    boot = boot_dense = None
     if not args.no_boot:
-        boot = run_bootstrap(seed + 500, args)
+        boot = run_bootstrap(seed + 500, args, sparse=True)
+        if not args.no_uniform_boot:
+            boot_dense = run_bootstrap(seed + 600, args, sparse=False)
 
     # ---- served request chains with continuous batching
     serving = None
@@ -448,6 +467,7 @@ def main():
         "cold": cold,
         "batched": batched,
         "bootstrap": boot,
+        "bootstrap_uniform_secret": boot_dense,
         "serving": serving,
         "ops": ops,
         "roofline": roofline,

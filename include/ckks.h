@@ -286,7 +286,10 @@ void ckks_batch_destroy(ckks_batch *batch);
  *
  * Schedule, derived by the library from the descriptor:
  * - ModRaise: the level-0 input's coefficients are lifted centred from q_0 to
- *   q_0..q_L (L = n_q - 1) and returned to the evaluation domain.
+ *   q_0..q_L (L = n_q - 1) and returned to the evaluation domain.  With
+ *   sparse-secret encapsulation (to_sparse and from_sparse set), the input is
+ *   first key-switched at level 0 with to_sparse (s -> a sparse s'), and the
+ *   raised ciphertext is key-switched back at level L with from_sparse.
  * - CoeffToSlot: the inverse special-FFT stages (butterflies pairing slots x
  *   and x + h, half-sizes n/2 down to 1, n = N/2) are merged into groups of
  *   cts_radix_logs[g] stages in that order; SlotToCoeff merges the forward
@@ -349,6 +352,7 @@ typedef struct {
     uint32_t double_angles;
     double top_scale;                    /* scale of level L */
     const ckks_key *relin, *conj;
+    const ckks_key *to_sparse, *from_sparse;  /* both null, or switching keys s -> s' and s' -> s */
     uint32_t n_rot;
     const int32_t *rot_steps;
     const ckks_key *const *rot_keys;

@@ -14,7 +14,11 @@ constants, so the two results are compared bit for bit.
 Schedule (n = N/2 slots, full packing):
 
 1. ModRaise: the level-0 ciphertext's coefficients are lifted centred from
-   q_0 to every prime of the top level L.
+   q_0 to every prime of the top level L.  With sparse-secret encapsulation
+   (optional), the ciphertext is first switched to a sparse secret s' (h
+   nonzero coefficients), so that t = c0 + c1 s' stays within a small
+   multiple K of q_0, and switched back to s right after ModRaise (the
+   encapsulation of Bossuat, Troncoso-Pastoriza and Hubaux, ACNS 2022).
 2. CoeffToSlot: the stages of the special FFT (the iterative transform whose
    butterfly at half-size h pairs slots x and x + h with the twiddle
    zeta^((5^j mod 8h) * 2N / 8h)) are merged into groups and inverted, the
@@ -63,7 +67,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from . import apply_galois, galois_conjugate, galois_for_rotation, hmult_relin, hoisted_rotate
-from . import Params, intt, ntt, reduce_f64, rescale, vec
+from . import Params, intt, keyswitch, ntt, reduce_f64, rescale, vec
 from .client import embed_inverse
 
 
@@ -329,12 +333,14 @@ def plan(P: Params, bp: BootParams) -> BootPlan:
 class Executor:
     """Runs the schedule with the oracle's primitives on ciphertexts (c0, c1, level)."""
 
-    def __init__(self, P: Params, pl: BootPlan, relin_key, conj_key, rot_keys: dict):
+    def __init__(self, P: Params, pl: BootPlan, relin_key, conj_key, rot_keys: dict, to_sparse=None,
+                 from_sparse=None):
         self.P, self.bp, self.pl = P, pl.params, pl
         self.q = [int(x) for x in P.q]
         self.L = P.nq - 1
         self.sc = level_scales(self.q, self.L, self.bp.top_scale)
         self.rlk, self.ck, self.rk = relin_key, conj_key, rot_keys
+        self.to_sparse, self.from_sparse = to_sparse, from_sparse
 
     # -- elementary steps
     def mods(self, l):
@@ -392,6 +398,12 @@ class Executor:
             e[i, k % N] = 1 if k < N else m - 1
         E = ntt(self.mods(l), e, self.P.logn)
         return (vec(self.mods(l), c0, E, "mul", self.P.logn), vec(self.mods(l), c1, E, "mul", self.P.logn), l)
+
+    def switch(self, ct, key):
+        """Key switching of (c0, c1) with a switching key: (c0 + k0, k1)."""
+        c0, c1, l = ct
+        k0, k1 = keyswitch(self.P, c1, key, l)
+        return (vec(self.mods(l), c0, k0, "add", self.P.logn), k1, l)
 
     def conj(self, ct):
         o0, o1 = apply_galois(self.P, (ct[0], ct[1]), galois_conjugate(self.P.logn), self.ck, ct[2])
@@ -519,7 +531,12 @@ class Executor:
 
     def bootstrap(self, ct):
         N = 1 << self.bp.logn
-        ct = self.coeff_to_slot(self.modraise(ct))
+        if self.to_sparse is not None:
+            ct = self.switch(ct, self.to_sparse)
+        ct = self.modraise(ct)
+        if self.from_sparse is not None:
+            ct = self.switch(ct, self.from_sparse)
+        ct = self.coeff_to_slot(ct)
         cj = self.conj(ct)
         re = self.add(ct, cj)
         im = self.monomial(self.add(ct, cj, "sub"), 3 * N // 2)

@@ -59,16 +59,22 @@ class BootConfig:
 
 
 # The schedule used for the full-slot workloads: three merged groups each way.
-def default_config(logn: int, scale: float) -> BootConfig:
-    """Stages split as evenly as possible over three groups; at N = 2^16 a
-    degree-119 Chebyshev interpolant over K = 512 with 6 double angles, at
-    smaller N degree 63 over K = 128 with 5 (K bounds |t_k / q_0| for a
-    uniform ternary secret)."""
+def default_config(logn: int, scale: float, sparse: bool = True) -> BootConfig:
+    """Stages split as evenly as possible over three groups.  With sparse-secret
+    encapsulation (h = 32, so |t_k / q_0| stays below K = 12) a degree-31
+    interpolant with 3 double angles; for the uniform ternary secret itself a
+    degree-119 interpolant over K = 512 with 6 double angles at N = 2^16, or
+    degree 63 over K = 128 with 5 at smaller N."""
     s = logn - 1
     parts = [s // 3 + (1 if i < s % 3 else 0) for i in range(3)]
+    if sparse:
+        return BootConfig(logn, parts, parts[::-1], 31, 3, 12.0, scale, scale)
     if logn >= 16:
         return BootConfig(logn, parts, parts[::-1], 119, 6, 512.0, scale, scale)
     return BootConfig(logn, parts, parts[::-1], 63, 5, 128.0, scale, scale)
+
+
+SPARSE_H = 32  # nonzero coefficients of the encapsulation secret
 
 
 def _scales(q, top: float) -> list:

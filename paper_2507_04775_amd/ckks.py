@@ -45,6 +45,7 @@ class _BootDesc(ctypes.Structure):
                 ("stc_radix_logs", ctypes.POINTER(_u32)), ("cts_diags", ctypes.POINTER(_vp)),
                 ("stc_diags", ctypes.POINTER(_vp)), ("cheb_degree", _u32), ("cheb", ctypes.POINTER(ctypes.c_double)),
                 ("cheb_baby", _u32), ("double_angles", _u32), ("top_scale", ctypes.c_double), ("relin", _vp), ("conj", _vp),
+                ("to_sparse", _vp), ("from_sparse", _vp),
                 ("n_rot", _u32), ("rot_steps", ctypes.POINTER(_i32)), ("rot_keys", ctypes.POINTER(_vp))]
 
 
@@ -426,10 +427,12 @@ class Boot:
     keys are passed in."""
 
     def __init__(self, ctx: "Context", cts_radix_logs, stc_radix_logs, cts_diags, stc_diags, cheb,
-                 double_angles: int, top_scale: float, relin: Key, conj: Key, rot_keys: dict, cheb_baby: int = 0):
+                 double_angles: int, top_scale: float, relin: Key, conj: Key, rot_keys: dict, cheb_baby: int = 0,
+                 sparse: Optional[tuple] = None):
         import numpy as np
         self.ctx = ctx
         self._keys = [relin, conj] + list(rot_keys.values())
+        # (to_sparse, from_sparse): switching keys s -> s' and s' -> s for sparse-secret encapsulation
         d = _BootDesc()
         d.n_cts, d.n_stc = len(cts_radix_logs), len(stc_radix_logs)
         cr = (_u32 * d.n_cts)(*cts_radix_logs)
@@ -448,6 +451,9 @@ class Boot:
         d.cheb_baby = cheb_baby
         d.top_scale = top_scale
         d.relin, d.conj = relin.handle, conj.handle
+        if sparse is not None:
+            d.to_sparse, d.from_sparse = sparse[0].handle, sparse[1].handle
+            self._keys += list(sparse)
         d.n_rot, d.rot_steps, d.rot_keys = len(steps), rs, rk
         h = _vp()
         _check(_lib.ckks_boot_create(ctx.handle, ctypes.byref(d), ctypes.byref(h)), "ckks_boot_create")

@@ -120,8 +120,10 @@ class Client:
         return self.decode(m, l, ct.scale)
 
     # -- evaluation keys
-    def switch_key(self, s_prime: torch.Tensor, galois: int) -> ckks.Key:
+    def switch_key(self, s_prime: torch.Tensor, galois: int, target: torch.Tensor | None = None) -> ckks.Key:
+        """Key switching s' to `target` (the secret key by default)."""
         ps, R, N = self.ps, self.rows, self.N
+        target = self.s if target is None else target
         nq = len(ps.q)
         alpha = -(-nq // ps.dnum)
         key = torch.empty((ps.dnum, 2, R, N), dtype=torch.uint64, device=self.ctx.device)
@@ -129,7 +131,7 @@ class Client:
         for j in range(ps.dnum):
             a = self._uniform(R)
             b = self._error(R)
-            self.ctx.ckks_poly_mul(a, self.s, t, R - 1)
+            self.ctx.ckks_poly_mul(a, target, t, R - 1)
             self.ctx.ckks_poly_sub(b, t, b, R - 1)
             sc = [self.P_mod_q[i] if j * alpha <= i < min((j + 1) * alpha, nq) else 0 for i in range(R)]
             self.ctx.ckks_poly_scalar_mul(s_prime, sc, t, R - 1)
@@ -153,3 +155,9 @@ class Client:
 
     def conjugation_key(self) -> ckks.Key:
         return self.galois_key(2 * self.N - 1)
+
+    def sparse_keys(self, h: int) -> tuple:
+        """Switching keys s -> s' and s' -> s for a fresh sparse secret s' with h
+        nonzero coefficients (the encapsulation used by bootstrapping)."""
+        sp = self._small(inputs.sparse_ternary(self.g, self.N, h), self.rows)
+        return self.switch_key(self.s, 0, target=sp), self.switch_key(sp, 0)

@@ -130,7 +130,7 @@ struct ckks_boot {
     int t_leaf = 0;
     std::vector<ChebNode> nodes;
     uint64_t *leaf_cst = nullptr;
-    const ckks_key *relin = nullptr, *conj = nullptr;
+    const ckks_key *relin = nullptr, *conj = nullptr, *to_sparse = nullptr, *from_sparse = nullptr;
     std::map<uint32_t, const ckks_key *> rot;  // slot rotation mod n -> key
     void *dev = nullptr;
     size_t bytes = 0;
@@ -452,10 +452,29 @@ struct Runner {
                    "ckks_bootstrap modraise");
     }
 
+    // (c0, c1) -> (c0 + k0, k1), (k0, k1) = KeySwitch(c1, key); the result's c1 lives in tmp
+    ckks_status switch_key(const Ct &c, const ckks_key *key, const Ct &tmp, Ct &out)
+    {
+        TRY(ckks_keyswitch(ctx(), c.c1, c.level, key, tmp.c0, tmp.c1, b->ws, st));
+        TRY(ckks_poly_add(ctx(), c.c0, tmp.c0, c.c0, c.level, st));
+        out = Ct{c.c0, tmp.c1, c.level};
+        return CKKS_OK;
+    }
+
     ckks_status run(const ckks_ct &in, const ckks_ct &out)
     {
         Ct x = b->slot(b->s_x(), b->L);
-        TRY(modraise(in, x));
+        if (b->to_sparse) {  // encapsulation: switch the input to the sparse secret first
+            const Ct c = b->slot(b->s_re(0), 0), tmp = b->slot(b->s_cj(), 0);
+            const size_t bytes = b->N * 8;
+            TRY(dev(hipMemcpyAsync(c.c0, in.c0, bytes, hipMemcpyDeviceToDevice, st), "ckks_bootstrap copy"));
+            Ct sp;
+            TRY(switch_key(Ct{c.c0, in.c1, 0}, b->to_sparse, tmp, sp));
+            TRY(modraise(ckks_ct{sp.c0, sp.c1, 0, 1.0}, x));
+            TRY(switch_key(x, b->from_sparse, b->slot(b->s_cj(), b->L), x));
+        } else {
+            TRY(modraise(in, x));
+        }
         uint32_t ai = 0;
         for (const Group &g : b->cts) {
             TRY(linear_transform(g, x, b->s_acc(ai), nullptr, x));
@@ -488,7 +507,7 @@ struct Runner {
 
 uint32_t keyswitches_of(const ckks_boot &b)
 {
-    uint32_t ks = 1;  // conjugation
+    uint32_t ks = 1 + (b.to_sparse ? 2 : 0);  // conjugation, encapsulation
     for (const auto *gs : {&b.cts, &b.stc})
         for (const Group &g : *gs) {
             ks += (uint32_t)g.baby_k.size();
@@ -531,6 +550,13 @@ extern "C" ckks_status ckks_boot_create(ckks_ctx *ctx, const ckks_boot_desc *des
     b->cheb.assign(desc->cheb, desc->cheb + desc->cheb_degree + 1);
     b->relin = desc->relin;
     b->conj = desc->conj;
+    if ((desc->to_sparse == nullptr) != (desc->from_sparse == nullptr) ||
+        (desc->to_sparse && (desc->to_sparse->ctx != ctx || desc->from_sparse->ctx != ctx))) {
+        delete b;
+        return fail(CKKS_E_KEY, "ckks_boot_create: sparse-secret keys must be given together");
+    }
+    b->to_sparse = desc->to_sparse;
+    b->from_sparse = desc->from_sparse;
     auto bail = [&](ckks_status s, const std::string &m) {
         ckks_boot_destroy(b);
         return fail(s, "ckks_boot_create: " + m);

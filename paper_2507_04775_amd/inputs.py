@@ -179,6 +179,14 @@ def ternary(g: np.random.Generator, N: int) -> np.ndarray:
     return g.integers(-1, 2, size=N).astype(np.int64)
 
 
+def sparse_ternary(g: np.random.Generator, N: int, h: int) -> np.ndarray:
+    """h coefficients +-1 (uniform signs) at uniformly chosen positions, the rest 0."""
+    out = np.zeros(N, dtype=np.int64)
+    pos = g.choice(N, size=h, replace=False)
+    out[pos] = 2 * g.integers(0, 2, size=h) - 1
+    return out
+
+
 def gaussian(g: np.random.Generator, N: int, sigma: float = 3.2) -> np.ndarray:
     """Rounded Gaussian errors, truncated at 6 sigma."""
     e = np.rint(g.normal(0.0, sigma, size=N))

@@ -43,6 +43,15 @@ class ClientSetup:
             self._keys[g] = client.gen_galois_key(self.P, self.sk, g, *self._masks_errors())
         return self._keys[g]
 
+    def sparse_keys(self, h: int):
+        """Switching keys s -> s' and s' -> s for a sparse secret s' with h nonzero coefficients."""
+        if ("sparse", h) not in self._keys:
+            sp = client.SecretKey(self.P, inputs.sparse_ternary(self.g, self.ps.N, h))
+            to_sp = client.gen_switch_key(self.P, sp, self.sk.eval_all, *self._masks_errors())
+            from_sp = client.gen_switch_key(self.P, self.sk, sp.eval_all, *self._masks_errors())
+            self._keys[("sparse", h)] = (to_sp, from_sp)
+        return self._keys[("sparse", h)]
+
     def encrypt(self, z, level: int, scale: float | None = None):
         scale = float(2 ** self.ps.log_scale) if scale is None else scale
         pt = client.encode(self.P, z, level, scale)

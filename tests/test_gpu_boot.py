@@ -2,7 +2,7 @@
 oracle's executor, bit for bit on every limb of the output: at N = 2^12 with
 the full schedule (valid keys, so the decrypted error is reported too) and at
 N = 2^16 with the three-group CoeffToSlot / SlotToCoeff of the full-slot
-workload and a short EvalMod.  HIP-graph replays must match the eager run."""
+workload, sparse-secret encapsulation and a short EvalMod.  HIP-graph replays must match the eager run."""
 import sys
 
 import numpy as np
@@ -22,9 +22,9 @@ def _say(msg):
     sys.stdout.flush()
 
 
-def _boot_handle(s, bp, pl, relin, conj, rot):
+def _boot_handle(s, bp, pl, relin, conj, rot, sparse=None):
     return s.ckks.Boot(s.ctx, bp.cts_radix_logs, bp.stc_radix_logs, pl.cts, pl.stc, pl.cheb, bp.double_angles,
-                       bp.top_scale, relin, conj, rot, cheb_baby=bp.cheb_baby)
+                       bp.top_scale, relin, conj, rot, cheb_baby=bp.cheb_baby, sparse=sparse)
 
 
 def _check_ct(s, got, want, what):
@@ -33,24 +33,28 @@ def _check_ct(s, got, want, what):
     assert_equal(s.host(got.c1)[: want[2] + 1], want[1], what + " c1")
 
 
-@pytest.mark.parametrize("baby,bound", [(0, -9.5), (64, -12)])
-def test_bootstrap_small_full_schedule(baby, bound):
-    _say("bootstrap boot-small (baby %d): keys and plan" % baby)
+@pytest.mark.parametrize("baby,bound,sparse", [(0, -9.5, False), (64, -12, False), (0, -14, True)])
+def test_bootstrap_small_full_schedule(baby, bound, sparse):
+    _say("bootstrap boot-small (baby %d, sparse %s): keys and plan" % (baby, sparse))
     s = Setup("boot-small")
     cs = ClientSetup(s.ps, seed=31)
-    bp = B.BootParams(logn=12, cts_radix_logs=[4, 4, 3], stc_radix_logs=[3, 4, 4], cheb_degree=63,
-                      double_angles=5, k_range=128.0, top_scale=2.0 ** 50, in_scale=2.0 ** 50, cheb_baby=baby)
+    ev = dict(cheb_degree=31, double_angles=3, k_range=12.0) if sparse else \
+        dict(cheb_degree=63, double_angles=5, k_range=128.0)
+    bp = B.BootParams(logn=12, cts_radix_logs=[4, 4, 3], stc_radix_logs=[3, 4, 4], top_scale=2.0 ** 50,
+                      in_scale=2.0 ** 50, cheb_baby=baby, **ev)
     pl = B.plan(s.P, bp)
     rot_np = {k: cs.galois_key(oracle.galois_for_rotation(12, k)) for k in B.rotations_needed(bp)}
     conj_np = cs.galois_key(oracle.galois_conjugate(12))
     rlk_np = cs.relin_key()
     z = inputs.complex_slots(inputs.rng(32), s.N // 2)
     c0, c1 = cs.encrypt(z, 0, bp.in_scale)
-    want = B.Executor(s.P, pl, rlk_np, conj_np, rot_np).bootstrap((c0, c1, 0))
+    sp_np = cs.sparse_keys(32) if sparse else (None, None)
+    want = B.Executor(s.P, pl, rlk_np, conj_np, rot_np, *sp_np).bootstrap((c0, c1, 0))
 
     _say("bootstrap boot-small: GPU")
     rot = {k: s.ctx.key(s.dev(v), oracle.galois_for_rotation(12, k)) for k, v in rot_np.items()}
-    boot = _boot_handle(s, bp, pl, s.ctx.key(s.dev(rlk_np), 0), s.ctx.key(s.dev(conj_np), 2 * s.N - 1), rot)
+    sp = (s.ctx.key(s.dev(sp_np[0]), 0), s.ctx.key(s.dev(sp_np[1]), 0)) if sparse else None
+    boot = _boot_handle(s, bp, pl, s.ctx.key(s.dev(rlk_np), 0), s.ctx.key(s.dev(conj_np), 2 * s.N - 1), rot, sp)
     assert boot.output_level == B.output_level(s.P, bp)
     inp = s.ckks.Ciphertext(s.dev(c0), s.dev(c1), 0, bp.in_scale)
     out = s.ctx.empty_ct(boot.output_level)
@@ -80,7 +84,8 @@ def test_bootstrap_large_graph_replay():
         rot[k] = _random_key(s, 1000 + k, oracle.galois_for_rotation(16, k))
     rlk = _random_key(s, 1, 0)
     conj = _random_key(s, 2, 2 * s.N - 1)
-    boot = _boot_handle(s, bp, pl, rlk[1], conj[1], {k: v[1] for k, v in rot.items()})
+    to_sp, from_sp = _random_key(s, 3, 0), _random_key(s, 4, 0)
+    boot = _boot_handle(s, bp, pl, rlk[1], conj[1], {k: v[1] for k, v in rot.items()}, (to_sp[1], from_sp[1]))
     c0, c1 = inputs.random_ct(5, s.ps, 0)
     inp = s.ckks.Ciphertext(s.dev(c0), s.dev(c1), 0, bp.in_scale)
     out = s.ctx.empty_ct(boot.output_level)
@@ -90,8 +95,8 @@ def test_bootstrap_large_graph_replay():
 
     _say("bootstrap large: oracle")
     host = lambda t: t.cpu().numpy()
-    want = B.Executor(s.P, pl, host(rlk[0]), host(conj[0]), {k: host(v[0]) for k, v in rot.items()}).bootstrap(
-        (c0, c1, 0))
+    want = B.Executor(s.P, pl, host(rlk[0]), host(conj[0]), {k: host(v[0]) for k, v in rot.items()},
+                      host(to_sp[0]), host(from_sp[0])).bootstrap((c0, c1, 0))
     _check_ct(s, out, want, "bootstrap")
 
     _say("bootstrap large: graph replays")

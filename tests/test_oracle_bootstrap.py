@@ -180,6 +180,29 @@ def test_bootstrap_with_one_leaf_is_more_precise(boot_small):
     assert err < -12, err
 
 
+def test_bootstrap_with_sparse_secret_encapsulation():
+    """Switching to a sparse secret (h = 32) around ModRaise keeps |I| small, so
+    K = 12 with a degree-31 interpolant and 3 double angles suffices: three
+    more levels left and about 2^-15."""
+    ps = inputs.params("boot-small")
+    cs = ClientSetup(ps, seed=31)
+    bp = B.BootParams(**dict(BP_SMALL, cheb_degree=31, double_angles=3, k_range=12.0))
+    pl = B.plan(cs.P, bp)
+    rk = {k: cs.galois_key(oracle.galois_for_rotation(ps.logn, k)) for k in B.rotations_needed(bp)}
+    to_sp, from_sp = cs.sparse_keys(32)
+    ex = B.Executor(cs.P, pl, cs.relin_key(), cs.galois_key(oracle.galois_conjugate(ps.logn)), rk, to_sp, from_sp)
+    z = inputs.complex_slots(inputs.rng(34), ps.N // 2)
+    c0, c1 = cs.encrypt(z, 0, bp.in_scale)
+    r = ex.switch((c0, c1, 0), to_sp)
+    t = _raised_coefficients(cs, ex.switch(ex.modraise(r), from_sp))
+    q0 = ps.q[0]
+    assert max(abs(round(int(v) / q0)) for v in t) < 12
+    out = ex.bootstrap((c0, c1, 0))
+    assert out[2] == B.output_level(cs.P, bp) == 4
+    err = max_err_bits(cs.decrypt((out[0], out[1]), out[2], ex.sc[out[2]]), z)
+    assert err < -14, err
+
+
 def test_chebyshev_split_reconstructs_the_series():
     """q T_G + r equals the series on [-1, 1] (Chebyshev product identity)."""
     c = list(inputs.rng(9).normal(size=40))
