@@ -388,12 +388,15 @@ def main():
     ops["intt_35_limbs"] = op_stats(lambda s: ctx.ckks_intt(ntt_poly), reps)
 
     if args.copy_calibration:
-        src = torch.empty(32 << 20, dtype=torch.int64, device="cuda").fill_(1)
+        # 1 GiB copied once; a 512 MiB fill in between evicts the source from the 256 MiB last-level
+        # cache, so the copy's counters see the full read and write
+        src = torch.empty(128 << 20, dtype=torch.int64, device="cuda").fill_(1)
+        flush = torch.empty(64 << 20, dtype=torch.int64, device="cuda").fill_(2)
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
         dst.copy_(src)
         torch.cuda.synchronize()
-        del src, dst
+        del src, dst, flush
 
     # ---- dominant kernel: the forward NTT over all 35 limbs (two passes, 16 x 35 workgroups each),
     # timed on the library's stream; algorithmic bytes = read + write of every limb once.
