@@ -16,49 +16,30 @@ __device__ __forceinline__ uint32_t row_prime(uint32_t r, uint32_t level, uint32
     return r <= level ? r : nq + (r - level - 1);
 }
 
+// Read-only tables read through the scalar cache when the address is uniform.
+typedef const __attribute__((address_space(4))) uint64_t ConstU64;
+
 // Conv_{B->C}: y_i = [x_i (B/b_i)^-1]_{b_i} (Shoup; skipped when the inverse
 // NTT already produced y_i), then every output row c gets
 // [sum_i y_i [B/b_i]_c]_c, accumulated exactly in 128 bits and reduced once
 // (as the paper does).  blockIdx.y selects the job (digit or polynomial),
-// blockIdx.z a group of kBconvRowGroup output rows whose constants are staged
-// in LDS.
-struct BconvLds {
-    uint64_t hm[kBconvRowGroup][kMaxDigitPrimes];
-    Prime pr[kBconvRowGroup];
-};
-
-__device__ __forceinline__ void bconv_unit(const BconvArgs &a, uint32_t job, uint32_t bx, uint32_t bz, BconvLds &S)
+// blockIdx.z a group of kBconvRowGroup output rows.  The source count NS is a
+// template parameter (no predicated iterations), and the constants [B/b_i]_c,
+// uniform over the workgroup, come through the scalar cache.
+template <int NS>
+__device__ __forceinline__ void bconv_rows(const BconvArgs &a, const BconvJob &J, uint32_t n, uint32_t r0,
+                                           uint32_t r1)
 {
-    const BconvJob &J = a.job[job];
     const uint32_t N = a.N;
-    const uint32_t n = bx * kThreads + threadIdx.x;
-    const uint32_t r0 = bz * kBconvRowGroup;
-    if (r0 >= a.nrows) return;
-    const uint32_t r1 = min(r0 + kBconvRowGroup, a.nrows);
-    uint64_t (&hm)[kBconvRowGroup][kMaxDigitPrimes] = S.hm;
-    Prime (&pr)[kBconvRowGroup] = S.pr;
-    if (threadIdx.x < kBconvRowGroup * kMaxDigitPrimes) {
-        const uint32_t rr = threadIdx.x / kMaxDigitPrimes, i = threadIdx.x % kMaxDigitPrimes;
-        if (r0 + rr < r1) {
-            const uint32_t pi = row_prime(r0 + rr, a.level, a.nq);
-            hm[rr][i] = J.hmod[(size_t)pi * kMaxDigitPrimes + i];
-            if (i == 0) pr[rr] = a.primes[pi];
-        }
-    }
-    __syncthreads();
-    uint64_t y[kMaxDigitPrimes];
+    uint64_t y[NS];
 #pragma unroll
-    for (int i = 0; i < kMaxDigitPrimes; ++i) {
-        if (i < (int)J.ns) {
-            const uint64_t x = J.src[(size_t)i * N + n];
-            if (a.prescaled) {
-                y[i] = x;
-            } else {
-                const ulonglong2 h = J.hinv[i];
-                y[i] = shoup(x, h.x, h.y, a.primes[J.src_prime0 + i].q);
-            }
+    for (int i = 0; i < NS; ++i) {
+        const uint64_t x = J.src[(size_t)i * N + n];
+        if (a.prescaled) {
+            y[i] = x;
         } else {
-            y[i] = 0;
+            const ulonglong2 h = J.hinv[i];
+            y[i] = shoup(x, h.x, h.y, a.primes[J.src_prime0 + i].q);
         }
     }
     for (uint32_t r = r0; r < r1; ++r) {
@@ -68,34 +49,46 @@ __device__ __forceinline__ void bconv_unit(const BconvArgs &a, uint32_t job, uin
                     J.copy_src[(size_t)r * N + (a.copy_galois == 1 ? n : galois_src(n, a.copy_galois, a.logn))];
             continue;
         }
-        const uint64_t *h = hm[r - r0];
+        const uint32_t pi = row_prime(r, a.level, a.nq);
+        ConstU64 *h = (ConstU64 *)(J.hmod + (size_t)pi * kMaxDigitPrimes);
         u128 acc = {0, 0};
 #pragma unroll
-        for (int i = 0; i < kMaxDigitPrimes; ++i)
-            if (i < (int)J.ns) acc = add128(acc, mul_wide(y[i], h[i]));
-        J.dst[(size_t)r * N + n] = reduce128(acc, pr[r - r0]);
+        for (int i = 0; i < NS; ++i) acc = add128(acc, mul_wide(y[i], h[i]));
+        J.dst[(size_t)r * N + n] = reduce128(acc, a.primes[pi]);
+    }
+}
+
+__device__ __forceinline__ void bconv_unit(const BconvArgs &a, uint32_t job, uint32_t bx, uint32_t bz)
+{
+    const BconvJob &J = a.job[job];
+    const uint32_t n = bx * kThreads + threadIdx.x;
+    const uint32_t r0 = bz * kBconvRowGroup;
+    if (r0 >= a.nrows) return;
+    const uint32_t r1 = min(r0 + kBconvRowGroup, a.nrows);
+    switch (J.ns) {
+#define BC_CASE(k) \
+    case k: bconv_rows<k>(a, J, n, r0, r1); break;
+        BC_CASE(1) BC_CASE(2) BC_CASE(3) BC_CASE(4) BC_CASE(5) BC_CASE(6) BC_CASE(7) BC_CASE(8)
+        BC_CASE(9) BC_CASE(10) BC_CASE(11) BC_CASE(12) BC_CASE(13) BC_CASE(14) BC_CASE(15) BC_CASE(16)
+#undef BC_CASE
+    default: break;
     }
 }
 
 __global__ __launch_bounds__(kThreads) void k_bconv(BconvArgs a)
 {
-    __shared__ BconvLds S;
-    bconv_unit(a, blockIdx.y, blockIdx.x, blockIdx.z, S);
+    bconv_unit(a, blockIdx.y, blockIdx.x, blockIdx.z);
 }
 
 // persistent: tile t of record (inst, job) covers kQueueBlocks coefficient blocks
 // ((t % (N / (256 kQueueBlocks))) kQueueBlocks ..) of row group t / (N / (256 kQueueBlocks))
 __global__ __launch_bounds__(kThreads) void q_bconv(const BconvArgs *insts, WorkQueue q)
 {
-    __shared__ BconvLds S;
     __shared__ BconvArgs sa;
     __shared__ uint32_t claim;
     run_work_queue(insts, q, sa, &claim, [&](const BconvArgs &a, uint32_t job, uint32_t t) {
         const uint32_t nb = a.N / (kThreads * kQueueBlocks);
-        for (uint32_t i = 0; i < kQueueBlocks; ++i) {
-            if (i) __syncthreads();  // the row-group constants in S are rewritten
-            bconv_unit(a, job, (t % nb) * kQueueBlocks + i, t / nb, S);
-        }
+        for (uint32_t i = 0; i < kQueueBlocks; ++i) bconv_unit(a, job, (t % nb) * kQueueBlocks + i, t / nb);
     });
 }
 

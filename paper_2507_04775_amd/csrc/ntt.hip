@@ -304,6 +304,8 @@ __device__ __forceinline__ BcSrc bc_source(const NttArgs &a, uint32_t poly, uint
 
 // v[i] = Conv(y)[pos(i)]: sum_k y_k[pos] [B/b_k]_q accumulated exactly, reduced
 // once; two halves of eight elements keep the 128-bit sums in few registers.
+// The loads of source row k+1 are issued before the products of row k, so
+// the latency of the source rows overlaps the arithmetic.
 template <class A, class Pos>
 __device__ __forceinline__ void bconv_load16(typename A::V (&v)[16], const A &ar, const BcSrc &b, const Prime &P,
                                              size_t N, Pos pos)
@@ -312,20 +314,31 @@ __device__ __forceinline__ void bconv_load16(typename A::V (&v)[16], const A &ar
     for (int half = 0; half < 2; ++half) {
         u128 acc[8];
         uint32_t high[8];
+        uint64_t cur[8];
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             acc[i] = u128{0, 0};
             high[i] = 0;
+            cur[i] = b.y[pos(8 * half + i)];
         }
         for (uint32_t k = 0; k < b.ns; ++k) {
-            const uint64_t h = b.hm[k];
-            const uint64_t *yk = b.y + (size_t)k * N;
+            const bool more = k + 1 < b.ns;
+            uint64_t nxt[8];
+            if (more) {
+                const uint64_t *yn = b.y + (size_t)(k + 1) * N;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) nxt[i] = yn[pos(8 * half + i)];
+            }
+            const uint64_t h = ((const __attribute__((address_space(4))) uint64_t *)b.hm)[k];  // scalar cache
             const uint64_t half_k = b.src ? (b.src[k].q - 1) >> 1 : ~0ull;
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
-                const uint64_t y = yk[pos(8 * half + i)];
-                acc[i] = add128(acc[i], mul_wide(y, h));
-                high[i] += y > half_k;
+                acc[i] = add128(acc[i], mul_wide(cur[i], h));
+                high[i] += cur[i] > half_k;
+            }
+            if (more) {
+#pragma unroll
+                for (int i = 0; i < 8; ++i) cur[i] = nxt[i];
             }
         }
 #pragma unroll
