@@ -61,6 +61,22 @@ def percentile(xs, p):
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
+def measured_traffic():
+    """HBM bytes per launch of the roofline kernel, from the committed counter
+    summary, valid only while the NTT source is the one the counters were
+    taken on (else None)."""
+    import hashlib
+    prof = os.path.join(ROOT, "profiles", "ntt_fwd_logn16_35limbs_hbm_counters.md")
+    src = os.path.join(ROOT, "paper_2507_04775_amd", "csrc", "ntt.hip")
+    try:
+        fields = dict(l.split(":", 1) for l in open(prof) if l.startswith(("traffic_bytes_per_launch:", "ntt_hip_sha256:")))
+        if hashlib.sha256(open(src, "rb").read()).hexdigest() != fields["ntt_hip_sha256"].strip():
+            return None
+        return int(fields["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def run_batch(ctx, ps, seed, args):
     """C3-style batch: one graph replay of the persistent stage kernels vs the same
     items issued as plain per-operation calls on one stream."""
@@ -405,7 +421,7 @@ def main():
     achieved = ntt_bytes / (ntt_ms / 1e3) / 1e9
     roofline = {"bound": "hbm", "kernel": "ntt16_fwd (column + row pass) over 35 limbs",
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
                 "algorithmic_bytes_per_launch": ntt_bytes, "launch_us": round(ntt_ms * 1e3, 2)}
 
     # ---- batched: 128 ciphertexts at levels 4..30, half HMult+relin, half hoisted 8-way rotations
