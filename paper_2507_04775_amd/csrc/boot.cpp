@@ -108,6 +108,24 @@ void cheb_split(const std::vector<double> &c, uint32_t G, std::vector<double> &q
     }
 }
 
+// Resources of one execution lane: the caller's stream (lane 0) or an
+// internal stream, its own workspace and buffers, so lanes never share a
+// buffer.  Independent work (giant steps of a linear transform, the two EvalMod
+// halves) runs on different lanes and overlaps on the GPU; every lane's work
+// is forked from and joined back into the caller's stream with events, which
+// also makes the whole bootstrap capturable as one graph.  Lanes 0 and 1 run
+// an EvalMod half each and hold its buffers; lanes 2 and 3 only giant steps.
+struct Lane {
+    hipStream_t aux = nullptr;       // internal stream (null for lane 0)
+    void *ws = nullptr;
+    uint32_t p = 0, r = 0, acc = 0;  // BSGS partial sum, rotated partial sum, lane accumulator
+    uint32_t d = 0;                  // three level-down temporaries d, d+1, d+2
+    uint32_t t = 0, g = 0, pool = 0; // babies T_2.., giants, Chebyshev buffer pool
+};
+
+constexpr uint32_t kLanes = 4;
+constexpr uint32_t kEvents = 8;
+
 // A ciphertext held in one of the executor's buffers (or the caller's output).
 struct Ct {
     uint64_t *c0, *c1;
@@ -138,25 +156,51 @@ struct ckks_boot {
     uint64_t *slots = nullptr;  // nslots buffers of 2 (L+1) N words
     size_t slot_words = 0;
     uint32_t nslots = 0, max_baby = 1;
-    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    Lane lanes[kLanes];
+    hipEvent_t events[kEvents] = {};
+    uint32_t next_event = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 
-    // buffer indices
+    // buffers shared by the lanes: hoisted babies, group outputs, the split and EvalMod halves
     uint32_t s_babies() const { return 0; }  // max_baby - 1 buffers
-    uint32_t s_p() const { return max_baby - 1; }
-    uint32_t s_r() const { return max_baby; }
-    uint32_t s_acc(uint32_t i) const { return max_baby + 1 + i; }  // i = 0, 1
-    uint32_t s_x() const { return max_baby + 3; }
-    uint32_t s_cj() const { return max_baby + 4; }
-    uint32_t s_re(uint32_t i) const { return max_baby + 5 + i; }
-    uint32_t s_im(uint32_t i) const { return max_baby + 7 + i; }
-    uint32_t s_d(uint32_t i) const { return max_baby + 9 + i; }  // level-down temporaries 0..2
-    uint32_t s_t(uint32_t k) const { return max_baby + 12 + (k - 2); }  // babies T_k, k = 2..nbaby
-    uint32_t s_g(uint32_t j) const { return max_baby + 12 + (nbaby - 1) + j; }  // giants
-    uint32_t pool0() const { return s_g((uint32_t)giants.size()); }
+    uint32_t s_out(uint32_t i) const { return max_baby - 1 + i; }  // i = 0, 1
+    uint32_t s_x() const { return max_baby + 1; }
+    uint32_t s_cj() const { return max_baby + 2; }
+    uint32_t s_re(uint32_t i) const { return max_baby + 3 + i; }
+    uint32_t s_im(uint32_t i) const { return max_baby + 5 + i; }
+    uint32_t shared_slots() const { return max_baby + 7; }
     uint32_t pool_size() const { return 2 * (uint32_t)giants.size() + 6; }
-    uint32_t slot_count() const { return pool0() + pool_size(); }
+    // lane 0 accumulates into the transform's output buffer, the others into their own
+    uint32_t lane_slots(uint32_t l) const
+    {
+        return 2 + (l > 0) + (l < 2 ? 3 + (nbaby - 1) + (uint32_t)giants.size() + pool_size() : 0);
+    }
+    uint32_t slot_count() const
+    {
+        uint32_t c = shared_slots();
+        for (uint32_t l = 0; l < kLanes; ++l) c += lane_slots(l);
+        return c;
+    }
+    void assign_lanes(uint8_t *ws_base)
+    {
+        uint32_t next = shared_slots();
+        for (uint32_t l = 0; l < kLanes; ++l) {
+            Lane &ln = lanes[l];
+            const uint32_t b0 = next;
+            ln.p = b0;
+            ln.r = b0 + 1;
+            ln.acc = l > 0 ? b0 + 2 : UINT32_MAX;
+            ln.d = b0 + 2 + (l > 0);
+            ln.t = ln.d + 3;
+            ln.g = ln.t + (nbaby - 1);
+            ln.pool = ln.g + (uint32_t)giants.size();
+            next += lane_slots(l);
+            ln.ws = ws_base + l * ws_bytes;
+        }
+    }
+    hipEvent_t event() { return events[next_event++ % kEvents]; }
 
     Ct slot(uint32_t i, uint32_t level) const
     {
@@ -172,6 +216,7 @@ ckks_ct as_ct(const Ct &c) { return ckks_ct{c.c0, c.c1, c.level, 1.0}; }
 struct Runner {
     ckks_boot *b;
     hipStream_t st;
+    const Lane *ln;
     std::vector<uint64_t> res;
 
     ckks_ctx *ctx() const { return b->ctx; }
@@ -190,7 +235,7 @@ struct Runner {
     ckks_status rescale(Ct &c, const Ct *dst = nullptr)
     {
         ckks_ct in = as_ct(c), out = dst ? as_ct(*dst) : in;
-        TRY(ckks_rescale(ctx(), &in, &out, b->ws, st));
+        TRY(ckks_rescale(ctx(), &in, &out, ln->ws, st));
         c = Ct{out.c0, out.c1, c.level - 1};
         return CKKS_OK;
     }
@@ -240,14 +285,14 @@ struct Runner {
     {
         const uint32_t l = std::min(x.level, y.level);
         Ct a, c;
-        TRY(level_down(x, l, b->slot(b->s_d(0), 0), a));
+        TRY(level_down(x, l, b->slot(ln->d, 0), a));
         if (y.c0 == x.c0) {
             c = a;
         } else {
-            TRY(level_down(y, l, b->slot(b->s_d(1), 0), c));
+            TRY(level_down(y, l, b->slot(ln->d + 1, 0), c));
         }
         ckks_ct A = as_ct(a), B = as_ct(c), O = as_ct(Ct{dst_buf.c0, dst_buf.c1, l});
-        TRY(ckks_hmult_relin(ctx(), &A, &B, b->relin, &O, b->ws, st));
+        TRY(ckks_hmult_relin(ctx(), &A, &B, b->relin, &O, ln->ws, st));
         out = Ct{dst_buf.c0, dst_buf.c1, l};
         return rescale(out);
     }
@@ -269,10 +314,26 @@ struct Runner {
             }
             ckks_ct I = as_ct(in);
             TRY(ckks_hrotate_hoisted(ctx(), &I, (uint32_t)g.baby_k.size(), g.baby_k.data(), keys.data(), outs.data(),
-                                     b->ws, st));
+                                     ln->ws, st));
         }
-        const Ct acc = b->slot(acc_slot, lvl), P = b->slot(b->s_p(), lvl), R = b->slot(b->s_r(), lvl);
+        // giant steps round-robin over the lanes, each accumulating its own sum
+        Runner lr[kLanes] = {*this, *this, *this, *this};
+        const uint32_t nl = std::min<uint32_t>(kLanes, g.lay.giants);
+        hipEvent_t fork = b->event();
+        if (nl > 1) TRY(dev(hipEventRecord(fork, st), "ckks_bootstrap fork"));
+        for (uint32_t l = 1; l < nl; ++l) {
+            lr[l].st = b->lanes[l].aux;
+            lr[l].ln = &b->lanes[l];
+            TRY(dev(hipStreamWaitEvent(lr[l].st, fork, 0), "ckks_bootstrap fork"));
+        }
+        bool started[kLanes] = {};
         for (uint32_t gi = 0; gi < g.lay.giants; ++gi) {
+            Runner &R_ = lr[gi % nl];
+            const Lane &L_ = *R_.ln;
+            const Ct acc = b->slot(gi % nl == 0 ? acc_slot : L_.acc, lvl), P = b->slot(L_.p, lvl),
+                     R = b->slot(L_.r, lvl);
+            const bool first = !started[gi % nl];
+            started[gi % nl] = true;
             const uint32_t i0 = gi * g.lay.baby, nb = std::min(g.lay.baby, g.lay.count - i0);
             const uint32_t G = (uint32_t)(((int64_t)g.giant[gi] % b->n + b->n) % b->n);
             LincombArgs la;
@@ -282,20 +343,27 @@ struct Runner {
                 la.a1[j] = src[j].c1;
                 la.pt[j] = g.pt + (size_t)(i0 + j) * limb;
             }
-            const Ct &target = (G == 0 && gi == 0) ? acc : P;
+            const Ct &target = (G == 0 && first) ? acc : P;
             la.out0 = target.c0;
             la.out1 = target.c1;
             la.primes = ctx()->d_primes;
             la.n = nb;
             la.logn = ctx()->logn;
-            TRY(dev(launch_lincomb(la, lvl + 1, st), "ckks_bootstrap lincomb"));
+            TRY(dev(launch_lincomb(la, lvl + 1, R_.st), "ckks_bootstrap lincomb"));
             Ct part = P;
             if (G != 0) {
-                part = gi == 0 ? acc : R;
+                part = first ? acc : R;
                 ckks_ct I = as_ct(P), O = as_ct(part);
-                TRY(ckks_hrotate(ctx(), &I, (int32_t)G, b->rot.at(G), &O, b->ws, st));
+                TRY(ckks_hrotate(ctx(), &I, (int32_t)G, b->rot.at(G), &O, L_.ws, R_.st));
             }
-            if (gi > 0) TRY(add(acc, part, acc));
+            if (!first) TRY(R_.add(acc, part, acc));
+        }
+        const Ct acc = b->slot(acc_slot, lvl);
+        for (uint32_t l = 1; l < nl; ++l) {
+            hipEvent_t join = b->event();
+            TRY(dev(hipEventRecord(join, lr[l].st), "ckks_bootstrap join"));
+            TRY(dev(hipStreamWaitEvent(st, join, 0), "ckks_bootstrap join"));
+            TRY(add(acc, b->slot(b->lanes[l].acc, lvl), acc));
         }
         Ct c = acc;
         for (uint32_t r = 0; r < g.rescales; ++r) TRY(rescale(c, (r + 1 == g.rescales) ? final_out : nullptr));
@@ -374,11 +442,11 @@ struct Runner {
     {
         T.clear();
         pool.clear();
-        for (uint32_t i = 0; i < b->pool_size(); ++i) pool.push_back(b->pool0() + i);
+        for (uint32_t i = 0; i < b->pool_size(); ++i) pool.push_back(ln->pool + i);
         T[1] = b->slot(s0, b->evalmod_in);
         Ct tmp;
         for (uint32_t k = 2; k <= b->nbaby; ++k) {
-            const Ct buf = b->slot(b->s_t(k), 0);
+            const Ct buf = b->slot(ln->t + (k - 2), 0);
             Ct v;
             if (k % 2 == 0) {
                 TRY(mul(T.at(k / 2), T.at(k / 2), buf, v));
@@ -387,7 +455,7 @@ struct Runner {
             } else {
                 TRY(mul(T.at(k / 2), T.at(k / 2 + 1), buf, v));
                 TRY(scalar_mul(v, v, 2));
-                TRY(level_down(T.at(1), v.level, b->slot(b->s_d(2), 0), tmp));
+                TRY(level_down(T.at(1), v.level, b->slot(ln->d + 2, 0), tmp));
                 TRY(add(v, tmp, v, true));
             }
             T[k] = v;
@@ -395,7 +463,7 @@ struct Runner {
         for (size_t j = 0; j < b->giants.size(); ++j) {
             const uint32_t G = b->giants[j];
             Ct v;
-            TRY(mul(T.at(G / 2), T.at(G / 2), b->slot(b->s_g((uint32_t)j), 0), v));
+            TRY(mul(T.at(G / 2), T.at(G / 2), b->slot(ln->g + (uint32_t)j, 0), v));
             TRY(scalar_mul(v, v, 2));
             TRY(scalar_add(v, -1.0));
             T[G] = v;
@@ -428,7 +496,7 @@ struct Runner {
     {
         const ckks_ctx *c = ctx();
         const size_t N = c->N;
-        uint64_t *v = (uint64_t *)b->ws;
+        uint64_t *v = (uint64_t *)ln->ws;
         NttArgs ia = base_args(c, true);
         ia.src = in.c0;
         ia.dst = v;
@@ -455,7 +523,7 @@ struct Runner {
     // (c0, c1) -> (c0 + k0, k1), (k0, k1) = KeySwitch(c1, key); the result's c1 lives in tmp
     ckks_status switch_key(const Ct &c, const ckks_key *key, const Ct &tmp, Ct &out)
     {
-        TRY(ckks_keyswitch(ctx(), c.c1, c.level, key, tmp.c0, tmp.c1, b->ws, st));
+        TRY(ckks_keyswitch(ctx(), c.c1, c.level, key, tmp.c0, tmp.c1, ln->ws, st));
         TRY(ckks_poly_add(ctx(), c.c0, tmp.c0, c.c0, c.level, st));
         out = Ct{c.c0, tmp.c1, c.level};
         return CKKS_OK;
@@ -477,28 +545,37 @@ struct Runner {
         }
         uint32_t ai = 0;
         for (const Group &g : b->cts) {
-            TRY(linear_transform(g, x, b->s_acc(ai), nullptr, x));
+            TRY(linear_transform(g, x, b->s_out(ai), nullptr, x));
             ai ^= 1;
         }
         // split: re = x + conj(x), im = (conj(x) - x) X^(N/2)
         const uint32_t l = x.level;
         const Ct cj = b->slot(b->s_cj(), l), re = b->slot(b->s_re(0), l), im = b->slot(b->s_im(0), l);
         ckks_ct X = as_ct(x), CJ = as_ct(cj);
-        TRY(ckks_conjugate(ctx(), &X, b->conj, &CJ, b->ws, st));
+        TRY(ckks_conjugate(ctx(), &X, b->conj, &CJ, ln->ws, st));
         TRY(add(x, cj, re));
         TRY(add(cj, x, im, true));
         TRY(ckks_poly_mul(ctx(), im.c0, b->mono, im.c0, l, st));
         TRY(ckks_poly_mul(ctx(), im.c1, b->mono, im.c1, l, st));
+        // the two halves on lanes 0 and 1
         Ct yr, yi;
+        Runner im_r = *this;
+        im_r.st = b->lanes[1].aux;
+        im_r.ln = &b->lanes[1];
+        hipEvent_t fork = b->event(), join = b->event();
+        TRY(dev(hipEventRecord(fork, st), "ckks_bootstrap fork"));
+        TRY(dev(hipStreamWaitEvent(im_r.st, fork, 0), "ckks_bootstrap fork"));
+        TRY(im_r.eval_mod(b->s_im(0), b->s_im(1), yi));
         TRY(eval_mod(b->s_re(0), b->s_re(1), yr));
-        TRY(eval_mod(b->s_im(0), b->s_im(1), yi));
+        TRY(dev(hipEventRecord(join, im_r.st), "ckks_bootstrap join"));
+        TRY(dev(hipStreamWaitEvent(st, join, 0), "ckks_bootstrap join"));
         TRY(ckks_poly_mul(ctx(), yi.c0, b->mono, yi.c0, yi.level, st));
         TRY(ckks_poly_mul(ctx(), yi.c1, b->mono, yi.c1, yi.level, st));
         TRY(add(yr, yi, yi));
         x = yi;
         const Ct fin{out.c0, out.c1, b->out_level};
         for (size_t i = 0; i < b->stc.size(); ++i) {
-            TRY(linear_transform(b->stc[i], x, b->s_acc(ai), i + 1 == b->stc.size() ? &fin : nullptr, x));
+            TRY(linear_transform(b->stc[i], x, b->s_out(ai), i + 1 == b->stc.size() ? &fin : nullptr, x));
             ai ^= 1;
         }
         return CKKS_OK;
@@ -699,7 +776,8 @@ extern "C" ckks_status ckks_boot_create(ckks_ctx *ctx, const ckks_boot_desc *des
     const size_t off_mono = off_cst + up(std::max<size_t>(cst.size(), 1) * 8),
                  off_slots = off_mono + up((size_t)(L + 1) * N * 8);
     const size_t off_ws = off_slots + up(b->nslots * b->slot_words * 8);
-    b->bytes = off_ws + up(wsb);
+    b->ws_bytes = up(wsb);
+    b->bytes = off_ws + kLanes * b->ws_bytes;
     if (hipSetDevice(ctx->device) != hipSuccess || hipMalloc(&b->dev, b->bytes) != hipSuccess) {
         b->dev = nullptr;
         return bail(CKKS_E_NOMEM, "device allocation of " + std::to_string(b->bytes) + " bytes failed");
@@ -708,7 +786,17 @@ extern "C" ckks_status ckks_boot_create(ckks_ctx *ctx, const ckks_boot_desc *des
     b->mono = (uint64_t *)(base + off_mono);
     b->leaf_cst = (uint64_t *)(base + off_cst);
     b->slots = (uint64_t *)(base + off_slots);
-    b->ws = base + off_ws;
+    b->assign_lanes(base + off_ws);
+    for (uint32_t l = 1; l < kLanes; ++l)
+        if (hipStreamCreateWithFlags(&b->lanes[l].aux, hipStreamNonBlocking) != hipSuccess) {
+            b->lanes[l].aux = nullptr;
+            return bail(CKKS_E_DEVICE, "stream creation failed");
+        }
+    for (uint32_t i = 0; i < kEvents; ++i)
+        if (hipEventCreateWithFlags(&b->events[i], hipEventDisableTiming) != hipSuccess) {
+            b->events[i] = nullptr;
+            return bail(CKKS_E_DEVICE, "event creation failed");
+        }
 
     // plaintexts: integer-valued doubles -> residues -> evaluation domain
     size_t max_count = 0;
@@ -797,7 +885,7 @@ static ckks_status check_io(const ckks_boot *b, const ckks_ct *in, const ckks_ct
 extern "C" ckks_status ckks_bootstrap(ckks_boot *b, const ckks_ct *in, ckks_ct *out, void *stream)
 {
     TRY(check_io(b, in, out, "ckks_bootstrap"));
-    Runner r{b, S(stream), {}};
+    Runner r{b, S(stream), &b->lanes[0], {}};
     TRY(r.run(*in, *out));
     out->level = b->out_level;
     out->scale = b->sc[b->out_level];
@@ -815,7 +903,7 @@ extern "C" ckks_status ckks_boot_capture(ckks_boot *b, const ckks_ct *in, ckks_c
     b->graph = nullptr;
     if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return fail(CKKS_E_DEVICE, "ckks_boot_capture: begin capture failed");
-    Runner r{b, st, {}};
+    Runner r{b, st, &b->lanes[0], {}};
     ckks_status s = r.run(*in, *out);
     hipError_t e = hipStreamEndCapture(st, &b->graph);
     if (s != CKKS_OK) return s;
@@ -840,6 +928,10 @@ extern "C" void ckks_boot_destroy(ckks_boot *b)
     if (!b) return;
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
+    for (uint32_t i = 0; i < kEvents; ++i)
+        if (b->events[i]) (void)hipEventDestroy(b->events[i]);
+    for (uint32_t l = 1; l < kLanes; ++l)
+        if (b->lanes[l].aux) (void)hipStreamDestroy(b->lanes[l].aux);
     if (b->dev) (void)hipFree(b->dev);
     delete b;
 }
