@@ -34,6 +34,14 @@ constexpr int kThreads = 256;
 
 __device__ __forceinline__ uint32_t pad(uint32_t x) { return x + (x >> 4); }
 
+// LDS slot of element e of column `col` in a column pass.  The 16 columns of
+// a tile are interleaved (element-major), so the 64 lanes of a wave touch
+// consecutive words when they store s + 16 i and at most two 128-byte bank
+// groups per half-wave when they load 16 s + i; a column-major layout with a
+// 272-word stride maps the 16 columns onto two bank offsets only, which made
+// the exchange cost as much as the pass's HBM traffic.
+__device__ __forceinline__ uint32_t col_slot(uint32_t e, uint32_t col) { return 16 * pad(e) + col; }
+
 // ----------------------------------------------------------- integer path
 
 struct IntArith {
@@ -371,12 +379,11 @@ __device__ __forceinline__ void fwd_col_body(const NttArgs &a, const LimbPos &lp
         for (int i = 0; i < 16; ++i) v[i] = ar.from_u64(load_fwd<PRO>(a, lp, src, (s + 16 * i) * 256 + c, P));
     }
     fwd16<256, 16>(v, s, ar, 1);
-    uint64_t *L = lds + col * 272;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) L[pad(s + 16 * i)] = ar.to_bits(v[i]);
+    for (int i = 0; i < 16; ++i) lds[col_slot(s + 16 * i, col)] = ar.to_bits(v[i]);
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < 16; ++i) v[i] = ar.from_bits(L[pad(16 * s + i)]);
+    for (int i = 0; i < 16; ++i) v[i] = ar.from_bits(lds[col_slot(16 * s + i, col)]);
     ar.reduce_all(v);
     fwd16<256, 1>(v, 16 * s, ar, 1);
     uint64_t *m = a.mid + (int64_t)lp.poly * a.mid_stride + (size_t)lp.row * 65536;
@@ -510,12 +517,11 @@ __device__ __forceinline__ void inv_col_body(const NttArgs &a, const LimbPos &lp
     for (int i = 0; i < 16; ++i) v[i] = ar.from_bits(m[(16 * s + i) * 256 + c]);
     ar.reduce_all(v);
     inv16<256, 1>(v, 16 * s, ar, 1);
-    uint64_t *L = lds + col * 272;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) L[pad(16 * s + i)] = ar.to_bits(v[i]);
+    for (int i = 0; i < 16; ++i) lds[col_slot(16 * s + i, col)] = ar.to_bits(v[i]);
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < 16; ++i) v[i] = ar.from_bits(L[pad(s + 16 * i)]);
+    for (int i = 0; i < 16; ++i) v[i] = ar.from_bits(lds[col_slot(s + 16 * i, col)]);
     ar.reduce_all(v);
     inv16<256, 16>(v, s, ar, 1);
     uint64_t *dst = a.dst + (int64_t)lp.poly * a.map.dst_poly_stride + (size_t)lp.row * 65536;
