@@ -6,14 +6,18 @@
 // butterfly of stage m at index j uses w = psi^br(m + j div 2t) from the
 // context tables.
 //
-// Layout of the work: every thread owns 16 elements and runs four radix-2
-// stages on them in registers ("radix-16 rounds"); rounds exchange data
-// through LDS.  N = 2^12 fits one workgroup (three rounds).  N = 2^16 is the
-// paper's 2-D / hierarchical scheme: viewed as a 256 x 256 matrix, a column
-// pass runs the first eight stages (each column is an independent 256-point
-// problem) and a row pass runs the last eight (each row of 256 contiguous
-// elements is independent, with its own twiddle subset).  Each pass reads and
-// writes every element once: four global accesses per element in total.
+// Layout of the work: threads own a few elements each and run several radix-2
+// stages on them in registers ("rounds"); rounds exchange data through LDS.
+// N = 2^12 fits one workgroup of 256 threads with 16 elements each (three
+// rounds of four stages).  N = 2^16 is the paper's 2-D / hierarchical scheme:
+// viewed as a 256 x 256 matrix, a column pass runs the first eight stages
+// (each column is an independent 256-point problem) and a row pass runs the
+// last eight (each row of 256 contiguous elements is independent, with its own
+// twiddle subset).  Each pass reads and writes every element once: four global
+// accesses per element in total.  A pass workgroup holds 16 columns (rows) with
+// 32 threads on each and 8 elements per thread, in rounds of 3, 3 and 2
+// stages: short dependency chains per thread and twice the waves of a
+// 16-element layout, which matters most for the slower integer path.
 //
 // Two arithmetic paths, chosen per limb (uniform per workgroup):
 // - primes below 2^50: exact FP64 arithmetic (modarith.h).  Values are
@@ -34,13 +38,6 @@ constexpr int kThreads = 256;
 
 __device__ __forceinline__ uint32_t pad(uint32_t x) { return x + (x >> 4); }
 
-// LDS slot of element e of column `col` in a column pass.  The 16 columns of
-// a tile are interleaved (element-major), so the 64 lanes of a wave touch
-// consecutive words when they store s + 16 i and at most two 128-byte bank
-// groups per half-wave when they load 16 s + i; a column-major layout with a
-// 272-word stride maps the 16 columns onto two bank offsets only, which made
-// the exchange cost as much as the pass's HBM traffic.
-__device__ __forceinline__ uint32_t col_slot(uint32_t e, uint32_t col) { return 16 * pad(e) + col; }
 
 // ----------------------------------------------------------- integer path
 
@@ -54,7 +51,8 @@ struct IntArith {
     __device__ __forceinline__ V from_bits(uint64_t x) const { return x; }
     __device__ __forceinline__ uint64_t to_bits(V x) const { return x; }
     __device__ __forceinline__ W tw(uint32_t i) const { return T[i]; }
-    __device__ __forceinline__ void reduce_all(V (&)[16]) const {}
+    template <int NV>
+    __device__ __forceinline__ void reduce_all(V (&)[NV]) const {}
     // Harvey forward butterfly: x, y in [0, 4q) -> [0, 4q)
     __device__ __forceinline__ void ct(V &x, V &y, W w) const
     {
@@ -97,10 +95,11 @@ struct FpArith {
     __device__ __forceinline__ V from_bits(uint64_t x) const { return __longlong_as_double((long long)x); }
     __device__ __forceinline__ uint64_t to_bits(V x) const { return (uint64_t)__double_as_longlong(x); }
     __device__ __forceinline__ W tw(uint32_t i) const { return T[i]; }
-    __device__ __forceinline__ void reduce_all(V (&v)[16]) const
+    template <int NV>
+    __device__ __forceinline__ void reduce_all(V (&v)[NV]) const
     {
 #pragma unroll
-        for (int i = 0; i < 16; ++i) v[i] = fp_reduce(v[i], m);
+        for (int i = 0; i < NV; ++i) v[i] = fp_reduce(v[i], m);
     }
     __device__ __forceinline__ void ct(V &x, V &y, W w) const
     {
@@ -128,15 +127,15 @@ struct FpArith {
     __device__ __forceinline__ uint64_t acc_final(V acc) const { return fp_canonical(acc, m); }
 };
 
-// Four forward stages on v[i] = element base + STRIDE i of an NS-point
-// problem: t = 8 STRIDE, 4 STRIDE, 2 STRIDE, STRIDE.  base = a 16 STRIDE + s
-// with s < STRIDE.  Twiddles come from T[m B + j div 2t], m = NS / 2t.
-template <int NS, int STRIDE, class A>
-__device__ __forceinline__ void fwd16(typename A::V (&v)[16], uint32_t base, const A &ar, uint32_t B)
+// LOG forward stages on v[i] = element base + STRIDE i (i < 2^LOG) of an
+// NS-point problem: t = 2^(LOG-1) STRIDE, ..., STRIDE.  base = a 2^LOG STRIDE
+// + s with s < STRIDE.  Twiddles come from T[m B + j div 2t], m = NS / 2t.
+template <int LOG, int NS, int STRIDE, class A>
+__device__ __forceinline__ void fwd_r(typename A::V *v, uint32_t base, const A &ar, uint32_t B)
 {
 #pragma unroll
-    for (int st = 0; st < 4; ++st) {
-        const int h = 8 >> st;
+    for (int st = 0; st < LOG; ++st) {
+        const int h = (1 << (LOG - 1)) >> st;
         const uint32_t t = h * STRIDE;
         const uint32_t m = NS / (2 * t);
         const uint32_t g0 = m * B + base / (2 * t);
@@ -149,23 +148,37 @@ __device__ __forceinline__ void fwd16(typename A::V (&v)[16], uint32_t base, con
     }
 }
 
-// Four inverse stages: t = STRIDE, 2 STRIDE, 4 STRIDE, 8 STRIDE.
-template <int NS, int STRIDE, class A>
-__device__ __forceinline__ void inv16(typename A::V (&v)[16], uint32_t base, const A &ar, uint32_t B)
+// LOG inverse stages: t = STRIDE, 2 STRIDE, ..., 2^(LOG-1) STRIDE.  Rounds
+// of four stages re-centre the sums of their third stage (FP64 path); three
+// stages from a centred start stay below 4 q + 8 without it.
+template <int LOG, int NS, int STRIDE, class A>
+__device__ __forceinline__ void inv_r(typename A::V *v, uint32_t base, const A &ar, uint32_t B)
 {
 #pragma unroll
-    for (int st = 0; st < 4; ++st) {
+    for (int st = 0; st < LOG; ++st) {
         const int h = 1 << st;
         const uint32_t t = h * STRIDE;
         const uint32_t m = NS / (2 * t);
         const uint32_t g0 = m * B + base / (2 * t);
 #pragma unroll
-        for (int g = 0; g < (8 >> st); ++g) {
+        for (int g = 0; g < ((1 << (LOG - 1)) >> st); ++g) {
             const typename A::W w = ar.tw(g0 + g);
 #pragma unroll
-            for (int k = 0; k < h; ++k) ar.gs(v[g * 2 * h + k], v[g * 2 * h + k + h], w, st);
+            for (int k = 0; k < h; ++k) ar.gs(v[g * 2 * h + k], v[g * 2 * h + k + h], w, LOG == 4 ? st : -1);
         }
     }
+}
+
+template <int NS, int STRIDE, class A>
+__device__ __forceinline__ void fwd16(typename A::V (&v)[16], uint32_t base, const A &ar, uint32_t B)
+{
+    fwd_r<4, NS, STRIDE>(v, base, ar, B);
+}
+
+template <int NS, int STRIDE, class A>
+__device__ __forceinline__ void inv16(typename A::V (&v)[16], uint32_t base, const A &ar, uint32_t B)
+{
+    inv_r<4, NS, STRIDE>(v, base, ar, B);
 }
 
 struct LimbPos {
@@ -311,15 +324,16 @@ __device__ __forceinline__ BcSrc bc_source(const NttArgs &a, uint32_t poly, uint
 }
 
 // v[i] = Conv(y)[pos(i)]: sum_k y_k[pos] [B/b_k]_q accumulated exactly, reduced
-// once; two halves of eight elements keep the 128-bit sums in few registers.
+// once; groups of eight elements keep the 128-bit sums in few registers.
 // The loads of source row k+1 are issued before the products of row k, so
 // the latency of the source rows overlaps the arithmetic.
-template <class A, class Pos>
-__device__ __forceinline__ void bconv_load16(typename A::V (&v)[16], const A &ar, const BcSrc &b, const Prime &P,
-                                             size_t N, Pos pos)
+template <int NV, class A, class Pos>
+__device__ __forceinline__ void bconv_load(typename A::V (&v)[NV], const A &ar, const BcSrc &b, const Prime &P,
+                                           size_t N, Pos pos)
 {
+    static_assert(NV % 8 == 0, "groups of eight elements");
 #pragma unroll
-    for (int half = 0; half < 2; ++half) {
+    for (int half = 0; half < NV / 8; ++half) {
         u128 acc[8];
         uint32_t high[8];
         uint64_t cur[8];
@@ -363,6 +377,40 @@ __device__ __forceinline__ void bconv_load16(typename A::V (&v)[16], const A &ar
 // of the 256 x 256 view) of limb `limb` of a launch described by NttArgs.
 // Grid kernels take (tile, limb) from (blockIdx.x, blockIdx.y); persistent
 // kernels claim units from a work queue (see the end of this file).
+//
+// A unit runs on 512 threads: 32 per column (row), each holding 8 of its 256
+// elements.  Element positions within the 256-point problem in the three
+// layouts a thread s < 32 takes:
+//   wide   s + 32 i          (stages t = 128, 64, 32; coalesced global access)
+//   mid    32 (s/4) + s%4 + 4 i (stages t = 16, 8, 4)
+//   narrow 8 s + i            (stages t = 2, 1 as two radix-4 groups)
+// Between layouts each thread stores what it holds and, after one barrier,
+// loads the next layout; a thread only ever overwrites slots it loaded itself,
+// so one barrier per exchange suffices.
+
+constexpr int kThreads16 = 512;
+
+__device__ __forceinline__ uint32_t pos_wide(uint32_t s, int i) { return s + 32 * i; }
+__device__ __forceinline__ uint32_t pos_mid(uint32_t s, int i) { return 32 * (s >> 2) + (s & 3) + 4 * i; }
+__device__ __forceinline__ uint32_t pos_narrow(uint32_t s, int i) { return 8 * s + i; }
+
+// LDS slot of element e of column `col` in a column pass: the tile's 16
+// columns interleaved (element-major) and every group of 8 elements padded by
+// one word.  A half-wave (16 columns x 2 threads) then touches 32 consecutive
+// words in the wide and mid layouts and two 128-byte halves of the banks in
+// the narrow one.
+__device__ __forceinline__ uint32_t col_slot(uint32_t e, uint32_t col) { return 16 * (e + (e >> 3)) + col; }
+constexpr int kColLds = 16 * (255 + 31 + 1);
+
+// LDS slot of element e of a row (256 words per row): the low five bits are
+// XOR-swizzled with f(e / 32), f(h) = h ^ 4h, so that the 32 threads of a row
+// (one half-wave) hit 32 distinct banks in each of the three layouts.
+__device__ __forceinline__ uint32_t row_slot(uint32_t e)
+{
+    const uint32_t h = e >> 5;
+    return (e & ~31u) | ((e ^ h ^ (h << 2)) & 31u);
+}
+constexpr int kLds16 = kColLds > 16 * 256 ? kColLds : 16 * 256;
 
 template <int PRO, class A>
 __device__ __forceinline__ void fwd_col_body(const NttArgs &a, const LimbPos &lp, const Prime &P, const A &ar,
@@ -370,25 +418,33 @@ __device__ __forceinline__ void fwd_col_body(const NttArgs &a, const LimbPos &lp
 {
     const uint32_t col = threadIdx.x & 15, s = threadIdx.x >> 4, c = tile * 16 + col;
     const uint64_t *src = a.src + (int64_t)lp.poly * a.map.src_poly_stride + (size_t)lp.row * 65536;
-    typename A::V v[16];
+    typename A::V v[8];
     if (PRO == PRO_BCONV) {
-        bconv_load16(v, ar, bc_source(a, lp.poly, lp.prime, 65536), P, 65536,
-                     [&](int i) { return (s + 16 * i) * 256 + c; });
+        bconv_load(v, ar, bc_source(a, lp.poly, lp.prime, 65536), P, 65536,
+                   [&](int i) { return pos_wide(s, i) * 256 + c; });
     } else {
 #pragma unroll
-        for (int i = 0; i < 16; ++i) v[i] = ar.from_u64(load_fwd<PRO>(a, lp, src, (s + 16 * i) * 256 + c, P));
+        for (int i = 0; i < 8; ++i) v[i] = ar.from_u64(load_fwd<PRO>(a, lp, src, pos_wide(s, i) * 256 + c, P));
     }
-    fwd16<256, 16>(v, s, ar, 1);
+    fwd_r<3, 256, 32>(v, s, ar, 1);
 #pragma unroll
-    for (int i = 0; i < 16; ++i) lds[col_slot(s + 16 * i, col)] = ar.to_bits(v[i]);
+    for (int i = 0; i < 8; ++i) lds[col_slot(pos_wide(s, i), col)] = ar.to_bits(v[i]);
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < 16; ++i) v[i] = ar.from_bits(lds[col_slot(16 * s + i, col)]);
+    for (int i = 0; i < 8; ++i) v[i] = ar.from_bits(lds[col_slot(pos_mid(s, i), col)]);
     ar.reduce_all(v);
-    fwd16<256, 1>(v, 16 * s, ar, 1);
+    fwd_r<3, 256, 4>(v, pos_mid(s, 0), ar, 1);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) lds[col_slot(pos_mid(s, i), col)] = ar.to_bits(v[i]);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = ar.from_bits(lds[col_slot(pos_narrow(s, i), col)]);
+    ar.reduce_all(v);
+    fwd_r<2, 256, 1>(v, 8 * s, ar, 1);
+    fwd_r<2, 256, 1>(v + 4, 8 * s + 4, ar, 1);
     uint64_t *m = a.mid + (int64_t)lp.poly * a.mid_stride + (size_t)lp.row * 65536;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) m[(16 * s + i) * 256 + c] = ar.to_bits(v[i]);
+    for (int i = 0; i < 8; ++i) m[pos_narrow(s, i) * 256 + c] = ar.to_bits(v[i]);
 }
 
 template <int PRO>
@@ -407,28 +463,36 @@ template <int EPI, class A>
 __device__ __forceinline__ void fwd_row_body(const NttArgs &a, const LimbPos &lp, const Prime &P, const A &ar,
                                              uint64_t *lds, uint32_t tile)
 {
-    const uint32_t blk = threadIdx.x >> 4, s = threadIdx.x & 15, b = tile * 16 + blk;
+    const uint32_t blk = threadIdx.x >> 5, s = threadIdx.x & 31, b = tile * 16 + blk;
     const uint64_t *m = a.mid + (int64_t)lp.poly * a.mid_stride + (size_t)lp.row * 65536 + b * 256;
-    typename A::V v[16];
+    uint64_t *L = lds + blk * 256;
+    typename A::V v[8];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) v[i] = ar.from_bits(m[s + 16 * i]);
+    for (int i = 0; i < 8; ++i) v[i] = ar.from_bits(m[pos_wide(s, i)]);
     ar.reduce_all(v);
-    fwd16<256, 16>(v, s, ar, 256 + b);
-    uint64_t *L = lds + blk * 272;
+    fwd_r<3, 256, 32>(v, s, ar, 256 + b);
 #pragma unroll
-    for (int i = 0; i < 16; ++i) L[pad(s + 16 * i)] = ar.to_bits(v[i]);
+    for (int i = 0; i < 8; ++i) L[row_slot(pos_wide(s, i))] = ar.to_bits(v[i]);
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < 16; ++i) v[i] = ar.from_bits(L[pad(16 * s + i)]);
+    for (int i = 0; i < 8; ++i) v[i] = ar.from_bits(L[row_slot(pos_mid(s, i))]);
     ar.reduce_all(v);
-    fwd16<256, 1>(v, 16 * s, ar, 256 + b);
+    fwd_r<3, 256, 4>(v, pos_mid(s, 0), ar, 256 + b);
 #pragma unroll
-    for (int i = 0; i < 16; ++i) L[pad(16 * s + i)] = ar.fwd_final(v[i]);
+    for (int i = 0; i < 8; ++i) L[row_slot(pos_mid(s, i))] = ar.to_bits(v[i]);
     __syncthreads();
-    uint64_t x[16], addv[16];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        x[i] = L[pad(s + 16 * i)];
+    for (int i = 0; i < 8; ++i) v[i] = ar.from_bits(L[row_slot(pos_narrow(s, i))]);
+    ar.reduce_all(v);
+    fwd_r<2, 256, 1>(v, 8 * s, ar, 256 + b);
+    fwd_r<2, 256, 1>(v + 4, 8 * s + 4, ar, 256 + b);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) L[row_slot(pos_narrow(s, i))] = ar.fwd_final(v[i]);
+    __syncthreads();
+    uint64_t x[8], addv[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        x[i] = L[row_slot(pos_wide(s, i))];
         addv[i] = 0;
     }
     const uint64_t *add = EPI == EPI_MODDOWN ? a.add[lp.poly] : nullptr;
@@ -436,20 +500,21 @@ __device__ __forceinline__ void fwd_row_body(const NttArgs &a, const LimbPos &lp
         add += (size_t)lp.row * 65536;
         if (a.galois == 1) {
 #pragma unroll
-            for (int i = 0; i < 16; ++i) addv[i] = add[b * 256 + s + 16 * i];
+            for (int i = 0; i < 8; ++i) addv[i] = add[b * 256 + pos_wide(s, i)];
         } else {  // block b's addend comes from one block sb: stage it through LDS
             const uint32_t sb = galois_src(b * 256, a.galois, 16) & ~255u;
             __syncthreads();
 #pragma unroll
-            for (int i = 0; i < 16; ++i) L[pad(s + 16 * i)] = add[sb + s + 16 * i];
+            for (int i = 0; i < 8; ++i) L[row_slot(pos_wide(s, i))] = add[sb + pos_wide(s, i)];
             __syncthreads();
 #pragma unroll
-            for (int i = 0; i < 16; ++i) addv[i] = L[pad(galois_src(b * 256 + s + 16 * i, a.galois, 16) - sb)];
+            for (int i = 0; i < 8; ++i)
+                addv[i] = L[row_slot(galois_src(b * 256 + pos_wide(s, i), a.galois, 16) - sb)];
         }
     }
     uint64_t *dst = a.dst + (int64_t)lp.poly * a.map.dst_poly_stride + (size_t)lp.row * 65536;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) store_fwd<EPI>(a, lp, dst, b * 256 + s + 16 * i, x[i], addv[i], P, 65536);
+    for (int i = 0; i < 8; ++i) store_fwd<EPI>(a, lp, dst, b * 256 + pos_wide(s, i), x[i], addv[i], P, 65536);
 }
 
 template <int EPI>
@@ -468,30 +533,38 @@ template <int PRO, class A>
 __device__ __forceinline__ void inv_row_body(const NttArgs &a, const LimbPos &lp, const A &ar, uint64_t *lds,
                                              uint32_t tile)
 {
-    const uint32_t blk = threadIdx.x >> 4, s = threadIdx.x & 15, b = tile * 16 + blk;
+    const uint32_t blk = threadIdx.x >> 5, s = threadIdx.x & 31, b = tile * 16 + blk;
     const uint64_t *src = a.src + (int64_t)lp.poly * a.map.src_poly_stride + (size_t)lp.row * 65536;
-    uint64_t *L = lds + blk * 272;
+    uint64_t *L = lds + blk * 256;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        uint32_t e = b * 256 + s + 16 * i;
-        L[pad(s + 16 * i)] = src[PRO == PRO_GALOIS ? galois_src(e, a.galois, 16) : e];
+    for (int i = 0; i < 8; ++i) {
+        const uint32_t e = b * 256 + pos_wide(s, i);
+        L[row_slot(pos_wide(s, i))] = src[PRO == PRO_GALOIS ? galois_src(e, a.galois, 16) : e];
     }
     __syncthreads();
-    typename A::V v[16];
+    typename A::V v[8];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) v[i] = ar.from_u64(L[pad(16 * s + i)]);
+    for (int i = 0; i < 8; ++i) v[i] = ar.from_u64(L[row_slot(pos_narrow(s, i))]);
     ar.reduce_all(v);
-    inv16<256, 1>(v, 16 * s, ar, 256 + b);
+    inv_r<2, 256, 1>(v, 8 * s, ar, 256 + b);
+    inv_r<2, 256, 1>(v + 4, 8 * s + 4, ar, 256 + b);
 #pragma unroll
-    for (int i = 0; i < 16; ++i) L[pad(16 * s + i)] = ar.to_bits(v[i]);
+    for (int i = 0; i < 8; ++i) L[row_slot(pos_narrow(s, i))] = ar.to_bits(v[i]);
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < 16; ++i) v[i] = ar.from_bits(L[pad(s + 16 * i)]);
+    for (int i = 0; i < 8; ++i) v[i] = ar.from_bits(L[row_slot(pos_mid(s, i))]);
     ar.reduce_all(v);
-    inv16<256, 16>(v, s, ar, 256 + b);
+    inv_r<3, 256, 4>(v, pos_mid(s, 0), ar, 256 + b);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) L[row_slot(pos_mid(s, i))] = ar.to_bits(v[i]);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = ar.from_bits(L[row_slot(pos_wide(s, i))]);
+    ar.reduce_all(v);
+    inv_r<3, 256, 32>(v, s, ar, 256 + b);
     uint64_t *m = a.mid + (int64_t)lp.poly * a.mid_stride + (size_t)lp.row * 65536 + b * 256;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) m[s + 16 * i] = ar.to_bits(v[i]);
+    for (int i = 0; i < 8; ++i) m[pos_wide(s, i)] = ar.to_bits(v[i]);
 }
 
 template <int PRO>
@@ -512,21 +585,29 @@ __device__ __forceinline__ void inv_col_body(const NttArgs &a, const LimbPos &lp
 {
     const uint32_t col = threadIdx.x & 15, s = threadIdx.x >> 4, c = tile * 16 + col;
     const uint64_t *m = a.mid + (int64_t)lp.poly * a.mid_stride + (size_t)lp.row * 65536;
-    typename A::V v[16];
+    typename A::V v[8];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) v[i] = ar.from_bits(m[(16 * s + i) * 256 + c]);
+    for (int i = 0; i < 8; ++i) v[i] = ar.from_bits(m[pos_narrow(s, i) * 256 + c]);
     ar.reduce_all(v);
-    inv16<256, 1>(v, 16 * s, ar, 1);
+    inv_r<2, 256, 1>(v, 8 * s, ar, 1);
+    inv_r<2, 256, 1>(v + 4, 8 * s + 4, ar, 1);
 #pragma unroll
-    for (int i = 0; i < 16; ++i) lds[col_slot(16 * s + i, col)] = ar.to_bits(v[i]);
+    for (int i = 0; i < 8; ++i) lds[col_slot(pos_narrow(s, i), col)] = ar.to_bits(v[i]);
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < 16; ++i) v[i] = ar.from_bits(lds[col_slot(s + 16 * i, col)]);
+    for (int i = 0; i < 8; ++i) v[i] = ar.from_bits(lds[col_slot(pos_mid(s, i), col)]);
     ar.reduce_all(v);
-    inv16<256, 16>(v, s, ar, 1);
+    inv_r<3, 256, 4>(v, pos_mid(s, 0), ar, 1);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) lds[col_slot(pos_mid(s, i), col)] = ar.to_bits(v[i]);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = ar.from_bits(lds[col_slot(pos_wide(s, i), col)]);
+    ar.reduce_all(v);
+    inv_r<3, 256, 32>(v, s, ar, 1);
     uint64_t *dst = a.dst + (int64_t)lp.poly * a.map.dst_poly_stride + (size_t)lp.row * 65536;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) dst[(s + 16 * i) * 256 + c] = ar.inv_final(v[i]);
+    for (int i = 0; i < 8; ++i) dst[pos_wide(s, i) * 256 + c] = ar.inv_final(v[i]);
 }
 
 __device__ __forceinline__ void inv_col_unit(const NttArgs &a, uint32_t limb, uint32_t tile, uint64_t *lds)
@@ -550,7 +631,7 @@ __device__ __forceinline__ void fwd12_body(const NttArgs &a, const LimbPos &lp, 
     const uint64_t *src = a.src + (int64_t)lp.poly * a.map.src_poly_stride + (size_t)lp.row * 4096;
     typename A::V v[16];
     if (PRO == PRO_BCONV) {
-        bconv_load16(v, ar, bc_source(a, lp.poly, lp.prime, 4096), P, 4096, [&](int i) { return t + 256 * i; });
+        bconv_load(v, ar, bc_source(a, lp.poly, lp.prime, 4096), P, 4096, [&](int i) { return t + 256 * i; });
     } else {
 #pragma unroll
         for (int i = 0; i < 16; ++i) v[i] = ar.from_u64(load_fwd<PRO>(a, lp, src, t + 256 * i, P));
@@ -664,15 +745,15 @@ __device__ __forceinline__ void inv12_unit(const NttArgs &a, uint32_t limb, uint
 // (instance, limb, tile) of many launches from a work queue, so a whole batch
 // of ciphertexts at different levels goes through one launch per stage.
 
-constexpr int kLds16 = 16 * 272, kLds12 = 4352;
+constexpr int kLds12 = 4352;
 
-#define NTT_KERNELS(NAME, LDS, UNIT)                                                              \
-    __global__ __launch_bounds__(kThreads) void k_##NAME(NttArgs a)                              \
+#define NTT_KERNELS(NAME, LDS, UNIT, THREADS)                                                     \
+    __global__ __launch_bounds__(THREADS) void k_##NAME(NttArgs a)                               \
     {                                                                                             \
         __shared__ uint64_t lds[LDS];                                                             \
         UNIT(a, blockIdx.y, blockIdx.x, lds);                                                     \
     }                                                                                             \
-    __global__ __launch_bounds__(kThreads) void q_##NAME(const NttArgs *insts, WorkQueue q)       \
+    __global__ __launch_bounds__(THREADS) void q_##NAME(const NttArgs *insts, WorkQueue q)        \
     {                                                                                             \
         __shared__ uint64_t lds[LDS];                                                             \
         __shared__ NttArgs sa;                                                                    \
@@ -681,27 +762,27 @@ constexpr int kLds16 = 16 * 272, kLds12 = 4352;
                        [&](const NttArgs &a, uint32_t limb, uint32_t tile) { UNIT(a, limb, tile, lds); }); \
     }
 
-NTT_KERNELS(fwd_col_plain, kLds16, fwd_col_unit<PRO_PLAIN>)
-NTT_KERNELS(fwd_col_rescale, kLds16, fwd_col_unit<PRO_RESCALE>)
-NTT_KERNELS(fwd_col_bconv, kLds16, fwd_col_unit<PRO_BCONV>)
-NTT_KERNELS(fwd_row_plain, kLds16, fwd_row_unit<EPI_PLAIN>)
-NTT_KERNELS(fwd_row_moddown, kLds16, fwd_row_unit<EPI_MODDOWN>)
-NTT_KERNELS(fwd_row_rescale, kLds16, fwd_row_unit<EPI_RESCALE>)
-NTT_KERNELS(inv_row_plain, kLds16, inv_row_unit<PRO_PLAIN>)
-NTT_KERNELS(inv_row_galois, kLds16, inv_row_unit<PRO_GALOIS>)
-NTT_KERNELS(inv_col, kLds16, inv_col_unit)
+NTT_KERNELS(fwd_col_plain, kLds16, fwd_col_unit<PRO_PLAIN>, kThreads16)
+NTT_KERNELS(fwd_col_rescale, kLds16, fwd_col_unit<PRO_RESCALE>, kThreads16)
+NTT_KERNELS(fwd_col_bconv, kLds16, fwd_col_unit<PRO_BCONV>, kThreads16)
+NTT_KERNELS(fwd_row_plain, kLds16, fwd_row_unit<EPI_PLAIN>, kThreads16)
+NTT_KERNELS(fwd_row_moddown, kLds16, fwd_row_unit<EPI_MODDOWN>, kThreads16)
+NTT_KERNELS(fwd_row_rescale, kLds16, fwd_row_unit<EPI_RESCALE>, kThreads16)
+NTT_KERNELS(inv_row_plain, kLds16, inv_row_unit<PRO_PLAIN>, kThreads16)
+NTT_KERNELS(inv_row_galois, kLds16, inv_row_unit<PRO_GALOIS>, kThreads16)
+NTT_KERNELS(inv_col, kLds16, inv_col_unit, kThreads16)
 #define FWD12_PP fwd12_unit<PRO_PLAIN, EPI_PLAIN>
 #define FWD12_PM fwd12_unit<PRO_PLAIN, EPI_MODDOWN>
 #define FWD12_RR fwd12_unit<PRO_RESCALE, EPI_RESCALE>
 #define FWD12_RP fwd12_unit<PRO_RESCALE, EPI_PLAIN>
 #define FWD12_BM fwd12_unit<PRO_BCONV, EPI_MODDOWN>
-NTT_KERNELS(fwd12_plain, kLds12, FWD12_PP)
-NTT_KERNELS(fwd12_moddown, kLds12, FWD12_PM)
-NTT_KERNELS(fwd12_rescale, kLds12, FWD12_RR)
-NTT_KERNELS(fwd12_lift, kLds12, FWD12_RP)
-NTT_KERNELS(fwd12_bconv_moddown, kLds12, FWD12_BM)
-NTT_KERNELS(inv12_plain, kLds12, inv12_unit<PRO_PLAIN>)
-NTT_KERNELS(inv12_galois, kLds12, inv12_unit<PRO_GALOIS>)
+NTT_KERNELS(fwd12_plain, kLds12, FWD12_PP, kThreads)
+NTT_KERNELS(fwd12_moddown, kLds12, FWD12_PM, kThreads)
+NTT_KERNELS(fwd12_rescale, kLds12, FWD12_RR, kThreads)
+NTT_KERNELS(fwd12_lift, kLds12, FWD12_RP, kThreads)
+NTT_KERNELS(fwd12_bconv_moddown, kLds12, FWD12_BM, kThreads)
+NTT_KERNELS(inv12_plain, kLds12, inv12_unit<PRO_PLAIN>, kThreads)
+NTT_KERNELS(inv12_galois, kLds12, inv12_unit<PRO_GALOIS>, kThreads)
 #undef FWD12_PP
 #undef FWD12_PM
 #undef FWD12_RR
@@ -761,6 +842,7 @@ bool stage_kernels(NttStage st, uint32_t logn, int pass, StageKernels &k)
 
 uint32_t ntt_passes(uint32_t logn) { return logn == 12 ? 1 : 2; }
 uint32_t ntt_tiles(uint32_t logn) { return logn == 12 ? 1 : 16; }
+static uint32_t ntt_threads(uint32_t logn) { return logn == 12 ? kThreads : kThreads16; }
 
 hipError_t launch_ntt_stage(NttStage st, const NttArgs &a, uint32_t nlimbs, hipStream_t stream)
 {
@@ -768,7 +850,7 @@ hipError_t launch_ntt_stage(NttStage st, const NttArgs &a, uint32_t nlimbs, hipS
     for (uint32_t pass = 0; pass < ntt_passes(a.logn); ++pass) {
         StageKernels k;
         if (!stage_kernels(st, a.logn, pass, k)) return hipErrorInvalidValue;
-        hipLaunchKernelGGL(k.grid, dim3(ntt_tiles(a.logn), nlimbs), dim3(kThreads), 0, stream, a);
+        hipLaunchKernelGGL(k.grid, dim3(ntt_tiles(a.logn), nlimbs), dim3(ntt_threads(a.logn)), 0, stream, a);
     }
     return hipGetLastError();
 }
@@ -778,7 +860,7 @@ hipError_t launch_ntt_stage_queue(NttStage st, uint32_t logn, uint32_t pass, con
 {
     StageKernels k;
     if (!stage_kernels(st, logn, pass, k)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k.queue, dim3(grid), dim3(kThreads), 0, stream, insts, q);
+    hipLaunchKernelGGL(k.queue, dim3(grid), dim3(ntt_threads(logn)), 0, stream, insts, q);
     return hipGetLastError();
 }
 
