@@ -130,43 +130,84 @@ struct FpArith {
 // LOG forward stages on v[i] = element base + STRIDE i (i < 2^LOG) of an
 // NS-point problem: t = 2^(LOG-1) STRIDE, ..., STRIDE.  base = a 2^LOG STRIDE
 // + s with s < STRIDE.  Twiddles come from T[m B + j div 2t], m = NS / 2t.
+// tw_fwd loads the 2^LOG - 1 twiddles a round uses (stage by stage, group by
+// group) and fwd_rw applies them, so a pass can issue a round's twiddle loads
+// before the barrier that precedes the round.
 template <int LOG, int NS, int STRIDE, class A>
-__device__ __forceinline__ void fwd_r(typename A::V *v, uint32_t base, const A &ar, uint32_t B)
+__device__ __forceinline__ void tw_fwd(typename A::W *w, uint32_t base, const A &ar, uint32_t B)
 {
+    int k = 0;
+#pragma unroll
+    for (int st = 0; st < LOG; ++st) {
+        const uint32_t t = ((1u << (LOG - 1)) >> st) * STRIDE;
+        const uint32_t g0 = (NS / (2 * t)) * B + base / (2 * t);
+#pragma unroll
+        for (int g = 0; g < (1 << st); ++g) w[k++] = ar.tw(g0 + g);
+    }
+}
+
+template <int LOG, class A>
+__device__ __forceinline__ void fwd_rw(typename A::V *v, const typename A::W *w, const A &ar)
+{
+    int k = 0;
 #pragma unroll
     for (int st = 0; st < LOG; ++st) {
         const int h = (1 << (LOG - 1)) >> st;
-        const uint32_t t = h * STRIDE;
-        const uint32_t m = NS / (2 * t);
-        const uint32_t g0 = m * B + base / (2 * t);
 #pragma unroll
         for (int g = 0; g < (1 << st); ++g) {
-            const typename A::W w = ar.tw(g0 + g);
+            const typename A::W ww = w[k++];
 #pragma unroll
-            for (int k = 0; k < h; ++k) ar.ct(v[g * 2 * h + k], v[g * 2 * h + k + h], w);
+            for (int kk = 0; kk < h; ++kk) ar.ct(v[g * 2 * h + kk], v[g * 2 * h + kk + h], ww);
         }
     }
+}
+
+template <int LOG, int NS, int STRIDE, class A>
+__device__ __forceinline__ void fwd_r(typename A::V *v, uint32_t base, const A &ar, uint32_t B)
+{
+    typename A::W w[(1 << LOG) - 1];
+    tw_fwd<LOG, NS, STRIDE>(w, base, ar, B);
+    fwd_rw<LOG>(v, w, ar);
 }
 
 // LOG inverse stages: t = STRIDE, 2 STRIDE, ..., 2^(LOG-1) STRIDE.  Rounds
 // of four stages re-centre the sums of their third stage (FP64 path); three
 // stages from a centred start stay below 4 q + 8 without it.
 template <int LOG, int NS, int STRIDE, class A>
-__device__ __forceinline__ void inv_r(typename A::V *v, uint32_t base, const A &ar, uint32_t B)
+__device__ __forceinline__ void tw_inv(typename A::W *w, uint32_t base, const A &ar, uint32_t B)
 {
+    int k = 0;
+#pragma unroll
+    for (int st = 0; st < LOG; ++st) {
+        const uint32_t t = (1u << st) * STRIDE;
+        const uint32_t g0 = (NS / (2 * t)) * B + base / (2 * t);
+#pragma unroll
+        for (int g = 0; g < ((1 << (LOG - 1)) >> st); ++g) w[k++] = ar.tw(g0 + g);
+    }
+}
+
+template <int LOG, class A>
+__device__ __forceinline__ void inv_rw(typename A::V *v, const typename A::W *w, const A &ar)
+{
+    int k = 0;
 #pragma unroll
     for (int st = 0; st < LOG; ++st) {
         const int h = 1 << st;
-        const uint32_t t = h * STRIDE;
-        const uint32_t m = NS / (2 * t);
-        const uint32_t g0 = m * B + base / (2 * t);
 #pragma unroll
         for (int g = 0; g < ((1 << (LOG - 1)) >> st); ++g) {
-            const typename A::W w = ar.tw(g0 + g);
+            const typename A::W ww = w[k++];
 #pragma unroll
-            for (int k = 0; k < h; ++k) ar.gs(v[g * 2 * h + k], v[g * 2 * h + k + h], w, LOG == 4 ? st : -1);
+            for (int kk = 0; kk < h; ++kk) ar.gs(v[g * 2 * h + kk], v[g * 2 * h + kk + h], ww, LOG == 4 ? st : -1);
         }
     }
+}
+
+template <int LOG, int NS, int STRIDE, class A>
+__device__ __forceinline__ void inv_r(typename A::V *v, uint32_t base, const A &ar, uint32_t B)
+{
+    typename A::W w[(1 << LOG) - 1];
+    tw_inv<LOG, NS, STRIDE>(w, base, ar, B);
+    inv_rw<LOG>(v, w, ar);
 }
 
 template <int NS, int STRIDE, class A>
@@ -418,6 +459,8 @@ __device__ __forceinline__ void fwd_col_body(const NttArgs &a, const LimbPos &lp
 {
     const uint32_t col = threadIdx.x & 15, s = threadIdx.x >> 4, c = tile * 16 + col;
     const uint64_t *src = a.src + (int64_t)lp.poly * a.map.src_poly_stride + (size_t)lp.row * 65536;
+    typename A::W wa[7], wb[7], wc[6];
+    tw_fwd<3, 256, 32>(wa, s, ar, 1);
     typename A::V v[8];
     if (PRO == PRO_BCONV) {
         bconv_load(v, ar, bc_source(a, lp.poly, lp.prime, 65536), P, 65536,
@@ -426,22 +469,25 @@ __device__ __forceinline__ void fwd_col_body(const NttArgs &a, const LimbPos &lp
 #pragma unroll
         for (int i = 0; i < 8; ++i) v[i] = ar.from_u64(load_fwd<PRO>(a, lp, src, pos_wide(s, i) * 256 + c, P));
     }
-    fwd_r<3, 256, 32>(v, s, ar, 1);
+    fwd_rw<3>(v, wa, ar);
+    tw_fwd<3, 256, 4>(wb, pos_mid(s, 0), ar, 1);  // in flight across the exchange
 #pragma unroll
     for (int i = 0; i < 8; ++i) lds[col_slot(pos_wide(s, i), col)] = ar.to_bits(v[i]);
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < 8; ++i) v[i] = ar.from_bits(lds[col_slot(pos_mid(s, i), col)]);
     ar.reduce_all(v);
-    fwd_r<3, 256, 4>(v, pos_mid(s, 0), ar, 1);
+    fwd_rw<3>(v, wb, ar);
+    tw_fwd<2, 256, 1>(wc, 8 * s, ar, 1);
+    tw_fwd<2, 256, 1>(wc + 3, 8 * s + 4, ar, 1);
 #pragma unroll
     for (int i = 0; i < 8; ++i) lds[col_slot(pos_mid(s, i), col)] = ar.to_bits(v[i]);
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < 8; ++i) v[i] = ar.from_bits(lds[col_slot(pos_narrow(s, i), col)]);
     ar.reduce_all(v);
-    fwd_r<2, 256, 1>(v, 8 * s, ar, 1);
-    fwd_r<2, 256, 1>(v + 4, 8 * s + 4, ar, 1);
+    fwd_rw<2>(v, wc, ar);
+    fwd_rw<2>(v + 4, wc + 3, ar);
     uint64_t *m = a.mid + (int64_t)lp.poly * a.mid_stride + (size_t)lp.row * 65536;
 #pragma unroll
     for (int i = 0; i < 8; ++i) m[pos_narrow(s, i) * 256 + c] = ar.to_bits(v[i]);
@@ -466,26 +512,31 @@ __device__ __forceinline__ void fwd_row_body(const NttArgs &a, const LimbPos &lp
     const uint32_t blk = threadIdx.x >> 5, s = threadIdx.x & 31, b = tile * 16 + blk;
     const uint64_t *m = a.mid + (int64_t)lp.poly * a.mid_stride + (size_t)lp.row * 65536 + b * 256;
     uint64_t *L = lds + blk * 256;
+    typename A::W wa[7], wb[7], wc[6];
+    tw_fwd<3, 256, 32>(wa, s, ar, 256 + b);
     typename A::V v[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) v[i] = ar.from_bits(m[pos_wide(s, i)]);
     ar.reduce_all(v);
-    fwd_r<3, 256, 32>(v, s, ar, 256 + b);
+    fwd_rw<3>(v, wa, ar);
+    tw_fwd<3, 256, 4>(wb, pos_mid(s, 0), ar, 256 + b);  // in flight across the exchange
 #pragma unroll
     for (int i = 0; i < 8; ++i) L[row_slot(pos_wide(s, i))] = ar.to_bits(v[i]);
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < 8; ++i) v[i] = ar.from_bits(L[row_slot(pos_mid(s, i))]);
     ar.reduce_all(v);
-    fwd_r<3, 256, 4>(v, pos_mid(s, 0), ar, 256 + b);
+    fwd_rw<3>(v, wb, ar);
+    tw_fwd<2, 256, 1>(wc, 8 * s, ar, 256 + b);
+    tw_fwd<2, 256, 1>(wc + 3, 8 * s + 4, ar, 256 + b);
 #pragma unroll
     for (int i = 0; i < 8; ++i) L[row_slot(pos_mid(s, i))] = ar.to_bits(v[i]);
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < 8; ++i) v[i] = ar.from_bits(L[row_slot(pos_narrow(s, i))]);
     ar.reduce_all(v);
-    fwd_r<2, 256, 1>(v, 8 * s, ar, 256 + b);
-    fwd_r<2, 256, 1>(v + 4, 8 * s + 4, ar, 256 + b);
+    fwd_rw<2>(v, wc, ar);
+    fwd_rw<2>(v + 4, wc + 3, ar);
 #pragma unroll
     for (int i = 0; i < 8; ++i) L[row_slot(pos_narrow(s, i))] = ar.fwd_final(v[i]);
     __syncthreads();
@@ -536,6 +587,9 @@ __device__ __forceinline__ void inv_row_body(const NttArgs &a, const LimbPos &lp
     const uint32_t blk = threadIdx.x >> 5, s = threadIdx.x & 31, b = tile * 16 + blk;
     const uint64_t *src = a.src + (int64_t)lp.poly * a.map.src_poly_stride + (size_t)lp.row * 65536;
     uint64_t *L = lds + blk * 256;
+    typename A::W wa[6], wb[7], wc[7];
+    tw_inv<2, 256, 1>(wa, 8 * s, ar, 256 + b);
+    tw_inv<2, 256, 1>(wa + 3, 8 * s + 4, ar, 256 + b);
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
         const uint32_t e = b * 256 + pos_wide(s, i);
@@ -546,22 +600,24 @@ __device__ __forceinline__ void inv_row_body(const NttArgs &a, const LimbPos &lp
 #pragma unroll
     for (int i = 0; i < 8; ++i) v[i] = ar.from_u64(L[row_slot(pos_narrow(s, i))]);
     ar.reduce_all(v);
-    inv_r<2, 256, 1>(v, 8 * s, ar, 256 + b);
-    inv_r<2, 256, 1>(v + 4, 8 * s + 4, ar, 256 + b);
+    inv_rw<2>(v, wa, ar);
+    inv_rw<2>(v + 4, wa + 3, ar);
+    tw_inv<3, 256, 4>(wb, pos_mid(s, 0), ar, 256 + b);  // in flight across the exchange
 #pragma unroll
     for (int i = 0; i < 8; ++i) L[row_slot(pos_narrow(s, i))] = ar.to_bits(v[i]);
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < 8; ++i) v[i] = ar.from_bits(L[row_slot(pos_mid(s, i))]);
     ar.reduce_all(v);
-    inv_r<3, 256, 4>(v, pos_mid(s, 0), ar, 256 + b);
+    inv_rw<3>(v, wb, ar);
+    tw_inv<3, 256, 32>(wc, s, ar, 256 + b);
 #pragma unroll
     for (int i = 0; i < 8; ++i) L[row_slot(pos_mid(s, i))] = ar.to_bits(v[i]);
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < 8; ++i) v[i] = ar.from_bits(L[row_slot(pos_wide(s, i))]);
     ar.reduce_all(v);
-    inv_r<3, 256, 32>(v, s, ar, 256 + b);
+    inv_rw<3>(v, wc, ar);
     uint64_t *m = a.mid + (int64_t)lp.poly * a.mid_stride + (size_t)lp.row * 65536 + b * 256;
 #pragma unroll
     for (int i = 0; i < 8; ++i) m[pos_wide(s, i)] = ar.to_bits(v[i]);
@@ -585,26 +641,31 @@ __device__ __forceinline__ void inv_col_body(const NttArgs &a, const LimbPos &lp
 {
     const uint32_t col = threadIdx.x & 15, s = threadIdx.x >> 4, c = tile * 16 + col;
     const uint64_t *m = a.mid + (int64_t)lp.poly * a.mid_stride + (size_t)lp.row * 65536;
+    typename A::W wa[6], wb[7], wc[7];
+    tw_inv<2, 256, 1>(wa, 8 * s, ar, 1);
+    tw_inv<2, 256, 1>(wa + 3, 8 * s + 4, ar, 1);
     typename A::V v[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) v[i] = ar.from_bits(m[pos_narrow(s, i) * 256 + c]);
     ar.reduce_all(v);
-    inv_r<2, 256, 1>(v, 8 * s, ar, 1);
-    inv_r<2, 256, 1>(v + 4, 8 * s + 4, ar, 1);
+    inv_rw<2>(v, wa, ar);
+    inv_rw<2>(v + 4, wa + 3, ar);
+    tw_inv<3, 256, 4>(wb, pos_mid(s, 0), ar, 1);  // in flight across the exchange
 #pragma unroll
     for (int i = 0; i < 8; ++i) lds[col_slot(pos_narrow(s, i), col)] = ar.to_bits(v[i]);
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < 8; ++i) v[i] = ar.from_bits(lds[col_slot(pos_mid(s, i), col)]);
     ar.reduce_all(v);
-    inv_r<3, 256, 4>(v, pos_mid(s, 0), ar, 1);
+    inv_rw<3>(v, wb, ar);
+    tw_inv<3, 256, 32>(wc, s, ar, 1);
 #pragma unroll
     for (int i = 0; i < 8; ++i) lds[col_slot(pos_mid(s, i), col)] = ar.to_bits(v[i]);
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < 8; ++i) v[i] = ar.from_bits(lds[col_slot(pos_wide(s, i), col)]);
     ar.reduce_all(v);
-    inv_r<3, 256, 32>(v, s, ar, 1);
+    inv_rw<3>(v, wc, ar);
     uint64_t *dst = a.dst + (int64_t)lp.poly * a.map.dst_poly_stride + (size_t)lp.row * 65536;
 #pragma unroll
     for (int i = 0; i < 8; ++i) dst[pos_wide(s, i) * 256 + c] = ar.inv_final(v[i]);
