@@ -403,6 +403,32 @@ def main():
     ops["ntt_35_limbs"] = op_stats(lambda s: ctx.ckks_ntt(ntt_poly), reps)
     ops["intt_35_limbs"] = op_stats(lambda s: ctx.ckks_intt(ntt_poly), reps)
 
+    # ---- the rest of Table I at level L: HSquare, then the support operations on whole ciphertexts
+    # (memory-bound: HAdd reads 4 and writes 2 polynomials of L+1 limbs)
+    pt = ctx.empty_poly(level)
+    pt.copy_(ckks.to_device(inputs.random_poly(seed + 98, ps, level)))
+    scal = [int(q) - 7 for q in ps.q[: level + 1]]
+    sup = ctx.empty_ct(level)
+    ops["hsquare"] = op_stats(lambda s: ctx.ckks_hsquare(s[0], s[2], m, ws_h), reps)
+    ops["hadd"] = op_stats(lambda s: ctx.ckks_hadd(s[0], s[1], sup), reps)
+    ops["ptadd"] = op_stats(lambda s: ctx.ckks_ptadd(s[0], pt, sup), reps)
+    ops["ptmult"] = op_stats(lambda s: ctx.ckks_ptmult(s[0], pt, 2.0 ** ps.log_scale, sup), reps)
+    ops["scalar_add"] = op_stats(lambda s: ctx.ckks_scalar_add(s[0], scal, sup), reps)
+    ops["scalar_mult"] = op_stats(lambda s: ctx.ckks_scalar_mult(s[0], scal, 1.0, sup), reps)
+
+    # ---- PtMult + Rescale against the level (the paper's Fig. 5 workload), mean us per pair
+    ptmult_rescale = {}
+    for lv in (30, 25, 20, 15, 10, 5, 1):
+        src = ckks.Ciphertext(sets[0][0].c0[: lv + 1], sets[0][0].c1[: lv + 1], lv, 2.0 ** ps.log_scale)
+        prod, low = ctx.empty_ct(lv), ctx.empty_ct(lv - 1)
+        ws_lv = ctx.workspace(ckks.OP_RESCALE, lv)
+
+        def pair(s, src=src, prod=prod, low=low, ws_lv=ws_lv, lv=lv):
+            ctx.ckks_ptmult(src, pt[: lv + 1], 2.0 ** ps.log_scale, prod)
+            ctx.ckks_rescale(prod, low, ws_lv)
+
+        ptmult_rescale[str(lv)] = op_stats(pair, reps)["mean_us"]
+
     if args.copy_calibration:
         # 1 GiB copied once; a 512 MiB fill in between evicts the source from the 256 MiB last-level
         # cache, so the copy's counters see the full read and write
@@ -489,6 +515,7 @@ def main():
         "bootstrap_uniform_secret": boot_dense,
         "serving": serving,
         "ops": ops,
+        "ptmult_rescale_us_by_level": ptmult_rescale,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

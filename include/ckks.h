@@ -225,6 +225,37 @@ ckks_status ckks_poly_scalar_mul(ckks_ctx *ctx, const uint64_t *a, const uint64_
 ckks_status ckks_poly_scalar_add(ckks_ctx *ctx, const uint64_t *a, const uint64_t *s, uint64_t *out, uint32_t level,
                                  void *stream);
 
+/*
+ * Ciphertext-level support operations of Table I (ScalarAdd, PtAdd, HAdd,
+ * ScalarMult, PtMult), each one launch over both halves at the level of a:
+ *   ckks_hadd        : out = (a0 + b0, a1 + b1)        out->scale = a->scale
+ *   ckks_ptadd       : out = (a0 + pt, a1)             out->scale = a->scale
+ *   ckks_ptmult      : out = (a0 pt, a1 pt)            out->scale = a->scale * pt_scale
+ *   ckks_scalar_add  : out = (a0 + s, a1)              out->scale = a->scale
+ *   ckks_scalar_mult : out = (a0 s, a1 s)              out->scale = a->scale * s_scale
+ * b must be at a's level (else CKKS_E_LEVEL).  pt: device [l+1][N] in the
+ * evaluation domain (rows q_0..q_l of an encoded plaintext; the caller keeps
+ * its scale).  s: host array [l+1], s[i] < q_i, an integer constant in RNS
+ * form (else CKKS_E_ARG).  Scales are host metadata: adding operands of
+ * different scales is the caller's error, not detected.  out is either the
+ * same buffers as a (or b) or disjoint from them and from pt (else
+ * CKKS_E_ARG); out->level = a->level.  No workspace.
+ */
+ckks_status ckks_hadd(ckks_ctx *ctx, const ckks_ct *a, const ckks_ct *b, ckks_ct *out, void *stream);
+ckks_status ckks_ptadd(ckks_ctx *ctx, const ckks_ct *a, const uint64_t *pt, ckks_ct *out, void *stream);
+ckks_status ckks_ptmult(ckks_ctx *ctx, const ckks_ct *a, const uint64_t *pt, double pt_scale, ckks_ct *out,
+                        void *stream);
+ckks_status ckks_scalar_add(ckks_ctx *ctx, const ckks_ct *a, const uint64_t *s, ckks_ct *out, void *stream);
+ckks_status ckks_scalar_mult(ckks_ctx *ctx, const ckks_ct *a, const uint64_t *s, double s_scale, ckks_ct *out,
+                             void *stream);
+
+/*
+ * HSquare: HMult of a ciphertext with itself (d0 = a0^2, d1 = 2 a0 a1,
+ * d2 = a1^2), relinearised; the contract of ckks_hmult_relin with b = a.
+ * ws: CKKS_OP_HMULT.
+ */
+ckks_status ckks_hsquare(ckks_ctx *ctx, const ckks_ct *a, const ckks_key *rlk, ckks_ct *out, void *ws, void *stream);
+
 /* Eval-domain automorphism alone: out[k] = in[br(((2 br(k)+1) g mod 2N - 1)/2)] on n_limbs limbs. */
 ckks_status ckks_automorph(ckks_ctx *ctx, const uint64_t *in, uint32_t galois, uint64_t *out, uint32_t n_limbs,
                            void *stream);

@@ -78,6 +78,12 @@ _sigs = {
     "ckks_poly_scalar_mul": (ctypes.c_int, [_vp, _vp, _u64p, _vp, _u32, _vp]),
     "ckks_poly_scalar_add": (ctypes.c_int, [_vp, _vp, _u64p, _vp, _u32, _vp]),
     "ckks_automorph": (ctypes.c_int, [_vp, _vp, _u32, _vp, _u32, _vp]),
+    "ckks_hadd": (ctypes.c_int, [_vp, ctypes.POINTER(_Ct), ctypes.POINTER(_Ct), ctypes.POINTER(_Ct), _vp]),
+    "ckks_ptadd": (ctypes.c_int, [_vp, ctypes.POINTER(_Ct), _vp, ctypes.POINTER(_Ct), _vp]),
+    "ckks_ptmult": (ctypes.c_int, [_vp, ctypes.POINTER(_Ct), _vp, ctypes.c_double, ctypes.POINTER(_Ct), _vp]),
+    "ckks_scalar_add": (ctypes.c_int, [_vp, ctypes.POINTER(_Ct), _u64p, ctypes.POINTER(_Ct), _vp]),
+    "ckks_scalar_mult": (ctypes.c_int, [_vp, ctypes.POINTER(_Ct), _u64p, ctypes.c_double, ctypes.POINTER(_Ct), _vp]),
+    "ckks_hsquare": (ctypes.c_int, [_vp, ctypes.POINTER(_Ct), _vp, ctypes.POINTER(_Ct), _vp, _vp]),
     "ckks_batch_workspace_bytes": (ctypes.c_size_t, [_vp, ctypes.POINTER(_Work), _u32]),
     "ckks_batch_create": (ctypes.c_int, [_vp, ctypes.POINTER(_Work), _u32, _vp, ctypes.POINTER(_vp)]),
     "ckks_batch_run": (ctypes.c_int, [_vp, _vp]),
@@ -253,6 +259,44 @@ class Context:
         ca, cb, co = a._c(), b._c(), out._c()
         _check(_lib.ckks_hmult_relin(self.handle, ctypes.byref(ca), ctypes.byref(cb), rlk.handle, ctypes.byref(co),
                                      _ptr(ws), _stream(stream)), "ckks_hmult_relin")
+        out.level, out.scale = co.level, co.scale
+
+    def ckks_hsquare(self, a: Ciphertext, rlk: Key, out: Ciphertext, ws=None, stream=None):
+        ws = self.workspace(OP_HMULT, a.level) if ws is None else ws
+        ca, co = a._c(), out._c()
+        _check(_lib.ckks_hsquare(self.handle, ctypes.byref(ca), rlk.handle, ctypes.byref(co), _ptr(ws),
+                                 _stream(stream)), "ckks_hsquare")
+        out.level, out.scale = co.level, co.scale
+
+    # Table I support operations on whole ciphertexts
+    def ckks_hadd(self, a: Ciphertext, b: Ciphertext, out: Ciphertext, stream=None):
+        ca, cb, co = a._c(), b._c(), out._c()
+        _check(_lib.ckks_hadd(self.handle, ctypes.byref(ca), ctypes.byref(cb), ctypes.byref(co), _stream(stream)),
+               "ckks_hadd")
+        out.level, out.scale = co.level, co.scale
+
+    def ckks_ptadd(self, a: Ciphertext, pt, out: Ciphertext, stream=None):
+        ca, co = a._c(), out._c()
+        _check(_lib.ckks_ptadd(self.handle, ctypes.byref(ca), _ptr(pt), ctypes.byref(co), _stream(stream)),
+               "ckks_ptadd")
+        out.level, out.scale = co.level, co.scale
+
+    def ckks_ptmult(self, a: Ciphertext, pt, pt_scale: float, out: Ciphertext, stream=None):
+        ca, co = a._c(), out._c()
+        _check(_lib.ckks_ptmult(self.handle, ctypes.byref(ca), _ptr(pt), pt_scale, ctypes.byref(co),
+                                _stream(stream)), "ckks_ptmult")
+        out.level, out.scale = co.level, co.scale
+
+    def ckks_scalar_add(self, a: Ciphertext, residues, out: Ciphertext, stream=None):
+        ca, co = a._c(), out._c()
+        _check(_lib.ckks_scalar_add(self.handle, ctypes.byref(ca), _u64arr(residues), ctypes.byref(co),
+                                    _stream(stream)), "ckks_scalar_add")
+        out.level, out.scale = co.level, co.scale
+
+    def ckks_scalar_mult(self, a: Ciphertext, residues, scale: float, out: Ciphertext, stream=None):
+        ca, co = a._c(), out._c()
+        _check(_lib.ckks_scalar_mult(self.handle, ctypes.byref(ca), _u64arr(residues), scale, ctypes.byref(co),
+                                     _stream(stream)), "ckks_scalar_mult")
         out.level, out.scale = co.level, co.scale
 
     def ckks_rescale(self, inp: Ciphertext, out: Ciphertext, ws=None, stream=None):

@@ -541,6 +541,89 @@ extern "C" ckks_status ckks_poly_scalar_add(ckks_ctx *ctx, const uint64_t *a, co
     return elementwise(ctx, 5, a, nullptr, nullptr, out, s, level, stream, "ckks_poly_scalar_add");
 }
 
+// Table I support operations on whole ciphertexts (one launch over both halves)
+static ckks_status ct_op(ckks_ctx *ctx, int op, const ckks_ct *a, const ckks_ct *b, const uint64_t *pt,
+                         const uint64_t *s, double scale_mul, ckks_ct *out, void *stream, const char *what)
+{
+    TRY(check_ctx(ctx));
+    TRY(check_ct(ctx, a, what));
+    const uint32_t level = a->level;
+    if (op == CT_HADD) {
+        TRY(check_ct(ctx, b, what));
+        if (b->level != level) return fail(CKKS_E_LEVEL, std::string(what) + ": operands at different levels");
+    }
+    const bool uses_pt = op == CT_PTADD || op == CT_PTMULT, uses_s = op == CT_SCALAR_ADD || op == CT_SCALAR_MULT;
+    if (uses_pt) TRY(check_ptr(pt, what));
+    if (uses_s) {
+        if (!s) return fail(CKKS_E_ARG, std::string(what) + ": null scalars");
+        for (uint32_t i = 0; i <= level; ++i)
+            if (s[i] >= ctx->primes[i]) return fail(CKKS_E_ARG, std::string(what) + ": scalar not reduced modulo its prime");
+    }
+    if (!out) return fail(CKKS_E_ARG, std::string(what) + ": null output");
+    ckks_ct o = *out;
+    o.level = level;
+    TRY(check_ct(ctx, &o, what));
+    const size_t pb = poly_bytes(ctx, level);
+    // the output is either exactly an input's buffers (in place) or disjoint from every input
+    const ckks_ct *ins[2] = {a, op == CT_HADD ? b : nullptr};
+    for (const ckks_ct *x : ins)
+        if (x && !(o.c0 == x->c0 && o.c1 == x->c1))
+            TRY(check_disjoint(ctx, &o, x, level, level, what));
+    if (uses_pt && (overlap(pt, pb, o.c0, pb) || overlap(pt, pb, o.c1, pb)))
+        return fail(CKKS_E_ARG, std::string(what) + ": output overlaps the plaintext");
+    CtOpArgs args;
+    memset(&args, 0, sizeof(args));
+    args.a[0] = a->c0;
+    args.a[1] = a->c1;
+    args.b[0] = op == CT_HADD ? b->c0 : pt;
+    args.b[1] = op == CT_HADD ? b->c1 : pt;
+    args.out[0] = o.c0;
+    args.out[1] = o.c1;
+    args.primes = ctx->d_primes;
+    args.logn = ctx->logn;
+    if (uses_s)
+        for (uint32_t i = 0; i <= level; ++i) args.s[i] = s[i];
+    const bool copy_half = op == CT_PTADD || op == CT_SCALAR_ADD;
+    const uint32_t halves = copy_half && o.c1 == a->c1 ? 1 : 2;
+    TRY(dev(launch_ct_op(op, args, level + 1, halves, S(stream)), what));
+    out->level = level;
+    out->scale = a->scale * scale_mul;
+    return CKKS_OK;
+}
+
+extern "C" ckks_status ckks_hadd(ckks_ctx *ctx, const ckks_ct *a, const ckks_ct *b, ckks_ct *out, void *stream)
+{
+    return ct_op(ctx, CT_HADD, a, b, nullptr, nullptr, 1.0, out, stream, "ckks_hadd");
+}
+
+extern "C" ckks_status ckks_ptadd(ckks_ctx *ctx, const ckks_ct *a, const uint64_t *pt, ckks_ct *out, void *stream)
+{
+    return ct_op(ctx, CT_PTADD, a, nullptr, pt, nullptr, 1.0, out, stream, "ckks_ptadd");
+}
+
+extern "C" ckks_status ckks_ptmult(ckks_ctx *ctx, const ckks_ct *a, const uint64_t *pt, double pt_scale, ckks_ct *out,
+                                   void *stream)
+{
+    return ct_op(ctx, CT_PTMULT, a, nullptr, pt, nullptr, pt_scale, out, stream, "ckks_ptmult");
+}
+
+extern "C" ckks_status ckks_scalar_add(ckks_ctx *ctx, const ckks_ct *a, const uint64_t *s, ckks_ct *out, void *stream)
+{
+    return ct_op(ctx, CT_SCALAR_ADD, a, nullptr, nullptr, s, 1.0, out, stream, "ckks_scalar_add");
+}
+
+extern "C" ckks_status ckks_scalar_mult(ckks_ctx *ctx, const ckks_ct *a, const uint64_t *s, double s_scale,
+                                        ckks_ct *out, void *stream)
+{
+    return ct_op(ctx, CT_SCALAR_MULT, a, nullptr, nullptr, s, s_scale, out, stream, "ckks_scalar_mult");
+}
+
+extern "C" ckks_status ckks_hsquare(ckks_ctx *ctx, const ckks_ct *a, const ckks_key *rlk, ckks_ct *out, void *ws,
+                                    void *stream)
+{
+    return ckks_hmult_relin(ctx, a, a, rlk, out, ws, stream);
+}
+
 extern "C" ckks_status ckks_automorph(ckks_ctx *ctx, const uint64_t *in, uint32_t galois, uint64_t *out,
                                       uint32_t n_limbs, void *stream)
 {

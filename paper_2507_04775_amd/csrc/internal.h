@@ -194,6 +194,18 @@ struct IpArgs {
     uint32_t own_galois;        // own_galois), not from ext
 };
 
+enum CtOp { CT_HADD = 0, CT_PTADD, CT_PTMULT, CT_SCALAR_ADD, CT_SCALAR_MULT };
+
+// One ciphertext-level support operation: halves t = 0, 1 of a (and b, or the
+// plaintext in b[0]), scalars s[l] per limb, written to out[t].
+struct CtOpArgs {
+    const uint64_t *a[2], *b[2];
+    uint64_t *out[2];
+    const Prime *primes;
+    uint32_t logn, pad;
+    uint64_t s[kMaxPrimes];
+};
+
 struct TensorArgs {
     const uint64_t *a0, *a1, *b0, *b1;
     uint64_t *d0, *d1, *d2;
@@ -247,6 +259,8 @@ hipError_t launch_tensor(const uint64_t *a0, const uint64_t *a1, const uint64_t 
 hipError_t launch_elementwise(int op, const uint64_t *a, const uint64_t *b, const uint64_t *c, uint64_t *out,
                               const uint64_t *host_scalars, const Prime *primes, uint32_t nlimbs, uint32_t logn,
                               hipStream_t stream);
+// halves: 2, or 1 to leave half 1 untouched (in place PtAdd / ScalarAdd)
+hipError_t launch_ct_op(int op, const CtOpArgs &a, uint32_t nlimbs, uint32_t halves, hipStream_t stream);
 hipError_t launch_automorph(const uint64_t *in, uint64_t *out, uint32_t nlimbs, uint32_t logn, uint32_t galois,
                             hipStream_t stream);
 hipError_t launch_lincomb(const LincombArgs &a, uint32_t nlimbs, hipStream_t stream);

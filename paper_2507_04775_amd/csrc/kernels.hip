@@ -197,6 +197,26 @@ __global__ __launch_bounds__(kThreads) void k_elementwise(const uint64_t *a, con
     out[i] = r;
 }
 
+// Ciphertext-level support operations of Table I over both halves in one
+// launch (blockIdx.z = half t): HAdd a_t + b_t; PtAdd a_0 + pt and a copy of
+// a_1; PtMult a_t pt; ScalarAdd a_0 + s and a copy of a_1; ScalarMult a_t s.
+// The copy half is skipped (grid z = 1) when the output is the input.
+template <int OP>
+__global__ __launch_bounds__(kThreads) void k_ct_op(CtOpArgs a)
+{
+    const uint32_t l = blockIdx.y, t = blockIdx.z;
+    const size_t i = ((size_t)l << a.logn) + blockIdx.x * kThreads + threadIdx.x;
+    const Prime P = a.primes[l];
+    const uint64_t x = a.a[t][i];
+    uint64_t r;
+    if (OP == CT_HADD) r = addmod(x, a.b[t][i], P.q);
+    else if (OP == CT_PTADD) r = t == 0 ? addmod(x, a.b[0][i], P.q) : x;
+    else if (OP == CT_PTMULT) r = mulmod(x, a.b[0][i], P);
+    else if (OP == CT_SCALAR_ADD) r = t == 0 ? addmod(x, a.s[l], P.q) : x;
+    else r = mulmod(x, a.s[l], P);
+    a.out[t][i] = r;
+}
+
 __global__ __launch_bounds__(kThreads) void k_automorph(const uint64_t *__restrict__ in, uint64_t *__restrict__ out,
                                                         uint32_t logn, uint32_t g)
 {
@@ -372,6 +392,20 @@ hipError_t launch_elementwise(int op, const uint64_t *a, const uint64_t *b, cons
     case 3: hipLaunchKernelGGL((k_elementwise<3>), grid, block, 0, stream, a, b, c, out, sc, primes, logn); break;
     case 4: hipLaunchKernelGGL((k_elementwise<4>), grid, block, 0, stream, a, b, c, out, sc, primes, logn); break;
     case 5: hipLaunchKernelGGL((k_elementwise<5>), grid, block, 0, stream, a, b, c, out, sc, primes, logn); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_ct_op(int op, const CtOpArgs &a, uint32_t nlimbs, uint32_t halves, hipStream_t stream)
+{
+    dim3 grid((1u << a.logn) / kThreads, nlimbs, halves), block(kThreads);
+    switch (op) {
+    case CT_HADD: hipLaunchKernelGGL((k_ct_op<CT_HADD>), grid, block, 0, stream, a); break;
+    case CT_PTADD: hipLaunchKernelGGL((k_ct_op<CT_PTADD>), grid, block, 0, stream, a); break;
+    case CT_PTMULT: hipLaunchKernelGGL((k_ct_op<CT_PTMULT>), grid, block, 0, stream, a); break;
+    case CT_SCALAR_ADD: hipLaunchKernelGGL((k_ct_op<CT_SCALAR_ADD>), grid, block, 0, stream, a); break;
+    case CT_SCALAR_MULT: hipLaunchKernelGGL((k_ct_op<CT_SCALAR_MULT>), grid, block, 0, stream, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

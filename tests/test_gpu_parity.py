@@ -208,3 +208,65 @@ def test_elementwise_ops(name):
     g = oracle.galois_for_rotation(lg, 7)
     s.ctx.ckks_automorph(ta, g, out)
     assert_equal(s.host(out), oracle.automorph_eval(lg, g, a), "automorph")
+
+
+@pytest.mark.parametrize("name", ["small", "large"])
+def test_table_i_ciphertext_ops(name):
+    """HAdd, PtAdd, PtMult, ScalarAdd, ScalarMult on whole ciphertexts (out of
+    place and in place) and HSquare, each against the oracle applied per half."""
+    s = setup(name)
+    lg = s.ps.logn
+    key, kh = s.key(9, 0)
+    for level in (LEVELS[name][0], LEVELS[name][2], 0):
+        mods = s.ps.q[: level + 1]
+        (a0, a1), ta = s.ct(400 + level, level)
+        (b0, b1), tb = s.ct(410 + level, level)
+        pt = inputs.random_poly(420 + level, s.ps, level)
+        tpt = s.dev(pt)
+        sc = [int(m) - 2 - 3 * i for i, m in enumerate(mods)]
+        scal = np.array([[v] * s.N for v in sc], dtype=np.uint64)
+        add = lambda x, y: oracle.vec(mods, x, y, "add", lg)
+        mul = lambda x, y: oracle.vec(mods, x, y, "mul", lg)
+        cases = [
+            ("hadd", lambda o: s.ctx.ckks_hadd(ta, tb, o), (add(a0, b0), add(a1, b1))),
+            ("ptadd", lambda o: s.ctx.ckks_ptadd(ta, tpt, o), (add(a0, pt), a1)),
+            ("ptmult", lambda o: s.ctx.ckks_ptmult(ta, tpt, 2.0 ** 40, o), (mul(a0, pt), mul(a1, pt))),
+            ("scalar_add", lambda o: s.ctx.ckks_scalar_add(ta, sc, o), (add(a0, scal), a1)),
+            ("scalar_mult", lambda o: s.ctx.ckks_scalar_mult(ta, sc, 3.0, o), (mul(a0, scal), mul(a1, scal))),
+        ]
+        for what, run, (w0, w1) in cases:
+            out = s.ctx.empty_ct(level)
+            run(out)
+            assert out.level == level
+            assert_equal(s.host(out.c0), w0, "%s c0 level %d" % (what, level))
+            assert_equal(s.host(out.c1), w1, "%s c1 level %d" % (what, level))
+        assert out.scale == 3.0 * ta.scale
+        # in place: the output is the input's own buffers
+        c0, c1 = ta.c0.clone(), ta.c1.clone()
+        tin = s.ckks.Ciphertext(c0, c1, level, 1.0)
+        s.ctx.ckks_ptadd(tin, tpt, tin)
+        s.ctx.ckks_hadd(tin, tb, tin)
+        s.ctx.ckks_scalar_mult(tin, sc, 1.0, tin)
+        assert_equal(s.host(c0), mul(add(add(a0, pt), b0), scal), "in place c0 level %d" % level)
+        assert_equal(s.host(c1), mul(add(a1, b1), scal), "in place c1 level %d" % level)
+        if level > 0:
+            out = s.ctx.empty_ct(level)
+            s.ctx.ckks_hsquare(ta, kh, out)
+            w0, w1 = oracle.hmult_relin(s.P, (a0, a1), (a0, a1), key, level)
+            assert_equal(s.host(out.c0), w0, "hsquare c0 level %d" % level)
+            assert_equal(s.host(out.c1), w1, "hsquare c1 level %d" % level)
+
+
+@pytest.mark.parametrize("name", ["small"])
+def test_table_i_ops_reject_bad_arguments(name):
+    s = setup(name)
+    (_, _), ta = s.ct(430, 2)
+    (_, _), tb = s.ct(431, 1)
+    out = s.ctx.empty_ct(2)
+    with pytest.raises(s.ckks.CkksError, match="different levels"):
+        s.ctx.ckks_hadd(ta, tb, out)
+    with pytest.raises(s.ckks.CkksError, match="not reduced"):
+        s.ctx.ckks_scalar_add(ta, [int(m) for m in s.ps.q[:3]], out)
+    part = s.ckks.Ciphertext(ta.c0, out.c1, 2, 1.0)  # shares c0 with the input but not c1
+    with pytest.raises(s.ckks.CkksError, match="overlaps"):
+        s.ctx.ckks_ptadd(ta, s.dev(inputs.random_poly(432, s.ps, 2)), part)
