@@ -66,8 +66,8 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from . import apply_galois, galois_conjugate, galois_for_rotation, hmult_relin, hoisted_rotate
-from . import Params, intt, keyswitch, ntt, reduce_f64, rescale, vec
+from . import apply_galois, automorph_eval, galois_conjugate, galois_for_rotation, hmult_relin, hoisted_rotate
+from . import Params, inner_product, intt, keyswitch, moddown, modup, ntt, reduce_f64, rescale, vec
 from .client import embed_inverse
 
 
@@ -82,6 +82,7 @@ class BootParams:
     top_scale: float              # Delta_L
     in_scale: float               # scale of the level-0 input
     cheb_baby: int = 0            # baby-step size of the Chebyshev evaluation (0: smallest b with b^2 > d)
+    hoist_moddown: bool = False   # giant steps key-switched without ModDown, summed over Q u P, one ModDown per group
 
     @property
     def baby(self) -> int:
@@ -224,6 +225,21 @@ def output_level(P: Params, bp: BootParams) -> int:
 
 
 # ------------------------------------------------------------------ planner
+
+def ext_p(P: Params, x: np.ndarray, l: int, g: int = 1) -> np.ndarray:
+    """The extended polynomial equal to P phi_g(x) for x at level l: rows
+    q_0..q_l hold [P]_(q_i) phi_g(x), rows p_0..p_(K-1) are zero (P vanishes
+    there)."""
+    src = x if g == 1 else automorph_eval(P.logn, g, x)
+    Pp = 1
+    for m in P.p:
+        Pp *= int(m)
+    mods = P.q[: l + 1]
+    consts = np.array([[Pp % int(m)] * P.N for m in mods], dtype=np.uint64)
+    out = np.zeros((l + 1 + len(P.p), P.N), dtype=np.uint64)
+    out[: l + 1] = vec(mods, src, consts, "mul", P.logn)
+    return out
+
 
 def special_fft_stage(n: int, logn: int, h: int, inverse: bool):
     """One butterfly stage of the special FFT (or its inverse) as {offset mod n: diagonal}."""
@@ -446,6 +462,8 @@ class Executor:
             rots = [(ct[0], ct[1])]
         mods = self.mods(l)
         G = giant_offsets(n, halves)
+        if self.bp.hoist_moddown:
+            return self._linear_transform_hoisted(rots, diags, count, baby, giants, G, l, rescales)
         total = None
         for g in range(giants):
             s0 = s1 = None
@@ -462,6 +480,43 @@ class Executor:
             if G[g] % n:
                 part = self.rotate(part, G[g])
             total = part if total is None else self.add(total, part)
+        for _ in range(rescales):
+            total = self.rescale(total)
+        return total
+
+    def _linear_transform_hoisted(self, rots, diags, count, baby, giants, G, l, rescales):
+        """Giant steps with the ModDown hoisted out of the loop.  Each giant's
+        sum s = sum_b pt_b rot_b is rotated by G without its ModDown: the key
+        switch of phi_G(s_1) stays in the extended basis Q u P and P phi_G(s_0)
+        joins it there, so (k_0 + P phi_G(s_0), k_1) is P times the rotation
+        of s before rounding.  A giant with G = 0 enters as P s.  The parts
+        are summed over Q u P and divided by P with one ModDown per half;
+        ModDown(P y + z) = y + ModDown(z) exactly, so each giant contributes as
+        in the plain schedule except for the single rounding."""
+        n, lg = self.bp.n, self.P.logn
+        mods = self.mods(l)
+        emods = list(mods) + [int(m) for m in self.P.p]
+        tot = None
+        for g in range(giants):
+            s0 = s1 = None
+            for b in range(baby):
+                i = g * baby + b
+                if i >= count:
+                    break
+                pt = self.plaintext(diags[i], l)
+                t0 = vec(mods, rots[b][0], pt, "mul", lg)
+                t1 = vec(mods, rots[b][1], pt, "mul", lg)
+                s0 = t0 if s0 is None else vec(mods, s0, t0, "add", lg)
+                s1 = t1 if s1 is None else vec(mods, s1, t1, "add", lg)
+            k = G[g] % n
+            if k:
+                gal = galois_for_rotation(lg, k)
+                acc = inner_product(self.P, modup(self.P, automorph_eval(lg, gal, s1), l), self.rk[k], l)
+                part = (vec(emods, acc[0], ext_p(self.P, s0, l, gal), "add", lg), acc[1])
+            else:
+                part = (ext_p(self.P, s0, l), ext_p(self.P, s1, l))
+            tot = part if tot is None else tuple(vec(emods, tot[t], part[t], "add", lg) for t in range(2))
+        total = (moddown(self.P, tot[0], l), moddown(self.P, tot[1], l), l)
         for _ in range(rescales):
             total = self.rescale(total)
         return total

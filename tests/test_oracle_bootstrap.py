@@ -212,3 +212,55 @@ def test_chebyshev_split_reconstructs_the_series():
         TG = np.cos(G * np.arccos(y))
         got = np.polynomial.chebyshev.chebval(y, q) * TG + np.polynomial.chebyshev.chebval(y, r)
         assert np.max(np.abs(got - np.polynomial.chebyshev.chebval(y, c))) < 1e-12
+
+
+def test_moddown_passes_multiples_of_p_exactly():
+    """ModDown(P y + z) = y + ModDown(z) on every limb: the identity that lets
+    a hoisted schedule add P-scaled terms in the extended basis."""
+    ps = inputs.params("boot-small")
+    cs = ClientSetup(ps, seed=5)
+    l = 3
+    g = inputs.rng(77)
+    y = inputs.uniform_residues(g, ps.q[: l + 1], ps.N)
+    z = inputs.uniform_residues(g, list(ps.q[: l + 1]) + list(ps.p), ps.N)
+    emods = list(ps.q[: l + 1]) + list(ps.p)
+    lhs = oracle.moddown(cs.P, oracle.vec(emods, B.ext_p(cs.P, y, l), z, "add", ps.logn), l)
+    rhs = oracle.vec(ps.q[: l + 1], y, oracle.moddown(cs.P, z, l), "add", ps.logn)
+    assert np.array_equal(lhs, rhs)
+
+
+def test_hoisted_giant_with_one_part_is_the_plain_rotation():
+    """One giant of the hoisted schedule, ModDown applied to it alone, is
+    bit-identical to the oracle's plain HRotate of the same ciphertext."""
+    ps = inputs.params("boot-small")
+    cs = ClientSetup(ps, seed=6)
+    l, k = 3, 5
+    gal = oracle.galois_for_rotation(ps.logn, k)
+    key = cs.galois_key(gal)
+    g = inputs.rng(78)
+    s0, s1 = (inputs.uniform_residues(g, ps.q[: l + 1], ps.N) for _ in range(2))
+    emods = list(ps.q[: l + 1]) + list(ps.p)
+    acc = oracle.inner_product(cs.P, oracle.modup(cs.P, oracle.automorph_eval(ps.logn, gal, s1), l), key, l)
+    got0 = oracle.moddown(cs.P, oracle.vec(emods, acc[0], B.ext_p(cs.P, s0, l, gal), "add", ps.logn), l)
+    got1 = oracle.moddown(cs.P, acc[1], l)
+    want0, want1 = oracle.apply_galois(cs.P, (s0, s1), gal, key, l)
+    assert np.array_equal(got0, want0) and np.array_equal(got1, want1)
+
+
+def test_hoisted_coeff_to_slot_and_bootstrap(boot_small):
+    """ModDown hoisted out of every giant-step loop: CoeffToSlot still moves
+    the coefficients into the slots, and the bootstrap recovers the input as
+    precisely as the plain schedule."""
+    cs, ex0, z, ct = boot_small
+    ex = B.Executor(cs.P, ex0.pl, ex0.rlk, ex0.ck, ex0.rk)
+    ex.bp = B.BootParams(**dict(BP_SMALL, hoist_moddown=True))
+    r = ex.modraise(ct)
+    t = _raised_coefficients(cs, r)
+    n, q0, K = cs.ps.N // 2, cs.ps.q[0], ex.bp.k_range
+    c = ex.coeff_to_slot(r)
+    perm = np.array([br(x, cs.ps.logn - 1) for x in range(n)])
+    want = (t[:n].astype(float) + 1j * t[n:].astype(float))[perm] / (2 * q0 * K)
+    assert max_err_bits(cs.decrypt((c[0], c[1]), c[2], ex.sc[c[2]]), want) < -30
+    out = ex.bootstrap(ct)
+    err = max_err_bits(cs.decrypt((out[0], out[1]), out[2], ex.sc[out[2]]), z)
+    assert out[2] == 1 and err < -9.5, err
