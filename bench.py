@@ -191,36 +191,44 @@ def run_bootstrap(seed, args, sparse=True):
     sp = cl.sparse_keys(bootplan.SPARSE_H) if sparse else None
     torch.cuda.synchronize()
     t_keys = time.perf_counter() - t0
-    boot = ckks.Boot(ctx, cfg.cts_radix_logs, cfg.stc_radix_logs, pl.cts, pl.stc, pl.cheb, cfg.double_angles,
-                     cfg.top_scale, relin, conj, rot, sparse=sp)
     z = inputs.complex_slots(inputs.rng(seed + 5), ps.N // 2)
     ct = cl.encrypt(z, 0, scale)
-    out = ctx.empty_ct(boot.output_level)
-    stream = torch.cuda.current_stream()
-    boot.ckks_bootstrap(ct, out)
-    torch.cuda.synchronize()
-    err = float(np.log2(np.max(np.abs(cl.decrypt(out) - z))))
     reps = max(3, args.boot_reps)
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
-    ev[0].record(stream)
-    for i in range(reps):
+
+    def measure(hoist):
+        boot = ckks.Boot(ctx, cfg.cts_radix_logs, cfg.stc_radix_logs, pl.cts, pl.stc, pl.cheb, cfg.double_angles,
+                         cfg.top_scale, relin, conj, rot, sparse=sp, hoist_moddown=hoist)
+        out = ctx.empty_ct(boot.output_level)
+        stream = torch.cuda.current_stream()
         boot.ckks_bootstrap(ct, out)
-        ev[i + 1].record(stream)
-    torch.cuda.synchronize()
-    eager = [ev[i].elapsed_time(ev[i + 1]) for i in range(reps)]
-    gs = torch.cuda.Stream()
-    out_g = ctx.empty_ct(boot.output_level)
-    boot.capture(ct, out_g, gs)
-    boot.replay(gs)
-    gs.synchronize()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
-    ev[0].record(gs)
-    for i in range(reps):
+        torch.cuda.synchronize()
+        err = float(np.log2(np.max(np.abs(cl.decrypt(out) - z))))
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+        ev[0].record(stream)
+        for i in range(reps):
+            boot.ckks_bootstrap(ct, out)
+            ev[i + 1].record(stream)
+        torch.cuda.synchronize()
+        eager = [ev[i].elapsed_time(ev[i + 1]) for i in range(reps)]
+        gs = torch.cuda.Stream()
+        out_g = ctx.empty_ct(boot.output_level)
+        boot.capture(ct, out_g, gs)
         boot.replay(gs)
-        ev[i + 1].record(gs)
-    gs.synchronize()
-    graph = [ev[i].elapsed_time(ev[i + 1]) for i in range(reps)]
-    same = bool(torch.equal(out_g.c0, out.c0) and torch.equal(out_g.c1, out.c1))
+        gs.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+        ev[0].record(gs)
+        for i in range(reps):
+            boot.replay(gs)
+            ev[i + 1].record(gs)
+        gs.synchronize()
+        graph = [ev[i].elapsed_time(ev[i + 1]) for i in range(reps)]
+        same = bool(torch.equal(out_g.c0, out.c0) and torch.equal(out_g.c1, out.c1))
+        return boot, err, eager, graph, same
+
+    # the plain schedule (one ModDown per rotation, as in the paper) for comparison
+    plain, perr, _, pgraph, _ = measure(False)
+    plain.close()
+    boot, err, eager, graph, same = measure(cfg.hoist_moddown)
     g50 = percentile(graph, 50)
     res = {"bootstraps_per_s": round(1e3 / g50, 2), "graph_p50_ms": round(g50, 3),
            "graph_p99_ms": round(percentile(graph, 99), 3), "eager_p50_ms": round(percentile(eager, 50), 3),
@@ -228,11 +236,14 @@ def run_bootstrap(seed, args, sparse=True):
            "key_switches": boot.keyswitches, "levels_left": boot.output_level, "slots": ps.N // 2,
            "decrypted_error_bits": round(err, 2), "device_bytes": boot.device_bytes,
            "rotation_keys": len(rot), "plan_s": round(t_plan, 2), "keygen_s": round(t_keys, 2),
+           "plain_schedule": {"graph_p50_ms": round(percentile(pgraph, 50), 3),
+                              "decrypted_error_bits": round(perr, 2)},
            "config": {"logN": ps.logn, "limbs": ps.L + 1, "special_primes": ps.K, "dnum": ps.dnum,
                       "cts_groups": cfg.cts_radix_logs, "stc_groups": cfg.stc_radix_logs,
                       "cheb_degree": cfg.cheb_degree, "cheb_baby": cfg.baby, "double_angles": cfg.double_angles,
                       "k_range": cfg.k_range, "sparse_secret_encapsulation": sparse,
-                      "sparse_h": bootplan.SPARSE_H if sparse else None, "scale_log2": ps.log_scale}}
+                      "sparse_h": bootplan.SPARSE_H if sparse else None, "scale_log2": ps.log_scale,
+                      "hoist_moddown": cfg.hoist_moddown}}
     boot.close()
     del rot, relin, conj, sp
     ctx.close()
@@ -263,7 +274,7 @@ def run_serving(ctx, ps, seed, args):
     bkeys = {k: rkey(seed + 5000 + k, pow(5, k, 2 * ps.N)) for k in pl.rotations}
     boot = ckks.Boot(ctx, cfg.cts_radix_logs, cfg.stc_radix_logs, pl.cts, pl.stc, pl.cheb, cfg.double_angles,
                      cfg.top_scale, relin, rkey(seed + 2, 2 * ps.N - 1), bkeys,
-                     sparse=(rkey(seed + 3, 0), rkey(seed + 4, 0)))
+                     sparse=(rkey(seed + 3, 0), rkey(seed + 4, 0)), hoist_moddown=cfg.hoist_moddown)
     srv = Server(ctx, relin, rot, pts, boot, slots=args.serve_slots, mem_budget=args.serve_mem_gib << 30)
     n = args.serve_requests
     gen = lambda rate, sd: inputs.serving_requests(sd, n, ps.logn, rate)

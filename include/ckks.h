@@ -387,6 +387,9 @@ typedef struct {
     uint32_t n_rot;
     const int32_t *rot_steps;
     const ckks_key *const *rot_keys;
+    uint32_t hoist_moddown;              /* 1: giant steps key-switched without ModDown, summed over Q u P,
+                                            one ModDown per group (fewer roundings, less time); 0: the plain
+                                            schedule, one ModDown per rotation as in the paper */
 } ckks_boot_desc;
 
 ckks_status ckks_boot_create(ckks_ctx *ctx, const ckks_boot_desc *desc, ckks_boot **out);

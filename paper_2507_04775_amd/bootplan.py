@@ -43,6 +43,7 @@ class BootConfig:
     top_scale: float
     in_scale: float
     cheb_baby: int = 0   # baby-step size of the Chebyshev evaluation (0: smallest power of two b with b^2 > d)
+    hoist_moddown: bool = True  # giant steps summed over Q u P with one ModDown per group
 
     @property
     def n(self) -> int:

@@ -46,7 +46,8 @@ class _BootDesc(ctypes.Structure):
                 ("stc_diags", ctypes.POINTER(_vp)), ("cheb_degree", _u32), ("cheb", ctypes.POINTER(ctypes.c_double)),
                 ("cheb_baby", _u32), ("double_angles", _u32), ("top_scale", ctypes.c_double), ("relin", _vp), ("conj", _vp),
                 ("to_sparse", _vp), ("from_sparse", _vp),
-                ("n_rot", _u32), ("rot_steps", ctypes.POINTER(_i32)), ("rot_keys", ctypes.POINTER(_vp))]
+                ("n_rot", _u32), ("rot_steps", ctypes.POINTER(_i32)), ("rot_keys", ctypes.POINTER(_vp)),
+                ("hoist_moddown", _u32)]
 
 
 _sigs = {
@@ -472,7 +473,7 @@ class Boot:
 
     def __init__(self, ctx: "Context", cts_radix_logs, stc_radix_logs, cts_diags, stc_diags, cheb,
                  double_angles: int, top_scale: float, relin: Key, conj: Key, rot_keys: dict, cheb_baby: int = 0,
-                 sparse: Optional[tuple] = None):
+                 sparse: Optional[tuple] = None, hoist_moddown: bool = False):
         import numpy as np
         self.ctx = ctx
         self._keys = [relin, conj] + list(rot_keys.values())
@@ -499,6 +500,7 @@ class Boot:
             d.to_sparse, d.from_sparse = sparse[0].handle, sparse[1].handle
             self._keys += list(sparse)
         d.n_rot, d.rot_steps, d.rot_keys = len(steps), rs, rk
+        d.hoist_moddown = 1 if hoist_moddown else 0
         h = _vp()
         _check(_lib.ckks_boot_create(ctx.handle, ctypes.byref(d), ctypes.byref(h)), "ckks_boot_create")
         self.handle = h

@@ -161,6 +161,31 @@ uint32_t galois_of_rotation(const ckks_ctx *c, int32_t k)
 
 }  // namespace
 
+namespace ckks {
+
+hipError_t keyswitch_extended(ckks_ctx *c, const uint64_t *d, uint32_t g, uint32_t level, const uint64_t *key,
+                              void *ws, hipStream_t st, uint64_t **acc)
+{
+    KsWs w = ks_ws(c, level, ws);
+    *acc = w.acc;
+    hipError_t e = modup_intt(c, d, g, level, w.dc, st);
+    if (e == hipSuccess) e = modup_from_coeffs(c, d, g, level, w.dc, w.ext, false, st);
+    if (e == hipSuccess) e = inner_product(c, w.ext, level, key, 1, w.acc, st, d, g);
+    return e;
+}
+
+hipError_t moddown_pair(ckks_ctx *c, const uint64_t *x, uint32_t level, uint64_t *out0, uint64_t *out1, void *ws,
+                        hipStream_t st)
+{
+    const KsSizes s = ks_sizes(c, level);
+    KsWs w = ks_ws(c, level, ws);
+    uint64_t *outs[2] = {out0, out1};
+    const uint64_t *adds[2] = {nullptr, nullptr};
+    return moddown(c, x, (int64_t)s.rows * s.N, 2, level, outs, adds, 1, w.pc, w.conv, st);
+}
+
+}  // namespace ckks
+
 extern "C" ckks_status ckks_sync(ckks_ctx *ctx, void *stream)
 {
     TRY(check_ctx(ctx));

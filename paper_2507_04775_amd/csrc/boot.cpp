@@ -157,6 +157,10 @@ struct ckks_boot {
     size_t slot_words = 0;
     uint32_t nslots = 0, max_baby = 1;
     size_t ws_bytes = 0;
+    // hoisted ModDown: per lane an extended accumulator pair [2][l+1+K][N] (qp_words per lane)
+    bool hoist = false;
+    uint64_t *qp = nullptr;
+    size_t qp_words = 0;
     Lane lanes[kLanes];
     hipEvent_t events[kEvents] = {};
     uint32_t next_event = 0;
@@ -297,6 +301,88 @@ struct Runner {
         return rescale(out);
     }
 
+    // Giant steps with the ModDown hoisted out of the loop: each lane sums its
+    // giants' parts over Q u P (a key switch left in the extended basis plus
+    // P phi_G(s_0), or P s for G = 0), the lanes' sums are added after the
+    // join, and one ModDown per half brings the total back to Q.
+    ckks_status giants_hoisted(const Group &g, const std::vector<Ct> &src, uint32_t acc_slot)
+    {
+        const uint32_t lvl = g.level, rows = lvl + 1 + ctx()->np;
+        const size_t N = b->N, limb = (size_t)(lvl + 1) * N;
+        Runner lr[kLanes] = {*this, *this, *this, *this};
+        const uint32_t nl = std::min<uint32_t>(kLanes, g.lay.giants);
+        hipEvent_t fork = b->event();
+        if (nl > 1) TRY(dev(hipEventRecord(fork, st), "ckks_bootstrap fork"));
+        for (uint32_t l = 1; l < nl; ++l) {
+            lr[l].st = b->lanes[l].aux;
+            lr[l].ln = &b->lanes[l];
+            TRY(dev(hipStreamWaitEvent(lr[l].st, fork, 0), "ckks_bootstrap fork"));
+        }
+        auto tot = [&](uint32_t l) { return b->qp + (size_t)l * b->qp_words; };
+        FoldArgs base;
+        memset(&base, 0, sizeof(base));
+        base.pmod = ctx()->d_pmod;
+        base.primes = ctx()->d_primes;
+        base.level = lvl;
+        base.nq = ctx()->nq;
+        base.logn = ctx()->logn;
+        bool started[kLanes] = {};
+        for (uint32_t gi = 0; gi < g.lay.giants; ++gi) {
+            const uint32_t ln = gi % nl;
+            Runner &R_ = lr[ln];
+            const Lane &L_ = *R_.ln;
+            const Ct P = b->slot(L_.p, lvl);
+            const uint32_t i0 = gi * g.lay.baby, nb = std::min(g.lay.baby, g.lay.count - i0);
+            const uint32_t G = (uint32_t)(((int64_t)g.giant[gi] % b->n + b->n) % b->n);
+            LincombArgs la;
+            memset(&la, 0, sizeof(la));
+            for (uint32_t j = 0; j < nb; ++j) {
+                la.a0[j] = src[j].c0;
+                la.a1[j] = src[j].c1;
+                la.pt[j] = g.pt + (size_t)(i0 + j) * limb;
+            }
+            la.out0 = P.c0;
+            la.out1 = P.c1;
+            la.primes = ctx()->d_primes;
+            la.n = nb;
+            la.logn = ctx()->logn;
+            TRY(dev(launch_lincomb(la, lvl + 1, R_.st), "ckks_bootstrap lincomb"));
+            FoldArgs fa = base;
+            fa.tot[0] = tot(ln);
+            fa.tot[1] = tot(ln) + (size_t)rows * N;
+            fa.first = !started[ln];
+            started[ln] = true;
+            fa.s[0] = P.c0;
+            if (G != 0) {
+                const ckks_key *rk = b->rot.at(G);
+                uint64_t *acc = nullptr;
+                TRY(dev(keyswitch_extended(ctx(), P.c1, rk->galois, lvl, rk->data, L_.ws, R_.st, &acc),
+                        "ckks_bootstrap giant key switch"));
+                fa.acc[0] = acc;
+                fa.acc[1] = acc + (size_t)rows * N;
+                fa.galois = rk->galois;
+            } else {
+                fa.s[1] = P.c1;
+                fa.galois = 1;
+            }
+            TRY(dev(launch_fold_ext(fa, rows, R_.st), "ckks_bootstrap fold"));
+        }
+        for (uint32_t l = 1; l < nl; ++l) {
+            hipEvent_t join = b->event();
+            TRY(dev(hipEventRecord(join, lr[l].st), "ckks_bootstrap join"));
+            TRY(dev(hipStreamWaitEvent(st, join, 0), "ckks_bootstrap join"));
+            FoldArgs fa = base;
+            fa.tot[0] = tot(0);
+            fa.tot[1] = tot(0) + (size_t)rows * N;
+            fa.acc[0] = tot(l);
+            fa.acc[1] = tot(l) + (size_t)rows * N;
+            fa.galois = 1;
+            TRY(dev(launch_fold_ext(fa, rows, st), "ckks_bootstrap fold"));
+        }
+        const Ct acc = b->slot(acc_slot, lvl);
+        return dev(moddown_pair(ctx(), tot(0), lvl, acc.c0, acc.c1, ln->ws, st), "ckks_bootstrap moddown");
+    }
+
     ckks_status linear_transform(const Group &g, const Ct &in, uint32_t acc_slot, const Ct *final_out, Ct &out)
     {
         const uint32_t lvl = in.level;
@@ -315,6 +401,13 @@ struct Runner {
             ckks_ct I = as_ct(in);
             TRY(ckks_hrotate_hoisted(ctx(), &I, (uint32_t)g.baby_k.size(), g.baby_k.data(), keys.data(), outs.data(),
                                      ln->ws, st));
+        }
+        if (b->hoist) {
+            TRY(giants_hoisted(g, src, acc_slot));
+            Ct c = b->slot(acc_slot, lvl);
+            for (uint32_t r = 0; r < g.rescales; ++r) TRY(rescale(c, (r + 1 == g.rescales) ? final_out : nullptr));
+            out = c;
+            return CKKS_OK;
         }
         // giant steps round-robin over the lanes, each accumulating its own sum
         Runner lr[kLanes] = {*this, *this, *this, *this};
@@ -633,6 +726,7 @@ extern "C" ckks_status ckks_boot_create(ckks_ctx *ctx, const ckks_boot_desc *des
         return fail(CKKS_E_KEY, "ckks_boot_create: sparse-secret keys must be given together");
     }
     b->to_sparse = desc->to_sparse;
+    b->hoist = desc->hoist_moddown != 0;
     b->from_sparse = desc->from_sparse;
     auto bail = [&](ckks_status s, const std::string &m) {
         ckks_boot_destroy(b);
@@ -776,8 +870,10 @@ extern "C" ckks_status ckks_boot_create(ckks_ctx *ctx, const ckks_boot_desc *des
     const size_t off_mono = off_cst + up(std::max<size_t>(cst.size(), 1) * 8),
                  off_slots = off_mono + up((size_t)(L + 1) * N * 8);
     const size_t off_ws = off_slots + up(b->nslots * b->slot_words * 8);
+    b->qp_words = b->hoist ? 2 * (size_t)(L + 1 + ctx->np) * N : 0;
+    const size_t off_qp = off_ws + kLanes * up(wsb);
     b->ws_bytes = up(wsb);
-    b->bytes = off_ws + kLanes * b->ws_bytes;
+    b->bytes = off_qp + kLanes * b->qp_words * 8;
     if (hipSetDevice(ctx->device) != hipSuccess || hipMalloc(&b->dev, b->bytes) != hipSuccess) {
         b->dev = nullptr;
         return bail(CKKS_E_NOMEM, "device allocation of " + std::to_string(b->bytes) + " bytes failed");
@@ -787,6 +883,7 @@ extern "C" ckks_status ckks_boot_create(ckks_ctx *ctx, const ckks_boot_desc *des
     b->leaf_cst = (uint64_t *)(base + off_cst);
     b->slots = (uint64_t *)(base + off_slots);
     b->assign_lanes(base + off_ws);
+    b->qp = b->hoist ? (uint64_t *)(base + off_qp) : nullptr;
     for (uint32_t l = 1; l < kLanes; ++l)
         if (hipStreamCreateWithFlags(&b->lanes[l].aux, hipStreamNonBlocking) != hipSuccess) {
             b->lanes[l].aux = nullptr;

@@ -206,6 +206,19 @@ struct CtOpArgs {
     uint64_t s[kMaxPrimes];
 };
 
+// Accumulation of one giant step in the extended basis (hoisted ModDown):
+// for half t and row r (q_0..q_l, then p_0..p_{K-1}),
+//   part = (acc[t] ? acc[t][r] : 0) + (s[t] && r <= l ? [P]_(q_r) phi_g(s[t])[r] : 0)
+//   tot[t][r] = first ? part : tot[t][r] + part.
+struct FoldArgs {
+    uint64_t *tot[2];
+    const uint64_t *acc[2];
+    const uint64_t *s[2];
+    const uint64_t *pmod;       // [n_primes] P mod q_i
+    const Prime *primes;
+    uint32_t level, nq, logn, galois, first, pad;
+};
+
 struct TensorArgs {
     const uint64_t *a0, *a1, *b0, *b1;
     uint64_t *d0, *d1, *d2;
@@ -259,6 +272,8 @@ hipError_t launch_tensor(const uint64_t *a0, const uint64_t *a1, const uint64_t 
 hipError_t launch_elementwise(int op, const uint64_t *a, const uint64_t *b, const uint64_t *c, uint64_t *out,
                               const uint64_t *host_scalars, const Prime *primes, uint32_t nlimbs, uint32_t logn,
                               hipStream_t stream);
+// rows = l+1+K extended rows
+hipError_t launch_fold_ext(const FoldArgs &a, uint32_t rows, hipStream_t stream);
 // halves: 2, or 1 to leave half 1 untouched (in place PtAdd / ScalarAdd)
 hipError_t launch_ct_op(int op, const CtOpArgs &a, uint32_t nlimbs, uint32_t halves, hipStream_t stream);
 hipError_t launch_automorph(const uint64_t *in, uint64_t *out, uint32_t nlimbs, uint32_t logn, uint32_t galois,
@@ -304,3 +319,17 @@ struct ckks_key {
     uint32_t galois;
     const ckks_ctx *ctx;
 };
+
+namespace ckks {
+
+// Key switch of phi_g(d) (d at `level`, eval domain) without the ModDown: the
+// two accumulators [2][l+1+K][N] over q_0..q_l, p_0..p_{K-1} are left in the
+// workspace (CKKS_OP_KEYSWITCH size) at *acc.
+hipError_t keyswitch_extended(ckks_ctx *c, const uint64_t *d, uint32_t g, uint32_t level, const uint64_t *key,
+                              void *ws, hipStream_t st, uint64_t **acc);
+// ModDown of an extended pair x = [2][l+1+K][N] into out0, out1 at `level`
+// (workspace of CKKS_OP_KEYSWITCH size; x must not lie in it).
+hipError_t moddown_pair(ckks_ctx *c, const uint64_t *x, uint32_t level, uint64_t *out0, uint64_t *out1, void *ws,
+                        hipStream_t st);
+
+}  // namespace ckks

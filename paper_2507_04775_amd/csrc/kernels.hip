@@ -217,6 +217,21 @@ __global__ __launch_bounds__(kThreads) void k_ct_op(CtOpArgs a)
     a.out[t][i] = r;
 }
 
+__global__ __launch_bounds__(kThreads) void k_fold_ext(FoldArgs a)
+{
+    const uint32_t r = blockIdx.y, t = blockIdx.z, N = 1u << a.logn;
+    const uint32_t n = blockIdx.x * kThreads + threadIdx.x;
+    const uint32_t pi = row_prime(r, a.level, a.nq);
+    const Prime P = a.primes[pi];
+    const size_t i = (size_t)r * N + n;
+    uint64_t v = a.acc[t] ? a.acc[t][i] : 0;
+    if (a.s[t] && r <= a.level) {
+        const uint64_t x = a.s[t][(size_t)r * N + (a.galois == 1 ? n : galois_src(n, a.galois, a.logn))];
+        v = addmod(v, mulmod(a.pmod[r], x, P), P.q);
+    }
+    a.tot[t][i] = a.first ? v : addmod(a.tot[t][i], v, P.q);
+}
+
 __global__ __launch_bounds__(kThreads) void k_automorph(const uint64_t *__restrict__ in, uint64_t *__restrict__ out,
                                                         uint32_t logn, uint32_t g)
 {
@@ -394,6 +409,12 @@ hipError_t launch_elementwise(int op, const uint64_t *a, const uint64_t *b, cons
     case 5: hipLaunchKernelGGL((k_elementwise<5>), grid, block, 0, stream, a, b, c, out, sc, primes, logn); break;
     default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_fold_ext(const FoldArgs &a, uint32_t rows, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_fold_ext, dim3((1u << a.logn) / kThreads, rows, 2), dim3(kThreads), 0, stream, a);
     return hipGetLastError();
 }
 

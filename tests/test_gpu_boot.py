@@ -2,7 +2,8 @@
 oracle's executor, bit for bit on every limb of the output: at N = 2^12 with
 the full schedule (valid keys, so the decrypted error is reported too) and at
 N = 2^16 with the three-group CoeffToSlot / SlotToCoeff of the full-slot
-workload, sparse-secret encapsulation and a short EvalMod.  HIP-graph replays must match the eager run."""
+workload, sparse-secret encapsulation, the ModDown hoisted out of the
+giant-step loops and a short EvalMod.  HIP-graph replays must match the eager run."""
 import sys
 
 import numpy as np
@@ -24,7 +25,8 @@ def _say(msg):
 
 def _boot_handle(s, bp, pl, relin, conj, rot, sparse=None):
     return s.ckks.Boot(s.ctx, bp.cts_radix_logs, bp.stc_radix_logs, pl.cts, pl.stc, pl.cheb, bp.double_angles,
-                       bp.top_scale, relin, conj, rot, cheb_baby=bp.cheb_baby, sparse=sparse)
+                       bp.top_scale, relin, conj, rot, cheb_baby=bp.cheb_baby, sparse=sparse,
+                       hoist_moddown=bp.hoist_moddown)
 
 
 def _check_ct(s, got, want, what):
@@ -33,15 +35,16 @@ def _check_ct(s, got, want, what):
     assert_equal(s.host(got.c1)[: want[2] + 1], want[1], what + " c1")
 
 
-@pytest.mark.parametrize("baby,bound,sparse", [(0, -9.5, False), (64, -12, False), (0, -14, True)])
-def test_bootstrap_small_full_schedule(baby, bound, sparse):
-    _say("bootstrap boot-small (baby %d, sparse %s): keys and plan" % (baby, sparse))
+@pytest.mark.parametrize("baby,bound,sparse,hoist", [(0, -9.5, False, False), (64, -12, False, False),
+                                                     (0, -14, True, False), (0, -14, True, True)])
+def test_bootstrap_small_full_schedule(baby, bound, sparse, hoist):
+    _say("bootstrap boot-small (baby %d, sparse %s, hoisted ModDown %s): keys and plan" % (baby, sparse, hoist))
     s = Setup("boot-small")
     cs = ClientSetup(s.ps, seed=31)
     ev = dict(cheb_degree=31, double_angles=3, k_range=12.0) if sparse else \
         dict(cheb_degree=63, double_angles=5, k_range=128.0)
     bp = B.BootParams(logn=12, cts_radix_logs=[4, 4, 3], stc_radix_logs=[3, 4, 4], top_scale=2.0 ** 50,
-                      in_scale=2.0 ** 50, cheb_baby=baby, **ev)
+                      in_scale=2.0 ** 50, cheb_baby=baby, hoist_moddown=hoist, **ev)
     pl = B.plan(s.P, bp)
     rot_np = {k: cs.galois_key(oracle.galois_for_rotation(12, k)) for k in B.rotations_needed(bp)}
     conj_np = cs.galois_key(oracle.galois_conjugate(12))
@@ -77,7 +80,7 @@ def test_bootstrap_large_graph_replay():
     _say("bootstrap large: plan and keys")
     s = Setup("large")
     bp = B.BootParams(logn=16, cts_radix_logs=[5, 5, 5], stc_radix_logs=[5, 5, 5], cheb_degree=7,
-                      double_angles=1, k_range=512.0, top_scale=2.0 ** 50, in_scale=2.0 ** 50)
+                      double_angles=1, k_range=512.0, top_scale=2.0 ** 50, in_scale=2.0 ** 50, hoist_moddown=True)
     pl = B.plan(s.P, bp)
     rot = {}
     for k in B.rotations_needed(bp):

@@ -31,7 +31,7 @@ def _server(s, slots, budget):
     bkeys = {k: rkey(5000 + k, pow(5, k, 2 * s.N))[1] for k in pl.rotations}
     boot = ckks.Boot(s.ctx, cfg.cts_radix_logs, cfg.stc_radix_logs, pl.cts, pl.stc, pl.cheb, cfg.double_angles,
                      cfg.top_scale, relin[1], rkey(2, 2 * s.N - 1)[1], bkeys,
-                     sparse=(rkey(3, 0)[1], rkey(4, 0)[1]))
+                     sparse=(rkey(3, 0)[1], rkey(4, 0)[1]), hoist_moddown=cfg.hoist_moddown)
     srv = Server(s.ctx, relin[1], {k: v[1] for k, v in rot.items()}, pts, boot, slots=slots, mem_budget=budget)
     return srv, relin[0], {k: v[0] for k, v in rot.items()}, pts
 
