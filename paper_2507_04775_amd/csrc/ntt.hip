@@ -431,6 +431,17 @@ __device__ __forceinline__ void bconv_load(typename A::V (&v)[NV], const A &ar, 
 
 constexpr int kThreads16 = 512;
 
+// The 32 threads of a row lie in one 64-wide wave (a wave holds two rows), so
+// the row passes exchange data through LDS within the wave: a release fence,
+// a wave barrier and an acquire fence order the LDS stores before the loads of
+// other lanes, with no workgroup barrier.
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ __forceinline__ uint32_t pos_wide(uint32_t s, int i) { return s + 32 * i; }
 __device__ __forceinline__ uint32_t pos_mid(uint32_t s, int i) { return 32 * (s >> 2) + (s & 3) + 4 * i; }
 __device__ __forceinline__ uint32_t pos_narrow(uint32_t s, int i) { return 8 * s + i; }
@@ -522,7 +533,7 @@ __device__ __forceinline__ void fwd_row_body(const NttArgs &a, const LimbPos &lp
     tw_fwd<3, 256, 4>(wb, pos_mid(s, 0), ar, 256 + b);  // in flight across the exchange
 #pragma unroll
     for (int i = 0; i < 8; ++i) L[row_slot(pos_wide(s, i))] = ar.to_bits(v[i]);
-    __syncthreads();
+    wave_sync();
 #pragma unroll
     for (int i = 0; i < 8; ++i) v[i] = ar.from_bits(L[row_slot(pos_mid(s, i))]);
     ar.reduce_all(v);
@@ -531,7 +542,7 @@ __device__ __forceinline__ void fwd_row_body(const NttArgs &a, const LimbPos &lp
     tw_fwd<2, 256, 1>(wc + 3, 8 * s + 4, ar, 256 + b);
 #pragma unroll
     for (int i = 0; i < 8; ++i) L[row_slot(pos_mid(s, i))] = ar.to_bits(v[i]);
-    __syncthreads();
+    wave_sync();
 #pragma unroll
     for (int i = 0; i < 8; ++i) v[i] = ar.from_bits(L[row_slot(pos_narrow(s, i))]);
     ar.reduce_all(v);
@@ -539,7 +550,7 @@ __device__ __forceinline__ void fwd_row_body(const NttArgs &a, const LimbPos &lp
     fwd_rw<2>(v + 4, wc + 3, ar);
 #pragma unroll
     for (int i = 0; i < 8; ++i) L[row_slot(pos_narrow(s, i))] = ar.fwd_final(v[i]);
-    __syncthreads();
+    wave_sync();
     uint64_t x[8], addv[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
@@ -554,10 +565,10 @@ __device__ __forceinline__ void fwd_row_body(const NttArgs &a, const LimbPos &lp
             for (int i = 0; i < 8; ++i) addv[i] = add[b * 256 + pos_wide(s, i)];
         } else {  // block b's addend comes from one block sb: stage it through LDS
             const uint32_t sb = galois_src(b * 256, a.galois, 16) & ~255u;
-            __syncthreads();
+            wave_sync();
 #pragma unroll
             for (int i = 0; i < 8; ++i) L[row_slot(pos_wide(s, i))] = add[sb + pos_wide(s, i)];
-            __syncthreads();
+            wave_sync();
 #pragma unroll
             for (int i = 0; i < 8; ++i)
                 addv[i] = L[row_slot(galois_src(b * 256 + pos_wide(s, i), a.galois, 16) - sb)];
@@ -595,7 +606,7 @@ __device__ __forceinline__ void inv_row_body(const NttArgs &a, const LimbPos &lp
         const uint32_t e = b * 256 + pos_wide(s, i);
         L[row_slot(pos_wide(s, i))] = src[PRO == PRO_GALOIS ? galois_src(e, a.galois, 16) : e];
     }
-    __syncthreads();
+    wave_sync();
     typename A::V v[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) v[i] = ar.from_u64(L[row_slot(pos_narrow(s, i))]);
@@ -605,7 +616,7 @@ __device__ __forceinline__ void inv_row_body(const NttArgs &a, const LimbPos &lp
     tw_inv<3, 256, 4>(wb, pos_mid(s, 0), ar, 256 + b);  // in flight across the exchange
 #pragma unroll
     for (int i = 0; i < 8; ++i) L[row_slot(pos_narrow(s, i))] = ar.to_bits(v[i]);
-    __syncthreads();
+    wave_sync();
 #pragma unroll
     for (int i = 0; i < 8; ++i) v[i] = ar.from_bits(L[row_slot(pos_mid(s, i))]);
     ar.reduce_all(v);
@@ -613,7 +624,7 @@ __device__ __forceinline__ void inv_row_body(const NttArgs &a, const LimbPos &lp
     tw_inv<3, 256, 32>(wc, s, ar, 256 + b);
 #pragma unroll
     for (int i = 0; i < 8; ++i) L[row_slot(pos_mid(s, i))] = ar.to_bits(v[i]);
-    __syncthreads();
+    wave_sync();
 #pragma unroll
     for (int i = 0; i < 8; ++i) v[i] = ar.from_bits(L[row_slot(pos_wide(s, i))]);
     ar.reduce_all(v);
