@@ -471,12 +471,13 @@ __device__ __forceinline__ void fwd_col_body(const NttArgs &a, const LimbPos &lp
     const uint32_t col = threadIdx.x & 15, s = threadIdx.x >> 4, c = tile * 16 + col;
     const uint64_t *src = a.src + (int64_t)lp.poly * a.map.src_poly_stride + (size_t)lp.row * 65536;
     typename A::W wa[7], wb[7], wc[6];
-    tw_fwd<3, 256, 32>(wa, s, ar, 1);
     typename A::V v[8];
-    if (PRO == PRO_BCONV) {
+    if (PRO == PRO_BCONV) {  // the twiddles after the conversion: not live across its loop
         bconv_load(v, ar, bc_source(a, lp.poly, lp.prime, 65536), P, 65536,
                    [&](int i) { return pos_wide(s, i) * 256 + c; });
+        tw_fwd<3, 256, 32>(wa, s, ar, 1);
     } else {
+        tw_fwd<3, 256, 32>(wa, s, ar, 1);
 #pragma unroll
         for (int i = 0; i < 8; ++i) v[i] = ar.from_u64(load_fwd<PRO>(a, lp, src, pos_wide(s, i) * 256 + c, P));
     }
