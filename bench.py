@@ -427,6 +427,19 @@ def main():
     ops["scalar_add"] = op_stats(lambda s: ctx.ckks_scalar_add(s[0], scal, sup), reps)
     ops["scalar_mult"] = op_stats(lambda s: ctx.ckks_scalar_mult(s[0], scal, 1.0, sup), reps)
 
+    # ---- NTT / INTT over the 31 ciphertext limbs alone
+    ops["ntt_31_limbs"] = op_stats(lambda s: ctx.ckks_ntt(ntt_poly[: ps.L + 1], 0, ps.L + 1), reps)
+    ops["intt_31_limbs"] = op_stats(lambda s: ctx.ckks_intt(ntt_poly[: ps.L + 1], 0, ps.L + 1), reps)
+
+    # ---- HMult+relin (one key switch) against the level (the paper's Fig. 6 workload), mean us
+    hmult_by_level = {}
+    for lv in (30, 25, 20, 15, 10, 5, 1, 0):
+        xa = ckks.Ciphertext(sets[0][0].c0[: lv + 1], sets[0][0].c1[: lv + 1], lv, 1.0)
+        xb = ckks.Ciphertext(sets[0][1].c0[: lv + 1], sets[0][1].c1[: lv + 1], lv, 1.0)
+        xo, wlv = ctx.empty_ct(lv), ctx.workspace(ckks.OP_HMULT, lv)
+        hmult_by_level[str(lv)] = op_stats(
+            lambda s, xa=xa, xb=xb, xo=xo, wlv=wlv: ctx.ckks_hmult_relin(xa, xb, s[2], xo, wlv), reps)["mean_us"]
+
     # ---- PtMult + Rescale against the level (the paper's Fig. 5 workload), mean us per pair
     ptmult_rescale = {}
     for lv in (30, 25, 20, 15, 10, 5, 1):
@@ -527,6 +540,7 @@ def main():
         "serving": serving,
         "ops": ops,
         "ptmult_rescale_us_by_level": ptmult_rescale,
+        "hmult_relin_us_by_level": hmult_by_level,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
