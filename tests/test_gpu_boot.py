@@ -1,9 +1,9 @@
 """Bootstrapping on the GPU (ckks_boot_* through the C ABI) against the
 oracle's executor, bit for bit on every limb of the output: at N = 2^12 with
 the full schedule (valid keys, so the decrypted error is reported too) and at
-N = 2^16 with the three-group CoeffToSlot / SlotToCoeff of the full-slot
-workload, sparse-secret encapsulation, the ModDown hoisted out of the
-giant-step loops and a short EvalMod.  HIP-graph replays must match the eager run."""
+N = 2^16 in the bench's full configuration (three-group CoeffToSlot /
+SlotToCoeff, sparse-secret encapsulation, the ModDown hoisted out of the
+giant-step loops, degree-31 EvalMod with three double angles).  HIP-graph replays must match the eager run."""
 import sys
 
 import numpy as np
@@ -76,11 +76,18 @@ def _random_key(s, seed, galois):
 
 
 def test_bootstrap_large_graph_replay():
+    """The bench's configuration exactly (the package defaults at N = 2^16 with
+    ten special primes: groups [5, 5, 5], degree 31, K = 12, 3 double angles,
+    sparse-secret encapsulation, hoisted ModDown), bit for bit against the
+    oracle (about a minute of CPU), then three graph replays."""
     import torch
-    _say("bootstrap large: plan and keys")
-    s = Setup("large")
-    bp = B.BootParams(logn=16, cts_radix_logs=[5, 5, 5], stc_radix_logs=[5, 5, 5], cheb_degree=7,
-                      double_angles=1, k_range=512.0, top_scale=2.0 ** 50, in_scale=2.0 ** 50, hoist_moddown=True)
+    from paper_2507_04775_amd import bootplan
+    _say("bootstrap large-nv (bench configuration): plan and keys")
+    s = Setup("large-nv")
+    cfg = bootplan.default_config(16, 2.0 ** 50)
+    bp = B.BootParams(logn=16, cts_radix_logs=cfg.cts_radix_logs, stc_radix_logs=cfg.stc_radix_logs,
+                      cheb_degree=cfg.cheb_degree, double_angles=cfg.double_angles, k_range=cfg.k_range,
+                      top_scale=cfg.top_scale, in_scale=cfg.in_scale, hoist_moddown=cfg.hoist_moddown)
     pl = B.plan(s.P, bp)
     rot = {}
     for k in B.rotations_needed(bp):
