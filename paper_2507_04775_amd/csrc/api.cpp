@@ -60,7 +60,10 @@ hipError_t modup_from_coeffs(const ckks_ctx *c, const uint64_t *d, uint32_t g, u
     KsSizes s = ks_sizes(c, level);
     hipError_t e = launch_bconv(args_modup_bconv(c, d, g, level, dc, ext, copy_own), s.beta, st);
     if (e != hipSuccess) return e;
-    return launch_ntt_stage(STAGE_FWD_PLAIN, args_modup_ntt(c, level, ext), s.beta * s.rows, st);
+    // only the converted rows: every digit leaves out its own rows, which partition q_0..q_l
+    NttArgs a = args_modup_ntt(c, level, ext);
+    a.map.dense = 1;
+    return launch_ntt_stage(STAGE_FWD_PLAIN, a, s.beta * s.rows - s.n, st);
 }
 
 hipError_t inner_product(const ckks_ctx *c, const uint64_t *ext, uint32_t level, const uint64_t *key, uint32_t g,

@@ -29,6 +29,7 @@ struct LimbMap {
     uint32_t nq;
     uint32_t row0;
     uint32_t skip_alpha;
+    uint32_t dense;           // with skip_alpha: limb indices enumerate only the rows that are not skipped
     int64_t src_poly_stride;  // elements between polynomials of the input (may be negative)
     int64_t dst_poly_stride;  // elements between polynomials of the output
 };

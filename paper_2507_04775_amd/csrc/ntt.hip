@@ -230,9 +230,28 @@ struct LimbPos {
 __device__ __forceinline__ LimbPos limb_pos(const LimbMap &m, uint32_t limb)
 {
     LimbPos p;
-    p.poly = limb / m.rows;
-    p.row = limb - p.poly * m.rows;
-    p.skip = limb_skipped(m, p.poly, p.row);
+    if (m.dense && m.skip_alpha) {
+        // the limb-th row that is not skipped: polynomial j leaves out its rows
+        // [j alpha, min(j alpha + alpha, level + 1)) (row0 = 0 in such launches)
+        uint32_t rem = limb, poly = 0;
+        for (;;) {
+            const uint32_t lo = poly * m.skip_alpha;
+            const uint32_t hi = lo + m.skip_alpha < m.level + 1 ? lo + m.skip_alpha : m.level + 1;
+            const uint32_t gap = hi > lo ? hi - lo : 0, kept = m.rows - gap;
+            if (rem < kept) {
+                p.poly = poly;
+                p.row = rem < lo ? rem : rem + gap;
+                break;
+            }
+            rem -= kept;
+            ++poly;
+        }
+        p.skip = false;
+    } else {
+        p.poly = limb / m.rows;
+        p.row = limb - p.poly * m.rows;
+        p.skip = limb_skipped(m, p.poly, p.row);
+    }
     p.prime = limb_prime(m, p.row);
     return p;
 }
@@ -818,13 +837,43 @@ __device__ __forceinline__ void inv12_unit(const NttArgs &a, uint32_t limb, uint
 // (instance, limb, tile) of many launches from a work queue, so a whole batch
 // of ciphertexts at different levels goes through one launch per stage.
 
+// XCD-aware unit of a grid launch.  Workgroups go to the eight XCDs round
+// robin (linear id k to XCD k mod 8), each XCD with its own L2.  Launches of
+// 16 tiles per limb hand XCD x the contiguous run x W/8 .. (x+1) W/8 - 1 of
+// the limb-major unit list (W = 16 limbs), so a limb's tiles sit on one or two
+// XCDs, the same ones in both passes: the row pass finds the column pass's
+// output and the limb's twiddles in that XCD's L2.  A bijection on the units.
+// Grid launches whose limb indices include skipped limbs keep the plain
+// assignment, which spreads every limb's tiles over all XCDs: contiguous runs
+// would leave some XCDs with skipped limbs only.  ModUp's single-operation
+// launch enumerates only the converted rows (LimbMap::dense) instead.
+struct UnitId {
+    uint32_t limb, tile;
+};
+
+__device__ __forceinline__ UnitId grid_unit(const NttArgs &a)
+{
+    UnitId u;
+    if (gridDim.x != 16 || (a.map.skip_alpha != 0 && !a.map.dense)) {  // N = 2^12, or skipped limbs in the grid
+        u.limb = blockIdx.y;
+        u.tile = blockIdx.x;
+        return u;
+    }
+    const uint32_t k = blockIdx.y * 16 + blockIdx.x, per = gridDim.y * 2;  // W / 8
+    const uint32_t w = (k & 7) * per + (k >> 3);
+    u.limb = w >> 4;
+    u.tile = w & 15;
+    return u;
+}
+
 constexpr int kLds12 = 4352;
 
 #define NTT_KERNELS(NAME, LDS, UNIT, THREADS)                                                     \
     __global__ __launch_bounds__(THREADS) void k_##NAME(NttArgs a)                               \
     {                                                                                             \
         __shared__ uint64_t lds[LDS];                                                             \
-        UNIT(a, blockIdx.y, blockIdx.x, lds);                                                     \
+        const UnitId u = grid_unit(a);                                                            \
+        UNIT(a, u.limb, u.tile, lds);                                                             \
     }                                                                                             \
     __global__ __launch_bounds__(THREADS) void q_##NAME(const NttArgs *insts, WorkQueue q)        \
     {                                                                                             \
