@@ -838,11 +838,14 @@ __device__ __forceinline__ void inv12_unit(const NttArgs &a, uint32_t limb, uint
 // of ciphertexts at different levels goes through one launch per stage.
 
 // XCD-aware unit of a grid launch.  Workgroups go to the eight XCDs round
-// robin (linear id k to XCD k mod 8), each XCD with its own L2.  Launches of
-// 16 tiles per limb hand XCD x the contiguous run x W/8 .. (x+1) W/8 - 1 of
-// the limb-major unit list (W = 16 limbs), so a limb's tiles sit on one or two
-// XCDs, the same ones in both passes: the row pass finds the column pass's
-// output and the limb's twiddles in that XCD's L2.  A bijection on the units.
+// robin (linear id k to XCD k mod 8), each XCD with its own L2, and each XCD
+// receives 2 n of the 16 n units of an n-limb launch.  XCD x takes whole limbs
+// x, x + 8, x + 16, ... of the first 8 floor(n/8) limbs, and the last n mod 8
+// limbs are spread evenly over all XCDs.  A limb's two passes then run on the
+// same XCD, so the row pass finds the column pass's output and the limb's
+// twiddles in that XCD's L2; the round-robin choice also spreads the slower
+// 60-bit limbs (q_0, the special primes) over the XCDs.  A bijection on the
+// units.
 // Grid launches whose limb indices include skipped limbs keep the plain
 // assignment, which spreads every limb's tiles over all XCDs: contiguous runs
 // would leave some XCDs with skipped limbs only.  ModUp's single-operation
@@ -859,10 +862,16 @@ __device__ __forceinline__ UnitId grid_unit(const NttArgs &a)
         u.tile = blockIdx.x;
         return u;
     }
-    const uint32_t k = blockIdx.y * 16 + blockIdx.x, per = gridDim.y * 2;  // W / 8
-    const uint32_t w = (k & 7) * per + (k >> 3);
-    u.limb = w >> 4;
-    u.tile = w & 15;
+    const uint32_t k = blockIdx.y * 16 + blockIdx.x, x = k & 7, j = k >> 3;
+    const uint32_t whole = gridDim.y >> 3, rest = gridDim.y - 8 * whole;
+    if (j < 16 * whole) {
+        u.limb = x + 8 * (j >> 4);
+        u.tile = j & 15;
+    } else {  // XCD x's 2 rest units of the remaining limbs
+        const uint32_t v = x * 2 * rest + (j - 16 * whole);
+        u.limb = 8 * whole + (v >> 4);
+        u.tile = v & 15;
+    }
     return u;
 }
 
