@@ -424,6 +424,21 @@ def main():
     ops["ntt_35_limbs"] = op_stats(lambda s: ntt_next(False), reps)
     ops["intt_35_limbs"] = op_stats(lambda s: ntt_next(True), reps)
 
+    # the roofline launch time: one event pair around a burst of back-to-back launches, so no event
+    # and no host-side delay between calls falls inside the average (per-call events add both)
+    def burst_us(inverse, n):
+        for _ in range(4):
+            ntt_next(inverse)
+        b0, b1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        b0.record(stream)
+        for _ in range(n):
+            ntt_next(inverse)
+        b1.record(stream)
+        torch.cuda.synchronize()
+        return b0.elapsed_time(b1) / n * 1e3
+
+    ntt_burst_us = burst_us(False, 4 * reps)
+
     # ---- the rest of Table I at level L: HSquare, then the support operations on whole ciphertexts
     # (memory-bound: HAdd reads 4 and writes 2 polynomials of L+1 limbs)
     pt = ctx.empty_poly(level)
@@ -480,9 +495,9 @@ def main():
         del src, dst, flush
 
     # ---- dominant kernel: the forward NTT over all 35 limbs (two passes, 16 x 35 workgroups each),
-    # timed on the library's stream with inputs in HBM (rotating buffers, above); algorithmic bytes =
-    # read + write of every limb once.
-    ntt_ms = ops["ntt_35_limbs"]["mean_us"] / 1e3
+    # timed on the library's stream with inputs in HBM (rotating buffers, above) as the mean over a
+    # burst of launches; algorithmic bytes = read + write of every limb once.
+    ntt_ms = ntt_burst_us / 1e3
     ntt_bytes = (ps.L + 1 + ps.K) * ps.N * 8 * 2
     achieved = ntt_bytes / (ntt_ms / 1e3) / 1e9
     roofline = {"bound": "hbm", "kernel": "ntt16_fwd (column + row pass) over 35 limbs",

@@ -16,6 +16,7 @@ constexpr int kMaxDigitPrimes = 16;  // primes per digit / in the special basis
 constexpr int kMaxDigits = 16;
 constexpr int kMaxPrimes = 64;
 constexpr uint32_t kAllPrimes = 0xFFFFFFFFu;
+constexpr int kMaxHeavy = 32;  // integer-path limbs a grid launch places apart
 
 // Row -> prime map of a launch over limbs.  Limb y of a launch is row
 // (y % rows) of polynomial (y / rows).  With level == kAllPrimes row r uses
@@ -103,6 +104,11 @@ struct NttArgs {
     // bc_mode 2 converts with centred inputs y_k in [-(p_k-1)/2, (p_k-1)/2]: every y_k above
     // (p_k-1)/2 subtracts [P]_q once, read from pmod[prime]
     const uint64_t *pmod;
+    // Grid launches at N = 2^16 place the limbs on the 64-bit integer path (primes of 2^50 and
+    // above, about 2.4 times the work of an FP64 limb) apart from the others; see grid_unit.
+    uint64_t int_primes;        // bit i: prime i is on the integer path
+    uint32_t n_heavy, heavy_pad;
+    uint8_t heavy[kMaxHeavy];   // launch limbs on the integer path, ascending (n_heavy of them)
 };
 
 // A unit of work of a persistent stage kernel is one tile of limb `limb` of

@@ -45,6 +45,8 @@ NttArgs base_args(const ckks_ctx *c, bool inverse)
     a.galois = 1;
     a.map.nq = c->nq;
     a.map.level = kAllPrimes;
+    for (size_t i = 0; i < c->primes.size() && i < 64; ++i)
+        if (c->primes[i] >= kFpMaxPrime) a.int_primes |= 1ull << i;
     return a;
 }
 
