@@ -117,6 +117,7 @@ struct NttArgs {
 struct UnitRec {
     uint32_t inst, limb;
 };
+static_assert(sizeof(UnitRec) == 8, "a unit record is two words: inst, then limb");
 
 struct WorkQueue {
     const UnitRec *recs;
@@ -153,6 +154,42 @@ __device__ __forceinline__ void run_work_queue(const Args *insts, const WorkQueu
         body(sa, rec.limb, u % q.tiles);
         __syncthreads();
         u = *claim;
+    }
+}
+
+// The same loop for argument blocks without dynamically indexed fields (the
+// NTT passes): the claim is made wave-uniform and the unit record and the
+// argument block are read through the constant address space, so they come in
+// with scalar loads into scalar registers, as a grid kernel receives its
+// arguments.  An argument block in LDS occupies vector registers instead: the
+// Rescale prologue pass needed 142 per thread that way (128 here) and the
+// first inverse pass 130 (122), above the 128 that two 512-thread workgroups
+// per CU allow.  Both blocks are written before the launch and only read
+// here.
+template <class Args, class Body>
+__device__ __forceinline__ void run_work_queue_uniform(const Args *insts, const WorkQueue &q, uint32_t *claim,
+                                                       Body body)
+{
+    static_assert(sizeof(Args) % 4 == 0, "argument blocks are read as 4-byte words");
+    typedef const __attribute__((address_space(4))) uint32_t ConstWord;
+    const uint32_t total = q.nrecs * q.tiles;
+    if (threadIdx.x == 0) *claim = atomicAdd(q.counter, 1u);
+    __syncthreads();
+    uint32_t u = __builtin_amdgcn_readfirstlane(*claim);
+    while (u < total) {
+        const uint32_t ri = __builtin_amdgcn_readfirstlane(u / q.tiles);
+        ConstWord *rec = (ConstWord *)((uintptr_t)q.recs + (uintptr_t)ri * sizeof(UnitRec));
+        const uint32_t inst = __builtin_amdgcn_readfirstlane(rec[0]);  // UnitRec::inst
+        const uint32_t limb = __builtin_amdgcn_readfirstlane(rec[1]);  // UnitRec::limb
+        __syncthreads();  // every thread has read *claim and is done with the unit's LDS
+        if (threadIdx.x == 0) *claim = atomicAdd(q.counter, 1u);
+        Args a;
+        ConstWord *src = (ConstWord *)((uintptr_t)insts + (uintptr_t)inst * sizeof(Args));
+#pragma unroll
+        for (uint32_t i = 0; i < sizeof(Args) / 4; ++i) ((uint32_t *)&a)[i] = src[i];
+        body(a, limb, u - ri * q.tiles);
+        __syncthreads();
+        u = __builtin_amdgcn_readfirstlane(*claim);
     }
 }
 

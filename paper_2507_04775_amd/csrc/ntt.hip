@@ -227,6 +227,15 @@ struct LimbPos {
     bool skip;
 };
 
+// Field of polynomial p (0 or 1) of a two-entry argument array, as a select:
+// the argument block then has no dynamically indexed field and a persistent
+// kernel keeps it in scalar registers.
+template <class T>
+__device__ __forceinline__ T pick(T const (&v)[2], uint32_t p)
+{
+    return p ? v[1] : v[0];
+}
+
 __host__ __device__ __forceinline__ LimbPos limb_pos(const LimbMap &m, uint32_t limb)
 {
     LimbPos p;
@@ -268,7 +277,7 @@ __device__ __forceinline__ uint64_t load_fwd(const NttArgs &a, const LimbPos &lp
                                              const Prime &P)
 {
     if (PRO == PRO_RESCALE) {
-        return switch_modulo(a.rs_src[lp.poly][e], (a.rs_ql - 1) >> 1, a.rs_qlmod[lp.prime], P);
+        return switch_modulo(pick(a.rs_src, lp.poly)[e], (a.rs_ql - 1) >> 1, a.rs_qlmod[lp.prime], P);
     } else {
         return src[e];
     }
@@ -285,9 +294,9 @@ __device__ __forceinline__ void store_fwd(const NttArgs &a, const LimbPos &lp, u
     } else {
         const size_t off = (size_t)lp.row * N;
         const ulonglong2 c = a.cst[lp.prime];
-        uint64_t r = shoup(submod(a.aux[lp.poly][off + e], x, P.q), c.x, c.y, P.q);
+        uint64_t r = shoup(submod(pick(a.aux, lp.poly)[off + e], x, P.q), c.x, c.y, P.q);
         if (EPI == EPI_MODDOWN) r = addmod(r, addv, P.q);
-        a.out[lp.poly][off + e] = r;
+        pick(a.out, lp.poly)[off + e] = r;
     }
 }
 
@@ -423,11 +432,13 @@ __device__ __forceinline__ void bconv_load(typename A::V (&v)[NV], const A &ar, 
                 for (int i = 0; i < 8; ++i) cur[i] = nxt[i];
             }
         }
+        // y_k - p_k for the high inputs: subtracting high [P]_q equals adding high (q - [P]_q), which
+        // joins the exact sum before its one reduction (high <= 16, so the sum stays below 2^127)
+        const uint64_t nbq = b.src ? P.q - b.bq : 0;
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
-            uint64_t r = reduce128(acc[i], P);
-            if (b.src) r = submod(r, mulmod(high[i], b.bq, P), P.q);  // y_k - p_k for the high inputs
-            v[8 * half + i] = ar.from_u64(r);
+            const u128 z = b.src ? add128(acc[i], mul_wide((uint64_t)high[i], nbq)) : acc[i];
+            v[8 * half + i] = ar.from_u64(reduce128(z, P));
         }
     }
 }
@@ -577,7 +588,7 @@ __device__ __forceinline__ void fwd_row_body(const NttArgs &a, const LimbPos &lp
         x[i] = L[row_slot(pos_wide(s, i))];
         addv[i] = 0;
     }
-    const uint64_t *add = EPI == EPI_MODDOWN ? a.add[lp.poly] : nullptr;
+    const uint64_t *add = EPI == EPI_MODDOWN ? pick(a.add, lp.poly) : nullptr;
     if (add) {
         add += (size_t)lp.row * 65536;
         if (a.galois == 1) {
@@ -752,7 +763,7 @@ __device__ __forceinline__ void fwd12_body(const NttArgs &a, const LimbPos &lp, 
         x[i] = lds[pad(t + 256 * i)];
         addv[i] = 0;
     }
-    const uint64_t *add = EPI == EPI_MODDOWN ? a.add[lp.poly] : nullptr;
+    const uint64_t *add = EPI == EPI_MODDOWN ? pick(a.add, lp.poly) : nullptr;
     if (add) {
         add += (size_t)lp.row * 4096;
         if (a.galois == 1) {
@@ -903,7 +914,11 @@ __device__ __forceinline__ UnitId grid_unit(const NttArgs &a)
 
 constexpr int kLds12 = 4352;
 
-#define NTT_KERNELS(NAME, LDS, UNIT, THREADS)                                                     \
+// Persistent kernels at N = 2^16 read their argument block with scalar loads
+// (run_work_queue_uniform).  Those at N = 2^12 keep it in LDS: with 16
+// elements per thread they already need close to the scalar register file,
+// and a scalar copy would spill to scratch.
+#define NTT_KERNELS(NAME, LDS, UNIT, THREADS, UNIFORM)                                          \
     __global__ __launch_bounds__(THREADS) void k_##NAME(NttArgs a)                               \
     {                                                                                             \
         __shared__ uint64_t lds[LDS];                                                             \
@@ -913,33 +928,37 @@ constexpr int kLds12 = 4352;
     __global__ __launch_bounds__(THREADS) void q_##NAME(const NttArgs *insts, WorkQueue q)        \
     {                                                                                             \
         __shared__ uint64_t lds[LDS];                                                             \
-        __shared__ NttArgs sa;                                                                    \
         __shared__ uint32_t claim;                                                                \
-        run_work_queue(insts, q, sa, &claim,                                                      \
-                       [&](const NttArgs &a, uint32_t limb, uint32_t tile) { UNIT(a, limb, tile, lds); }); \
+        auto body = [&](const NttArgs &a, uint32_t limb, uint32_t tile) { UNIT(a, limb, tile, lds); }; \
+        if constexpr (UNIFORM) {                                                                  \
+            run_work_queue_uniform(insts, q, &claim, body);                                       \
+        } else {                                                                                  \
+            __shared__ NttArgs sa;                                                                \
+            run_work_queue(insts, q, sa, &claim, body);                                           \
+        }                                                                                         \
     }
 
-NTT_KERNELS(fwd_col_plain, kLds16, fwd_col_unit<PRO_PLAIN>, kThreads16)
-NTT_KERNELS(fwd_col_rescale, kLds16, fwd_col_unit<PRO_RESCALE>, kThreads16)
-NTT_KERNELS(fwd_col_bconv, kLds16, fwd_col_unit<PRO_BCONV>, kThreads16)
-NTT_KERNELS(fwd_row_plain, kLds16, fwd_row_unit<EPI_PLAIN>, kThreads16)
-NTT_KERNELS(fwd_row_moddown, kLds16, fwd_row_unit<EPI_MODDOWN>, kThreads16)
-NTT_KERNELS(fwd_row_rescale, kLds16, fwd_row_unit<EPI_RESCALE>, kThreads16)
-NTT_KERNELS(inv_row_plain, kLds16, inv_row_unit<PRO_PLAIN>, kThreads16)
-NTT_KERNELS(inv_row_galois, kLds16, inv_row_unit<PRO_GALOIS>, kThreads16)
-NTT_KERNELS(inv_col, kLds16, inv_col_unit, kThreads16)
+NTT_KERNELS(fwd_col_plain, kLds16, fwd_col_unit<PRO_PLAIN>, kThreads16, true)
+NTT_KERNELS(fwd_col_rescale, kLds16, fwd_col_unit<PRO_RESCALE>, kThreads16, true)
+NTT_KERNELS(fwd_col_bconv, kLds16, fwd_col_unit<PRO_BCONV>, kThreads16, true)
+NTT_KERNELS(fwd_row_plain, kLds16, fwd_row_unit<EPI_PLAIN>, kThreads16, true)
+NTT_KERNELS(fwd_row_moddown, kLds16, fwd_row_unit<EPI_MODDOWN>, kThreads16, true)
+NTT_KERNELS(fwd_row_rescale, kLds16, fwd_row_unit<EPI_RESCALE>, kThreads16, true)
+NTT_KERNELS(inv_row_plain, kLds16, inv_row_unit<PRO_PLAIN>, kThreads16, true)
+NTT_KERNELS(inv_row_galois, kLds16, inv_row_unit<PRO_GALOIS>, kThreads16, true)
+NTT_KERNELS(inv_col, kLds16, inv_col_unit, kThreads16, true)
 #define FWD12_PP fwd12_unit<PRO_PLAIN, EPI_PLAIN>
 #define FWD12_PM fwd12_unit<PRO_PLAIN, EPI_MODDOWN>
 #define FWD12_RR fwd12_unit<PRO_RESCALE, EPI_RESCALE>
 #define FWD12_RP fwd12_unit<PRO_RESCALE, EPI_PLAIN>
 #define FWD12_BM fwd12_unit<PRO_BCONV, EPI_MODDOWN>
-NTT_KERNELS(fwd12_plain, kLds12, FWD12_PP, kThreads)
-NTT_KERNELS(fwd12_moddown, kLds12, FWD12_PM, kThreads)
-NTT_KERNELS(fwd12_rescale, kLds12, FWD12_RR, kThreads)
-NTT_KERNELS(fwd12_lift, kLds12, FWD12_RP, kThreads)
-NTT_KERNELS(fwd12_bconv_moddown, kLds12, FWD12_BM, kThreads)
-NTT_KERNELS(inv12_plain, kLds12, inv12_unit<PRO_PLAIN>, kThreads)
-NTT_KERNELS(inv12_galois, kLds12, inv12_unit<PRO_GALOIS>, kThreads)
+NTT_KERNELS(fwd12_plain, kLds12, FWD12_PP, kThreads, false)
+NTT_KERNELS(fwd12_moddown, kLds12, FWD12_PM, kThreads, false)
+NTT_KERNELS(fwd12_rescale, kLds12, FWD12_RR, kThreads, false)
+NTT_KERNELS(fwd12_lift, kLds12, FWD12_RP, kThreads, false)
+NTT_KERNELS(fwd12_bconv_moddown, kLds12, FWD12_BM, kThreads, false)
+NTT_KERNELS(inv12_plain, kLds12, inv12_unit<PRO_PLAIN>, kThreads, false)
+NTT_KERNELS(inv12_galois, kLds12, inv12_unit<PRO_GALOIS>, kThreads, false)
 #undef FWD12_PP
 #undef FWD12_PM
 #undef FWD12_RR
