@@ -61,16 +61,27 @@ def percentile(xs, p):
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
+NTT_SOURCES = ("ntt.hip", "unit_map.h", "internal.h", "modarith.h")
+
+
+def ntt_sources_sha256():
+    """SHA-256 over the NTT kernel sources, in NTT_SOURCES order."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in NTT_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2507_04775_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
 def measured_traffic():
     """HBM bytes per launch of the roofline kernel, from the committed counter
-    summary, valid only while the NTT source is the one the counters were
-    taken on (else None)."""
+    summary, valid only while the NTT sources (the kernel file and the headers
+    it builds on) are the ones the counters were taken on (else None)."""
     import hashlib
     prof = os.path.join(ROOT, "profiles", "ntt_fwd_logn16_35limbs_hbm_counters.md")
-    src = os.path.join(ROOT, "paper_2507_04775_amd", "csrc", "ntt.hip")
     try:
-        fields = dict(l.split(":", 1) for l in open(prof) if l.startswith(("traffic_bytes_per_launch:", "ntt_hip_sha256:")))
-        if hashlib.sha256(open(src, "rb").read()).hexdigest() != fields["ntt_hip_sha256"].strip():
+        fields = dict(l.split(":", 1) for l in open(prof) if l.startswith(("traffic_bytes_per_launch:", "ntt_sources_sha256:")))
+        if ntt_sources_sha256() != fields["ntt_sources_sha256"].strip():
             return None
         return int(fields["traffic_bytes_per_launch"])
     except (OSError, KeyError, ValueError):

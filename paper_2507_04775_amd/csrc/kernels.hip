@@ -96,33 +96,54 @@ __global__ __launch_bounds__(kThreads) void q_bconv(const BconvArgs *insts, Work
 // Under X -> X^g the 256 positions of a block all come from one source block
 // (the low bits of the natural index are fixed inside a block of bit-reversed
 // positions), so a gathered row is read as one coalesced block into LDS and
-// permuted there.
-__device__ __forceinline__ uint64_t ip_read(const uint64_t *row, uint32_t n, uint32_t bx, uint32_t g, uint32_t logn,
-                                            uint64_t *stage)
-{
-    if (g == 1) return row[n];
-    const uint32_t sb = galois_src(bx * kThreads, g, logn) & ~(uint32_t)(kThreads - 1);
-    __syncthreads();
-    stage[threadIdx.x] = row[sb + threadIdx.x];
-    __syncthreads();
-    return stage[galois_src(n, g, logn) - sb];
-}
+// permuted there.  The source blocks of up to kIpStage digits are loaded
+// before one barrier, so their load latencies overlap: a barrier per digit
+// would expose one HBM round trip per digit and block.
+constexpr uint32_t kIpStage = 4;
 
+// Row r of one key switch's inner product on block bx; stage holds
+// kIpStage * kThreads words.
 __device__ __forceinline__ void ip_unit(const IpArgs &a, uint32_t r, uint32_t bx, uint64_t *stage)
 {
     const uint32_t N = 1u << a.logn;
     const uint32_t n = bx * kThreads + threadIdx.x;
     const uint32_t pi = row_prime(r, a.level, a.nq);  // also the key row
     const size_t krows = a.nq + a.np;
+    const bool gather = a.galois != 1 || (a.own && a.own_galois != 1);
     u128 s0 = {0, 0}, s1 = {0, 0};
-    for (uint32_t j = 0; j < a.beta; ++j) {
-        const bool own = a.own && r >= j * a.alpha && r < min(j * a.alpha + a.alpha, a.level + 1);
-        const uint64_t x = own ? ip_read(a.own + (size_t)r * N, n, bx, a.own_galois, a.logn, stage)
-                               : ip_read(a.ext + ((size_t)j * a.rows + r) * N, n, bx, a.galois, a.logn, stage);
-        const uint64_t k0 = a.key[(((size_t)j * 2 + 0) * krows + pi) * N + n];
-        const uint64_t k1 = a.key[(((size_t)j * 2 + 1) * krows + pi) * N + n];
-        s0 = add128(s0, mul_wide(x, k0));
-        s1 = add128(s1, mul_wide(x, k1));
+    for (uint32_t j0 = 0; j0 < a.beta; j0 += kIpStage) {
+        const uint32_t nj = min(kIpStage, a.beta - j0);
+        uint64_t x[kIpStage];
+        uint32_t g[kIpStage], sb[kIpStage];
+#pragma unroll
+        for (uint32_t t = 0; t < kIpStage; ++t) {
+            if (t >= nj) break;
+            const uint32_t j = j0 + t;
+            const bool own = a.own && r >= j * a.alpha && r < min(j * a.alpha + a.alpha, a.level + 1);
+            const uint64_t *row = own ? a.own + (size_t)r * N : a.ext + ((size_t)j * a.rows + r) * N;
+            g[t] = own ? a.own_galois : a.galois;
+            sb[t] = g[t] == 1 ? bx * kThreads : galois_src(bx * kThreads, g[t], a.logn) & ~(uint32_t)(kThreads - 1);
+            x[t] = row[sb[t] + threadIdx.x];
+        }
+        if (gather) {
+            __syncthreads();  // the previous group's permuted reads are done
+#pragma unroll
+            for (uint32_t t = 0; t < kIpStage; ++t)
+                if (t < nj) stage[t * kThreads + threadIdx.x] = x[t];
+            __syncthreads();
+#pragma unroll
+            for (uint32_t t = 0; t < kIpStage; ++t)
+                if (t < nj && g[t] != 1) x[t] = stage[t * kThreads + galois_src(n, g[t], a.logn) - sb[t]];
+        }
+#pragma unroll
+        for (uint32_t t = 0; t < kIpStage; ++t) {
+            if (t >= nj) break;
+            const uint32_t j = j0 + t;
+            const uint64_t k0 = a.key[(((size_t)j * 2 + 0) * krows + pi) * N + n];
+            const uint64_t k1 = a.key[(((size_t)j * 2 + 1) * krows + pi) * N + n];
+            s0 = add128(s0, mul_wide(x[t], k0));
+            s1 = add128(s1, mul_wide(x[t], k1));
+        }
     }
     const Prime P = a.primes[pi];
     a.acc[(size_t)r * N + n] = reduce128(s0, P);
@@ -131,13 +152,13 @@ __device__ __forceinline__ void ip_unit(const IpArgs &a, uint32_t r, uint32_t bx
 
 __global__ __launch_bounds__(kThreads) void k_inner_product(IpArgs a)
 {
-    __shared__ uint64_t stage[kThreads];
+    __shared__ uint64_t stage[kIpStage * kThreads];
     ip_unit(a, blockIdx.y, blockIdx.x, stage);
 }
 
 __global__ __launch_bounds__(kThreads) void q_inner_product(const IpArgs *insts, WorkQueue q)
 {
-    __shared__ uint64_t stage[kThreads];
+    __shared__ uint64_t stage[kIpStage * kThreads];
     __shared__ IpArgs sa;
     __shared__ uint32_t claim;
     run_work_queue(insts, q, sa, &claim, [&](const IpArgs &a, uint32_t row, uint32_t t) {

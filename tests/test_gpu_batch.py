@@ -23,7 +23,15 @@ def setup(name):
 PLANS = {
     "small": dict(hmult=[3, 1], ks=[2], rot=[(3, 1)], hoisted=[(2, [1, 3])]),
     "large": dict(hmult=[30, 4], ks=[17], rot=[(21, 5)], hoisted=[(12, [1, 2, 64])]),
+    # items sharing keys, as in a serving batch: ten relinearisations (more than one group of
+    # inner products per key) and rotations by the same amounts at different levels
+    "small_shared": dict(params="small", shared_keys=True, hmult=[3, 1, 2, 3, 0, 1, 2, 3, 1, 2], ks=[2],
+                         rot=[(3, 1), (0, 3)], hoisted=[(2, [1, 3]), (3, [1, 3]), (1, [3, 1]), (0, [1])]),
 }
+
+
+def params_of(name):
+    return PLANS[name].get("params", name)
 
 
 def build_batch(s, plan, seed):
@@ -33,6 +41,15 @@ def build_batch(s, plan, seed):
     b = ck.Batch(ctx)
     checks = []
     rlk_np, rlk = s.key(seed, 0)
+    cache = {}
+
+    def rot_key(key_seed, g):
+        """A rotation key; with shared keys, one key object per Galois element."""
+        if not plan.get("shared_keys"):
+            return s.key(key_seed, g)
+        if g not in cache:
+            cache[g] = s.key(seed + 50 + g, g)
+        return cache[g]
     for i, lv in enumerate(plan["hmult"]):
         a_np, a = s.ct(seed + 10 + i, lv)
         b_np, bb = s.ct(seed + 20 + i, lv)
@@ -47,14 +64,14 @@ def build_batch(s, plan, seed):
         checks.append(("ks", lv, (d, rlk), [ck.Ciphertext(o0, o1, lv)], (d_np, rlk_np)))
     for i, (lv, k) in enumerate(plan["rot"]):
         g = oracle.galois_for_rotation(s.ps.logn, k)
-        key_np, key = s.key(seed + 40 + i, g)
+        key_np, key = rot_key(seed + 40 + i, g)
         c_np, c = s.ct(seed + 45 + i, lv)
         out = ctx.empty_ct(lv)
         b.rotate(c, g, key, out)
         checks.append(("rot", lv, (c, g, key), [out], (c_np, key_np)))
     for i, (lv, ks) in enumerate(plan["hoisted"]):
         gs = [oracle.galois_for_rotation(s.ps.logn, k) for k in ks]
-        keys = [s.key(seed + 50 + 5 * i + j, g) for j, g in enumerate(gs)]
+        keys = [rot_key(seed + 50 + 5 * i + j, g) for j, g in enumerate(gs)]
         c_np, c = s.ct(seed + 60 + i, lv)
         outs = [ctx.empty_ct(lv) for _ in ks]
         b.hoisted(c, ks, [k[1] for k in keys], outs)
@@ -93,9 +110,9 @@ def compare_to_single(s, checks, tag):
             assert_equal(s.host(o.c1), s.host(w.c1), "%s %s level %d c1" % (tag, kind, lv))
 
 
-@pytest.mark.parametrize("name", ["small", "large"])
+@pytest.mark.parametrize("name", ["small", "large", "small_shared"])
 def test_batch_matches_single_ops_and_oracle(name):
-    s = setup(name)
+    s = setup(params_of(name))
     b, checks = build_batch(s, PLANS[name], 700)
     assert b.keyswitches == sum(len(c[3]) for c in checks)
     b.run()
@@ -114,10 +131,10 @@ def test_batch_matches_single_ops_and_oracle(name):
     b.close()
 
 
-@pytest.mark.parametrize("name", ["small", "large"])
+@pytest.mark.parametrize("name", ["small", "large", "small_shared"])
 def test_batch_graph_replays_and_tuning_are_bit_stable(name):
     import torch
-    s = setup(name)
+    s = setup(params_of(name))
     b, checks = build_batch(s, PLANS[name], 900)
     st = torch.cuda.Stream()
     with torch.cuda.stream(st):
