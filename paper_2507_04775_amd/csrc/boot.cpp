@@ -327,45 +327,65 @@ struct Runner {
         base.nq = ctx()->nq;
         base.logn = ctx()->logn;
         bool started[kLanes] = {};
-        for (uint32_t gi = 0; gi < g.lay.giants; ++gi) {
-            const uint32_t ln = gi % nl;
-            Runner &R_ = lr[ln];
-            const Lane &L_ = *R_.ln;
-            const Ct P = b->slot(L_.p, lvl);
-            const uint32_t i0 = gi * g.lay.baby, nb = std::min(g.lay.baby, g.lay.count - i0);
-            const uint32_t G = (uint32_t)(((int64_t)g.giant[gi] % b->n + b->n) % b->n);
-            LincombArgs la;
-            memset(&la, 0, sizeof(la));
-            for (uint32_t j = 0; j < nb; ++j) {
-                la.a0[j] = src[j].c0;
-                la.a1[j] = src[j].c1;
-                la.pt[j] = g.pt + (size_t)(i0 + j) * limb;
+        // each lane takes giants gi = lane mod nl; two of them with the same number of babies share
+        // one lincomb, which reads the babies once (outputs in the lane's slots p and r)
+        std::vector<uint32_t> mine[kLanes];
+        for (uint32_t gi = 0; gi < g.lay.giants; ++gi) mine[gi % nl].push_back(gi);
+        auto babies = [&](uint32_t gi) { return std::min(g.lay.baby, g.lay.count - gi * g.lay.baby); };
+        size_t next[kLanes] = {};
+        for (bool more = true; more;) {
+            more = false;
+            for (uint32_t ln = 0; ln < nl; ++ln) {
+                if (next[ln] >= mine[ln].size()) continue;
+                more = true;
+                Runner &R_ = lr[ln];
+                const Lane &L_ = *R_.ln;
+                uint32_t pair[2] = {mine[ln][next[ln]], 0}, cnt = 1;
+                if (next[ln] + 1 < mine[ln].size() && babies(mine[ln][next[ln] + 1]) == babies(pair[0]))
+                    pair[cnt++] = mine[ln][next[ln] + 1];
+                next[ln] += cnt;
+                const Ct outs[2] = {b->slot(L_.p, lvl), b->slot(L_.r, lvl)};
+                const uint32_t nb = babies(pair[0]);
+                LincombArgs la;
+                memset(&la, 0, sizeof(la));
+                for (uint32_t j = 0; j < nb; ++j) {
+                    la.a0[j] = src[j].c0;
+                    la.a1[j] = src[j].c1;
+                    for (uint32_t o = 0; o < cnt; ++o) la.pt[o][j] = g.pt + (size_t)(pair[o] * g.lay.baby + j) * limb;
+                }
+                for (uint32_t o = 0; o < cnt; ++o) {
+                    la.out0[o] = outs[o].c0;
+                    la.out1[o] = outs[o].c1;
+                }
+                la.primes = ctx()->d_primes;
+                la.n = nb;
+                la.nout = cnt;
+                la.logn = ctx()->logn;
+                TRY(dev(launch_lincomb(la, lvl + 1, R_.st), "ckks_bootstrap lincomb"));
+                for (uint32_t o = 0; o < cnt; ++o) {
+                    const Ct &P = outs[o];
+                    const uint32_t G = (uint32_t)(((int64_t)g.giant[pair[o]] % b->n + b->n) % b->n);
+                    FoldArgs fa = base;
+                    fa.tot[0] = tot(ln);
+                    fa.tot[1] = tot(ln) + (size_t)rows * N;
+                    fa.first = !started[ln];
+                    started[ln] = true;
+                    fa.s[0] = P.c0;
+                    if (G != 0) {
+                        const ckks_key *rk = b->rot.at(G);
+                        uint64_t *acc = nullptr;
+                        TRY(dev(keyswitch_extended(ctx(), P.c1, rk->galois, lvl, rk->data, L_.ws, R_.st, &acc),
+                                "ckks_bootstrap giant key switch"));
+                        fa.acc[0] = acc;
+                        fa.acc[1] = acc + (size_t)rows * N;
+                        fa.galois = rk->galois;
+                    } else {
+                        fa.s[1] = P.c1;
+                        fa.galois = 1;
+                    }
+                    TRY(dev(launch_fold_ext(fa, rows, R_.st), "ckks_bootstrap fold"));
+                }
             }
-            la.out0 = P.c0;
-            la.out1 = P.c1;
-            la.primes = ctx()->d_primes;
-            la.n = nb;
-            la.logn = ctx()->logn;
-            TRY(dev(launch_lincomb(la, lvl + 1, R_.st), "ckks_bootstrap lincomb"));
-            FoldArgs fa = base;
-            fa.tot[0] = tot(ln);
-            fa.tot[1] = tot(ln) + (size_t)rows * N;
-            fa.first = !started[ln];
-            started[ln] = true;
-            fa.s[0] = P.c0;
-            if (G != 0) {
-                const ckks_key *rk = b->rot.at(G);
-                uint64_t *acc = nullptr;
-                TRY(dev(keyswitch_extended(ctx(), P.c1, rk->galois, lvl, rk->data, L_.ws, R_.st, &acc),
-                        "ckks_bootstrap giant key switch"));
-                fa.acc[0] = acc;
-                fa.acc[1] = acc + (size_t)rows * N;
-                fa.galois = rk->galois;
-            } else {
-                fa.s[1] = P.c1;
-                fa.galois = 1;
-            }
-            TRY(dev(launch_fold_ext(fa, rows, R_.st), "ckks_bootstrap fold"));
         }
         for (uint32_t l = 1; l < nl; ++l) {
             hipEvent_t join = b->event();
@@ -434,13 +454,14 @@ struct Runner {
             for (uint32_t j = 0; j < nb; ++j) {
                 la.a0[j] = src[j].c0;
                 la.a1[j] = src[j].c1;
-                la.pt[j] = g.pt + (size_t)(i0 + j) * limb;
+                la.pt[0][j] = g.pt + (size_t)(i0 + j) * limb;
             }
             const Ct &target = (G == 0 && first) ? acc : P;
-            la.out0 = target.c0;
-            la.out1 = target.c1;
+            la.out0[0] = target.c0;
+            la.out1[0] = target.c1;
             la.primes = ctx()->d_primes;
             la.n = nb;
+            la.nout = 1;
             la.logn = ctx()->logn;
             TRY(dev(launch_lincomb(la, lvl + 1, R_.st), "ckks_bootstrap lincomb"));
             Ct part = P;

@@ -270,15 +270,18 @@ struct TensorArgs {
     uint32_t logn, pad;
 };
 
-// Linear combination of ciphertexts with plaintexts (the baby-step sums of
-// the bootstrap's linear transforms): out_t = sum_b a_t[b] * pt[b], t = 0, 1.
+// Linear combinations of ciphertexts with plaintexts (the baby-step sums of
+// the bootstrap's linear transforms): for each output o < nout (1 or 2),
+// out_t[o] = sum_b a_t[b] * pt[o][b], t = 0, 1.  Two outputs (two giant steps
+// over the same babies) read the babies once.
 constexpr uint32_t kMaxLincomb = 16;
+constexpr uint32_t kLincombOut = 2;
 
 struct LincombArgs {
-    const uint64_t *a0[kMaxLincomb], *a1[kMaxLincomb], *pt[kMaxLincomb];
-    uint64_t *out0, *out1;
+    const uint64_t *a0[kMaxLincomb], *a1[kMaxLincomb], *pt[kLincombOut][kMaxLincomb];
+    uint64_t *out0[kLincombOut], *out1[kLincombOut];
     const Prime *primes;
-    uint32_t n, logn;
+    uint32_t n, logn, nout, pad;
 };
 
 // out_t = acc_t + sum_b a_t[b] * c[b][limb] with per-limb scalar residues

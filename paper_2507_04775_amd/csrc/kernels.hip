@@ -262,22 +262,32 @@ __global__ __launch_bounds__(kThreads) void k_automorph(const uint64_t *__restri
     out[base + e] = in[base + galois_src(e, g, logn)];
 }
 
-// out_t = sum_b a_t[b] pt[b] on every coefficient of every limb: the products
-// are summed exactly in 128 bits (n <= 16 products below 2^122 each) and
-// reduced once.
+// out_t[o] = sum_b a_t[b] pt[o][b] on every coefficient of every limb: the
+// products are summed exactly in 128 bits (n <= 16 products below 2^122 each)
+// and reduced once; each baby coefficient is read once for all NOUT outputs.
+template <int NOUT>
 __global__ __launch_bounds__(kThreads) void k_lincomb(LincombArgs a)
 {
     const uint32_t l = blockIdx.y;
     const size_t i = ((size_t)l << a.logn) + blockIdx.x * kThreads + threadIdx.x;
     const Prime P = a.primes[l];
-    u128 s0 = {0, 0}, s1 = {0, 0};
+    u128 s0[NOUT], s1[NOUT];
+#pragma unroll
+    for (int o = 0; o < NOUT; ++o) s0[o] = s1[o] = u128{0, 0};
     for (uint32_t b = 0; b < a.n; ++b) {
-        const uint64_t w = a.pt[b][i];
-        s0 = add128(s0, mul_wide(a.a0[b][i], w));
-        s1 = add128(s1, mul_wide(a.a1[b][i], w));
+        const uint64_t x0 = a.a0[b][i], x1 = a.a1[b][i];
+#pragma unroll
+        for (int o = 0; o < NOUT; ++o) {
+            const uint64_t w = a.pt[o][b][i];
+            s0[o] = add128(s0[o], mul_wide(x0, w));
+            s1[o] = add128(s1[o], mul_wide(x1, w));
+        }
     }
-    a.out0[i] = reduce128(s0, P);
-    a.out1[i] = reduce128(s1, P);
+#pragma unroll
+    for (int o = 0; o < NOUT; ++o) {
+        a.out0[o][i] = reduce128(s0[o], P);
+        a.out1[o][i] = reduce128(s1[o], P);
+    }
 }
 
 // out_t = acc_t + sum_b a_t[b] c_b (c_b a residue per limb), summed exactly in
@@ -339,7 +349,12 @@ __global__ __launch_bounds__(kThreads) void k_half_monomial(uint64_t *out, uint3
 hipError_t launch_lincomb(const LincombArgs &a, uint32_t nlimbs, hipStream_t stream)
 {
     if (a.n == 0 || a.n > kMaxLincomb) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_lincomb, dim3((1u << a.logn) / kThreads, nlimbs), dim3(kThreads), 0, stream, a);
+    if (a.nout == 1)
+        hipLaunchKernelGGL(k_lincomb<1>, dim3((1u << a.logn) / kThreads, nlimbs), dim3(kThreads), 0, stream, a);
+    else if (a.nout == 2)
+        hipLaunchKernelGGL(k_lincomb<2>, dim3((1u << a.logn) / kThreads, nlimbs), dim3(kThreads), 0, stream, a);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

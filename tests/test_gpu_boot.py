@@ -35,15 +35,20 @@ def _check_ct(s, got, want, what):
     assert_equal(s.host(got.c1)[: want[2] + 1], want[1], what + " c1")
 
 
-@pytest.mark.parametrize("baby,bound,sparse,hoist", [(0, -9.5, False, False), (64, -12, False, False),
-                                                     (0, -14, True, False), (0, -14, True, True)])
-def test_bootstrap_small_full_schedule(baby, bound, sparse, hoist):
-    _say("bootstrap boot-small (baby %d, sparse %s, hoisted ModDown %s): keys and plan" % (baby, sparse, hoist))
+# the last case merges five and six FFT stages per group: eight giant steps per transform, two per
+# lane, so pairs of giants share one baby-step combination (and the last pair has unequal babies)
+@pytest.mark.parametrize("baby,bound,sparse,hoist,cts,stc", [
+    (0, -9.5, False, False, [4, 4, 3], [3, 4, 4]), (64, -12, False, False, [4, 4, 3], [3, 4, 4]),
+    (0, -14, True, False, [4, 4, 3], [3, 4, 4]), (0, -14, True, True, [4, 4, 3], [3, 4, 4]),
+    (0, -12, True, True, [6, 5], [5, 6])])
+def test_bootstrap_small_full_schedule(baby, bound, sparse, hoist, cts, stc):
+    _say("bootstrap boot-small (baby %d, sparse %s, hoisted ModDown %s, groups %s / %s): keys and plan"
+         % (baby, sparse, hoist, cts, stc))
     s = Setup("boot-small")
     cs = ClientSetup(s.ps, seed=31)
     ev = dict(cheb_degree=31, double_angles=3, k_range=12.0) if sparse else \
         dict(cheb_degree=63, double_angles=5, k_range=128.0)
-    bp = B.BootParams(logn=12, cts_radix_logs=[4, 4, 3], stc_radix_logs=[3, 4, 4], top_scale=2.0 ** 50,
+    bp = B.BootParams(logn=12, cts_radix_logs=cts, stc_radix_logs=stc, top_scale=2.0 ** 50,
                       in_scale=2.0 ** 50, cheb_baby=baby, hoist_moddown=hoist, **ev)
     pl = B.plan(s.P, bp)
     rot_np = {k: cs.galois_key(oracle.galois_for_rotation(12, k)) for k in B.rotations_needed(bp)}
