@@ -156,13 +156,80 @@ __global__ __launch_bounds__(kThreads) void k_inner_product(IpArgs a)
     ip_unit(a, blockIdx.y, blockIdx.x, stage);
 }
 
+// Blocks bx0 .. bx0 + nb - 1 of row r, software-pipelined when all digits fit
+// one staging group (beta <= kIpStage): the digit and key loads of block i + 1
+// are issued before block i's barriers, so a unit exposes one HBM round trip
+// instead of one per block.
+__device__ __forceinline__ void ip_blocks(const IpArgs &a, uint32_t r, uint32_t bx0, uint32_t nb, uint64_t *stage)
+{
+    if (a.beta > kIpStage) {
+        for (uint32_t i = 0; i < nb; ++i) ip_unit(a, r, bx0 + i, stage);
+        return;
+    }
+    const uint32_t N = 1u << a.logn;
+    const uint32_t pi = row_prime(r, a.level, a.nq);
+    const size_t krows = a.nq + a.np;
+    const bool gather = a.galois != 1 || (a.own && a.own_galois != 1);
+    const uint64_t *row[kIpStage];
+    uint32_t g[kIpStage];
+#pragma unroll
+    for (uint32_t j = 0; j < kIpStage; ++j) {
+        if (j >= a.beta) break;
+        const bool own = a.own && r >= j * a.alpha && r < min(j * a.alpha + a.alpha, a.level + 1);
+        row[j] = own ? a.own + (size_t)r * N : a.ext + ((size_t)j * a.rows + r) * N;
+        g[j] = own ? a.own_galois : a.galois;
+    }
+    struct Loaded {
+        uint64_t x[kIpStage], k0[kIpStage], k1[kIpStage];
+        uint32_t sb[kIpStage];
+    };
+    auto load = [&](uint32_t bx, Loaded &L) {
+        const uint32_t n = bx * kThreads + threadIdx.x;
+#pragma unroll
+        for (uint32_t j = 0; j < kIpStage; ++j) {
+            if (j >= a.beta) break;
+            L.sb[j] = g[j] == 1 ? bx * kThreads : galois_src(bx * kThreads, g[j], a.logn) & ~(uint32_t)(kThreads - 1);
+            L.x[j] = row[j][L.sb[j] + threadIdx.x];
+            L.k0[j] = a.key[(((size_t)j * 2 + 0) * krows + pi) * N + n];
+            L.k1[j] = a.key[(((size_t)j * 2 + 1) * krows + pi) * N + n];
+        }
+    };
+    const Prime P = a.primes[pi];
+    Loaded cur, nxt;
+    load(bx0, cur);
+    for (uint32_t i = 0; i < nb; ++i) {
+        const uint32_t bx = bx0 + i, n = bx * kThreads + threadIdx.x;
+        if (i + 1 < nb) load(bx + 1, nxt);
+        if (gather) {
+            __syncthreads();  // the previous block's permuted reads are done
+#pragma unroll
+            for (uint32_t j = 0; j < kIpStage; ++j)
+                if (j < a.beta) stage[j * kThreads + threadIdx.x] = cur.x[j];
+            __syncthreads();
+#pragma unroll
+            for (uint32_t j = 0; j < kIpStage; ++j)
+                if (j < a.beta && g[j] != 1) cur.x[j] = stage[j * kThreads + galois_src(n, g[j], a.logn) - cur.sb[j]];
+        }
+        u128 s0 = {0, 0}, s1 = {0, 0};
+#pragma unroll
+        for (uint32_t j = 0; j < kIpStage; ++j) {
+            if (j >= a.beta) break;
+            s0 = add128(s0, mul_wide(cur.x[j], cur.k0[j]));
+            s1 = add128(s1, mul_wide(cur.x[j], cur.k1[j]));
+        }
+        a.acc[(size_t)r * N + n] = reduce128(s0, P);
+        a.acc[((size_t)a.rows + r) * N + n] = reduce128(s1, P);
+        if (i + 1 < nb) cur = nxt;
+    }
+}
+
 __global__ __launch_bounds__(kThreads) void q_inner_product(const IpArgs *insts, WorkQueue q)
 {
     __shared__ uint64_t stage[kIpStage * kThreads];
     __shared__ IpArgs sa;
     __shared__ uint32_t claim;
     run_work_queue(insts, q, sa, &claim, [&](const IpArgs &a, uint32_t row, uint32_t t) {
-        for (uint32_t i = 0; i < kQueueBlocks; ++i) ip_unit(a, row, t * kQueueBlocks + i, stage);
+        ip_blocks(a, row, t * kQueueBlocks, kQueueBlocks, stage);
     });
 }
 
