@@ -223,6 +223,19 @@ __device__ __forceinline__ void inv16(typename A::V (&v)[16], uint32_t base, con
     inv_r<4, NS, STRIDE>(v, base, ar, B);
 }
 
+// The thread's index, opaque to loop-invariant code motion, for the pass
+// bodies of the persistent kernels at N = 2^16.  Those run a body once per
+// claimed unit; offsets derived from threadIdx.x and hoisted out of that loop
+// stay live in vector registers across the whole body (ModDown's conversion
+// pass needed 154 per thread that way, 124 with this index, and the forward
+// column pass 118 against 70).  Grid kernels pass threadIdx.x itself.
+__device__ __forceinline__ uint32_t thread_index()
+{
+    uint32_t t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    return t;
+}
+
 struct LimbPos {
     uint32_t poly, row, prime;
     bool skip;
@@ -497,9 +510,9 @@ constexpr int kLds16 = kColLds > 16 * 256 ? kColLds : 16 * 256;
 
 template <int PRO, class A>
 __device__ __forceinline__ void fwd_col_body(const NttArgs &a, const LimbPos &lp, const Prime &P, const A &ar,
-                                             uint64_t *lds, uint32_t tile)
+                                             uint64_t *lds, uint32_t tile, uint32_t tx)
 {
-    const uint32_t col = threadIdx.x & 15, s = threadIdx.x >> 4, c = tile * 16 + col;
+    const uint32_t col = tx & 15, s = tx >> 4, c = tile * 16 + col;
     const uint64_t *src = a.src + (int64_t)lp.poly * a.map.src_poly_stride + (size_t)lp.row * 65536;
     typename A::W wa[7], wb[7], wc[6];
     typename A::V v[8];
@@ -537,22 +550,23 @@ __device__ __forceinline__ void fwd_col_body(const NttArgs &a, const LimbPos &lp
 }
 
 template <int PRO>
-__device__ __forceinline__ void fwd_col_unit(const NttArgs &a, uint32_t limb, uint32_t tile, uint64_t *lds)
+__device__ __forceinline__ void fwd_col_unit(const NttArgs &a, uint32_t limb, uint32_t tile, uint64_t *lds,
+                                             uint32_t tx)
 {
     const LimbPos lp = limb_pos(a.map, limb);
     if (lp.skip) return;
     const Prime P = a.primes[lp.prime];
     if (P.q < kFpMaxPrime)
-        fwd_col_body<PRO>(a, lp, P, fp_arith(a, P, lp.prime, 65536), lds, tile);
+        fwd_col_body<PRO>(a, lp, P, fp_arith(a, P, lp.prime, 65536), lds, tile, tx);
     else
-        fwd_col_body<PRO>(a, lp, P, int_arith(a, P, lp.prime, 65536), lds, tile);
+        fwd_col_body<PRO>(a, lp, P, int_arith(a, P, lp.prime, 65536), lds, tile, tx);
 }
 
 template <int EPI, class A>
 __device__ __forceinline__ void fwd_row_body(const NttArgs &a, const LimbPos &lp, const Prime &P, const A &ar,
-                                             uint64_t *lds, uint32_t tile)
+                                             uint64_t *lds, uint32_t tile, uint32_t tx)
 {
-    const uint32_t blk = threadIdx.x >> 5, s = threadIdx.x & 31, b = tile * 16 + blk;
+    const uint32_t blk = tx >> 5, s = tx & 31, b = tile * 16 + blk;
     const uint64_t *m = a.mid + (int64_t)lp.poly * a.mid_stride + (size_t)lp.row * 65536 + b * 256;
     uint64_t *L = lds + blk * 256;
     typename A::W wa[7], wb[7], wc[6];
@@ -612,22 +626,23 @@ __device__ __forceinline__ void fwd_row_body(const NttArgs &a, const LimbPos &lp
 }
 
 template <int EPI>
-__device__ __forceinline__ void fwd_row_unit(const NttArgs &a, uint32_t limb, uint32_t tile, uint64_t *lds)
+__device__ __forceinline__ void fwd_row_unit(const NttArgs &a, uint32_t limb, uint32_t tile, uint64_t *lds,
+                                             uint32_t tx)
 {
     const LimbPos lp = limb_pos(a.map, limb);
     if (lp.skip) return;
     const Prime P = a.primes[lp.prime];
     if (P.q < kFpMaxPrime)
-        fwd_row_body<EPI>(a, lp, P, fp_arith(a, P, lp.prime, 65536), lds, tile);
+        fwd_row_body<EPI>(a, lp, P, fp_arith(a, P, lp.prime, 65536), lds, tile, tx);
     else
-        fwd_row_body<EPI>(a, lp, P, int_arith(a, P, lp.prime, 65536), lds, tile);
+        fwd_row_body<EPI>(a, lp, P, int_arith(a, P, lp.prime, 65536), lds, tile, tx);
 }
 
 template <int PRO, class A>
 __device__ __forceinline__ void inv_row_body(const NttArgs &a, const LimbPos &lp, const A &ar, uint64_t *lds,
-                                             uint32_t tile)
+                                             uint32_t tile, uint32_t tx)
 {
-    const uint32_t blk = threadIdx.x >> 5, s = threadIdx.x & 31, b = tile * 16 + blk;
+    const uint32_t blk = tx >> 5, s = tx & 31, b = tile * 16 + blk;
     const uint64_t *src = a.src + (int64_t)lp.poly * a.map.src_poly_stride + (size_t)lp.row * 65536;
     uint64_t *L = lds + blk * 256;
     typename A::W wa[6], wb[7], wc[7];
@@ -667,22 +682,23 @@ __device__ __forceinline__ void inv_row_body(const NttArgs &a, const LimbPos &lp
 }
 
 template <int PRO>
-__device__ __forceinline__ void inv_row_unit(const NttArgs &a, uint32_t limb, uint32_t tile, uint64_t *lds)
+__device__ __forceinline__ void inv_row_unit(const NttArgs &a, uint32_t limb, uint32_t tile, uint64_t *lds,
+                                             uint32_t tx)
 {
     const LimbPos lp = limb_pos(a.map, limb);
     if (lp.skip) return;
     const Prime P = a.primes[lp.prime];
     if (P.q < kFpMaxPrime)
-        inv_row_body<PRO>(a, lp, fp_arith(a, P, lp.prime, 65536), lds, tile);
+        inv_row_body<PRO>(a, lp, fp_arith(a, P, lp.prime, 65536), lds, tile, tx);
     else
-        inv_row_body<PRO>(a, lp, int_arith(a, P, lp.prime, 65536), lds, tile);
+        inv_row_body<PRO>(a, lp, int_arith(a, P, lp.prime, 65536), lds, tile, tx);
 }
 
 template <class A>
 __device__ __forceinline__ void inv_col_body(const NttArgs &a, const LimbPos &lp, const A &ar, uint64_t *lds,
-                                             uint32_t tile)
+                                             uint32_t tile, uint32_t tx)
 {
-    const uint32_t col = threadIdx.x & 15, s = threadIdx.x >> 4, c = tile * 16 + col;
+    const uint32_t col = tx & 15, s = tx >> 4, c = tile * 16 + col;
     const uint64_t *m = a.mid + (int64_t)lp.poly * a.mid_stride + (size_t)lp.row * 65536;
     typename A::W wa[6], wb[7], wc[7];
     tw_inv<2, 256, 1>(wa, 8 * s, ar, 1);
@@ -714,15 +730,16 @@ __device__ __forceinline__ void inv_col_body(const NttArgs &a, const LimbPos &lp
     for (int i = 0; i < 8; ++i) dst[pos_wide(s, i) * 256 + c] = ar.inv_final(v[i]);
 }
 
-__device__ __forceinline__ void inv_col_unit(const NttArgs &a, uint32_t limb, uint32_t tile, uint64_t *lds)
+__device__ __forceinline__ void inv_col_unit(const NttArgs &a, uint32_t limb, uint32_t tile, uint64_t *lds,
+                                             uint32_t tx)
 {
     const LimbPos lp = limb_pos(a.map, limb);
     if (lp.skip) return;
     const Prime P = a.primes[lp.prime];
     if (P.q < kFpMaxPrime)
-        inv_col_body(a, lp, inv_fp_arith(a, lp, P, 65536), lds, tile);
+        inv_col_body(a, lp, inv_fp_arith(a, lp, P, 65536), lds, tile, tx);
     else
-        inv_col_body(a, lp, inv_int_arith(a, lp, P, 65536), lds, tile);
+        inv_col_body(a, lp, inv_int_arith(a, lp, P, 65536), lds, tile, tx);
 }
 
 // ------------------------------------------------------------------ N = 2^12
@@ -785,7 +802,7 @@ __device__ __forceinline__ void fwd12_body(const NttArgs &a, const LimbPos &lp, 
 }
 
 template <int PRO, int EPI>
-__device__ __forceinline__ void fwd12_unit(const NttArgs &a, uint32_t limb, uint32_t, uint64_t *lds)
+__device__ __forceinline__ void fwd12_unit(const NttArgs &a, uint32_t limb, uint32_t, uint64_t *lds, uint32_t)
 {
     const LimbPos lp = limb_pos(a.map, limb);
     if (lp.skip) return;
@@ -832,7 +849,7 @@ __device__ __forceinline__ void inv12_body(const NttArgs &a, const LimbPos &lp, 
 }
 
 template <int PRO>
-__device__ __forceinline__ void inv12_unit(const NttArgs &a, uint32_t limb, uint32_t, uint64_t *lds)
+__device__ __forceinline__ void inv12_unit(const NttArgs &a, uint32_t limb, uint32_t, uint64_t *lds, uint32_t)
 {
     const LimbPos lp = limb_pos(a.map, limb);
     if (lp.skip) return;
@@ -871,13 +888,15 @@ constexpr int kLds12 = 4352;
     {                                                                                             \
         __shared__ uint64_t lds[LDS];                                                             \
         const UnitId u = grid_unit(a);                                                            \
-        UNIT(a, u.limb, u.tile, lds);                                                             \
+        UNIT(a, u.limb, u.tile, lds, threadIdx.x);                                                \
     }                                                                                             \
     __global__ __launch_bounds__(THREADS) void q_##NAME(const NttArgs *insts, WorkQueue q)        \
     {                                                                                             \
         __shared__ uint64_t lds[LDS];                                                             \
         __shared__ uint32_t claim;                                                                \
-        auto body = [&](const NttArgs &a, uint32_t limb, uint32_t tile) { UNIT(a, limb, tile, lds); }; \
+        auto body = [&](const NttArgs &a, uint32_t limb, uint32_t tile) {                        \
+            UNIT(a, limb, tile, lds, UNIFORM ? thread_index() : threadIdx.x);                     \
+        };                                                                                        \
         if constexpr (UNIFORM) {                                                                  \
             run_work_queue_uniform(insts, q, &claim, body);                                       \
         } else {                                                                                  \
