@@ -301,14 +301,14 @@ __device__ __forceinline__ uint64_t load_fwd(const NttArgs &a, const LimbPos &lp
 // addend of the ModDown epilogue (already gathered, 0 without addend).
 template <int EPI>
 __device__ __forceinline__ void store_fwd(const NttArgs &a, const LimbPos &lp, uint64_t *dst, uint32_t e, uint64_t x,
-                                          uint64_t addv, const Prime &P, size_t N)
+                                          uint64_t addv, uint64_t auxv, const Prime &P, size_t N)
 {
     if (EPI == EPI_PLAIN) {
         dst[e] = x;
     } else {
         const size_t off = (size_t)lp.row * N;
         const ulonglong2 c = a.cst[lp.prime];
-        uint64_t r = shoup(submod(pick(a.aux, lp.poly)[off + e], x, P.q), c.x, c.y, P.q);
+        uint64_t r = shoup(submod(auxv, x, P.q), c.x, c.y, P.q);
         if (EPI == EPI_MODDOWN) r = addmod(r, addv, P.q);
         pick(a.out, lp.poly)[off + e] = r;
     }
@@ -584,6 +584,25 @@ __device__ __forceinline__ void fwd_row_body(const NttArgs &a, const LimbPos &lp
     for (int i = 0; i < 8; ++i) v[i] = ar.from_bits(L[row_slot(pos_mid(s, i))]);
     ar.reduce_all(v);
     fwd_rw<3>(v, wb, ar);
+    // the epilogue's operands are loaded here, so their latency overlaps the last round: the
+    // subtrahend row (ModDown, Rescale) and the addend (ModDown; block b's addend under X -> X^g
+    // comes from one block sb and is permuted through LDS at the end)
+    uint64_t auxv[8], addv[8];
+    const uint64_t *add = EPI == EPI_MODDOWN ? pick(a.add, lp.poly) : nullptr;
+    uint32_t sb = b * 256;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) auxv[i] = addv[i] = 0;
+    if (EPI != EPI_PLAIN) {
+        const uint64_t *ax = pick(a.aux, lp.poly) + (size_t)lp.row * 65536 + b * 256;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) auxv[i] = ax[pos_wide(s, i)];
+    }
+    if (add) {
+        add += (size_t)lp.row * 65536;
+        if (a.galois != 1) sb = galois_src(b * 256, a.galois, 16) & ~255u;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) addv[i] = add[sb + pos_wide(s, i)];
+    }
     tw_fwd<2, 256, 1>(wc, 8 * s, ar, 256 + b);
     tw_fwd<2, 256, 1>(wc + 3, 8 * s + 4, ar, 256 + b);
 #pragma unroll
@@ -597,32 +616,21 @@ __device__ __forceinline__ void fwd_row_body(const NttArgs &a, const LimbPos &lp
 #pragma unroll
     for (int i = 0; i < 8; ++i) L[row_slot(pos_narrow(s, i))] = ar.fwd_final(v[i]);
     wave_sync();
-    uint64_t x[8], addv[8];
+    uint64_t x[8];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        x[i] = L[row_slot(pos_wide(s, i))];
-        addv[i] = 0;
-    }
-    const uint64_t *add = EPI == EPI_MODDOWN ? pick(a.add, lp.poly) : nullptr;
-    if (add) {
-        add += (size_t)lp.row * 65536;
-        if (a.galois == 1) {
+    for (int i = 0; i < 8; ++i) x[i] = L[row_slot(pos_wide(s, i))];
+    if (add && a.galois != 1) {
+        wave_sync();
 #pragma unroll
-            for (int i = 0; i < 8; ++i) addv[i] = add[b * 256 + pos_wide(s, i)];
-        } else {  // block b's addend comes from one block sb: stage it through LDS
-            const uint32_t sb = galois_src(b * 256, a.galois, 16) & ~255u;
-            wave_sync();
+        for (int i = 0; i < 8; ++i) L[row_slot(pos_wide(s, i))] = addv[i];
+        wave_sync();
 #pragma unroll
-            for (int i = 0; i < 8; ++i) L[row_slot(pos_wide(s, i))] = add[sb + pos_wide(s, i)];
-            wave_sync();
-#pragma unroll
-            for (int i = 0; i < 8; ++i)
-                addv[i] = L[row_slot(galois_src(b * 256 + pos_wide(s, i), a.galois, 16) - sb)];
-        }
+        for (int i = 0; i < 8; ++i) addv[i] = L[row_slot(galois_src(b * 256 + pos_wide(s, i), a.galois, 16) - sb)];
     }
     uint64_t *dst = a.dst + (int64_t)lp.poly * a.map.dst_poly_stride + (size_t)lp.row * 65536;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) store_fwd<EPI>(a, lp, dst, b * 256 + pos_wide(s, i), x[i], addv[i], P, 65536);
+    for (int i = 0; i < 8; ++i)
+        store_fwd<EPI>(a, lp, dst, b * 256 + pos_wide(s, i), x[i], addv[i], auxv[i], P, 65536);
 }
 
 template <int EPI>
@@ -798,7 +806,10 @@ __device__ __forceinline__ void fwd12_body(const NttArgs &a, const LimbPos &lp, 
     }
     uint64_t *dst = a.dst + (int64_t)lp.poly * a.map.dst_poly_stride + (size_t)lp.row * 4096;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) store_fwd<EPI>(a, lp, dst, t + 256 * i, x[i], addv[i], P, 4096);
+    for (int i = 0; i < 16; ++i) {
+        const uint64_t auxv = EPI == EPI_PLAIN ? 0 : pick(a.aux, lp.poly)[(size_t)lp.row * 4096 + t + 256 * i];
+        store_fwd<EPI>(a, lp, dst, t + 256 * i, x[i], addv[i], auxv, P, 4096);
+    }
 }
 
 template <int PRO, int EPI>
