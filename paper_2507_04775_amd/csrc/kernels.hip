@@ -51,10 +51,10 @@ __device__ __forceinline__ void bconv_rows(const BconvArgs &a, const BconvJob &J
         }
         const uint32_t pi = row_prime(r, a.level, a.nq);
         ConstU64 *h = (ConstU64 *)(J.hmod + (size_t)pi * kMaxDigitPrimes);
-        u128 acc = {0, 0};
+        MacCols acc;
 #pragma unroll
-        for (int i = 0; i < NS; ++i) acc = add128(acc, mul_wide(y[i], h[i]));
-        J.dst[(size_t)r * N + n] = reduce128(acc, a.primes[pi]);
+        for (int i = 0; i < NS; ++i) mac_cols(acc, y[i], h[i]);
+        J.dst[(size_t)r * N + n] = reduce128(mac_total(acc), a.primes[pi]);
     }
 }
 

@@ -49,6 +49,47 @@ __device__ __forceinline__ u128 add128(u128 a, u128 b)
     return r;
 }
 
+// Exact sum of products y_i h_i (y_i, h_i < 2^61, fewer than 2^16 terms) with
+// h_i wave-uniform, accumulated by 32-bit columns: lo = sum y0 h0,
+// mid = sum (y0 h1 + y1 h0), hi = sum y1 h1, and the carries out of lo and mid
+// counted from the hardware carry-out of v_mad_u64_u32.  A term costs four
+// multiply-adds and three carry additions, where mul_wide + add128 spend
+// about twenty instructions (half of them register moves).  hi stays below
+// 2^62 (y1, h1 < 2^29), so it needs no carry.  The carry-outs go to separate
+// scalar pairs and are read three or more instructions later, after an
+// s_nop, which covers the VALU-writes-SGPR read hazard.
+struct MacCols {
+    uint64_t lo = 0, mid = 0, hi = 0;
+    uint32_t clo = 0, cmid = 0;
+};
+
+__device__ __forceinline__ void mac_cols(MacCols &c, uint64_t y, uint64_t h)
+{
+    const uint32_t y0 = (uint32_t)y, y1 = (uint32_t)(y >> 32);
+    const uint32_t h0 = (uint32_t)h, h1 = (uint32_t)(h >> 32);
+    uint64_t k0, k1, k2, kd;
+    asm("v_mad_u64_u32 %[lo], %[c0], %[y0], %[h0], %[lo]\n\t"
+        "v_mad_u64_u32 %[mid], %[c1], %[y0], %[h1], %[mid]\n\t"
+        "v_mad_u64_u32 %[mid], %[c2], %[y1], %[h0], %[mid]\n\t"
+        "v_mad_u64_u32 %[hi], %[cd], %[y1], %[h1], %[hi]\n\t"
+        "s_nop 1\n\t"
+        "v_addc_co_u32_e64 %[clo], %[cd], 0, %[clo], %[c0]\n\t"
+        "v_addc_co_u32_e64 %[cmid], %[cd], 0, %[cmid], %[c1]\n\t"
+        "v_addc_co_u32_e64 %[cmid], %[cd], 0, %[cmid], %[c2]"
+        : [lo] "+v"(c.lo), [mid] "+v"(c.mid), [hi] "+v"(c.hi), [clo] "+v"(c.clo), [cmid] "+v"(c.cmid),
+          [c0] "=&s"(k0), [c1] "=&s"(k1), [c2] "=&s"(k2), [cd] "=&s"(kd)
+        : [y0] "v"(y0), [y1] "v"(y1), [h0] "s"(h0), [h1] "s"(h1));
+}
+
+// The 128-bit value of the columns: lo + mid 2^32 + (hi + clo) 2^64 + cmid 2^96.
+__device__ __forceinline__ u128 mac_total(const MacCols &c)
+{
+    u128 r;
+    r.lo = c.lo + (c.mid << 32);
+    r.hi = c.hi + (c.mid >> 32) + ((uint64_t)c.cmid << 32) + c.clo + (r.lo < c.lo ? 1 : 0);
+    return r;
+}
+
 __device__ __forceinline__ uint64_t csub(uint64_t x, uint64_t m) { return x >= m ? x - m : x; }
 
 // Shoup: x * w mod q for any 64-bit x, with ws = floor(w 2^64 / q); result in [0, 2q)
