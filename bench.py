@@ -65,11 +65,17 @@ NTT_SOURCES = ("ntt.hip", "unit_map.h", "internal.h", "modarith.h")
 
 
 def ntt_sources_sha256():
-    """SHA-256 over the NTT kernel sources, in NTT_SOURCES order."""
+    """SHA-256 over the NTT kernel sources in NTT_SOURCES order, with comments
+    and runs of white space removed, so that only a change of code invalidates
+    the counters."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in NTT_SOURCES:
-        h.update(open(os.path.join(ROOT, "paper_2507_04775_amd", "csrc", f), "rb").read())
+        t = open(os.path.join(ROOT, "paper_2507_04775_amd", "csrc", f)).read()
+        t = re.sub(r"/\*.*?\*/", " ", t, flags=re.S)
+        t = re.sub(r"//[^\n]*", " ", t)
+        h.update(re.sub(r"\s+", " ", t).strip().encode())
     return h.hexdigest()
 
 

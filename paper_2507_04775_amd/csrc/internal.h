@@ -161,11 +161,11 @@ __device__ __forceinline__ void run_work_queue(const Args *insts, const WorkQueu
 // NTT passes): the claim is made wave-uniform and the unit record and the
 // argument block are read through the constant address space, so they come in
 // with scalar loads into scalar registers, as a grid kernel receives its
-// arguments.  An argument block in LDS occupies vector registers instead: the
-// Rescale prologue pass needed 142 per thread that way (128 here) and the
-// first inverse pass 130 (122), above the 128 that two 512-thread workgroups
-// per CU allow.  Both blocks are written before the launch and only read
-// here.
+// arguments.  An argument block in LDS occupies vector registers instead,
+// 8 to 14 more per thread in these passes, which put the Rescale prologue
+// pass and the first inverse pass above the 128 that two 512-thread
+// workgroups per CU allow.  Both blocks are written before the launch and
+// only read here.
 template <class Args, class Body>
 __device__ __forceinline__ void run_work_queue_uniform(const Args *insts, const WorkQueue &q, uint32_t *claim,
                                                        Body body)
