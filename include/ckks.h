@@ -136,6 +136,12 @@ ckks_status ckks_inner_product(ckks_ctx *ctx, const uint64_t *ext, uint32_t leve
 /*
  * ModDown (III-F.3, ModDown fusion of III-F.5): x [l+1+K][N] evaluation domain
  * -> out [l+1][N], out_i = [P^-1]_{q_i} (x_i - NTT(Conv_{P->q_i}(INTT(x|P)))).
+ * Conv is the fast base conversion of Eq. (1) with centred inputs: with
+ * a_k = INTT(x|P)_k and y_k = [a_k (P/p_k)^-1]_{p_k}, every y_k above
+ * (p_k - 1)/2 enters the sum as y_k - p_k, so Conv(a) = sum_k y_k^ctr [P/p_k]_{q_i}
+ * and, per coefficient, out = (X - v) / P exactly, with X the integer whose
+ * residues are x and v = sum_k y_k^ctr (P/p_k), so v = X (mod P) and
+ * |v| < K P / 2.  The error of the division then has zero mean.
  * ws: ckks_workspace_bytes(CKKS_OP_MODDOWN, l).
  */
 ckks_status ckks_moddown(ckks_ctx *ctx, const uint64_t *x, uint32_t level, uint64_t *out, void *ws, void *stream);

@@ -124,7 +124,6 @@ struct Lane {
 };
 
 constexpr uint32_t kLanes = 4;
-constexpr uint32_t kEvents = 8;
 
 // A ciphertext held in one of the executor's buffers (or the caller's output).
 struct Ct {
@@ -162,8 +161,14 @@ struct ckks_boot {
     uint64_t *qp = nullptr;
     size_t qp_words = 0;
     Lane lanes[kLanes];
-    hipEvent_t events[kEvents] = {};
+    // Fork / join events: one run records each event once, so within a capture
+    // no event is re-recorded after a wait on it has been captured.  The count
+    // is fixed by the schedule (events_per_run).  lane_open[l] is set while lane
+    // l has work that is not yet joined back into the caller's stream.
+    std::vector<hipEvent_t> events;
     uint32_t next_event = 0;
+    bool lane_open[kLanes] = {};
+    hipEvent_t close_events[kLanes] = {};
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 
@@ -204,7 +209,7 @@ struct ckks_boot {
             ln.ws = ws_base + l * ws_bytes;
         }
     }
-    hipEvent_t event() { return events[next_event++ % kEvents]; }
+    hipEvent_t event() { return next_event < events.size() ? events[next_event++] : nullptr; }
 
     Ct slot(uint32_t i, uint32_t level) const
     {
@@ -224,6 +229,31 @@ struct Runner {
     std::vector<uint64_t> res;
 
     ckks_ctx *ctx() const { return b->ctx; }
+
+    // Lanes 1..nl-1 start after the work issued so far on the caller's stream.
+    ckks_status fork(uint32_t nl)
+    {
+        if (nl < 2) return CKKS_OK;
+        hipEvent_t e = b->event();
+        if (!e) return fail(CKKS_E_DEVICE, "ckks_bootstrap: fork/join events exhausted");
+        TRY(dev(hipEventRecord(e, st), "ckks_bootstrap fork"));
+        for (uint32_t l = 1; l < nl; ++l) {
+            TRY(dev(hipStreamWaitEvent(b->lanes[l].aux, e, 0), "ckks_bootstrap fork"));
+            b->lane_open[l] = true;
+        }
+        return CKKS_OK;
+    }
+
+    // The caller's stream continues after everything issued so far on lane l.
+    ckks_status join(uint32_t l)
+    {
+        hipEvent_t e = b->event();
+        if (!e) return fail(CKKS_E_DEVICE, "ckks_bootstrap: fork/join events exhausted");
+        TRY(dev(hipEventRecord(e, b->lanes[l].aux), "ckks_bootstrap join"));
+        TRY(dev(hipStreamWaitEvent(st, e, 0), "ckks_bootstrap join"));
+        b->lane_open[l] = false;
+        return CKKS_OK;
+    }
 
     const uint64_t *residues(int64_t C, uint32_t level)
     {
@@ -311,12 +341,10 @@ struct Runner {
         const size_t N = b->N, limb = (size_t)(lvl + 1) * N;
         Runner lr[kLanes] = {*this, *this, *this, *this};
         const uint32_t nl = std::min<uint32_t>(kLanes, g.lay.giants);
-        hipEvent_t fork = b->event();
-        if (nl > 1) TRY(dev(hipEventRecord(fork, st), "ckks_bootstrap fork"));
+        TRY(fork(nl));
         for (uint32_t l = 1; l < nl; ++l) {
             lr[l].st = b->lanes[l].aux;
             lr[l].ln = &b->lanes[l];
-            TRY(dev(hipStreamWaitEvent(lr[l].st, fork, 0), "ckks_bootstrap fork"));
         }
         auto tot = [&](uint32_t l) { return b->qp + (size_t)l * b->qp_words; };
         FoldArgs base;
@@ -388,9 +416,7 @@ struct Runner {
             }
         }
         for (uint32_t l = 1; l < nl; ++l) {
-            hipEvent_t join = b->event();
-            TRY(dev(hipEventRecord(join, lr[l].st), "ckks_bootstrap join"));
-            TRY(dev(hipStreamWaitEvent(st, join, 0), "ckks_bootstrap join"));
+            TRY(join(l));
             FoldArgs fa = base;
             fa.tot[0] = tot(0);
             fa.tot[1] = tot(0) + (size_t)rows * N;
@@ -432,12 +458,10 @@ struct Runner {
         // giant steps round-robin over the lanes, each accumulating its own sum
         Runner lr[kLanes] = {*this, *this, *this, *this};
         const uint32_t nl = std::min<uint32_t>(kLanes, g.lay.giants);
-        hipEvent_t fork = b->event();
-        if (nl > 1) TRY(dev(hipEventRecord(fork, st), "ckks_bootstrap fork"));
+        TRY(fork(nl));
         for (uint32_t l = 1; l < nl; ++l) {
             lr[l].st = b->lanes[l].aux;
             lr[l].ln = &b->lanes[l];
-            TRY(dev(hipStreamWaitEvent(lr[l].st, fork, 0), "ckks_bootstrap fork"));
         }
         bool started[kLanes] = {};
         for (uint32_t gi = 0; gi < g.lay.giants; ++gi) {
@@ -474,9 +498,7 @@ struct Runner {
         }
         const Ct acc = b->slot(acc_slot, lvl);
         for (uint32_t l = 1; l < nl; ++l) {
-            hipEvent_t join = b->event();
-            TRY(dev(hipEventRecord(join, lr[l].st), "ckks_bootstrap join"));
-            TRY(dev(hipStreamWaitEvent(st, join, 0), "ckks_bootstrap join"));
+            TRY(join(l));
             TRY(add(acc, b->slot(b->lanes[l].acc, lvl), acc));
         }
         Ct c = acc;
@@ -643,7 +665,36 @@ struct Runner {
         return CKKS_OK;
     }
 
+    // One bootstrap.  On failure every lane that was forked is joined back, so
+    // the caller's stream (and a capture on it) is never left with work of
+    // another stream that it does not wait for.
     ckks_status run(const ckks_ct &in, const ckks_ct &out)
+    {
+        b->next_event = 0;
+        for (bool &o : b->lane_open) o = false;
+        ckks_status s = run_steps(in, out);
+        if (s != CKKS_OK) {
+            close_lanes();
+            return s;
+        }
+        for (uint32_t l = 1; l < kLanes; ++l)
+            if (b->lane_open[l]) return fail(CKKS_E_DEVICE, "ckks_bootstrap: a lane was not joined");
+        return CKKS_OK;
+    }
+
+    // Joins every open lane into the caller's stream with events outside the
+    // run's own set (error path only; later errors are not reported).
+    void close_lanes()
+    {
+        for (uint32_t l = 1; l < kLanes; ++l) {
+            if (!b->lane_open[l]) continue;
+            if (hipEventRecord(b->close_events[l], b->lanes[l].aux) == hipSuccess)
+                (void)hipStreamWaitEvent(st, b->close_events[l], 0);
+            b->lane_open[l] = false;
+        }
+    }
+
+    ckks_status run_steps(const ckks_ct &in, const ckks_ct &out)
     {
         Ct x = b->slot(b->s_x(), b->L);
         if (b->to_sparse) {  // encapsulation: switch the input to the sparse secret first
@@ -676,13 +727,10 @@ struct Runner {
         Runner im_r = *this;
         im_r.st = b->lanes[1].aux;
         im_r.ln = &b->lanes[1];
-        hipEvent_t fork = b->event(), join = b->event();
-        TRY(dev(hipEventRecord(fork, st), "ckks_bootstrap fork"));
-        TRY(dev(hipStreamWaitEvent(im_r.st, fork, 0), "ckks_bootstrap fork"));
+        TRY(fork(2));
         TRY(im_r.eval_mod(b->s_im(0), b->s_im(1), yi));
         TRY(eval_mod(b->s_re(0), b->s_re(1), yr));
-        TRY(dev(hipEventRecord(join, im_r.st), "ckks_bootstrap join"));
-        TRY(dev(hipStreamWaitEvent(st, join, 0), "ckks_bootstrap join"));
+        TRY(join(1));
         TRY(ckks_poly_mul(ctx(), yi.c0, b->mono, yi.c0, yi.level, st));
         TRY(ckks_poly_mul(ctx(), yi.c1, b->mono, yi.c1, yi.level, st));
         TRY(add(yr, yi, yi));
@@ -695,6 +743,19 @@ struct Runner {
         return CKKS_OK;
     }
 };
+
+// Fork and join events of one run: a transform group whose giant steps go to
+// nl > 1 lanes takes one fork and nl - 1 joins; the EvalMod halves take two.
+uint32_t events_per_run(const ckks_boot &b)
+{
+    uint32_t n = 2;
+    for (const auto *gs : {&b.cts, &b.stc})
+        for (const Group &g : *gs) {
+            const uint32_t nl = std::min<uint32_t>(kLanes, g.lay.giants);
+            if (nl > 1) n += nl;
+        }
+    return n;
+}
 
 uint32_t keyswitches_of(const ckks_boot &b)
 {
@@ -910,9 +971,15 @@ extern "C" ckks_status ckks_boot_create(ckks_ctx *ctx, const ckks_boot_desc *des
             b->lanes[l].aux = nullptr;
             return bail(CKKS_E_DEVICE, "stream creation failed");
         }
-    for (uint32_t i = 0; i < kEvents; ++i)
-        if (hipEventCreateWithFlags(&b->events[i], hipEventDisableTiming) != hipSuccess) {
-            b->events[i] = nullptr;
+    b->events.assign(events_per_run(*b), nullptr);
+    for (hipEvent_t &ev : b->events)
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+            ev = nullptr;
+            return bail(CKKS_E_DEVICE, "event creation failed");
+        }
+    for (hipEvent_t &ev : b->close_events)
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+            ev = nullptr;
             return bail(CKKS_E_DEVICE, "event creation failed");
         }
 
@@ -1019,15 +1086,26 @@ extern "C" ckks_status ckks_boot_capture(ckks_boot *b, const ckks_ct *in, ckks_c
     if (b->graph) (void)hipGraphDestroy(b->graph);
     b->exec = nullptr;
     b->graph = nullptr;
-    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess)
-        return fail(CKKS_E_DEVICE, "ckks_boot_capture: begin capture failed");
+    hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess)
+        return fail(CKKS_E_DEVICE, std::string("ckks_boot_capture: begin capture: ") + hipGetErrorString(e));
     Runner r{b, st, &b->lanes[0], {}};
-    ckks_status s = r.run(*in, *out);
-    hipError_t e = hipStreamEndCapture(st, &b->graph);
-    if (s != CKKS_OK) return s;
-    if (e != hipSuccess) return fail(CKKS_E_DEVICE, "ckks_boot_capture: capture failed");
-    if (hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess)
-        return fail(CKKS_E_DEVICE, "ckks_boot_capture: instantiate failed");
+    const ckks_status s = r.run(*in, *out);  // every forked lane is joined, also on failure
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(st, &g);
+    if (s != CKKS_OK || e != hipSuccess) {
+        if (e == hipSuccess && g) (void)hipGraphDestroy(g);
+        if (s != CKKS_OK) return s;
+        return fail(CKKS_E_DEVICE, std::string("ckks_boot_capture: end capture: ") + hipGetErrorString(e));
+    }
+    b->graph = g;
+    e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        b->exec = nullptr;
+        (void)hipGraphDestroy(b->graph);
+        b->graph = nullptr;
+        return fail(CKKS_E_DEVICE, std::string("ckks_boot_capture: instantiate: ") + hipGetErrorString(e));
+    }
     out->level = b->out_level;
     out->scale = b->sc[b->out_level];
     return CKKS_OK;
@@ -1046,8 +1124,10 @@ extern "C" void ckks_boot_destroy(ckks_boot *b)
     if (!b) return;
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
-    for (uint32_t i = 0; i < kEvents; ++i)
-        if (b->events[i]) (void)hipEventDestroy(b->events[i]);
+    for (hipEvent_t ev : b->events)
+        if (ev) (void)hipEventDestroy(ev);
+    for (hipEvent_t ev : b->close_events)
+        if (ev) (void)hipEventDestroy(ev);
     for (uint32_t l = 1; l < kLanes; ++l)
         if (b->lanes[l].aux) (void)hipStreamDestroy(b->lanes[l].aux);
     if (b->dev) (void)hipFree(b->dev);
