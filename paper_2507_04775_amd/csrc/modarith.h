@@ -15,13 +15,13 @@ struct u128 {
     uint64_t lo, hi;
 };
 
-__device__ __forceinline__ uint64_t mad32(uint32_t a, uint32_t b, uint64_t c)
+__host__ __device__ __forceinline__ uint64_t mad32(uint32_t a, uint32_t b, uint64_t c)
 {
     return (uint64_t)a * (uint64_t)b + c;  // one v_mad_u64_u32
 }
 
 // exact 64x64 -> 128 product from four 32x32 products
-__device__ __forceinline__ u128 mul_wide(uint64_t a, uint64_t b)
+__host__ __device__ __forceinline__ u128 mul_wide(uint64_t a, uint64_t b)
 {
     uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32);
     uint32_t b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
@@ -36,12 +36,12 @@ __device__ __forceinline__ u128 mul_wide(uint64_t a, uint64_t b)
 }
 
 // high 64 bits of a 64x64 product
-__device__ __forceinline__ uint64_t mul_hi(uint64_t a, uint64_t b)
+__host__ __device__ __forceinline__ uint64_t mul_hi(uint64_t a, uint64_t b)
 {
     return mul_wide(a, b).hi;
 }
 
-__device__ __forceinline__ u128 add128(u128 a, u128 b)
+__host__ __device__ __forceinline__ u128 add128(u128 a, u128 b)
 {
     u128 r;
     r.lo = a.lo + b.lo;
@@ -82,7 +82,7 @@ __device__ __forceinline__ void mac_cols(MacCols &c, uint64_t y, uint64_t h)
 }
 
 // The 128-bit value of the columns: lo + mid 2^32 + (hi + clo) 2^64 + cmid 2^96.
-__device__ __forceinline__ u128 mac_total(const MacCols &c)
+__host__ __device__ __forceinline__ u128 mac_total(const MacCols &c)
 {
     u128 r;
     r.lo = c.lo + (c.mid << 32);
@@ -90,16 +90,16 @@ __device__ __forceinline__ u128 mac_total(const MacCols &c)
     return r;
 }
 
-__device__ __forceinline__ uint64_t csub(uint64_t x, uint64_t m) { return x >= m ? x - m : x; }
+__host__ __device__ __forceinline__ uint64_t csub(uint64_t x, uint64_t m) { return x >= m ? x - m : x; }
 
 // Shoup: x * w mod q for any 64-bit x, with ws = floor(w 2^64 / q); result in [0, 2q)
-__device__ __forceinline__ uint64_t shoup_lazy(uint64_t x, uint64_t w, uint64_t ws, uint64_t q)
+__host__ __device__ __forceinline__ uint64_t shoup_lazy(uint64_t x, uint64_t w, uint64_t ws, uint64_t q)
 {
     uint64_t qt = mul_hi(x, ws);
     return x * w - qt * q;
 }
 
-__device__ __forceinline__ uint64_t shoup(uint64_t x, uint64_t w, uint64_t ws, uint64_t q)
+__host__ __device__ __forceinline__ uint64_t shoup(uint64_t x, uint64_t w, uint64_t ws, uint64_t q)
 {
     return csub(shoup_lazy(x, w, ws, q), q);
 }
@@ -116,7 +116,7 @@ struct Prime {
 
 // Reduce an exact 128-bit value z (any z < 2^128) modulo q:
 // z = h 2^64 + l == h (2^64 mod q) + l, both terms folded with Shoup.
-__device__ __forceinline__ uint64_t reduce128(u128 z, const Prime &P)
+__host__ __device__ __forceinline__ uint64_t reduce128(u128 z, const Prime &P)
 {
     uint64_t a = shoup_lazy(z.hi, P.r64, P.r64_s, P.q);   // [0, 2q)
     uint64_t b = z.lo - mul_hi(z.lo, P.one_s) * P.q;       // [0, 2q)
@@ -126,12 +126,12 @@ __device__ __forceinline__ uint64_t reduce128(u128 z, const Prime &P)
 }
 
 // variable x variable: x, y < 2^64 with x y < 2^128
-__device__ __forceinline__ uint64_t mulmod(uint64_t x, uint64_t y, const Prime &P)
+__host__ __device__ __forceinline__ uint64_t mulmod(uint64_t x, uint64_t y, const Prime &P)
 {
     return reduce128(mul_wide(x, y), P);
 }
 
-__device__ __forceinline__ uint64_t addmod(uint64_t a, uint64_t b, uint64_t q) { return csub(a + b, q); }
+__host__ __device__ __forceinline__ uint64_t addmod(uint64_t a, uint64_t b, uint64_t q) { return csub(a + b, q); }
 
 // ---------------------------------------------------------------- FP64 path
 // For primes below 2^50, residues are exact integers in doubles and a modular
@@ -173,6 +173,6 @@ __host__ __device__ __forceinline__ uint64_t fp_canonical(double x, FpMod m)
     r = r < 0.0 ? r + m.q : r;
     return (uint64_t)r;
 }
-__device__ __forceinline__ uint64_t submod(uint64_t a, uint64_t b, uint64_t q) { return a >= b ? a - b : a + q - b; }
+__host__ __device__ __forceinline__ uint64_t submod(uint64_t a, uint64_t b, uint64_t q) { return a >= b ? a - b : a + q - b; }
 
 }  // namespace ckks

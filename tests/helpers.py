@@ -66,3 +66,57 @@ class ClientSetup:
 def max_err_bits(a, b) -> float:
     d = np.max(np.abs(np.asarray(a) - np.asarray(b)))
     return float(np.log2(d)) if d > 0 else -np.inf
+
+
+def prod(xs) -> int:
+    r = 1
+    for x in xs:
+        r *= int(x)
+    return r
+
+
+def crt(res, mods) -> int:
+    """The integer in [0, prod(mods)) with the given residues (Python big ints)."""
+    M = prod(mods)
+    x = 0
+    for r, m in zip(res, mods):
+        Mi = M // int(m)
+        x += int(r) * Mi * pow(Mi, -1, int(m))
+    return x % M
+
+
+def scaled_inputs(y: np.ndarray, mods) -> np.ndarray:
+    """Coefficient rows a_i = [y_i (B/b_i)]_{b_i} over the basis B = mods, so that
+    the scaled inputs of a fast base conversion from B, y_i = [a_i (B/b_i)^-1]_{b_i},
+    are exactly the given y (canonical residues, shape [len(mods)][N])."""
+    B = prod(mods)
+    out = np.empty_like(y)
+    for i, m in enumerate(mods):
+        h = (B // int(m)) % int(m)
+        out[i] = np.array([(int(v) * h) % int(m) for v in y[i]], dtype=np.uint64)
+    return out
+
+
+def edge_values(m: int) -> list:
+    """Residues at the edges of the modular arithmetic for modulus m: 0, 1, the
+    centring threshold (m-1)/2 and (m+1)/2, m-2, m-1, and the 32-bit word
+    boundaries 2^32 - 1, 2^32, 2^32 + 1 (below m)."""
+    vals = [0, 1, (m - 1) // 2, (m + 1) // 2, m - 2, m - 1, (1 << 31), (1 << 32) - 1, 1 << 32, (1 << 32) + 1]
+    return [v for v in vals if v < m]
+
+
+def edge_rows(seed: int, mods, N: int, shift: int = 0) -> np.ndarray:
+    """Rows over `mods` whose first coefficients cycle through edge_values (row i
+    shifted by i + shift, so the rows of one coefficient mix different edges);
+    every fourth block of the rest is uniform, the others keep cycling."""
+    g = inputs.rng(seed)
+    out = np.empty((len(mods), N), dtype=np.uint64)
+    for i, m in enumerate(mods):
+        ev = edge_values(int(m))
+        idx = (np.arange(N) + i + shift) % len(ev)
+        row = np.array(ev, dtype=np.uint64)[idx]
+        rnd = g.integers(0, int(m), size=N, dtype=np.uint64)
+        blk = (np.arange(N) // 64) % 4 == 3
+        row[blk] = rnd[blk]
+        out[i] = row
+    return out

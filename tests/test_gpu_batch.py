@@ -68,7 +68,7 @@ def build_batch(s, plan, seed):
         c_np, c = s.ct(seed + 45 + i, lv)
         out = ctx.empty_ct(lv)
         b.rotate(c, g, key, out)
-        checks.append(("rot", lv, (c, g, key), [out], (c_np, key_np)))
+        checks.append(("rot", lv, (c, g, key), [out], (c_np, key_np, g)))
     for i, (lv, ks) in enumerate(plan["hoisted"]):
         gs = [oracle.galois_for_rotation(s.ps.logn, k) for k in ks]
         keys = [rot_key(seed + 50 + 5 * i + j, g) for j, g in enumerate(gs)]
@@ -117,18 +117,29 @@ def test_batch_matches_single_ops_and_oracle(name):
     assert b.keyswitches == sum(len(c[3]) for c in checks)
     b.run()
     compare_to_single(s, checks, "batch")
-    for kind, lv, args, outs, np_args in checks:   # the oracle on a subset
-        if kind == "hmult" and lv == min(PLANS[name]["hmult"]):
-            w0, w1 = oracle.hmult_relin(s.P, np_args[0], np_args[1], np_args[2], lv)
-            assert_equal(s.host(outs[0].c0), w0, "oracle hmult c0")
-            assert_equal(s.host(outs[0].c1), w1, "oracle hmult c1")
-        if kind == "hoisted":
-            c_np, gs, keys_np = np_args
-            w0, w1 = oracle.hoisted_rotate(s.P, c_np, gs, keys_np, lv)
-            for i in range(len(gs)):
-                assert_equal(s.host(outs[i].c0), w0[i], "oracle hoisted c0")
-                assert_equal(s.host(outs[i].c1), w1[i], "oracle hoisted c1")
+    # the oracle on every item of the N = 2^12 plans; at N = 2^16 on the lowest HMult and the hoisted items
+    every = params_of(name) == "small"
+    for kind, lv, args, outs, np_args in checks:
+        if not every and not (kind == "hoisted" or (kind == "hmult" and lv == min(PLANS[name]["hmult"]))):
+            continue
+        for i, (w0, w1) in enumerate(oracle_of(s, kind, lv, np_args)):
+            assert_equal(s.host(outs[i].c0), w0, "oracle %s level %d c0" % (kind, lv))
+            assert_equal(s.host(outs[i].c1), w1, "oracle %s level %d c1" % (kind, lv))
     b.close()
+
+
+def oracle_of(s, kind, lv, np_args):
+    """The oracle's results [(c0, c1), ...] for one batch item."""
+    if kind == "hmult":
+        return [oracle.hmult_relin(s.P, np_args[0], np_args[1], np_args[2], lv)]
+    if kind == "ks":
+        return [oracle.keyswitch(s.P, np_args[0], np_args[1], lv)]
+    if kind == "rot":
+        c_np, key_np, g = np_args
+        return [oracle.apply_galois(s.P, c_np, g, key_np, lv)]
+    c_np, gs, keys_np = np_args
+    w0, w1 = oracle.hoisted_rotate(s.P, c_np, gs, keys_np, lv)
+    return [(w0[i], w1[i]) for i in range(len(gs))]
 
 
 @pytest.mark.parametrize("name", ["small", "large", "small_shared"])
@@ -151,4 +162,71 @@ def test_batch_graph_replays_and_tuning_are_bit_stable(name):
         st.synchronize()
         compare_to_single(s, checks, "replay %d" % rep)   # eager single-op work between replays
         torch.cuda.synchronize()
+    b.close()
+
+
+def build_plan_batch(s, plan, seed):
+    """A batch of the bench's kind (inputs.batch_plan: HMult+relin items and
+    hoisted 8-way rotations at mixed levels) with uniform keys."""
+    b = s.ckks.Batch(s.ctx)
+    rlk_np, rlk = s.key(seed, 0)
+    keys = {}
+    checks = []
+    for i, (kind, lv, ks) in enumerate(plan):
+        c_np, c = s.ct(seed + 10 + 3 * i, lv)
+        if kind == "hmult":
+            d_np, d = s.ct(seed + 11 + 3 * i, lv)
+            out = s.ctx.empty_ct(lv)
+            b.hmult(c, d, rlk, out)
+            checks.append(("hmult", lv, (c, d, rlk), [out], (c_np, d_np, rlk_np)))
+        else:
+            gs = [oracle.galois_for_rotation(s.ps.logn, k) for k in ks]
+            for k, g in zip(ks, gs):
+                if k not in keys:
+                    keys[k] = s.key(seed + 1000 + k, g)
+            outs = [s.ctx.empty_ct(lv) for _ in ks]
+            b.hoisted(c, ks, [keys[k][1] for k in ks], outs)
+            checks.append(("hoisted", lv, (c, ks, [keys[k][1] for k in ks]), outs, (c_np, gs, [keys[k][0] for k in ks])))
+    b.build()
+    return b, checks
+
+
+def test_bench_kind_plan_every_item_against_oracle():
+    """The bench's batch shape at N = 2^12 (20 levels, 16 items, levels 4..20):
+    every item against the oracle, and the persistent-kernel run against the
+    single-operation calls."""
+    s = setup("boot-small")
+    plan = inputs.batch_plan(inputs.BASE_SEED + 77, 16, s.ps.logn, s.ps.L)
+    b, checks = build_plan_batch(s, plan, 1300)
+    b.run()
+    compare_to_single(s, checks, "plan batch")
+    for kind, lv, args, outs, np_args in checks:
+        for i, (w0, w1) in enumerate(oracle_of(s, kind, lv, np_args)):
+            assert_equal(s.host(outs[i].c0), w0, "oracle plan %s level %d c0" % (kind, lv))
+            assert_equal(s.host(outs[i].c1), w1, "oracle plan %s level %d c1" % (kind, lv))
+    b.close()
+
+
+def test_bench_batch_128_items_equals_single_ops():
+    """The bench's own 128-item batch at N = 2^16 (levels 4..30, 64 HMult+relin
+    and 64 hoisted 8-way rotations): the graph replay equals the single-operation
+    calls on every item, and the oracle on one item of each kind."""
+    import torch
+    s = setup("large")
+    plan = inputs.batch_plan(inputs.BASE_SEED + 1 + 500, 128, s.ps.logn, s.ps.L)
+    b, checks = build_plan_batch(s, plan, 1500)
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        b.capture(st)
+        b.replay(st)
+    st.synchronize()
+    compare_to_single(s, checks, "128-item batch")
+    done = set()
+    for kind, lv, args, outs, np_args in checks:
+        if kind in done:
+            continue
+        done.add(kind)
+        for i, (w0, w1) in enumerate(oracle_of(s, kind, lv, np_args)):
+            assert_equal(s.host(outs[i].c0), w0, "oracle 128-item %s level %d c0" % (kind, lv))
+            assert_equal(s.host(outs[i].c1), w1, "oracle 128-item %s level %d c1" % (kind, lv))
     b.close()

@@ -80,16 +80,19 @@ def _random_key(s, seed, galois):
     return d, s.ctx.key(d, galois)
 
 
-def test_bootstrap_large_graph_replay():
-    """The bench's configuration exactly (the package defaults at N = 2^16 with
-    ten special primes: groups [5, 5, 5], degree 31, K = 12, 3 double angles,
-    sparse-secret encapsulation, hoisted ModDown), bit for bit against the
-    oracle (about a minute of CPU), then three graph replays."""
+@pytest.mark.parametrize("sparse", [True, False])
+def test_bootstrap_large_graph_replay(sparse):
+    """The bench's two configurations exactly (the package defaults at N = 2^16
+    with ten special primes, groups [5, 5, 5], hoisted ModDown): with
+    sparse-secret encapsulation, degree 31, K = 12, 3 double angles; and for
+    the uniform secret itself, degree 119 (baby 16), K = 512, 6 double angles.
+    Bit for bit against the oracle (a minute or two of CPU), then three graph
+    replays."""
     import torch
     from paper_2507_04775_amd import bootplan
-    _say("bootstrap large-nv (bench configuration): plan and keys")
+    _say("bootstrap large-nv (bench configuration, sparse %s): plan and keys" % sparse)
     s = Setup("large-nv")
-    cfg = bootplan.default_config(16, 2.0 ** 50)
+    cfg = bootplan.default_config(16, 2.0 ** 50, sparse=sparse)
     bp = B.BootParams(logn=16, cts_radix_logs=cfg.cts_radix_logs, stc_radix_logs=cfg.stc_radix_logs,
                       cheb_degree=cfg.cheb_degree, double_angles=cfg.double_angles, k_range=cfg.k_range,
                       top_scale=cfg.top_scale, in_scale=cfg.in_scale, hoist_moddown=cfg.hoist_moddown)
@@ -99,8 +102,9 @@ def test_bootstrap_large_graph_replay():
         rot[k] = _random_key(s, 1000 + k, oracle.galois_for_rotation(16, k))
     rlk = _random_key(s, 1, 0)
     conj = _random_key(s, 2, 2 * s.N - 1)
-    to_sp, from_sp = _random_key(s, 3, 0), _random_key(s, 4, 0)
-    boot = _boot_handle(s, bp, pl, rlk[1], conj[1], {k: v[1] for k, v in rot.items()}, (to_sp[1], from_sp[1]))
+    to_sp, from_sp = (_random_key(s, 3, 0), _random_key(s, 4, 0)) if sparse else ((None, None), (None, None))
+    boot = _boot_handle(s, bp, pl, rlk[1], conj[1], {k: v[1] for k, v in rot.items()},
+                        (to_sp[1], from_sp[1]) if sparse else None)
     c0, c1 = inputs.random_ct(5, s.ps, 0)
     inp = s.ckks.Ciphertext(s.dev(c0), s.dev(c1), 0, bp.in_scale)
     out = s.ctx.empty_ct(boot.output_level)
@@ -110,8 +114,9 @@ def test_bootstrap_large_graph_replay():
 
     _say("bootstrap large: oracle")
     host = lambda t: t.cpu().numpy()
+    sp_np = (host(to_sp[0]), host(from_sp[0])) if sparse else (None, None)
     want = B.Executor(s.P, pl, host(rlk[0]), host(conj[0]), {k: host(v[0]) for k, v in rot.items()},
-                      host(to_sp[0]), host(from_sp[0])).bootstrap((c0, c1, 0))
+                      *sp_np).bootstrap((c0, c1, 0))
     _check_ct(s, out, want, "bootstrap")
 
     _say("bootstrap large: graph replays")

@@ -20,7 +20,7 @@ def setup(name):
     return _setups[name]
 
 
-LEVELS = {"small": [3, 2, 1, 0], "large": [30, 21, 12, 0]}
+LEVELS = {"small": [3, 2, 1, 0], "large": [30, 21, 12, 0], "large-nv": [30, 12, 0]}
 
 
 @pytest.mark.parametrize("name", ["small", "large"])
@@ -64,7 +64,7 @@ def test_ntt_edge_values(name):
     assert_equal(s.host(t), oracle.ntt(mods, a, s.ps.logn), "ntt edge")
 
 
-@pytest.mark.parametrize("name", ["small", "large"])
+@pytest.mark.parametrize("name", ["small", "large", "large-nv"])
 def test_modup(name):
     s = setup(name)
     for level in LEVELS[name]:
@@ -74,7 +74,7 @@ def test_modup(name):
         assert_equal(s.host(ext), oracle.modup(s.P, d, level), "modup level %d" % level)
 
 
-@pytest.mark.parametrize("name", ["small", "large"])
+@pytest.mark.parametrize("name", ["small", "large", "large-nv"])
 def test_inner_product(name):
     s = setup(name)
     key, kh = s.key(5, 0)
@@ -89,7 +89,7 @@ def test_inner_product(name):
             assert_equal(s.host(acc), oracle.inner_product(s.P, ext, key, level, g), "ip level %d g %d" % (level, g))
 
 
-@pytest.mark.parametrize("name", ["small", "large"])
+@pytest.mark.parametrize("name", ["small", "large", "large-nv"])
 def test_moddown(name):
     s = setup(name)
     for level in LEVELS[name]:
@@ -99,7 +99,7 @@ def test_moddown(name):
         assert_equal(s.host(out), oracle.moddown(s.P, x, level), "moddown level %d" % level)
 
 
-@pytest.mark.parametrize("name", ["small", "large"])
+@pytest.mark.parametrize("name", ["small", "large", "large-nv"])
 def test_keyswitch(name):
     s = setup(name)
     key, kh = s.key(6, 0)
@@ -180,6 +180,23 @@ def test_hoisted_rotations(name):
     for i in range(len(ks)):
         assert_equal(s.host(outs[i].c0), w0[i], "hoisted %d c0" % ks[i])
         assert_equal(s.host(outs[i].c1), w1[i], "hoisted %d c1" % ks[i])
+
+
+def test_hoisted_rotations_ten_special_primes_all_levels():
+    """Hoisted rotations with K = 10 (ten-source ModDown conversions, 41-row
+    extended polynomials) at l = 30, 12 and 0."""
+    s = setup("large-nv")
+    ks = [1, 3, 1024]
+    gs = [oracle.galois_for_rotation(s.ps.logn, k) for k in ks]
+    keys = [s.key(230 + i, g) for i, g in enumerate(gs)]
+    for level in LEVELS["large-nv"]:
+        c, tc = s.ct(82 + level, level)
+        outs = [s.ctx.empty_ct(level) for _ in ks]
+        s.ctx.ckks_hrotate_hoisted(tc, ks, [k[1] for k in keys], outs)
+        w0, w1 = oracle.hoisted_rotate(s.P, c, gs, [k[0] for k in keys], level)
+        for i in range(len(ks)):
+            assert_equal(s.host(outs[i].c0), w0[i], "hoisted K=10 level %d rot %d c0" % (level, ks[i]))
+            assert_equal(s.host(outs[i].c1), w1[i], "hoisted K=10 level %d rot %d c1" % (level, ks[i]))
 
 
 @pytest.mark.parametrize("name", ["small", "large"])

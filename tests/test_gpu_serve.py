@@ -1,7 +1,10 @@
 """The continuous-batching server: every request's result is the same when it
-runs alone and when it runs in the concurrent mix (bit for bit), chains
-without bootstrap match the oracle applying the same ops, and every request
-completes after it arrived."""
+runs alone and when it runs in the concurrent mix (bit for bit), at N = 2^12
+and at N = 2^16 (31 limbs, K = 4, the bench's serving shape), with
+bootstraps spread over two handles; chains without bootstrap match the oracle
+applying the same ops; every request completes after it arrived; device
+memory follows the requests in flight and a request larger than the memory
+budget is refused."""
 import numpy as np
 import pytest
 
@@ -12,7 +15,7 @@ from paper_2507_04775_amd import inputs
 pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
 
 
-def _server(s, slots, budget):
+def _server(s, slots, budget, n_boot=2):
     import torch
     from paper_2507_04775_amd import bootplan, ckks
     from paper_2507_04775_amd.serve import Server
@@ -29,10 +32,11 @@ def _server(s, slots, budget):
     cfg = bootplan.default_config(s.ps.logn, 2.0 ** s.ps.log_scale)
     pl = bootplan.plan(s.ps.q, cfg)
     bkeys = {k: rkey(5000 + k, pow(5, k, 2 * s.N))[1] for k in pl.rotations}
-    boot = ckks.Boot(s.ctx, cfg.cts_radix_logs, cfg.stc_radix_logs, pl.cts, pl.stc, pl.cheb, cfg.double_angles,
-                     cfg.top_scale, relin[1], rkey(2, 2 * s.N - 1)[1], bkeys,
-                     sparse=(rkey(3, 0)[1], rkey(4, 0)[1]), hoist_moddown=cfg.hoist_moddown)
-    srv = Server(s.ctx, relin[1], {k: v[1] for k, v in rot.items()}, pts, boot, slots=slots, mem_budget=budget)
+    conj, sparse = rkey(2, 2 * s.N - 1)[1], (rkey(3, 0)[1], rkey(4, 0)[1])
+    boots = [ckks.Boot(s.ctx, cfg.cts_radix_logs, cfg.stc_radix_logs, pl.cts, pl.stc, pl.cheb, cfg.double_angles,
+                       cfg.top_scale, relin[1], conj, bkeys, sparse=sparse, hoist_moddown=cfg.hoist_moddown)
+             for _ in range(n_boot)]
+    srv = Server(s.ctx, relin[1], {k: v[1] for k, v in rot.items()}, pts, boots, slots=slots, mem_budget=budget)
     return srv, relin[0], {k: v[0] for k, v in rot.items()}, pts
 
 
@@ -60,12 +64,7 @@ def _oracle_chain(s, r, rlk, rot, pts):
     return A, l
 
 
-def test_results_alone_equal_results_in_the_mix():
-    s = Setup("boot-small")
-    srv, rlk, rot, pts = _server(s, slots=4, budget=64 << 20)
-    reqs = inputs.serving_requests(inputs.BASE_SEED + 5, 14, s.ps.logn, rate=4000.0, min_level=4, max_level=20,
-                                   min_ops=3, max_ops=12, boot_frac=0.25)
-    assert any(r.boot for r in reqs) and not all(r.boot for r in reqs)
+def _alone_equals_mix(s, srv, rlk, rot, pts, reqs):
     mix = srv.run(reqs, keep_outputs=True, concurrent=True)
     alone = srv.run(reqs, keep_outputs=True, concurrent=False)
     assert [d.rid for d in mix] == [r.rid for r in reqs] == [d.rid for d in alone]
@@ -84,3 +83,52 @@ def test_results_alone_equal_results_in_the_mix():
         assert_equal(d.output[1], w1, "oracle chain %d c1" % r.rid)
         checked += 1
     assert checked == 2
+    return mix
+
+
+def test_results_alone_equal_results_in_the_mix():
+    s = Setup("boot-small")
+    srv, rlk, rot, pts = _server(s, slots=4, budget=64 << 20)
+    reqs = inputs.serving_requests(inputs.BASE_SEED + 5, 14, s.ps.logn, rate=4000.0, min_level=4, max_level=20,
+                                   min_ops=3, max_ops=12, boot_frac=0.25)
+    assert sum(r.boot for r in reqs) >= 2 and not all(r.boot for r in reqs)
+    _alone_equals_mix(s, srv, rlk, rot, pts, reqs)
+
+
+def test_results_alone_equal_results_in_the_mix_logn16():
+    """The bench's serving shape: N = 2^16, 31 limbs, K = 4, start levels
+    10..30, bootstraps (sparse-secret encapsulation, hoisted ModDown) on two
+    handles."""
+    s = Setup("large")
+    srv, rlk, rot, pts = _server(s, slots=4, budget=8 << 30)
+    reqs = inputs.serving_requests(inputs.BASE_SEED + 6, 8, s.ps.logn, rate=400.0, min_level=10, max_level=30,
+                                   min_ops=3, max_ops=8, boot_frac=0.3)
+    assert sum(r.boot for r in reqs) >= 2 and not all(r.boot for r in reqs)
+    _alone_equals_mix(s, srv, rlk, rot, pts, reqs)
+
+
+def test_memory_follows_requests_in_flight_and_oversized_is_refused():
+    import torch
+    s = Setup("boot-small")
+    srv, rlk, rot, pts = _server(s, slots=3, budget=16 << 20, n_boot=1)
+    reqs = inputs.serving_requests(inputs.BASE_SEED + 8, 12, s.ps.logn, rate=3000.0, min_level=4, max_level=20,
+                                   min_ops=2, max_ops=6, boot_frac=0.2)
+    torch.cuda.synchronize()
+    base = torch.cuda.memory_allocated()
+    res = srv.run(reqs)
+    assert not any(d.refused for d in res) and len(res) == len(reqs)
+    one_ct = 2 * (s.ps.L + 1) * s.N * 8
+    for inflight, budgeted, allocated in srv.mem_samples:
+        assert allocated - base <= budgeted + one_ct, (inflight, budgeted, allocated - base)
+    torch.cuda.synchronize()
+    assert torch.cuda.memory_allocated() == base
+    big = srv.footprint(reqs[0]) * 2
+    tight = _server(s, slots=3, budget=big // 2, n_boot=1)[0]
+    huge = [r for r in reqs if tight.footprint(r) > big // 2]
+    small = [r for r in reqs if tight.footprint(r) <= big // 2]
+    assert huge and small
+    res = tight.run(huge + small)
+    for d in res:
+        want_refused = any(d.rid == r.rid for r in huge)
+        assert d.refused == want_refused, d.rid
+        assert (d.output is None) if d.refused else d.finish >= d.arrival - 1e-3

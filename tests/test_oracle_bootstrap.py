@@ -81,6 +81,75 @@ def test_layout_counts_and_rotations():
     assert B.baby_offsets(n, g2) == [1, 2, 3]
 
 
+def test_layout_at_n_2_15_three_groups_each_way():
+    """The N = 2^16 full-slot layout (n = 2^15 slots, groups [5, 5, 5]) against
+    values derived by hand from the group definition: a group holding the stage
+    of half-size n/2 has R = 32 diagonals at m h0, m in [0, 32); the others 63
+    at m in [-31, 31]; baby 8 (the smallest power of two whose square reaches
+    the count), giants G_g = (8 g + m_lo) h0; 38 distinct rotations in all."""
+    n = 1 << 15
+    cts = B.stage_groups(16, [5, 5, 5], False)
+    stc = B.stage_groups(16, [5, 5, 5], True)
+    assert cts == [[16384, 8192, 4096, 2048, 1024], [512, 256, 128, 64, 32], [16, 8, 4, 2, 1]]
+    assert stc == [[1, 2, 4, 8, 16], [32, 64, 128, 256, 512], [1024, 2048, 4096, 8192, 16384]]
+    assert B.group_layout(n, cts[0]) == (0, 32, 8, 4, 1024)
+    assert B.group_layout(n, cts[1]) == (-31, 63, 8, 8, 32)
+    assert B.group_layout(n, cts[2]) == (-31, 63, 8, 8, 1)
+    assert B.group_layout(n, stc[2]) == (0, 32, 8, 4, 1024)
+    assert B.giant_offsets(n, cts[0]) == [0, 8192, 16384, 24576]
+    assert B.giant_offsets(n, cts[1]) == [-992, -736, -480, -224, 32, 288, 544, 800]
+    assert B.giant_offsets(n, cts[2]) == [-31, -23, -15, -7, 1, 9, 17, 25]
+    assert B.baby_offsets(n, cts[0]) == [1024 * b for b in range(1, 8)]
+    assert B.baby_offsets(n, stc[0]) == list(range(1, 8))
+    bp = B.BootParams(logn=16, cts_radix_logs=[5, 5, 5], stc_radix_logs=[5, 5, 5], cheb_degree=31,
+                      double_angles=3, k_range=12.0, top_scale=2.0 ** 50, in_scale=2.0 ** 50)
+    assert len(B.rotations_needed(bp)) == 38
+
+
+@pytest.fixture(scope="module")
+def stages_16():
+    n = 1 << 15
+    return {h: (B.special_fft_stage(n, 16, h, False), B.special_fft_stage(n, 16, h, True))
+            for h in [1 << i for i in range(15)]}
+
+
+@pytest.mark.parametrize("forward,gi", [(False, 0), (False, 1), (False, 2), (True, 0), (True, 1), (True, 2)])
+def test_groups_by_bsgs_equal_their_stages_at_n_2_15(stages_16, forward, gi):
+    """Each merged group of the N = 2^16 schedule, evaluated in the BSGS form
+    the executors use (pre-rotated diagonals, hoisted babies, giant steps),
+    equals its butterfly stages applied one by one to a vector of 2^15 slots."""
+    n = 1 << 15
+    halves = B.stage_groups(16, [5, 5, 5], forward)[gi]
+    v = inputs.complex_slots(inputs.rng(40 + gi + 3 * forward), n)
+    want = v
+    for h in halves:
+        want = _apply(stages_16[h][0 if forward else 1], want)
+    m_lo, count, baby, giants, h0 = B.group_layout(n, halves)
+    pds = B.group_diagonals(n, 16, halves, not forward)
+    G = B.giant_offsets(n, halves)
+    babies = [np.roll(v, -b * h0) for b in range(baby)]
+    got = 0
+    for g in range(giants):
+        part = sum(pds[i] * babies[i - g * baby] for i in range(g * baby, min(count, (g + 1) * baby)))
+        got = got + np.roll(part, -G[g])
+    assert np.max(np.abs(got - want)) < 1e-9
+
+
+def test_stages_compose_to_the_embedding_on_sampled_rows_at_n_2_15(stages_16):
+    """The 15 forward stages applied to bit-reversed slots reproduce sampled
+    rows of the canonical embedding z_j = sum_k zeta^(5^j k) w_k at N = 2^16."""
+    logn, n, N = 16, 1 << 15, 1 << 16
+    w = inputs.complex_slots(inputs.rng(77), n)
+    perm = np.array([br(x, logn - 1) for x in range(n)])
+    v = w[perm]
+    for h in [1 << i for i in range(logn - 1)]:
+        v = _apply(stages_16[h][0], v)
+    e = client.slot_exponents(logn)
+    for j in [0, 1, 2, 777, 12345, n // 2, n - 1]:
+        zj = np.sum(np.exp(1j * np.pi * (int(e[j]) * np.arange(n) % (2 * N)) / N) * w)
+        assert abs(v[j] - zj) < 1e-7 * np.sqrt(n)
+
+
 def test_scale_chain():
     ps = inputs.params("boot-small")
     q = ps.q

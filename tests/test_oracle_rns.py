@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 
 import oracle
-from helpers import oracle_params
+from helpers import crt, edge_rows, oracle_params, prod, scaled_inputs
 from paper_2507_04775_amd import inputs
 
 
@@ -107,6 +107,54 @@ def test_moddown_is_centred_division(name, level):
         assert 2 * abs(v) < ps.K * Pp
         if ps.K == 1:
             assert 2 * abs(v) < Pp
+
+
+def moddown_threshold_input(ps, level, seed):
+    """An extended polynomial (evaluation domain, rows q_0..q_l, p_0..p_{K-1})
+    whose special rows give scaled conversion inputs y_k (coefficient domain)
+    cycling through 0, 1, (p_k-1)/2, (p_k+1)/2, p_k-2, p_k-1 and the 32-bit
+    word boundaries, mixed across k; the q rows are uniform."""
+    rows = list(ps.q[: level + 1]) + list(ps.p)
+    g = inputs.rng(seed)
+    qc = inputs.uniform_residues(g, ps.q[: level + 1], ps.N)
+    pc = scaled_inputs(edge_rows(seed + 1, ps.p, ps.N), ps.p)
+    return oracle.ntt(rows, np.concatenate([qc, pc]), ps.logn)
+
+
+def centred_v(ps, pcoef) -> int:
+    """v = sum_k y_k^ctr (P/p_k), y_k = [a_k (P/p_k)^-1]_{p_k} lifted to
+    y_k - p_k above (p_k - 1)/2, for the special-row coefficients a_k."""
+    Pp = prod(ps.p)
+    v = 0
+    for a, pk in zip(pcoef, ps.p):
+        pk = int(pk)
+        Pk = Pp // pk
+        y = int(a) * pow(Pk, -1, pk) % pk
+        v += (y - pk if y > (pk - 1) // 2 else y) * Pk
+    return v
+
+
+@pytest.mark.parametrize("name,level", [("tiny", 3), ("small", 2), ("small-nv", 3), ("small-nv", 0),
+                                        ("large-nv", 30), ("large-nv", 0)])
+def test_moddown_exact_centred_conversion(name, level):
+    """Bit-determining for any K: out = (X - v) / P mod Q_l exactly, with v the
+    centred conversion sum (ModDown reading of Eq. (1), III-F.3), on inputs that
+    put y_k on both sides of the centring threshold (p_k-1)/2."""
+    ps = inputs.params(name)
+    P = oracle_params(ps)
+    rows = P.row_moduli(level)
+    x = moddown_threshold_input(ps, level, 40 + level)
+    out = oracle.moddown(P, x, level)
+    xc = oracle.intt(rows, x, ps.logn)
+    oc = oracle.intt(ps.q[: level + 1], out, ps.logn)
+    Pp, Ql = prod(ps.p), prod(ps.q[: level + 1])
+    coeffs = range(ps.N) if ps.N <= 4096 else list(range(0, 64)) + list(range(ps.N - 64, ps.N, 3))
+    nq = level + 1
+    for n in coeffs:
+        A = crt(xc[:, n], rows)
+        v = centred_v(ps, xc[nq:, n])
+        assert (A - v) % Pp == 0
+        assert crt(oc[:, n], ps.q[: level + 1]) == ((A - v) // Pp) % Ql, n
 
 
 @pytest.mark.parametrize("name", ["small", "small-nv"])
