@@ -26,6 +26,12 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# a bootstrap whose decrypted slot error (log2 of the largest slot difference) exceeds this gets no rate
+BOOT_PRECISION_BITS = -8.0
+# one wave64 VALU instruction per CU per cycle (four SIMDs of 16 lanes, four cycles each): 256 CUs at 2.4 GHz
+VALU_ISSUE_PEAK = 256 * 2.4e9
+# bytes of one limb at N = 2^16 (u64 residues)
+LIMB = 65536 * 8
 
 
 def parse():
@@ -34,17 +40,20 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-runs", type=int, default=3)
+    ap.add_argument("--no-probe", action="store_true", help="skip the multiply-add rate probe")
     ap.add_argument("--cold-sets", type=int, default=6)
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-items", type=int, default=128)
-    ap.add_argument("--batch-reps", type=int, default=5)
+    ap.add_argument("--batch-reps", type=int, default=20)
     ap.add_argument("--no-boot", action="store_true")
     ap.add_argument("--no-uniform-boot", action="store_true", help="skip the uniform-secret bootstrap variant")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 256 MiB device copy (the reference kernel for HBM counter scaling)")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=48)
+    ap.add_argument("--serve-requests", type=int, default=500)
+    ap.add_argument("--serve-loads", type=str, default="0.25,0.5,0.75,0.9,1.0,1.1")
+    ap.add_argument("--serve-boot-handles", type=int, default=2)
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--serve-mem-gib", type=int, default=16)
     ap.add_argument("--boot-reps", type=int, default=10)
@@ -79,6 +88,78 @@ def ntt_sources_sha256():
     return h.hexdigest()
 
 
+_SLEEP_CYCLES_PER_US = [None]
+
+
+def preload(stream, us: float):
+    """Holds `stream` for about `us` microseconds with a one-thread spin kernel,
+    so that the host enqueues the launches that follow before the GPU reaches
+    them: per-launch event pairs then time the GPU, not host submission gaps."""
+    import torch
+    if _SLEEP_CYCLES_PER_US[0] is None:
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(stream):
+            torch.cuda._sleep(1000)
+            e0.record(stream)
+            torch.cuda._sleep(2_000_000)
+            e1.record(stream)
+        stream.synchronize()
+        _SLEEP_CYCLES_PER_US[0] = 2_000_000 / max(1e-3, e0.elapsed_time(e1) * 1e3)
+    with torch.cuda.stream(stream):
+        torch.cuda._sleep(int(us * _SLEEP_CYCLES_PER_US[0]))
+
+
+def timed_launches(fn, reps: int, stream, host_us: float = 200.0):
+    """GPU time of each of `reps` back-to-back calls of fn() on `stream` (ms),
+    the stream held first long enough for all of them to be enqueued."""
+    import torch
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    torch.cuda.synchronize()
+    preload(stream, 2000.0 + reps * host_us)
+    ev[0].record(stream)
+    for i in range(reps):
+        fn()
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    return [ev[i].elapsed_time(ev[i + 1]) for i in range(reps)]
+
+
+def stats_ms(xs):
+    return {"p50_ms": round(percentile(xs, 50), 4), "p99_ms": round(percentile(xs, 99), 4),
+            "mean_ms": round(sum(xs) / len(xs), 4), "n": len(xs)}
+
+
+KERNEL_SOURCES = ("kernels.hip", "ntt.hip", "unit_map.h", "internal.h", "modarith.h", "ks_args.cpp", "api.cpp")
+
+
+def kernel_sources_sha256():
+    """The same digest over every source the key-switching kernels and their
+    launch sequence come from (validity of the VALU and inner-product counters)."""
+    import hashlib
+    import re
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        t = open(os.path.join(ROOT, "paper_2507_04775_amd", "csrc", f)).read()
+        t = re.sub(r"/\*.*?\*/", " ", t, flags=re.S)
+        t = re.sub(r"//[^\n]*", " ", t)
+        h.update(re.sub(r"\s+", " ", t).strip().encode())
+    return h.hexdigest()
+
+
+def measured_ip_traffic():
+    """HBM bytes per launch of k_inner_product from its committed counter
+    summary, while the kernel sources are the profiled ones (else None)."""
+    prof = os.path.join(ROOT, "profiles", "inner_product_logn16_l30_hbm_counters.md")
+    try:
+        fields = dict(l.split(":", 1) for l in open(prof)
+                      if l.startswith(("traffic_bytes_per_launch:", "kernel_sources_sha256:")))
+        if kernel_sources_sha256() != fields["kernel_sources_sha256"].strip():
+            return None
+        return int(fields["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def measured_traffic():
     """HBM bytes per launch of the roofline kernel, from the committed counter
     summary, valid only while the NTT sources (the kernel file and the headers
@@ -94,12 +175,163 @@ def measured_traffic():
         return None
 
 
-def run_batch(ctx, ps, seed, args):
+def inner_product_roofline(ctx, ps, seed, stream):
+    """Algorithmic HBM bytes of ckks_inner_product at the top level over its
+    measured launch time (k_inner_product is its only kernel)."""
+    import torch
+
+    from paper_2507_04775_amd import inputs
+    level = ps.L
+    rows, beta = level + 1 + ps.K, ctx.beta(level)
+    allm = list(ps.q) + list(ps.p)
+    rowm = list(ps.q[: level + 1]) + list(ps.p)
+    sets = []
+    for i in range(2):
+        ext = inputs.device_residues(seed + 800 + i, rowm * beta, ps.N).reshape(beta, rows, ps.N).contiguous()
+        kd = inputs.device_residues(seed + 810 + i, allm * (2 * ps.dnum), ps.N).reshape(ps.dnum, 2, len(allm), ps.N)
+        kd = kd.contiguous()
+        sets.append((ext, ctx.key(kd, 0), torch.empty((2, rows, ps.N), dtype=torch.uint64, device="cuda"), kd))
+    turn = [0]
+
+    def launch():
+        ext, key, acc, _ = sets[turn[0] % 2]
+        turn[0] += 1
+        ctx.ckks_inner_product(ext, level, key, 1, acc, stream)
+
+    for _ in range(4):
+        launch()
+    n = 40
+    torch.cuda.synchronize()
+    preload(stream, 2000.0 + 100.0 * n)
+    b0, b1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    b0.record(stream)
+    for _ in range(n):
+        launch()
+    b1.record(stream)
+    torch.cuda.synchronize()
+    us = b0.elapsed_time(b1) / n * 1e3
+    nbytes = (3 * beta + 2) * rows * LIMB
+    gbs = nbytes / (us / 1e6) / 1e9
+    return {"bound": "hbm", "kernel": "k_inner_product (key inner product, l = 30: 3 digits x 35 rows)",
+            "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "traffic": measured_ip_traffic(), "algorithmic_bytes_per_launch": nbytes, "launch_us": round(us, 2)}
+
+
+def run_probe(stream):
+    """Rate of the 32x32->64 multiply-add (v_mad_u64_u32) on the whole chip."""
+    import torch
+
+    from paper_2507_04775_amd import ckks
+    blocks, iters = 256 * 8, 2048
+    out = torch.empty(blocks * 256, dtype=torch.uint64, device="cuda")
+    for _ in range(3):
+        ckks.probe_mad64(out, blocks, iters, stream)
+    xs = []
+    n = 0
+    for _ in range(7):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        n = ckks.probe_mad64(out, blocks, iters, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        xs.append(e0.elapsed_time(e1))
+    ms = percentile(xs, 50)
+    wave = n / 64 / (ms / 1e3)
+    return {"workgroups": blocks, "threads": 256, "iters": iters, "chains": 8, "lane_mads_per_launch": n,
+            "launch_ms": round(ms, 4), "lane_mads_per_s": round(n / (ms / 1e3), 1),
+            "wave_instr_per_s": round(wave, 1), "frac_of_issue_peak": round(wave / VALU_ISSUE_PEAK, 4)}
+
+
+def valu_fractions(probe):
+    """VALU issue fractions of the key-switching kernels from the committed SQ
+    counter profile, valid while the kernel sources are the ones profiled (else
+    None): instructions per launch over the profiled duration, against the issue
+    peak and against the measured multiply-add rate."""
+    prof = os.path.join(ROOT, "profiles", "keyswitch_step_logn16_valu_counters.md")
+    try:
+        text = open(prof).read()
+    except OSError:
+        return None
+    sha = None
+    for line in text.splitlines():
+        if line.startswith("kernel_sources_sha256:"):
+            sha = line.split(":", 1)[1].strip()
+    if sha != kernel_sources_sha256():
+        return None
+    rows = {}
+    for line in text.splitlines():
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        if len(cells) == 7 and cells[0].startswith("k_") and cells[2].isdigit():
+            name = "%s %s" % (cells[0], cells[1])
+            if name in rows:
+                continue
+            waves, per, us = int(cells[2]), int(cells[3]), float(cells[4])
+            rate = waves * per / (us / 1e6)
+            rows[name] = {"wave_instr_per_launch": waves * per, "avg_us": us,
+                          "frac_of_issue_peak": round(rate / VALU_ISSUE_PEAK, 3)}
+    keep = ["k_fwd_col_bconv 8192x62x1", "k_inner_product 65536x35x1", "k_bconv 65536x3x5",
+            "k_fwd_row_moddown 8192x62x1", "k_fwd_col_plain 8192x74x1", "k_fwd_row_plain 8192x74x1"]
+    out = {"peak_wave_instr_per_s": VALU_ISSUE_PEAK, "source": os.path.relpath(prof, ROOT),
+           "kernels": {k: rows[k] for k in keep if k in rows}}
+    if probe:
+        out["mad64_wave_instr_per_s_measured"] = probe["wave_instr_per_s"]
+    return out
+
+
+def cpu_baseline(ps, seed, level, g_rot, ks_per_step, runs):
+    """The oracle on the host: one step (HMult+relin, Rescale, HRotate at the top
+    level) per run on one thread, several steps per run on all cores; medians."""
+    import oracle
+    from paper_2507_04775_amd import inputs
+    P = oracle.Params(ps.logn, ps.q, ps.p, ps.dnum)
+    a = inputs.random_ct(seed, ps, level)
+    b = inputs.random_ct(seed + 1, ps, level)
+    rlk = inputs.random_key(seed + 2, ps)
+    rk = inputs.random_key(seed + 3, ps)
+    all_threads = oracle.max_threads()
+
+    def step():
+        mm = oracle.hmult_relin(P, a, b, rlk, level)
+        oracle.rescale(P, mm, level)
+        oracle.apply_galois(P, a, g_rot, rk, level)
+
+    def measure(threads, steps):
+        oracle.set_threads(threads)
+        step()  # warm
+        rates = []
+        for _ in range(runs):
+            t1 = time.perf_counter()
+            for _ in range(steps):
+                step()
+            rates.append(ks_per_step * steps / (time.perf_counter() - t1))
+        return rates
+
+    one = measure(1, 1)
+    many = measure(all_threads, 4)
+    oracle.set_threads(all_threads)
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": round(percentile(many, 50), 3), "unit": "key-switches/s", "cores": all_threads,
+            "kind": "oracle", "cpu_model": model, "runs": runs,
+            "sample": "HMult+relin, Rescale, HRotate at l=30, N=2^16: %d runs of 4 steps on %d threads, "
+                      "%d runs of 1 step on 1 thread; medians" % (runs, all_threads, runs),
+            "all_cores_runs": [round(x, 3) for x in many],
+            "single_thread": {"value": round(percentile(one, 50), 4), "unit": "key-switches/s", "cores": 1,
+                              "runs": [round(x, 4) for x in one]}}
+
+
+def run_batch(ctx, ps, seed, args, tcache):
     """C3-style batch: one graph replay of the persistent stage kernels vs the same
     items issued as plain per-operation calls on one stream."""
     import torch
 
-    from paper_2507_04775_amd import ckks, inputs
+    from paper_2507_04775_amd import ckks, inputs, tune
 
     plan = inputs.batch_plan(seed + 500, args.batch_items, ps.logn, ps.L)
     allm = list(ps.q) + list(ps.p)
@@ -137,18 +369,13 @@ def run_batch(ctx, ps, seed, args):
     st = torch.cuda.Stream()
     n_ks = batch.keyswitches
     with torch.cuda.stream(st):
-        batch.tune(st)
+        t0 = time.perf_counter()
+        tune.tune_batch(batch, ctx, tune.batch_signature([(k, l) for k, l, _ in plan]), st, tcache)
+        t_tune = time.perf_counter() - t0
         batch.capture(st)
         batch.replay(st)
         st.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        reps = []
-        for _ in range(args.batch_reps):
-            e0.record(st)
-            batch.replay(st)
-            e1.record(st)
-            st.synchronize()
-            reps.append(e0.elapsed_time(e1))
+        reps = timed_launches(lambda: batch.replay(st), max(20, args.batch_reps), st, host_us=100.0)
         ws_h = ctx.workspace(ckks.OP_HMULT, ps.L)
         ws_o = ctx.workspace(ckks.OP_HOISTED, ps.L)
 
@@ -161,21 +388,22 @@ def run_batch(ctx, ps, seed, args):
 
         plain()
         st.synchronize()
-        preps = []
-        for _ in range(max(2, args.batch_reps // 2)):
-            e0.record(st)
-            plain()
-            e1.record(st)
-            st.synchronize()
-            preps.append(e0.elapsed_time(e1))
-    bt, pt = min(reps), min(preps)
+        t0 = time.perf_counter()
+        plain()
+        host_ms = (time.perf_counter() - t0) * 1e3
+        st.synchronize()
+        preps = timed_launches(plain, max(20, args.batch_reps), st, host_us=1.5e3 * host_ms)
+    bt, pt = percentile(reps, 50), percentile(preps, 50)
     res = {"workload": "%d ciphertexts, levels 4..%d, half HMult+relin, half hoisted 8-way rotations" % (
                len(plan), ps.L),
            "key_switches": n_ks, "batched_ms": round(bt, 3), "plain_ms": round(pt, 3),
+           "batched": stats_ms(reps), "plain": stats_ms(preps),
            "batched_key_switches_per_s": round(n_ks / (bt / 1e3), 1),
            "plain_key_switches_per_s": round(n_ks / (pt / 1e3), 1),
+           "batched_key_switches_per_s_at_p99": round(n_ks / (percentile(reps, 99) / 1e3), 1),
+           "plain_key_switches_per_s_at_p99": round(n_ks / (percentile(preps, 99) / 1e3), 1),
            "speedup": round(pt / bt, 3), "workspace_bytes": int(batch.ws.numel() * 8),
-           "tuned_grid_wg_per_cu": [batch.grid(i) for i in range(12)]}
+           "tune_s": round(t_tune, 2), "tuned_grid_wg_per_cu": [batch.grid(i) for i in range(12)]}
     batch.close()
     return res
 
@@ -214,7 +442,7 @@ def run_bootstrap(seed, args, sparse=True):
 
     def measure(hoist):
         boot = ckks.Boot(ctx, cfg.cts_radix_logs, cfg.stc_radix_logs, pl.cts, pl.stc, pl.cheb, cfg.double_angles,
-                         cfg.top_scale, relin, conj, rot, sparse=sp, hoist_moddown=hoist)
+                         cfg.top_scale, relin, conj, rot, sparse=sp, hoist_moddown=hoist, input_gain=cfg.input_gain)
         out = ctx.empty_ct(boot.output_level)
         stream = torch.cuda.current_stream()
         boot.ckks_bootstrap(ct, out)
@@ -247,7 +475,10 @@ def run_bootstrap(seed, args, sparse=True):
     plain.close()
     boot, err, eager, graph, same = measure(cfg.hoist_moddown)
     g50 = percentile(graph, 50)
-    res = {"bootstraps_per_s": round(1e3 / g50, 2), "graph_p50_ms": round(g50, 3),
+    usable = err <= BOOT_PRECISION_BITS
+    res = {"bootstraps_per_s": round(1e3 / g50, 2) if usable else None,
+           "precision_threshold_bits": BOOT_PRECISION_BITS, "meets_precision_threshold": usable,
+           "graph_p50_ms": round(g50, 3),
            "graph_p99_ms": round(percentile(graph, 99), 3), "eager_p50_ms": round(percentile(eager, 50), 3),
            "eager_p99_ms": round(percentile(eager, 99), 3), "reps": reps, "graph_equals_eager": same,
            "key_switches": boot.keyswitches, "levels_left": boot.output_level, "slots": ps.N // 2,
@@ -289,36 +520,43 @@ def run_serving(ctx, ps, seed, args):
     cfg = bootplan.default_config(ps.logn, 2.0 ** ps.log_scale)
     pl = bootplan.plan(ps.q, cfg)
     bkeys = {k: rkey(seed + 5000 + k, pow(5, k, 2 * ps.N)) for k in pl.rotations}
+    boot_conj, boot_sparse = rkey(seed + 2, 2 * ps.N - 1), (rkey(seed + 3, 0), rkey(seed + 4, 0))
     boot = ckks.Boot(ctx, cfg.cts_radix_logs, cfg.stc_radix_logs, pl.cts, pl.stc, pl.cheb, cfg.double_angles,
-                     cfg.top_scale, relin, rkey(seed + 2, 2 * ps.N - 1), bkeys,
-                     sparse=(rkey(seed + 3, 0), rkey(seed + 4, 0)), hoist_moddown=cfg.hoist_moddown)
-    srv = Server(ctx, relin, rot, pts, boot, slots=args.serve_slots, mem_budget=args.serve_mem_gib << 30)
+                     cfg.top_scale, relin, boot_conj, bkeys, sparse=boot_sparse, hoist_moddown=cfg.hoist_moddown, input_gain=cfg.input_gain)
+    boots = [boot] + [ckks.Boot(ctx, cfg.cts_radix_logs, cfg.stc_radix_logs, pl.cts, pl.stc, pl.cheb,
+                                cfg.double_angles, cfg.top_scale, relin, boot_conj, bkeys, sparse=boot_sparse,
+                                hoist_moddown=cfg.hoist_moddown, input_gain=cfg.input_gain) for _ in range(args.serve_boot_handles - 1)]
+    srv = Server(ctx, relin, rot, pts, boots, slots=args.serve_slots, mem_budget=args.serve_mem_gib << 30)
     n = args.serve_requests
-    gen = lambda rate, sd: inputs.serving_requests(sd, n, ps.logn, rate)
-    srv.run(gen(None, seed + 900)[: max(2, n // 8)])  # warm-up
+    gen = lambda rate, sd, m=n: inputs.serving_requests(sd, m, ps.logn, rate)
+    srv.run(gen(None, seed + 900, max(8, n // 16)))  # warm-up
 
     def summarise(done, reqs):
-        lat = [d.latency * 1e3 for d in done]
-        span = max(d.finish for d in done) - min(r.arrival for r in reqs)
-        ks = sum(d.keyswitches for d in done)
-        return {"requests_per_s": round(len(done) / span, 2), "key_switches_per_s": round(ks / span, 1),
+        ok = [d for d in done if not d.refused]
+        lat = [d.latency * 1e3 for d in ok]
+        span = max(d.finish for d in ok) - min(r.arrival for r in reqs)
+        ks = sum(d.keyswitches for d in ok)
+        return {"requests_per_s": round(len(ok) / span, 2), "key_switches_per_s": round(ks / span, 1),
                 "p50_ms": round(percentile(lat, 50), 3), "p99_ms": round(percentile(lat, 99), 3),
-                "makespan_s": round(span, 4)}
+                "makespan_s": round(span, 4), "completed": len(ok), "refused": len(done) - len(ok)}
 
     reqs = gen(None, seed + 901)
     sat = summarise(srv.run(reqs), reqs)
+    print("bench: serving saturation %.1f requests/s" % sat["requests_per_s"], file=sys.stderr, flush=True)
     plain = summarise(srv.run(reqs, concurrent=False), reqs)
     sweep = []
-    for f in (0.5, 0.9, 1.1):
+    for f in [float(x) for x in args.serve_loads.split(",") if x]:
         rate = f * sat["requests_per_s"]
         rq = gen(rate, seed + 902 + int(f * 100))
         r = summarise(srv.run(rq), rq)
         r.update({"load": f, "offered_rps": round(rate, 2)})
         sweep.append(r)
-    boot.close()
+        print("bench: serving load %.2f done" % f, file=sys.stderr, flush=True)
+    for b in boots:
+        b.close()
     return {"requests": n, "slots": args.serve_slots, "mem_budget_gib": args.serve_mem_gib,
-            "boot_fraction": 0.1, "saturation": sat, "plain_sequential": plain, "poisson": sweep,
-            "served_vs_plain": round(sat["requests_per_s"] / plain["requests_per_s"], 3)}
+            "boot_handles": len(boots), "boot_fraction": 0.1, "saturation": sat, "plain_sequential": plain,
+            "poisson": sweep, "served_vs_plain": round(sat["requests_per_s"] / plain["requests_per_s"], 3)}
 
 
 def main():
@@ -349,6 +587,20 @@ def main():
         rlk = ctx.key(ckks.to_device(inputs.random_key(s + 2, ps)), 0)
         rk = ctx.key(ckks.to_device(inputs.random_key(s + 3, ps)), g_rot)
         return ta, tb, rlk, rk
+
+    # ---- autotuner: NTT tile width per direction and launch size (cached by logN, limbs, K, op, arch)
+    from paper_2507_04775_amd import tune
+    tcache = tune.load_cache()
+    t0 = time.perf_counter()
+    tiles = tune.tune_ntt_tiles(ctx, cache=tcache)
+    big = tune.tune_op_launches(ctx, level, cache=tcache)
+    t_tune = time.perf_counter() - t0
+    tune.save_cache(tcache)
+    step_launches = {"ntt_inv": [31, 8, 2, 35], "ntt_fwd": [35, 31, 8, 2]}
+    autotune = {"ntt_tiles_s": round(t_tune, 2), "cache": tune.cache_path(),
+                "ntt_tiles": {op: {str(n): tiles[op][n] for n in ns if n in tiles.get(op, {})}
+                              for op, ns in step_launches.items()},
+                "ntt_tiles_in_ops": {str(k): v for k, v in big.get("ntt_fwd", {}).items()}}
 
     sets = [make_set(seed + 10 * i) for i in range(max(1, args.cold_sets))]
     m = ctx.empty_ct(level)
@@ -412,15 +664,9 @@ def main():
         cold = {"ms_per_step": round(cold_ms, 4), "key_switches_per_s": round(ks_per_step / (cold_ms / 1e3), 1),
                 "pool_bytes": pool_bytes, "sets": len(sets)}
 
-    # ---- per-operation latencies
+    # ---- per-operation latencies: GPU time of back-to-back calls, the stream held until all are enqueued
     def op_stats(fn, reps):
-        es = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
-        es[0].record(stream)
-        for i in range(reps):
-            fn(sets[0])
-            es[i + 1].record(stream)
-        torch.cuda.synchronize()
-        xs = [es[i].elapsed_time(es[i + 1]) for i in range(reps)]
+        xs = timed_launches(lambda: fn(sets[0]), reps, stream)
         return {"p50_us": round(percentile(xs, 50) * 1e3, 2), "p99_us": round(percentile(xs, 99) * 1e3, 2),
                 "mean_us": round(sum(xs) / len(xs) * 1e3, 2)}
 
@@ -511,21 +757,51 @@ def main():
         torch.cuda.synchronize()
         del src, dst, flush
 
-    # ---- dominant kernel: the forward NTT over all 35 limbs (two passes, 16 x 35 workgroups each),
-    # timed on the library's stream with inputs in HBM (rotating buffers, above) as the mean over a
-    # burst of launches; algorithmic bytes = read + write of every limb once.
+    # ---- the NTT over all 35 limbs (two passes, 16 x 35 workgroups each), timed on the library's stream
+    # with inputs in HBM (rotating buffers, above) as the mean over a burst of launches; algorithmic
+    # bytes = read + write of every limb once.
     ntt_ms = ntt_burst_us / 1e3
     ntt_bytes = (ps.L + 1 + ps.K) * ps.N * 8 * 2
-    achieved = ntt_bytes / (ntt_ms / 1e3) / 1e9
-    roofline = {"bound": "hbm", "kernel": "ntt16_fwd (column + row pass) over 35 limbs",
-                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
+    ntt_gbs = ntt_bytes / (ntt_ms / 1e3) / 1e9
+    ntt_roof = {"bound": "hbm", "kernel": "ntt16_fwd (column + row pass) over 35 limbs",
+                "achieved": round(ntt_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ntt_gbs / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
                 "algorithmic_bytes_per_launch": ntt_bytes, "launch_us": round(ntt_ms * 1e3, 2)}
+
+    # ---- the dominant kernel of the step: the key inner product (one launch per key switch, the largest
+    # single-kernel share of the step with ModDown's conversion pass), at l = 30 on inputs in HBM: two
+    # operand sets (ext, key, acc: 385 limbs, 202 MB each) in turn, so no launch finds its operands in the
+    # 256 MB last-level cache; mean over a burst of launches between two events on the library's stream.
+    roofline = inner_product_roofline(ctx, ps, seed, stream)
+
+    # ---- the step and one key switch against HBM in algorithmic bytes: per coefficient-limb, HMult+relin
+    # reads a, b (4n) and the key (2 beta (n+K)) and writes 2n; Rescale reads 2n and writes 2(n-1);
+    # HRotate reads 2n + key and writes 2n; a key switch reads d (n) and the key and writes 2n
+    n_l, beta = level + 1, ctx.beta(level)
+    key_limbs = 2 * beta * (n_l + ps.K)
+    step_limbs = (6 * n_l + key_limbs) + (4 * n_l - 2) + (4 * n_l + key_limbs)
+    step_bytes = step_limbs * LIMB
+    ks_bytes = (3 * n_l + key_limbs) * LIMB
+    ks_o0, ks_o1 = ctx.empty_poly(level), ctx.empty_poly(level)
+    ws_ks = ctx.workspace(ckks.OP_KEYSWITCH, level)
+    ks_ms = timed_launches(lambda: ctx.ckks_keyswitch(sets[0][1].c1, level, sets[0][2], ks_o0, ks_o1, ws_ks, stream),
+                           reps, stream)
+    ks50 = percentile(ks_ms, 50)
+    hbm = {"step": {"algorithmic_bytes": step_bytes, "ms": round(ms_per_step, 4),
+                    "achieved_GBs": round(step_bytes / (ms_per_step / 1e3) / 1e9, 1),
+                    "frac": round(step_bytes / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4)},
+           "keyswitch": {"algorithmic_bytes": ks_bytes, "p50_ms": round(ks50, 4),
+                         "p99_ms": round(percentile(ks_ms, 99), 4),
+                         "achieved_GBs": round(ks_bytes / (ks50 / 1e3) / 1e9, 1),
+                         "frac": round(ks_bytes / (ks50 / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}}
+    probe = None if args.no_probe else run_probe(stream)
+    valu = valu_fractions(probe)
 
     # ---- batched: 128 ciphertexts at levels 4..30, half HMult+relin, half hoisted 8-way rotations
     batched = None
     if not args.no_batch:
-        batched = run_batch(ctx, ps, seed, args)
+        batched = run_batch(ctx, ps, seed, args, tcache)
+        tune.save_cache(tcache)
 
     # ---- full-slot bootstrapping (its own context: ten special primes)
     boot = boot_dense = None
@@ -539,28 +815,10 @@ def main():
     if not args.no_serve:
         serving = run_serving(ctx, ps, seed + 700, args)
 
-    # ---- CPU oracle on a bounded sample of the same step
+    # ---- CPU oracle on a bounded sample of the same step: medians over runs on one thread and on all cores
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle
-        P = oracle.Params(ps.logn, ps.q, ps.p, ps.dnum)
-        a = inputs.random_ct(seed, ps, level)
-        b = inputs.random_ct(seed + 1, ps, level)
-        rlk = inputs.random_key(seed + 2, ps)
-        rk = inputs.random_key(seed + 3, ps)
-        oracle.lib()
-        n_steps, t_cpu = 0, 0.0
-        while t_cpu < args.cpu_seconds and n_steps < 50:
-            t1 = time.perf_counter()
-            mm = oracle.hmult_relin(P, a, b, rlk, level)
-            oracle.rescale(P, mm, level)
-            oracle.apply_galois(P, a, g_rot, rk, level)
-            t_cpu += time.perf_counter() - t1
-            n_steps += 1
-        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-        cpu = {"value": round(ks_per_step * n_steps / t_cpu, 3), "unit": "key-switches/s", "cores": threads,
-               "kind": "oracle",
-               "sample": "%d steps (HMult+relin, Rescale, HRotate at l=30, N=2^16) in %.1f s" % (n_steps, t_cpu)}
+        cpu = cpu_baseline(ps, seed, level, g_rot, ks_per_step, max(3, args.cpu_runs))
 
     out = {
         "metric": "key-switches/s and bootstraps/s at logN=16 (1 GPU), batched vs plain; p99 latency",
@@ -589,7 +847,12 @@ def main():
         "ops": ops,
         "ptmult_rescale_us_by_level": ptmult_rescale,
         "hmult_relin_us_by_level": hmult_by_level,
+        "autotune": autotune,
         "roofline": roofline,
+        "roofline_ntt_35_limbs": ntt_roof,
+        "hbm_fraction": hbm,
+        "valu": valu,
+        "mad64_probe": probe,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -114,6 +114,21 @@ ckks_status ckks_ntt(ckks_ctx *ctx, uint64_t *poly, uint32_t limb0, uint32_t n_l
 ckks_status ckks_intt(ckks_ctx *ctx, uint64_t *poly, uint32_t limb0, uint32_t n_limbs, void *stream);
 
 /*
+ * Launch shape of the NTT passes at N = 2^16 (Sec. III-F.4 runs the transform
+ * as a column pass and a row pass over the 256 x 256 view): a workgroup takes
+ * `tile` columns (rows) with 32 threads on each, tile 16 (512 threads), 8 (256)
+ * or 4 (128).  Narrow tiles give a launch over few limbs more workgroups to
+ * spread over the CUs.  The choice holds per direction (inverse 0 / 1) and per
+ * number of limbs in the launch (1..128), for every NTT launch of every
+ * operation in the process; tile 0 restores the default (16 from 24 limbs up,
+ * 8 from 6, else 4).  Results do not depend on it.  An autotuner sets it from
+ * measurements.  ckks_ntt_tile_get returns the width in effect (0 for bad
+ * arguments).  Persistent batch kernels always use 16.
+ */
+ckks_status ckks_ntt_tile_set(uint32_t inverse, uint32_t n_limbs, uint32_t tile);
+uint32_t ckks_ntt_tile_get(uint32_t inverse, uint32_t n_limbs);
+
+/*
  * ModUp of hybrid key switching (Sec. II-A, III-F.3, Eq. (1)):
  * d [l+1][N] (evaluation domain) -> ext [beta][l+1+K][N] (evaluation domain),
  * beta = ceil((l+1)/alpha).  Row r of ext[j] is d's row r for r in digit j;
@@ -281,8 +296,10 @@ ckks_status ckks_automorph(ckks_ctx *ctx, const uint64_t *in, uint32_t galois, u
  * one persistent work-queue launch per step on `stream`; ckks_batch_capture
  * records that launch sequence into a HIP graph that ckks_batch_replay
  * relaunches (a non-default stream is required to capture).  ckks_batch_tune
- * runs the batch with several persistent grid sizes and keeps, per step, the
- * fastest (it runs the batch, overwriting the outputs with the same values).
+ * runs the batch with each persistent grid size of {1, 2, 3, 4, 6, 8}
+ * workgroups per CU, once to warm up and five times measured, and keeps per
+ * step the size with the smallest median time (it runs the batch, overwriting
+ * the outputs with the same values).
  * Items must not share outputs, and no output may overlap another item's
  * input or workspace; inputs and keys must stay valid while the batch is used.
  */
@@ -315,6 +332,10 @@ ckks_status ckks_batch_capture(ckks_batch *batch, void *stream);
 ckks_status ckks_batch_replay(ckks_batch *batch, void *stream);
 uint32_t ckks_batch_keyswitches(const ckks_batch *batch); /* key switches performed per run */
 uint32_t ckks_batch_grid(const ckks_batch *batch, uint32_t step); /* persistent grid, in workgroups per CU */
+/* Sets one step's persistent grid (1..16 workgroups per CU), e.g. from a tuning
+ * cache; steps are numbered 0..ckks_batch_steps()-1. */
+ckks_status ckks_batch_set_grid(ckks_batch *batch, uint32_t step, uint32_t wg_per_cu);
+uint32_t ckks_batch_steps(void);
 void ckks_batch_destroy(ckks_batch *batch);
 
 /*
@@ -322,6 +343,10 @@ void ckks_batch_destroy(ckks_batch *batch);
  * for a fully packed ciphertext (N/2 slots).
  *
  * Schedule, derived by the library from the descriptor:
+ * - Input gain: with input_gain G > 1 the level-0 input is first multiplied by
+ *   the integer G (exact, no rescale), so that the message uses more of q_0
+ *   while its share of the EvalMod argument stays small; the caller's
+ *   SlotToCoeff constants carry 1/G.
  * - ModRaise: the level-0 input's coefficients are lifted centred from q_0 to
  *   q_0..q_L (L = n_q - 1) and returned to the evaluation domain.  With
  *   sparse-secret encapsulation (to_sparse and from_sparse set), the input is
@@ -396,6 +421,9 @@ typedef struct {
     uint32_t hoist_moddown;              /* 1: giant steps key-switched without ModDown, summed over Q u P,
                                             one ModDown per group (fewer roundings, less time); 0: the plain
                                             schedule, one ModDown per rotation as in the paper */
+    uint64_t input_gain;                 /* 0 or 1: none; else the level-0 input is multiplied by this integer
+                                            (below q_0) before ModRaise, so the message fills more of q_0; the
+                                            caller folds 1/input_gain into the SlotToCoeff constants */
 } ckks_boot_desc;
 
 ckks_status ckks_boot_create(ckks_ctx *ctx, const ckks_boot_desc *desc, ckks_boot **out);
@@ -406,6 +434,19 @@ ckks_status ckks_bootstrap(ckks_boot *boot, const ckks_ct *in, ckks_ct *out, voi
 ckks_status ckks_boot_capture(ckks_boot *boot, const ckks_ct *in, ckks_ct *out, void *stream);
 ckks_status ckks_boot_replay(ckks_boot *boot, void *stream);
 void ckks_boot_destroy(ckks_boot *boot);
+
+/*
+ * Measurement probe (no CKKS operation): one launch of `blocks` workgroups of
+ * 256 threads, each thread running 8 independent chains of `iters` dependent
+ * 32x32->64 multiply-adds (v_mad_u64_u32), the instruction every 64-bit
+ * modular product of the kernels is built from.  *mads_per_launch receives the
+ * number of multiply-adds per lane of the launch (blocks * 256 * iters * 8);
+ * timing the launch gives the chip's integer multiply-add rate, the ceiling
+ * the integer-VALU fractions of the key-switching kernels are reported against.
+ * out: device buffer of blocks * 256 words (each thread writes one sum).
+ */
+ckks_status ckks_probe_mad64(uint64_t *out, uint32_t blocks, uint32_t iters, void *stream,
+                             uint64_t *mads_per_launch);
 
 #ifdef __cplusplus
 }

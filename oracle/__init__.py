@@ -69,6 +69,8 @@ def lib():
         L.orc_hoisted_rotate.argtypes = [u32, u64p, u32, u64p, u32, u32, u32, u64p, u64p, u32, u64p,
                                          ctypes.POINTER(u64p), u64p, u64p]
         L.orc_reduce_f64.argtypes = [u64p, u32, u32, ctypes.POINTER(ctypes.c_double), u64p]
+        L.orc_set_threads.argtypes = [i32]
+        L.orc_max_threads.restype = i32
         _lib = L
     return _lib
 
@@ -249,6 +251,15 @@ def reduce_f64(mods, x: np.ndarray) -> np.ndarray:
     out = np.zeros((len(mods), len(x)), dtype=np.uint64)
     lib().orc_reduce_f64(_p(mods), len(mods), len(x), x.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _p(out))
     return out
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's OpenMP loops (results do not depend on it)."""
+    lib().orc_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return int(lib().orc_max_threads())
 
 
 def galois_for_rotation(logn: int, k: int) -> int:

@@ -83,6 +83,7 @@ class BootParams:
     in_scale: float               # scale of the level-0 input
     cheb_baby: int = 0            # baby-step size of the Chebyshev evaluation (0: smallest b with b^2 > d)
     hoist_moddown: bool = False   # giant steps key-switched without ModDown, summed over Q u P, one ModDown per group
+    input_gain: int = 1           # the level-0 input is multiplied by this integer before ModRaise
 
     @property
     def baby(self) -> int:
@@ -337,7 +338,7 @@ def plan(P: Params, bp: BootParams) -> BootPlan:
         lv -= k
     lv -= levels_used(bp)["evalmod"]
     for i, halves in enumerate(stage_groups(bp.logn, bp.stc_radix_logs, True)):
-        factor = q[0] / (2.0 * np.pi * bp.in_scale) if i == 0 else 1.0
+        factor = q[0] / (2.0 * np.pi * bp.in_scale * bp.input_gain) if i == 0 else 1.0
         pl.stc.append(plan_group(bp, halves, False, factor, pt_scale(sc, q, lv, 1)))
         lv -= 1
     pl.cheb = chebyshev_coeffs(bp)
@@ -586,6 +587,8 @@ class Executor:
 
     def bootstrap(self, ct):
         N = 1 << self.bp.logn
+        if self.bp.input_gain != 1:  # m -> G m: the message uses more of q_0, the sine's input stays small
+            ct = self.scalar_mul_int(ct, self.bp.input_gain)
         if self.to_sparse is not None:
             ct = self.switch(ct, self.to_sparse)
         ct = self.modraise(ct)

@@ -15,6 +15,7 @@
  * ciphertext basis q_0..q_L, the special basis p_0..p_{K-1}, dnum digits of
  * alpha = ceil((L+1)/dnum) limbs, level l meaning limbs q_0..q_l.
  */
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -559,3 +560,8 @@ void orc_reduce_f64(const uint64_t *mods, uint32_t nmods, uint32_t count, const 
         }
     }
 }
+
+/* Thread count of the OpenMP loops (timing of the oracle on 1 or all cores);
+ * results do not depend on it. */
+void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int orc_max_threads(void) { return omp_get_max_threads(); }

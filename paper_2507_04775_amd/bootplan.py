@@ -23,7 +23,9 @@ Scales follow the library's discipline: Delta_L = top_scale, Delta_(l-1) =
 before k rescales carries (Delta_(l-k) q_(l-k+1) .. q_l) / Delta_l.  The first
 CoeffToSlot group is taken at k = 2 and carries Delta_L / (2 q_0 K) so that
 EvalMod sees t / (q_0 K) for the raised coefficients t; the first SlotToCoeff
-group carries q_0 / (2 pi Delta_in).
+group carries q_0 / (2 pi Delta_in G), G the integer gain the level-0 input is
+multiplied by before ModRaise (the message then fills more of q_0 while the
+sine's argument stays small).
 """
 from __future__ import annotations
 
@@ -44,6 +46,7 @@ class BootConfig:
     in_scale: float
     cheb_baby: int = 0   # baby-step size of the Chebyshev evaluation (0: smallest power of two b with b^2 > d)
     hoist_moddown: bool = True  # giant steps summed over Q u P with one ModDown per group
+    input_gain: int = 1  # integer the level-0 input is multiplied by before ModRaise
 
     @property
     def n(self) -> int:
@@ -65,14 +68,21 @@ def default_config(logn: int, scale: float, sparse: bool = True) -> BootConfig:
     encapsulation (h = 32, so |t_k / q_0| stays below K = 12) a degree-31
     interpolant with 3 double angles; for the uniform ternary secret itself a
     degree-119 interpolant over K = 512 with 6 double angles at N = 2^16, or
-    degree 63 over K = 128 with 5 at smaller N."""
+    degree 63 over K = 128 with 5 at smaller N.  The input gain multiplies the
+    message before ModRaise: at scale 2^50 a full-slot message of slots in
+    [-1, 1]^2 fills about 2^-16 of q_0, the gain brings it to 2^-9 (sparse) or
+    2^-6 (uniform), where the sine's own error stays below the noise that
+    EvalMod amplifies; measured at N = 2^16 (oracle, CPU) the error went from
+    2^-9.1 to 2^-15.8 (sparse) and from 2^-0.8 to 2^-10.3 (uniform).  Smaller
+    N has larger coefficients for the same slots (they scale as N^-1/2), so
+    N = 2^12 takes 16."""
     s = logn - 1
     parts = [s // 3 + (1 if i < s % 3 else 0) for i in range(3)]
     if sparse:
-        return BootConfig(logn, parts, parts[::-1], 31, 3, 12.0, scale, scale)
+        return BootConfig(logn, parts, parts[::-1], 31, 3, 12.0, scale, scale, input_gain=128 if logn >= 16 else 16)
     if logn >= 16:
-        return BootConfig(logn, parts, parts[::-1], 119, 6, 512.0, scale, scale)
-    return BootConfig(logn, parts, parts[::-1], 63, 5, 128.0, scale, scale)
+        return BootConfig(logn, parts, parts[::-1], 119, 6, 512.0, scale, scale, input_gain=1024)
+    return BootConfig(logn, parts, parts[::-1], 63, 5, 128.0, scale, scale, input_gain=16)
 
 
 SPARSE_H = 32  # nonzero coefficients of the encapsulation secret
@@ -253,7 +263,7 @@ def plan(q, cfg: BootConfig) -> BootPlan:
         lv -= k
     lv -= cheb_depth(cfg.cheb_degree, cfg.baby) + cfg.double_angles
     for i, halves in enumerate(_halves(cfg.logn, cfg.stc_radix_logs, True)):
-        f = q[0] / (2.0 * np.pi * cfg.in_scale) if i == 0 else 1.0
+        f = q[0] / (2.0 * np.pi * cfg.in_scale * cfg.input_gain) if i == 0 else 1.0
         p.stc.append(encode_group(cfg, halves, False, f, _pt_scale(d, q, lv, 1)))
         lv -= 1
     if lv < 0:

@@ -47,7 +47,7 @@ class _BootDesc(ctypes.Structure):
                 ("cheb_baby", _u32), ("double_angles", _u32), ("top_scale", ctypes.c_double), ("relin", _vp), ("conj", _vp),
                 ("to_sparse", _vp), ("from_sparse", _vp),
                 ("n_rot", _u32), ("rot_steps", ctypes.POINTER(_i32)), ("rot_keys", ctypes.POINTER(_vp)),
-                ("hoist_moddown", _u32)]
+                ("hoist_moddown", _u32), ("input_gain", ctypes.c_uint64)]
 
 
 _sigs = {
@@ -58,6 +58,8 @@ _sigs = {
     "ckks_workspace_bytes": (ctypes.c_size_t, [_vp, _u32, _u32]),
     "ckks_get_twiddles": (ctypes.c_int, [_vp, _u32, _u64p]),
     "ckks_ntt": (ctypes.c_int, [_vp, _vp, _u32, _u32, _vp]),
+    "ckks_ntt_tile_set": (ctypes.c_int, [_u32, _u32, _u32]),
+    "ckks_ntt_tile_get": (_u32, [_u32, _u32]),
     "ckks_intt": (ctypes.c_int, [_vp, _vp, _u32, _u32, _vp]),
     "ckks_modup": (ctypes.c_int, [_vp, _vp, _u32, _vp, _vp, _vp]),
     "ckks_inner_product": (ctypes.c_int, [_vp, _vp, _u32, _vp, _u32, _vp, _vp]),
@@ -65,6 +67,7 @@ _sigs = {
     "ckks_key_wrap": (ctypes.c_int, [_vp, _vp, _u32, ctypes.POINTER(_vp)]),
     "ckks_key_release": (None, [_vp]),
     "ckks_keyswitch": (ctypes.c_int, [_vp, _vp, _u32, _vp, _vp, _vp, _vp, _vp]),
+    "ckks_probe_mad64": (ctypes.c_int, [_vp, _u32, _u32, _vp, ctypes.POINTER(ctypes.c_uint64)]),
     "ckks_hmult_relin": (ctypes.c_int, [_vp, ctypes.POINTER(_Ct), ctypes.POINTER(_Ct), _vp, ctypes.POINTER(_Ct), _vp, _vp]),
     "ckks_rescale": (ctypes.c_int, [_vp, ctypes.POINTER(_Ct), ctypes.POINTER(_Ct), _vp, _vp]),
     "ckks_apply_galois": (ctypes.c_int, [_vp, ctypes.POINTER(_Ct), _u32, _vp, ctypes.POINTER(_Ct), _vp, _vp]),
@@ -93,6 +96,8 @@ _sigs = {
     "ckks_batch_replay": (ctypes.c_int, [_vp, _vp]),
     "ckks_batch_keyswitches": (_u32, [_vp]),
     "ckks_batch_grid": (_u32, [_vp, _u32]),
+    "ckks_batch_set_grid": (ctypes.c_int, [_vp, _u32, _u32]),
+    "ckks_batch_steps": (_u32, []),
     "ckks_batch_destroy": (None, [_vp]),
     "ckks_boot_create": (ctypes.c_int, [_vp, ctypes.POINTER(_BootDesc), ctypes.POINTER(_vp)]),
     "ckks_boot_output_level": (_u32, [_vp]),
@@ -443,6 +448,13 @@ class Batch:
     def grid(self, step: int) -> int:
         return int(_lib.ckks_batch_grid(self.handle, step))
 
+    def set_grid(self, step: int, wg_per_cu: int):
+        _check(_lib.ckks_batch_set_grid(self.handle, step, wg_per_cu), "ckks_batch_set_grid")
+
+    @staticmethod
+    def steps() -> int:
+        return int(_lib.ckks_batch_steps())
+
     def run(self, stream=None):
         _check(_lib.ckks_batch_run(self.handle, _stream(stream)), "ckks_batch_run")
 
@@ -473,7 +485,7 @@ class Boot:
 
     def __init__(self, ctx: "Context", cts_radix_logs, stc_radix_logs, cts_diags, stc_diags, cheb,
                  double_angles: int, top_scale: float, relin: Key, conj: Key, rot_keys: dict, cheb_baby: int = 0,
-                 sparse: Optional[tuple] = None, hoist_moddown: bool = False):
+                 sparse: Optional[tuple] = None, hoist_moddown: bool = False, input_gain: int = 1):
         import numpy as np
         self.ctx = ctx
         self._keys = [relin, conj] + list(rot_keys.values())
@@ -501,6 +513,7 @@ class Boot:
             self._keys += list(sparse)
         d.n_rot, d.rot_steps, d.rot_keys = len(steps), rs, rk
         d.hoist_moddown = 1 if hoist_moddown else 0
+        d.input_gain = int(input_gain)
         h = _vp()
         _check(_lib.ckks_boot_create(ctx.handle, ctypes.byref(d), ctypes.byref(h)), "ckks_boot_create")
         self.handle = h
@@ -550,3 +563,20 @@ def to_device(a, device="cuda") -> torch.Tensor:
 
 def to_host(t: torch.Tensor):
     return t.cpu().numpy()
+
+
+def probe_mad64(out: torch.Tensor, blocks: int, iters: int, stream=None) -> int:
+    """Launches the multiply-add rate probe (ckks_probe_mad64); returns the
+    multiply-adds per lane the launch performs."""
+    n = ctypes.c_uint64(0)
+    _check(_lib.ckks_probe_mad64(_ptr(out), blocks, iters, _stream(stream), ctypes.byref(n)), "ckks_probe_mad64")
+    return int(n.value)
+
+
+def ntt_tile_set(inverse: bool, n_limbs: int, tile: int) -> None:
+    """Tile width of the N = 2^16 NTT grid launches over n_limbs limbs (0: default)."""
+    _check(_lib.ckks_ntt_tile_set(1 if inverse else 0, n_limbs, tile), "ckks_ntt_tile_set")
+
+
+def ntt_tile_get(inverse: bool, n_limbs: int) -> int:
+    return int(_lib.ckks_ntt_tile_get(1 if inverse else 0, n_limbs))

@@ -89,6 +89,10 @@ hipError_t moddown(const ckks_ctx *c, const uint64_t *acc, int64_t acc_stride, u
                             args_moddown_ntt(c, acc, acc_stride, npoly, level, out, add, g, pc, conv), npoly * s.n, st);
 }
 
+}  // namespace
+
+namespace ckks {
+
 // Full key switch of d (gathered through g_in) with `key`; outputs
 // out_t = KS_t + add_t (add gathered through g_add).  The digits' own rows are
 // never copied: the inner product reads them from d directly.
@@ -106,6 +110,10 @@ hipError_t keyswitch_core(const ckks_ctx *c, const uint64_t *d, uint32_t g_in, u
     const uint64_t *adds[2] = {add0, add1};
     return moddown(c, w.acc, (int64_t)s.rows * s.N, 2, level, outs, adds, g_add, w.pc, w.conv, st);
 }
+
+}  // namespace ckks
+
+namespace {
 
 ckks_status check_ctx(const ckks_ctx *c)
 {
@@ -230,6 +238,18 @@ static ckks_status ntt_common(ckks_ctx *ctx, uint64_t *poly, uint32_t limb0, uin
     return dev(e, inverse ? "ckks_intt" : "ckks_ntt");
 }
 
+extern "C" ckks_status ckks_ntt_tile_set(uint32_t inverse, uint32_t n_limbs, uint32_t tile)
+{
+    if (!ntt_tile_set(inverse, n_limbs, tile))
+        return fail(CKKS_E_ARG, "ckks_ntt_tile_set: inverse must be 0 or 1, n_limbs in [1, 128], tile 0, 4, 8 or 16");
+    return CKKS_OK;
+}
+
+extern "C" uint32_t ckks_ntt_tile_get(uint32_t inverse, uint32_t n_limbs)
+{
+    return inverse <= 1 && n_limbs ? ntt_tile_get(inverse, n_limbs) : 0;
+}
+
 extern "C" ckks_status ckks_ntt(ckks_ctx *ctx, uint64_t *poly, uint32_t limb0, uint32_t n_limbs, void *stream)
 {
     return ntt_common(ctx, poly, limb0, n_limbs, stream, false);
@@ -306,19 +326,33 @@ extern "C" ckks_status ckks_key_wrap(ckks_ctx *ctx, const uint64_t *dev_key, uin
 
 extern "C" void ckks_key_release(ckks_key *key) { delete key; }
 
-extern "C" ckks_status ckks_keyswitch(ckks_ctx *ctx, const uint64_t *d, uint32_t level, const ckks_key *key,
-                                      uint64_t *out0, uint64_t *out1, void *ws, void *stream)
+namespace ckks {
+
+// Validation shared by ckks_keyswitch and ckks_keyswitch_noalloc (everything but the workspace).
+ckks_status check_keyswitch_args(ckks_ctx *ctx, const uint64_t *d, uint32_t level, const ckks_key *key,
+                                 const uint64_t *out0, const uint64_t *out1, const char *what)
 {
     TRY(check_ctx(ctx));
     TRY(check_level(ctx, level));
     TRY(check_key(ctx, key));
-    TRY(check_ptr(d, "ckks_keyswitch d"));
-    TRY(check_ptr(out0, "ckks_keyswitch out0"));
-    TRY(check_ptr(out1, "ckks_keyswitch out1"));
+    TRY(check_ptr(d, (std::string(what) + " d").c_str()));
+    TRY(check_ptr(out0, (std::string(what) + " out0").c_str()));
+    TRY(check_ptr(out1, (std::string(what) + " out1").c_str()));
+    const size_t pb = poly_bytes(ctx, level);
+    if (overlap(out0, pb, d, pb) || overlap(out1, pb, d, pb) || overlap(out0, pb, out1, pb))
+        return fail(CKKS_E_ARG, std::string(what) + ": d, out0 and out1 must not overlap");
+    return CKKS_OK;
+}
+
+}  // namespace ckks
+
+extern "C" ckks_status ckks_keyswitch(ckks_ctx *ctx, const uint64_t *d, uint32_t level, const ckks_key *key,
+                                      uint64_t *out0, uint64_t *out1, void *ws, void *stream)
+{
+    TRY(check_keyswitch_args(ctx, d, level, key, out0, out1, "ckks_keyswitch"));
     TRY(check_ptr(ws, "ckks_keyswitch ws"));
     size_t pb = poly_bytes(ctx, level), wb = ckks_workspace_bytes(ctx, CKKS_OP_KEYSWITCH, level);
-    if (overlap(out0, pb, d, pb) || overlap(out1, pb, d, pb) || overlap(out0, pb, out1, pb) ||
-        overlap(ws, wb, d, pb) || overlap(ws, wb, out0, pb) || overlap(ws, wb, out1, pb))
+    if (overlap(ws, wb, d, pb) || overlap(ws, wb, out0, pb) || overlap(ws, wb, out1, pb))
         return fail(CKKS_E_ARG, "ckks_keyswitch: d, out0, out1 and ws must not overlap");
     return dev(keyswitch_core(ctx, d, 1, level, key->data, out0, out1, nullptr, nullptr, 1, ws, S(stream)),
                "ckks_keyswitch");

@@ -414,19 +414,24 @@ extern "C" ckks_status ckks_batch_run(ckks_batch *b, void *stream)
     return CKKS_OK;
 }
 
+// Persistent grid per step, in workgroups per CU: every candidate runs the
+// whole batch once to warm caches and code, then kTuneReps more times; each
+// step keeps the candidate with the smallest median time.
 extern "C" ckks_status ckks_batch_tune(ckks_batch *b, void *stream)
 {
     if (!b) return fail(CKKS_E_ARG, "ckks_batch_tune: null batch");
     static const uint32_t cand[] = {1, 2, 3, 4, 6, 8};
-    const int nc = sizeof(cand) / sizeof(cand[0]);
-    std::vector<float> best(QI_COUNT, 1e30f);
-    std::vector<uint32_t> pick(QI_COUNT, 2);
+    constexpr int nc = sizeof(cand) / sizeof(cand[0]), kTuneReps = 5;
+    std::vector<float> ms((size_t)nc * QI_COUNT * kTuneReps, 0.f);
     hipEvent_t ev[QI_COUNT + 1];
     for (int i = 0; i <= QI_COUNT; ++i)
-        if (hipEventCreate(&ev[i]) != hipSuccess) return fail(CKKS_E_DEVICE, "ckks_batch_tune: events");
+        if (hipEventCreate(&ev[i]) != hipSuccess) {
+            for (int j = 0; j < i; ++j) (void)hipEventDestroy(ev[j]);
+            return fail(CKKS_E_DEVICE, "ckks_batch_tune: events");
+        }
     hipStream_t st = S(stream);
     hipError_t e = hipSuccess;
-    for (int rep = 0; rep < 2 && e == hipSuccess; ++rep)
+    for (int rep = -1; rep < kTuneReps && e == hipSuccess; ++rep)
         for (int ci = 0; ci < nc && e == hipSuccess; ++ci) {
             e = launch_zero_u32(b->counters, QI_COUNT, st);
             for (int qi = 0; qi < QI_COUNT && e == hipSuccess; ++qi) {
@@ -435,20 +440,36 @@ extern "C" ckks_status ckks_batch_tune(ckks_batch *b, void *stream)
             }
             (void)hipEventRecord(ev[QI_COUNT], st);
             if (e == hipSuccess) e = hipEventSynchronize(ev[QI_COUNT]);
-            for (int qi = 0; qi < QI_COUNT && e == hipSuccess; ++qi) {
-                float ms = 0;
-                (void)hipEventElapsedTime(&ms, ev[qi], ev[qi + 1]);
-                if (rep == 1 && ms < best[qi]) {  // the first repetition warms caches and code
-                    best[qi] = ms;
-                    pick[qi] = cand[ci];
-                }
-            }
+            for (int qi = 0; qi < QI_COUNT && e == hipSuccess && rep >= 0; ++qi)
+                (void)hipEventElapsedTime(&ms[((size_t)ci * QI_COUNT + qi) * kTuneReps + rep], ev[qi], ev[qi + 1]);
         }
     for (int i = 0; i <= QI_COUNT; ++i) (void)hipEventDestroy(ev[i]);
     if (e != hipSuccess) return fail(CKKS_E_DEVICE, std::string("ckks_batch_tune: ") + hipGetErrorString(e));
-    for (int qi = 0; qi < QI_COUNT; ++qi) b->q[qi].grid_mult = pick[qi];
+    for (int qi = 0; qi < QI_COUNT; ++qi) {
+        float best = 1e30f;
+        uint32_t pick = 2;
+        for (int ci = 0; ci < nc; ++ci) {
+            float *x = &ms[((size_t)ci * QI_COUNT + qi) * kTuneReps];
+            std::sort(x, x + kTuneReps);
+            if (x[kTuneReps / 2] < best) {
+                best = x[kTuneReps / 2];
+                pick = cand[ci];
+            }
+        }
+        b->q[qi].grid_mult = pick;
+    }
     return CKKS_OK;
 }
+
+extern "C" ckks_status ckks_batch_set_grid(ckks_batch *b, uint32_t step, uint32_t wg_per_cu)
+{
+    if (!b || step >= QI_COUNT || wg_per_cu == 0 || wg_per_cu > 16)
+        return fail(CKKS_E_ARG, "ckks_batch_set_grid: null batch, step out of range or grid not in [1, 16]");
+    b->q[step].grid_mult = wg_per_cu;
+    return CKKS_OK;
+}
+
+extern "C" uint32_t ckks_batch_steps(void) { return QI_COUNT; }
 
 extern "C" ckks_status ckks_batch_capture(ckks_batch *b, void *stream)
 {
@@ -465,12 +486,20 @@ extern "C" ckks_status ckks_batch_capture(ckks_batch *b, void *stream)
     }
     if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return fail(CKKS_E_DEVICE, "ckks_batch_capture: begin capture failed");
-    hipError_t e = run(b, st);
-    hipError_t e2 = hipStreamEndCapture(st, &b->graph);
-    if (e != hipSuccess || e2 != hipSuccess)
-        return fail(CKKS_E_DEVICE, "ckks_batch_capture: capture failed");
-    if (hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess)
+    const hipError_t e = run(b, st);
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(st, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (e2 == hipSuccess && g) (void)hipGraphDestroy(g);
+        return fail(CKKS_E_DEVICE, std::string("ckks_batch_capture: ") + hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    b->graph = g;
+    if (hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess) {
+        b->exec = nullptr;
+        (void)hipGraphDestroy(b->graph);
+        b->graph = nullptr;
         return fail(CKKS_E_DEVICE, "ckks_batch_capture: instantiate failed");
+    }
     return CKKS_OK;
 }
 

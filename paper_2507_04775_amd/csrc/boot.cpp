@@ -158,6 +158,7 @@ struct ckks_boot {
     size_t ws_bytes = 0;
     // hoisted ModDown: per lane an extended accumulator pair [2][l+1+K][N] (qp_words per lane)
     bool hoist = false;
+    uint64_t gain = 1;  // integer the level-0 input is multiplied by before ModRaise
     uint64_t *qp = nullptr;
     size_t qp_words = 0;
     Lane lanes[kLanes];
@@ -694,9 +695,15 @@ struct Runner {
         }
     }
 
-    ckks_status run_steps(const ckks_ct &in, const ckks_ct &out)
+    ckks_status run_steps(const ckks_ct &in0, const ckks_ct &out)
     {
         Ct x = b->slot(b->s_x(), b->L);
+        ckks_ct in = in0;
+        if (b->gain > 1) {  // G m: the integer gain on the level-0 input, exact
+            const Ct g = b->slot(b->s_im(0), 0);
+            TRY(scalar_mul(Ct{in.c0, in.c1, 0}, g, (int64_t)b->gain));
+            in = ckks_ct{g.c0, g.c1, 0, in0.scale};
+        }
         if (b->to_sparse) {  // encapsulation: switch the input to the sparse secret first
             const Ct c = b->slot(b->s_re(0), 0), tmp = b->slot(b->s_cj(), 0);
             const size_t bytes = b->N * 8;
@@ -809,6 +816,11 @@ extern "C" ckks_status ckks_boot_create(ckks_ctx *ctx, const ckks_boot_desc *des
     }
     b->to_sparse = desc->to_sparse;
     b->hoist = desc->hoist_moddown != 0;
+    b->gain = desc->input_gain > 1 ? desc->input_gain : 1;
+    if (b->gain >= ctx->primes[0]) {
+        delete b;
+        return fail(CKKS_E_ARG, "ckks_boot_create: input_gain must be below q_0");
+    }
     b->from_sparse = desc->from_sparse;
     auto bail = [&](ckks_status s, const std::string &m) {
         ckks_boot_destroy(b);

@@ -302,7 +302,12 @@ hipError_t launch_ntt_fwd(const NttArgs &a, uint32_t nlimbs, NttPro pro, NttEpi 
 hipError_t launch_ntt_inv(const NttArgs &a, uint32_t nlimbs, NttPro pro, hipStream_t stream, uint64_t *mid,
                           int64_t mid_poly_stride);
 uint32_t ntt_passes(uint32_t logn);
-uint32_t ntt_tiles(uint32_t logn);
+uint32_t ntt_tiles(uint32_t logn);  // tiles per limb of the persistent passes
+// Tile width (16, 8 or 4 columns / rows per workgroup) of the N = 2^16 grid
+// launches over nlimbs limbs, per direction; 0 restores the default rule.
+constexpr uint32_t kMaxTileLimbs = 128;
+bool ntt_tile_set(uint32_t inverse, uint32_t nlimbs, uint32_t tile);
+uint32_t ntt_tile_get(uint32_t inverse, uint32_t nlimbs);
 hipError_t launch_ntt_stage(NttStage st, const NttArgs &a, uint32_t nlimbs, hipStream_t stream);
 hipError_t launch_ntt_stage_queue(NttStage st, uint32_t logn, uint32_t pass, const NttArgs *insts,
                                   const WorkQueue &q, uint32_t grid, hipStream_t stream);

@@ -28,6 +28,8 @@
 // - other primes (up to 2^61): 64-bit integers with Shoup twiddles and
 //   Harvey's lazy butterflies ([0, 4q) forward, [0, 2q) inverse).
 // Outputs of every transform are canonical.
+#include <atomic>
+
 #include "internal.h"
 #include "unit_map.h"
 
@@ -490,12 +492,13 @@ __device__ __forceinline__ uint32_t pos_wide(uint32_t s, int i) { return s + 32 
 __device__ __forceinline__ uint32_t pos_mid(uint32_t s, int i) { return 32 * (s >> 2) + (s & 3) + 4 * i; }
 __device__ __forceinline__ uint32_t pos_narrow(uint32_t s, int i) { return 8 * s + i; }
 
-// LDS slot of element e of column `col` in a column pass: the tile's 16
-// columns interleaved (element-major) and every group of 8 elements padded by
-// one word.  A half-wave (16 columns x 2 threads) then touches 32 consecutive
-// words in the wide and mid layouts and two 128-byte halves of the banks in
-// the narrow one.
-__device__ __forceinline__ uint32_t col_slot(uint32_t e, uint32_t col) { return 16 * (e + (e >> 3)) + col; }
+// LDS slot of element e of column `col` in a column pass over a tile of TW
+// columns: the columns interleaved (element-major) and every group of 8
+// elements padded by one word.  A half-wave (TW columns x 32/TW threads) then
+// touches 32 consecutive words in the wide and mid layouts and 32 / TW groups
+// of TW words spread over all banks in the narrow one (TW = 16, 8, 4).
+template <int TW>
+__device__ __forceinline__ uint32_t col_slot(uint32_t e, uint32_t col) { return TW * (e + (e >> 3)) + col; }
 constexpr int kColLds = 16 * (255 + 31 + 1);
 
 // LDS slot of element e of a row (256 words per row): the low five bits are
@@ -507,12 +510,19 @@ __device__ __forceinline__ uint32_t row_slot(uint32_t e)
     return (e & ~31u) | ((e ^ h ^ (h << 2)) & 31u);
 }
 constexpr int kLds16 = kColLds > 16 * 256 ? kColLds : 16 * 256;
+// Tile widths: 16 columns (rows) of the 256 x 256 view per workgroup of 512
+// threads, the layout of every persistent pass and of grid launches over many
+// limbs; 8 or 4 per workgroup of 256 or 128 threads for launches over few
+// limbs, which then have two or four times the workgroups to spread over the
+// 256 CUs.  LDS per workgroup: TW (255 + 31 + 1) words.
+template <int TW>
+constexpr int lds_words() { return TW * (255 + 31 + 1); }
 
-template <int PRO, class A>
+template <int PRO, int TW, class A>
 __device__ __forceinline__ void fwd_col_body(const NttArgs &a, const LimbPos &lp, const Prime &P, const A &ar,
                                              uint64_t *lds, uint32_t tile, uint32_t tx)
 {
-    const uint32_t col = tx & 15, s = tx >> 4, c = tile * 16 + col;
+    const uint32_t col = tx & (TW - 1), s = tx / TW, c = tile * TW + col;
     const uint64_t *src = a.src + (int64_t)lp.poly * a.map.src_poly_stride + (size_t)lp.row * 65536;
     typename A::W wa[7], wb[7], wc[6];
     typename A::V v[8];
@@ -528,19 +538,19 @@ __device__ __forceinline__ void fwd_col_body(const NttArgs &a, const LimbPos &lp
     fwd_rw<3>(v, wa, ar);
     tw_fwd<3, 256, 4>(wb, pos_mid(s, 0), ar, 1);  // in flight across the exchange
 #pragma unroll
-    for (int i = 0; i < 8; ++i) lds[col_slot(pos_wide(s, i), col)] = ar.to_bits(v[i]);
+    for (int i = 0; i < 8; ++i) lds[col_slot<TW>(pos_wide(s, i), col)] = ar.to_bits(v[i]);
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < 8; ++i) v[i] = ar.from_bits(lds[col_slot(pos_mid(s, i), col)]);
+    for (int i = 0; i < 8; ++i) v[i] = ar.from_bits(lds[col_slot<TW>(pos_mid(s, i), col)]);
     ar.reduce_all(v);
     fwd_rw<3>(v, wb, ar);
     tw_fwd<2, 256, 1>(wc, 8 * s, ar, 1);
     tw_fwd<2, 256, 1>(wc + 3, 8 * s + 4, ar, 1);
 #pragma unroll
-    for (int i = 0; i < 8; ++i) lds[col_slot(pos_mid(s, i), col)] = ar.to_bits(v[i]);
+    for (int i = 0; i < 8; ++i) lds[col_slot<TW>(pos_mid(s, i), col)] = ar.to_bits(v[i]);
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < 8; ++i) v[i] = ar.from_bits(lds[col_slot(pos_narrow(s, i), col)]);
+    for (int i = 0; i < 8; ++i) v[i] = ar.from_bits(lds[col_slot<TW>(pos_narrow(s, i), col)]);
     ar.reduce_all(v);
     fwd_rw<2>(v, wc, ar);
     fwd_rw<2>(v + 4, wc + 3, ar);
@@ -549,7 +559,7 @@ __device__ __forceinline__ void fwd_col_body(const NttArgs &a, const LimbPos &lp
     for (int i = 0; i < 8; ++i) m[pos_narrow(s, i) * 256 + c] = ar.to_bits(v[i]);
 }
 
-template <int PRO>
+template <int PRO, int TW = 16>
 __device__ __forceinline__ void fwd_col_unit(const NttArgs &a, uint32_t limb, uint32_t tile, uint64_t *lds,
                                              uint32_t tx)
 {
@@ -557,16 +567,16 @@ __device__ __forceinline__ void fwd_col_unit(const NttArgs &a, uint32_t limb, ui
     if (lp.skip) return;
     const Prime P = a.primes[lp.prime];
     if (P.q < kFpMaxPrime)
-        fwd_col_body<PRO>(a, lp, P, fp_arith(a, P, lp.prime, 65536), lds, tile, tx);
+        fwd_col_body<PRO, TW>(a, lp, P, fp_arith(a, P, lp.prime, 65536), lds, tile, tx);
     else
-        fwd_col_body<PRO>(a, lp, P, int_arith(a, P, lp.prime, 65536), lds, tile, tx);
+        fwd_col_body<PRO, TW>(a, lp, P, int_arith(a, P, lp.prime, 65536), lds, tile, tx);
 }
 
-template <int EPI, class A>
+template <int EPI, int TW, class A>
 __device__ __forceinline__ void fwd_row_body(const NttArgs &a, const LimbPos &lp, const Prime &P, const A &ar,
                                              uint64_t *lds, uint32_t tile, uint32_t tx)
 {
-    const uint32_t blk = tx >> 5, s = tx & 31, b = tile * 16 + blk;
+    const uint32_t blk = tx >> 5, s = tx & 31, b = tile * TW + blk;
     const uint64_t *m = a.mid + (int64_t)lp.poly * a.mid_stride + (size_t)lp.row * 65536 + b * 256;
     uint64_t *L = lds + blk * 256;
     typename A::W wa[7], wb[7], wc[6];
@@ -633,7 +643,7 @@ __device__ __forceinline__ void fwd_row_body(const NttArgs &a, const LimbPos &lp
         store_fwd<EPI>(a, lp, dst, b * 256 + pos_wide(s, i), x[i], addv[i], auxv[i], P, 65536);
 }
 
-template <int EPI>
+template <int EPI, int TW = 16>
 __device__ __forceinline__ void fwd_row_unit(const NttArgs &a, uint32_t limb, uint32_t tile, uint64_t *lds,
                                              uint32_t tx)
 {
@@ -641,16 +651,16 @@ __device__ __forceinline__ void fwd_row_unit(const NttArgs &a, uint32_t limb, ui
     if (lp.skip) return;
     const Prime P = a.primes[lp.prime];
     if (P.q < kFpMaxPrime)
-        fwd_row_body<EPI>(a, lp, P, fp_arith(a, P, lp.prime, 65536), lds, tile, tx);
+        fwd_row_body<EPI, TW>(a, lp, P, fp_arith(a, P, lp.prime, 65536), lds, tile, tx);
     else
-        fwd_row_body<EPI>(a, lp, P, int_arith(a, P, lp.prime, 65536), lds, tile, tx);
+        fwd_row_body<EPI, TW>(a, lp, P, int_arith(a, P, lp.prime, 65536), lds, tile, tx);
 }
 
-template <int PRO, class A>
+template <int PRO, int TW, class A>
 __device__ __forceinline__ void inv_row_body(const NttArgs &a, const LimbPos &lp, const A &ar, uint64_t *lds,
                                              uint32_t tile, uint32_t tx)
 {
-    const uint32_t blk = tx >> 5, s = tx & 31, b = tile * 16 + blk;
+    const uint32_t blk = tx >> 5, s = tx & 31, b = tile * TW + blk;
     const uint64_t *src = a.src + (int64_t)lp.poly * a.map.src_poly_stride + (size_t)lp.row * 65536;
     uint64_t *L = lds + blk * 256;
     typename A::W wa[6], wb[7], wc[7];
@@ -689,7 +699,7 @@ __device__ __forceinline__ void inv_row_body(const NttArgs &a, const LimbPos &lp
     for (int i = 0; i < 8; ++i) m[pos_wide(s, i)] = ar.to_bits(v[i]);
 }
 
-template <int PRO>
+template <int PRO, int TW = 16>
 __device__ __forceinline__ void inv_row_unit(const NttArgs &a, uint32_t limb, uint32_t tile, uint64_t *lds,
                                              uint32_t tx)
 {
@@ -697,16 +707,16 @@ __device__ __forceinline__ void inv_row_unit(const NttArgs &a, uint32_t limb, ui
     if (lp.skip) return;
     const Prime P = a.primes[lp.prime];
     if (P.q < kFpMaxPrime)
-        inv_row_body<PRO>(a, lp, fp_arith(a, P, lp.prime, 65536), lds, tile, tx);
+        inv_row_body<PRO, TW>(a, lp, fp_arith(a, P, lp.prime, 65536), lds, tile, tx);
     else
-        inv_row_body<PRO>(a, lp, int_arith(a, P, lp.prime, 65536), lds, tile, tx);
+        inv_row_body<PRO, TW>(a, lp, int_arith(a, P, lp.prime, 65536), lds, tile, tx);
 }
 
-template <class A>
+template <int TW, class A>
 __device__ __forceinline__ void inv_col_body(const NttArgs &a, const LimbPos &lp, const A &ar, uint64_t *lds,
                                              uint32_t tile, uint32_t tx)
 {
-    const uint32_t col = tx & 15, s = tx >> 4, c = tile * 16 + col;
+    const uint32_t col = tx & (TW - 1), s = tx / TW, c = tile * TW + col;
     const uint64_t *m = a.mid + (int64_t)lp.poly * a.mid_stride + (size_t)lp.row * 65536;
     typename A::W wa[6], wb[7], wc[7];
     tw_inv<2, 256, 1>(wa, 8 * s, ar, 1);
@@ -719,18 +729,18 @@ __device__ __forceinline__ void inv_col_body(const NttArgs &a, const LimbPos &lp
     inv_rw<2>(v + 4, wa + 3, ar);
     tw_inv<3, 256, 4>(wb, pos_mid(s, 0), ar, 1);  // in flight across the exchange
 #pragma unroll
-    for (int i = 0; i < 8; ++i) lds[col_slot(pos_narrow(s, i), col)] = ar.to_bits(v[i]);
+    for (int i = 0; i < 8; ++i) lds[col_slot<TW>(pos_narrow(s, i), col)] = ar.to_bits(v[i]);
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < 8; ++i) v[i] = ar.from_bits(lds[col_slot(pos_mid(s, i), col)]);
+    for (int i = 0; i < 8; ++i) v[i] = ar.from_bits(lds[col_slot<TW>(pos_mid(s, i), col)]);
     ar.reduce_all(v);
     inv_rw<3>(v, wb, ar);
     tw_inv<3, 256, 32>(wc, s, ar, 1);
 #pragma unroll
-    for (int i = 0; i < 8; ++i) lds[col_slot(pos_mid(s, i), col)] = ar.to_bits(v[i]);
+    for (int i = 0; i < 8; ++i) lds[col_slot<TW>(pos_mid(s, i), col)] = ar.to_bits(v[i]);
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < 8; ++i) v[i] = ar.from_bits(lds[col_slot(pos_wide(s, i), col)]);
+    for (int i = 0; i < 8; ++i) v[i] = ar.from_bits(lds[col_slot<TW>(pos_wide(s, i), col)]);
     ar.reduce_all(v);
     inv_rw<3>(v, wc, ar);
     uint64_t *dst = a.dst + (int64_t)lp.poly * a.map.dst_poly_stride + (size_t)lp.row * 65536;
@@ -738,6 +748,7 @@ __device__ __forceinline__ void inv_col_body(const NttArgs &a, const LimbPos &lp
     for (int i = 0; i < 8; ++i) dst[pos_wide(s, i) * 256 + c] = ar.inv_final(v[i]);
 }
 
+template <int TW = 16>
 __device__ __forceinline__ void inv_col_unit(const NttArgs &a, uint32_t limb, uint32_t tile, uint64_t *lds,
                                              uint32_t tx)
 {
@@ -745,9 +756,9 @@ __device__ __forceinline__ void inv_col_unit(const NttArgs &a, uint32_t limb, ui
     if (lp.skip) return;
     const Prime P = a.primes[lp.prime];
     if (P.q < kFpMaxPrime)
-        inv_col_body(a, lp, inv_fp_arith(a, lp, P, 65536), lds, tile, tx);
+        inv_col_body<TW>(a, lp, inv_fp_arith(a, lp, P, 65536), lds, tile, tx);
     else
-        inv_col_body(a, lp, inv_int_arith(a, lp, P, 65536), lds, tile, tx);
+        inv_col_body<TW>(a, lp, inv_int_arith(a, lp, P, 65536), lds, tile, tx);
 }
 
 // ------------------------------------------------------------------ N = 2^12
@@ -925,6 +936,48 @@ NTT_KERNELS(fwd_row_rescale, kLds16, fwd_row_unit<EPI_RESCALE>, kThreads16, true
 NTT_KERNELS(inv_row_plain, kLds16, inv_row_unit<PRO_PLAIN>, kThreads16, true)
 NTT_KERNELS(inv_row_galois, kLds16, inv_row_unit<PRO_GALOIS>, kThreads16, true)
 NTT_KERNELS(inv_col, kLds16, inv_col_unit, kThreads16, true)
+// Grid kernels with narrower tiles (TW = 8, 4 columns or rows per workgroup of
+// 32 TW threads), for launches over few limbs; unit = (blockIdx.x, blockIdx.y).
+#define NTT_NARROW(NAME, UNIT_T)                                                                    \
+    __global__ __launch_bounds__(256) void k_##NAME##_w8(NttArgs a)                                \
+    {                                                                                               \
+        __shared__ uint64_t lds[lds_words<8>()];                                                    \
+        UNIT_T(8)(a, blockIdx.y, blockIdx.x, lds, threadIdx.x);                                     \
+    }                                                                                               \
+    __global__ __launch_bounds__(128) void k_##NAME##_w4(NttArgs a)                                \
+    {                                                                                               \
+        __shared__ uint64_t lds[lds_words<4>()];                                                    \
+        UNIT_T(4)(a, blockIdx.y, blockIdx.x, lds, threadIdx.x);                                     \
+    }
+#define U_FCP(W) fwd_col_unit<PRO_PLAIN, W>
+#define U_FCR(W) fwd_col_unit<PRO_RESCALE, W>
+#define U_FCB(W) fwd_col_unit<PRO_BCONV, W>
+#define U_FRP(W) fwd_row_unit<EPI_PLAIN, W>
+#define U_FRM(W) fwd_row_unit<EPI_MODDOWN, W>
+#define U_FRR(W) fwd_row_unit<EPI_RESCALE, W>
+#define U_IRP(W) inv_row_unit<PRO_PLAIN, W>
+#define U_IRG(W) inv_row_unit<PRO_GALOIS, W>
+#define U_IC(W) inv_col_unit<W>
+NTT_NARROW(fwd_col_plain, U_FCP)
+NTT_NARROW(fwd_col_rescale, U_FCR)
+NTT_NARROW(fwd_col_bconv, U_FCB)
+NTT_NARROW(fwd_row_plain, U_FRP)
+NTT_NARROW(fwd_row_moddown, U_FRM)
+NTT_NARROW(fwd_row_rescale, U_FRR)
+NTT_NARROW(inv_row_plain, U_IRP)
+NTT_NARROW(inv_row_galois, U_IRG)
+NTT_NARROW(inv_col, U_IC)
+#undef U_FCP
+#undef U_FCR
+#undef U_FCB
+#undef U_FRP
+#undef U_FRM
+#undef U_FRR
+#undef U_IRP
+#undef U_IRG
+#undef U_IC
+#undef NTT_NARROW
+
 #define FWD12_PP fwd12_unit<PRO_PLAIN, EPI_PLAIN>
 #define FWD12_PM fwd12_unit<PRO_PLAIN, EPI_MODDOWN>
 #define FWD12_RR fwd12_unit<PRO_RESCALE, EPI_RESCALE>
@@ -952,23 +1005,28 @@ struct StageKernels {
     QueueKernel queue;
 };
 
-// The kernel that runs one pass of a stage (pass 0 = first, 1 = second at N = 2^16).
-bool stage_kernels(NttStage st, uint32_t logn, int pass, StageKernels &k)
+// The kernel that runs one pass of a stage (pass 0 = first, 1 = second at N =
+// 2^16) with tiles of tw columns (rows); the narrow tiles have grid kernels only.
+bool stage_kernels(NttStage st, uint32_t logn, int pass, StageKernels &k, uint32_t tw = 16)
 {
 #define SK(G) \
+    k.grid = tw == 8 ? k_##G##_w8 : tw == 4 ? k_##G##_w4 : k_##G; \
+    k.queue = tw == 16 ? q_##G : nullptr; \
+    return true;
+#define SK12(G) \
     k.grid = k_##G; \
     k.queue = q_##G; \
     return true;
     if (logn == 12) {
         if (pass != 0) return false;
         switch (st) {
-        case STAGE_FWD_PLAIN: SK(fwd12_plain)
-        case STAGE_FWD_MODDOWN: SK(fwd12_moddown)
-        case STAGE_FWD_RESCALE: SK(fwd12_rescale)
-        case STAGE_FWD_LIFT: SK(fwd12_lift)
-        case STAGE_FWD_BCONV_MODDOWN: SK(fwd12_bconv_moddown)
-        case STAGE_INV_PLAIN: SK(inv12_plain)
-        case STAGE_INV_GALOIS: SK(inv12_galois)
+        case STAGE_FWD_PLAIN: SK12(fwd12_plain)
+        case STAGE_FWD_MODDOWN: SK12(fwd12_moddown)
+        case STAGE_FWD_RESCALE: SK12(fwd12_rescale)
+        case STAGE_FWD_LIFT: SK12(fwd12_lift)
+        case STAGE_FWD_BCONV_MODDOWN: SK12(fwd12_bconv_moddown)
+        case STAGE_INV_PLAIN: SK12(inv12_plain)
+        case STAGE_INV_GALOIS: SK12(inv12_galois)
         default: return false;
         }
     }
@@ -990,6 +1048,7 @@ bool stage_kernels(NttStage st, uint32_t logn, int pass, StageKernels &k)
     default: return false;
     }
 #undef SK
+#undef SK12
 }
 
 }  // namespace
@@ -1021,17 +1080,52 @@ static void set_heavy(NttArgs &a, uint32_t nlimbs)
     a.n_heavy = nh < nlimbs ? nh : 0;  // all limbs alike: whole-limb placement
 }
 
+// Tile width of the grid launches at N = 2^16, per direction and launch size
+// (0: the default rule below).  Set by ckks_ntt_tile_set (an autotuner), read
+// by every grid launch.
+static std::atomic<uint8_t> g_tile[2][kMaxTileLimbs + 1];
+
+static uint32_t default_tile(uint32_t nlimbs)
+{
+    if (nlimbs >= 24) return 16;
+    return nlimbs >= 6 ? 8 : 4;
+}
+
+static uint32_t tile_width(NttStage st, uint32_t logn, uint32_t nlimbs)
+{
+    if (logn != 16) return 16;
+    const int inv = st == STAGE_INV_PLAIN || st == STAGE_INV_GALOIS;
+    const uint32_t t = nlimbs <= kMaxTileLimbs ? g_tile[inv][nlimbs].load(std::memory_order_relaxed) : 0;
+    return t ? t : default_tile(nlimbs);
+}
+
 hipError_t launch_ntt_stage(NttStage st, const NttArgs &a0, uint32_t nlimbs, hipStream_t stream)
 {
     if (nlimbs == 0) return hipSuccess;
     NttArgs a = a0;
-    set_heavy(a, nlimbs);
+    const uint32_t tw = tile_width(st, a.logn, nlimbs);
+    if (tw == 16) set_heavy(a, nlimbs);
+    else a.n_heavy = 0;
     for (uint32_t pass = 0; pass < ntt_passes(a.logn); ++pass) {
         StageKernels k;
-        if (!stage_kernels(st, a.logn, pass, k)) return hipErrorInvalidValue;
-        hipLaunchKernelGGL(k.grid, dim3(ntt_tiles(a.logn), nlimbs), dim3(ntt_threads(a.logn)), 0, stream, a);
+        if (!stage_kernels(st, a.logn, pass, k, tw)) return hipErrorInvalidValue;
+        const uint32_t tiles = a.logn == 12 ? 1 : 256 / tw, threads = a.logn == 12 ? kThreads : 32 * tw;
+        hipLaunchKernelGGL(k.grid, dim3(tiles, nlimbs), dim3(threads), 0, stream, a);
     }
     return hipGetLastError();
+}
+
+bool ntt_tile_set(uint32_t inverse, uint32_t nlimbs, uint32_t tile)
+{
+    if (inverse > 1 || nlimbs == 0 || nlimbs > kMaxTileLimbs || !(tile == 0 || tile == 4 || tile == 8 || tile == 16))
+        return false;
+    g_tile[inverse][nlimbs].store((uint8_t)tile, std::memory_order_relaxed);
+    return true;
+}
+
+uint32_t ntt_tile_get(uint32_t inverse, uint32_t nlimbs)
+{
+    return tile_width(inverse ? STAGE_INV_PLAIN : STAGE_FWD_PLAIN, 16, nlimbs);
 }
 
 hipError_t launch_ntt_stage_queue(NttStage st, uint32_t logn, uint32_t pass, const NttArgs *insts,

@@ -15,7 +15,7 @@ from paper_2507_04775_amd import inputs
 def _oracle_params(cfg):
     return OB.BootParams(logn=cfg.logn, cts_radix_logs=cfg.cts_radix_logs, stc_radix_logs=cfg.stc_radix_logs,
                          cheb_degree=cfg.cheb_degree, double_angles=cfg.double_angles, k_range=cfg.k_range,
-                         top_scale=cfg.top_scale, in_scale=cfg.in_scale)
+                         top_scale=cfg.top_scale, in_scale=cfg.in_scale, input_gain=cfg.input_gain)
 
 
 @pytest.mark.parametrize("logn,radix", [(6, [2, 2, 1]), (7, [1, 4, 1]), (8, [7])])
@@ -42,9 +42,12 @@ def test_coefficients_of_slots_invert_the_embedding():
         assert abs(np.polyval(m[::-1], zeta ** pow(5, j, 2 * N)) - z[j]) < 1e-12
 
 
-def test_plan_matches_the_oracle_planner():
+@pytest.mark.parametrize("sparse,gain", [(True, None), (False, None), (True, 1), (False, 7)])
+def test_plan_matches_the_oracle_planner(sparse, gain):
     ps = inputs.params("boot-small")
-    cfg = PB.default_config(12, 2.0 ** 50)
+    cfg = PB.default_config(12, 2.0 ** 50, sparse=sparse)
+    if gain is not None:
+        cfg.input_gain = gain
     mine = PB.plan(ps.q, cfg)
     P = oracle_params(ps)
     bp = _oracle_params(cfg)

@@ -26,7 +26,7 @@ def _say(msg):
 def _boot_handle(s, bp, pl, relin, conj, rot, sparse=None):
     return s.ckks.Boot(s.ctx, bp.cts_radix_logs, bp.stc_radix_logs, pl.cts, pl.stc, pl.cheb, bp.double_angles,
                        bp.top_scale, relin, conj, rot, cheb_baby=bp.cheb_baby, sparse=sparse,
-                       hoist_moddown=bp.hoist_moddown)
+                       hoist_moddown=bp.hoist_moddown, input_gain=bp.input_gain)
 
 
 def _check_ct(s, got, want, what):
@@ -37,19 +37,20 @@ def _check_ct(s, got, want, what):
 
 # the last case merges five and six FFT stages per group: eight giant steps per transform, two per
 # lane, so pairs of giants share one baby-step combination (and the last pair has unequal babies)
-@pytest.mark.parametrize("baby,bound,sparse,hoist,cts,stc", [
-    (0, -9.5, False, False, [4, 4, 3], [3, 4, 4]), (64, -12, False, False, [4, 4, 3], [3, 4, 4]),
-    (0, -14, True, False, [4, 4, 3], [3, 4, 4]), (0, -14, True, True, [4, 4, 3], [3, 4, 4]),
-    (0, -12, True, True, [6, 5], [5, 6])])
-def test_bootstrap_small_full_schedule(baby, bound, sparse, hoist, cts, stc):
-    _say("bootstrap boot-small (baby %d, sparse %s, hoisted ModDown %s, groups %s / %s): keys and plan"
-         % (baby, sparse, hoist, cts, stc))
+@pytest.mark.parametrize("baby,bound,sparse,hoist,cts,stc,gain", [
+    (0, -9.5, False, False, [4, 4, 3], [3, 4, 4], 1), (64, -12, False, False, [4, 4, 3], [3, 4, 4], 1),
+    (0, -14, True, False, [4, 4, 3], [3, 4, 4], 1), (0, -14, True, True, [4, 4, 3], [3, 4, 4], 1),
+    (0, -12, True, True, [6, 5], [5, 6], 1), (0, -17.5, True, True, [4, 4, 3], [3, 4, 4], 16),
+    (0, -13.5, False, True, [4, 4, 3], [3, 4, 4], 16)])
+def test_bootstrap_small_full_schedule(baby, bound, sparse, hoist, cts, stc, gain):
+    _say("bootstrap boot-small (baby %d, sparse %s, hoisted ModDown %s, groups %s / %s, gain %d): keys and plan"
+         % (baby, sparse, hoist, cts, stc, gain))
     s = Setup("boot-small")
     cs = ClientSetup(s.ps, seed=31)
     ev = dict(cheb_degree=31, double_angles=3, k_range=12.0) if sparse else \
         dict(cheb_degree=63, double_angles=5, k_range=128.0)
     bp = B.BootParams(logn=12, cts_radix_logs=cts, stc_radix_logs=stc, top_scale=2.0 ** 50,
-                      in_scale=2.0 ** 50, cheb_baby=baby, hoist_moddown=hoist, **ev)
+                      in_scale=2.0 ** 50, cheb_baby=baby, hoist_moddown=hoist, input_gain=gain, **ev)
     pl = B.plan(s.P, bp)
     rot_np = {k: cs.galois_key(oracle.galois_for_rotation(12, k)) for k in B.rotations_needed(bp)}
     conj_np = cs.galois_key(oracle.galois_conjugate(12))
@@ -95,7 +96,8 @@ def test_bootstrap_large_graph_replay(sparse):
     cfg = bootplan.default_config(16, 2.0 ** 50, sparse=sparse)
     bp = B.BootParams(logn=16, cts_radix_logs=cfg.cts_radix_logs, stc_radix_logs=cfg.stc_radix_logs,
                       cheb_degree=cfg.cheb_degree, double_angles=cfg.double_angles, k_range=cfg.k_range,
-                      top_scale=cfg.top_scale, in_scale=cfg.in_scale, hoist_moddown=cfg.hoist_moddown)
+                      top_scale=cfg.top_scale, in_scale=cfg.in_scale, hoist_moddown=cfg.hoist_moddown,
+                      input_gain=cfg.input_gain)
     pl = B.plan(s.P, bp)
     rot = {}
     for k in B.rotations_needed(bp):

@@ -287,3 +287,51 @@ def test_table_i_ops_reject_bad_arguments(name):
     part = s.ckks.Ciphertext(ta.c0, out.c1, 2, 1.0)  # shares c0 with the input but not c1
     with pytest.raises(s.ckks.CkksError, match="overlaps"):
         s.ctx.ckks_ptadd(ta, s.dev(inputs.random_poly(432, s.ps, 2)), part)
+
+
+@pytest.mark.parametrize("tile", [4, 8, 16])
+def test_every_ntt_tile_width_is_bit_exact(tile):
+    """The N = 2^16 passes with 4-, 8- and 16-wide tiles forced on every launch
+    (the autotuner's design space): NTT / INTT over all 35 limbs and over 2 and
+    8 limbs, HMult+relin, Rescale and HRotate at l = 30 and 12, each against
+    the oracle."""
+    from paper_2507_04775_amd import ckks
+    s = setup("large")
+    try:
+        for inv in (0, 1):
+            for n in range(1, 129):
+                ckks.ntt_tile_set(inv, n, tile)
+        assert ckks.ntt_tile_get(False, 35) == tile and ckks.ntt_tile_get(True, 2) == tile
+        mods = list(s.ps.q) + list(s.ps.p)
+        a = inputs.uniform_residues(inputs.rng(900 + tile), mods, s.N)
+        for lo, n in [(0, len(mods)), (s.ps.L + 1, s.ps.K), (3, 2), (0, 8)]:
+            t = s.dev(a[lo: lo + n])
+            s.ctx.ckks_ntt(t, lo, n)
+            assert_equal(s.host(t), oracle.ntt(mods[lo: lo + n], a[lo: lo + n], s.ps.logn), "ntt tile %d" % tile)
+            s.ctx.ckks_intt(t, lo, n)
+            assert_equal(s.host(t), a[lo: lo + n], "intt(ntt) tile %d" % tile)
+        key, kh = s.key(910, 0)
+        k = 5
+        g = oracle.galois_for_rotation(s.ps.logn, k)
+        rkey, rkh = s.key(911, g)
+        for level in (30, 12):
+            x, tx = s.ct(920 + level, level)
+            y, ty = s.ct(930 + level, level)
+            out = s.ctx.empty_ct(level)
+            s.ctx.ckks_hmult_relin(tx, ty, kh, out)
+            w0, w1 = oracle.hmult_relin(s.P, x, y, key, level)
+            assert_equal(s.host(out.c0), w0, "hmult tile %d level %d" % (tile, level))
+            assert_equal(s.host(out.c1), w1, "hmult tile %d level %d" % (tile, level))
+            low = s.ctx.empty_ct(level - 1)
+            s.ctx.ckks_rescale(tx, low)
+            w0, w1 = oracle.rescale(s.P, x, level)
+            assert_equal(s.host(low.c0), w0, "rescale tile %d level %d" % (tile, level))
+            assert_equal(s.host(low.c1), w1, "rescale tile %d level %d" % (tile, level))
+            s.ctx.ckks_hrotate(tx, k, rkh, out)
+            w0, w1 = oracle.apply_galois(s.P, x, g, rkey, level)
+            assert_equal(s.host(out.c0), w0, "hrotate tile %d level %d" % (tile, level))
+            assert_equal(s.host(out.c1), w1, "hrotate tile %d level %d" % (tile, level))
+    finally:
+        for inv in (0, 1):
+            for n in range(1, 129):
+                ckks.ntt_tile_set(inv, n, 0)

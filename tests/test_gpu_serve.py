@@ -34,7 +34,7 @@ def _server(s, slots, budget, n_boot=2):
     bkeys = {k: rkey(5000 + k, pow(5, k, 2 * s.N))[1] for k in pl.rotations}
     conj, sparse = rkey(2, 2 * s.N - 1)[1], (rkey(3, 0)[1], rkey(4, 0)[1])
     boots = [ckks.Boot(s.ctx, cfg.cts_radix_logs, cfg.stc_radix_logs, pl.cts, pl.stc, pl.cheb, cfg.double_angles,
-                       cfg.top_scale, relin[1], conj, bkeys, sparse=sparse, hoist_moddown=cfg.hoist_moddown)
+                       cfg.top_scale, relin[1], conj, bkeys, sparse=sparse, hoist_moddown=cfg.hoist_moddown, input_gain=cfg.input_gain)
              for _ in range(n_boot)]
     srv = Server(s.ctx, relin[1], {k: v[1] for k, v in rot.items()}, pts, boots, slots=slots, mem_budget=budget)
     return srv, relin[0], {k: v[0] for k, v in rot.items()}, pts
