@@ -179,6 +179,24 @@ ckks_status ckks_keyswitch(ckks_ctx *ctx, const uint64_t *d, uint32_t level, con
                            uint64_t *out1, void *ws, void *stream);
 
 /*
+ * Key switching for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same operation, kernels and output as ckks_keyswitch, with the workspace
+ * taken from a static device array of ckks_noalloc_scratch_bytes() bytes
+ * (160 MiB: every level of N = 2^16 with 31 ciphertext limbs and up to ten
+ * special primes) that the library holds on each GPU it runs on until the
+ * process ends.  The call allocates nothing.  A level whose workspace
+ * (ckks_workspace_bytes(CKKS_OP_KEYSWITCH, l)) exceeds the scratch returns
+ * CKKS_E_ARG.  Every call on one GPU shares that GPU's scratch: calls that
+ * overlap in time on one GPU (different streams or host threads without
+ * ordering between them) race and give undefined results; calls ordered on
+ * one stream are safe.  The scratch needs no initial contents.
+ */
+ckks_status ckks_keyswitch_noalloc(ckks_ctx *ctx, const uint64_t *d, uint32_t level, const ckks_key *key,
+                                   uint64_t *out0, uint64_t *out1, void *stream);
+size_t ckks_noalloc_scratch_bytes(void);
+
+/*
  * HMult with relinearisation (Table I): d0 = a0 b0, d1 = a0 b1 + a1 b0,
  * d2 = a1 b1, (k0, k1) = KeySwitch(d2, rlk), out = (d0 + k0, d1 + k1).
  * a, b at the same level (else CKKS_E_LEVEL); rlk must have galois 0

@@ -67,6 +67,8 @@ _sigs = {
     "ckks_key_wrap": (ctypes.c_int, [_vp, _vp, _u32, ctypes.POINTER(_vp)]),
     "ckks_key_release": (None, [_vp]),
     "ckks_keyswitch": (ctypes.c_int, [_vp, _vp, _u32, _vp, _vp, _vp, _vp, _vp]),
+    "ckks_keyswitch_noalloc": (ctypes.c_int, [_vp, _vp, _u32, _vp, _vp, _vp, _vp]),
+    "ckks_noalloc_scratch_bytes": (ctypes.c_size_t, []),
     "ckks_probe_mad64": (ctypes.c_int, [_vp, _u32, _u32, _vp, ctypes.POINTER(ctypes.c_uint64)]),
     "ckks_hmult_relin": (ctypes.c_int, [_vp, ctypes.POINTER(_Ct), ctypes.POINTER(_Ct), _vp, ctypes.POINTER(_Ct), _vp, _vp]),
     "ckks_rescale": (ctypes.c_int, [_vp, ctypes.POINTER(_Ct), ctypes.POINTER(_Ct), _vp, _vp]),
@@ -114,6 +116,11 @@ for _name, (_res, _args) in _sigs.items():
     _f.argtypes = _args
 
 EXPORTED = tuple(_sigs)
+
+
+def noalloc_scratch_bytes() -> int:
+    """Size of the static scratch behind ckks_keyswitch_noalloc (bytes)."""
+    return int(_lib.ckks_noalloc_scratch_bytes())
 
 
 class CkksError(RuntimeError):
@@ -259,6 +266,11 @@ class Context:
         ws = self.workspace(OP_KEYSWITCH, level) if ws is None else ws
         _check(_lib.ckks_keyswitch(self.handle, _ptr(d), level, key.handle, _ptr(out0), _ptr(out1), _ptr(ws),
                                    _stream(stream)), "ckks_keyswitch")
+
+    def ckks_keyswitch_noalloc(self, d: torch.Tensor, level: int, key: Key, out0: torch.Tensor, out1: torch.Tensor,
+                               stream=None):
+        _check(_lib.ckks_keyswitch_noalloc(self.handle, _ptr(d), level, key.handle, _ptr(out0), _ptr(out1),
+                                           _stream(stream)), "ckks_keyswitch_noalloc")
 
     def ckks_hmult_relin(self, a: Ciphertext, b: Ciphertext, rlk: Key, out: Ciphertext, ws=None, stream=None):
         ws = self.workspace(OP_HMULT, a.level) if ws is None else ws

@@ -20,6 +20,8 @@ ckks_status fail(ckks_status s, const std::string &msg)
     return s;
 }
 
+hipError_t scratch_setup(int device);  // noalloc.hip
+
 namespace {
 
 typedef unsigned __int128 wide;
@@ -128,6 +130,9 @@ extern "C" ckks_status ckks_ctx_create(uint32_t log_n, const uint64_t *q, uint32
             if (primes[k] == m) return fail(CKKS_E_ARG, "ckks_ctx_create: primes must be distinct");
     }
     if (hipSetDevice(hip_device) != hipSuccess) return fail(CKKS_E_DEVICE, "ckks_ctx_create: hipSetDevice failed");
+    // the device address of the no-allocation entry point's static scratch, once per device (a
+    // failure is kept and reported by that entry point; the other calls do not use the scratch)
+    (void)scratch_setup(hip_device);
 
     ckks_ctx *ctx = new ckks_ctx();
     ctx->device = hip_device;
