@@ -368,14 +368,29 @@ def run_batch(ctx, ps, seed, args, tcache):
     batch.build()
     st = torch.cuda.Stream()
     n_ks = batch.keyswitches
+    sig = tune.batch_signature([(k, l) for k, l, _ in plan])
     with torch.cuda.stream(st):
         t0 = time.perf_counter()
-        tune.tune_batch(batch, ctx, tune.batch_signature([(k, l) for k, l, _ in plan]), st, tcache)
+        tune.tune_batch(batch, ctx, sig, st, tcache)
+        sched = tune.tune_batch_schedule(batch, ctx, sig, len(plan), st, tcache)
         t_tune = time.perf_counter() - t0
-        batch.capture(st)
-        batch.replay(st)
-        st.synchronize()
-        reps = timed_launches(lambda: batch.replay(st), max(20, args.batch_reps), st, host_us=100.0)
+
+        def replays(window, wg):
+            batch.set_schedule(window, wg)
+            batch.capture(st)
+            batch.replay(st)
+            batch.faults(st)
+            xs = timed_launches(lambda: batch.replay(st), max(20, args.batch_reps), st, host_us=100.0)
+            batch.faults(st)
+            return xs
+
+        # both schedules as graph replays: per-step launches, and one launch at the best window the
+        # tuner measured for it
+        one = min(((w, g) for w, g in tune.schedule_candidates(len(plan), ps.logn) if w),
+                  key=lambda c: sched["ms"].get("%d/%d" % c, 1e30), default=None)
+        per_step = replays(0, 2)
+        one_launch = replays(*one) if one else None
+        reps = replays(sched["window"], sched["wg"])
         ws_h = ctx.workspace(ckks.OP_HMULT, ps.L)
         ws_o = ctx.workspace(ckks.OP_HOISTED, ps.L)
 
@@ -403,7 +418,11 @@ def run_batch(ctx, ps, seed, args, tcache):
            "batched_key_switches_per_s_at_p99": round(n_ks / (percentile(reps, 99) / 1e3), 1),
            "plain_key_switches_per_s_at_p99": round(n_ks / (percentile(preps, 99) / 1e3), 1),
            "speedup": round(pt / bt, 3), "workspace_bytes": int(batch.ws.numel() * 8),
-           "tune_s": round(t_tune, 2), "tuned_grid_wg_per_cu": [batch.grid(i) for i in range(12)]}
+           "tune_s": round(t_tune, 2), "tuned_grid_wg_per_cu": [batch.grid(i) for i in range(12)],
+           "schedule": {"chosen_window": sched["window"], "chosen_wg_per_cu": sched["wg"],
+                        "tuning_median_ms": sched["ms"],
+                        "per_step_launches": stats_ms(per_step),
+                        "one_launch": dict(stats_ms(one_launch), window=one[0], wg_per_cu=one[1]) if one else None}}
     batch.close()
     return res
 

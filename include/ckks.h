@@ -308,9 +308,9 @@ ckks_status ckks_automorph(ckks_ctx *ctx, const uint64_t *in, uint32_t galois, u
  *   CKKS_WORK_HOISTED     : out[i] = HRotate(a, rot[i], rot_keys[i]) for i < n_rot, one ModUp
  * Each item's result is bit-identical to the corresponding single-operation
  * call.  ckks_batch_create validates every item, binds the caller-owned
- * workspace `ws` (ckks_batch_workspace_bytes bytes, kept for the batch's
- * life) and uploads the batch's launch tables (the one allocation, freed by
- * ckks_batch_destroy).  ckks_batch_run executes every step of every item as
+ * workspace `ws` (ckks_batch_workspace_bytes bytes, 256-byte aligned, kept
+ * for the batch's life) and uploads the batch's launch tables into its tail:
+ * a batch allocates no device memory.  ckks_batch_run executes every step of every item as
  * one persistent work-queue launch per step on `stream`; ckks_batch_capture
  * records that launch sequence into a HIP graph that ckks_batch_replay
  * relaunches (a non-default stream is required to capture).  ckks_batch_tune
@@ -354,6 +354,29 @@ uint32_t ckks_batch_grid(const ckks_batch *batch, uint32_t step); /* persistent 
  * cache; steps are numbered 0..ckks_batch_steps()-1. */
 ckks_status ckks_batch_set_grid(ckks_batch *batch, uint32_t step, uint32_t wg_per_cu);
 uint32_t ckks_batch_steps(void);
+/*
+ * Schedule of ckks_batch_run / ckks_batch_capture (limb batching of
+ * Sec. III-F.1 carried to whole key switches).  window = 0: one persistent
+ * launch per step (the default above).  window >= 1 (N = 2^16 only): the
+ * whole batch in ONE persistent launch of wg_per_cu (1 or 2) workgroups per
+ * CU.  Every step of every key switch (ModUp's inverse NTT, conversion and
+ * NTT, the inner product, ModDown's inverse NTT and NTT, HMult's tensor) is a
+ * group of units; a unit starts once the previous step of its own key switch
+ * is done, through per-group counters in device memory, so the steps of
+ * different items overlap.  Items are taken in windows of `window` consecutive
+ * items and window w runs step s in slot w + s (a software pipeline over the
+ * batch); window >= n items is the step-by-step order without barriers.
+ * Results are bit-identical to every other schedule.  A change of window
+ * waits for the device, then writes the unit list into the workspace's tail.
+ * A change of schedule drops a captured graph (ckks_batch_replay then fails
+ * until the next ckks_batch_capture).
+ * A waiting workgroup gives up after a bounded number of polls, so a launch
+ * always ends; ckks_batch_faults then reports CKKS_E_DEVICE.
+ */
+ckks_status ckks_batch_set_schedule(ckks_batch *batch, uint32_t window, uint32_t wg_per_cu);
+uint32_t ckks_batch_schedule(const ckks_batch *batch); /* the window, 0 for per-step launches */
+/* Waits for `stream`; CKKS_E_DEVICE if a one-launch run gave up waiting (its outputs are then invalid). */
+ckks_status ckks_batch_faults(ckks_batch *batch, void *stream);
 void ckks_batch_destroy(ckks_batch *batch);
 
 /*
@@ -410,8 +433,8 @@ void ckks_batch_destroy(ckks_batch *batch);
  * ckks_boot_create validates the descriptor (CKKS_E_KEY when a rotation of
  * the schedule has no key, CKKS_E_UNSUPPORTED when a group needs more than
  * 16 baby steps or the levels run out), uploads and transforms the plaintexts
- * and allocates its buffers: one device allocation, freed by
- * ckks_boot_destroy.  ckks_bootstrap runs the whole pipeline on `stream`:
+ * and lays out its buffers in one block of device memory: the caller's
+ * device_buffer, or one allocation of its own, freed by ckks_boot_destroy.  ckks_bootstrap runs the whole pipeline on `stream`:
  * in->level must be 0, out receives level ckks_boot_output_level() (out's
  * buffers hold that many limbs + 1) and scale D_out.  Calls on one handle
  * must not overlap in time (they share its buffers).  ckks_boot_capture
@@ -442,9 +465,17 @@ typedef struct {
     uint64_t input_gain;                 /* 0 or 1: none; else the level-0 input is multiplied by this integer
                                             (below q_0) before ModRaise, so the message fills more of q_0; the
                                             caller folds 1/input_gain into the SlotToCoeff constants */
+    void *device_buffer;                 /* null: the handle allocates its device memory itself; else a
+                                            caller-owned device buffer, 256-byte aligned, of at least
+                                            ckks_boot_bytes() bytes, valid (and not touched by the caller)
+                                            while the handle lives; the handle then allocates nothing */
+    size_t device_buffer_bytes;
 } ckks_boot_desc;
 
 ckks_status ckks_boot_create(ckks_ctx *ctx, const ckks_boot_desc *desc, ckks_boot **out);
+/* Device bytes the handle of `desc` needs (plaintexts, buffers, workspaces): the size of a
+ * caller-owned device_buffer.  Validates the descriptor as ckks_boot_create does, on the host only. */
+ckks_status ckks_boot_bytes(ckks_ctx *ctx, const ckks_boot_desc *desc, size_t *bytes);
 uint32_t ckks_boot_output_level(const ckks_boot *boot);
 uint32_t ckks_boot_keyswitches(const ckks_boot *boot);  /* key switches per bootstrap */
 size_t ckks_boot_device_bytes(const ckks_boot *boot);   /* plaintexts, buffers and workspace */

@@ -47,7 +47,8 @@ class _BootDesc(ctypes.Structure):
                 ("cheb_baby", _u32), ("double_angles", _u32), ("top_scale", ctypes.c_double), ("relin", _vp), ("conj", _vp),
                 ("to_sparse", _vp), ("from_sparse", _vp),
                 ("n_rot", _u32), ("rot_steps", ctypes.POINTER(_i32)), ("rot_keys", ctypes.POINTER(_vp)),
-                ("hoist_moddown", _u32), ("input_gain", ctypes.c_uint64)]
+                ("hoist_moddown", _u32), ("input_gain", ctypes.c_uint64),
+                ("device_buffer", _vp), ("device_buffer_bytes", ctypes.c_size_t)]
 
 
 _sigs = {
@@ -100,8 +101,12 @@ _sigs = {
     "ckks_batch_grid": (_u32, [_vp, _u32]),
     "ckks_batch_set_grid": (ctypes.c_int, [_vp, _u32, _u32]),
     "ckks_batch_steps": (_u32, []),
+    "ckks_batch_set_schedule": (ctypes.c_int, [_vp, _u32, _u32]),
+    "ckks_batch_schedule": (_u32, [_vp]),
+    "ckks_batch_faults": (ctypes.c_int, [_vp, _vp]),
     "ckks_batch_destroy": (None, [_vp]),
     "ckks_boot_create": (ctypes.c_int, [_vp, ctypes.POINTER(_BootDesc), ctypes.POINTER(_vp)]),
+    "ckks_boot_bytes": (ctypes.c_int, [_vp, ctypes.POINTER(_BootDesc), ctypes.POINTER(ctypes.c_size_t)]),
     "ckks_boot_output_level": (_u32, [_vp]),
     "ckks_boot_keyswitches": (_u32, [_vp]),
     "ckks_boot_device_bytes": (ctypes.c_size_t, [_vp]),
@@ -467,6 +472,18 @@ class Batch:
     def steps() -> int:
         return int(_lib.ckks_batch_steps())
 
+    def set_schedule(self, window: int, wg_per_cu: int = 2):
+        """window 0: one persistent launch per step; window >= 1: the whole batch in one launch,
+        items pipelined in windows of `window` (ckks_batch_set_schedule)."""
+        _check(_lib.ckks_batch_set_schedule(self.handle, window, wg_per_cu), "ckks_batch_set_schedule")
+
+    @property
+    def schedule(self) -> int:
+        return int(_lib.ckks_batch_schedule(self.handle))
+
+    def faults(self, stream=None):
+        _check(_lib.ckks_batch_faults(self.handle, _stream(stream)), "ckks_batch_faults")
+
     def run(self, stream=None):
         _check(_lib.ckks_batch_run(self.handle, _stream(stream)), "ckks_batch_run")
 
@@ -526,6 +543,11 @@ class Boot:
         d.n_rot, d.rot_steps, d.rot_keys = len(steps), rs, rk
         d.hoist_moddown = 1 if hoist_moddown else 0
         d.input_gain = int(input_gain)
+        # the handle's device memory is a torch allocation (ckks_boot_bytes, then device_buffer)
+        nbytes = ctypes.c_size_t(0)
+        _check(_lib.ckks_boot_bytes(ctx.handle, ctypes.byref(d), ctypes.byref(nbytes)), "ckks_boot_bytes")
+        self._mem = torch.empty(((nbytes.value + 7) // 8,), dtype=torch.uint64, device=ctx.device)
+        d.device_buffer, d.device_buffer_bytes = self._mem.data_ptr(), self._mem.numel() * 8
         h = _vp()
         _check(_lib.ckks_boot_create(ctx.handle, ctypes.byref(d), ctypes.byref(h)), "ckks_boot_create")
         self.handle = h
@@ -562,6 +584,10 @@ class Boot:
         if getattr(self, "handle", None):
             _destroy(self.handle)
             self.handle = None
+            if getattr(self, "_mem", None) is not None:
+                # the handle's internal streams may still use the memory: wait before torch reuses it
+                torch.cuda.synchronize(self._mem.device)
+                self._mem = None
 
     def __del__(self):
         self.close()

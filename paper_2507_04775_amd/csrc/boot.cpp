@@ -135,6 +135,7 @@ struct Ct {
 
 struct ckks_boot {
     ckks_ctx *ctx = nullptr;
+    bool owns_dev = false;  // dev was allocated by the handle (else it is the caller's buffer)
     uint32_t L = 0, n = 0, N = 0;
     std::vector<Group> cts, stc;
     uint32_t degree = 0, double_angles = 0, evalmod_in = 0, out_level = 0, keyswitches = 0;
@@ -780,7 +781,9 @@ uint32_t keyswitches_of(const ckks_boot &b)
 
 }  // namespace
 
-extern "C" ckks_status ckks_boot_create(ckks_ctx *ctx, const ckks_boot_desc *desc, ckks_boot **out)
+// Builds a handle; with size_only, stops once the device bytes are known and
+// stores them there (nothing is allocated or uploaded).
+static ckks_status boot_create(ckks_ctx *ctx, const ckks_boot_desc *desc, ckks_boot **out, size_t *size_only)
 {
     if (!ctx || !desc || !out) return fail(CKKS_E_ARG, "ckks_boot_create: null argument");
     *out = nullptr;
@@ -963,15 +966,34 @@ extern "C" ckks_status ckks_boot_create(ckks_ctx *ctx, const ckks_boot_desc *des
     const size_t off_cst = up(pt_words * 8);
     const size_t off_mono = off_cst + up(std::max<size_t>(cst.size(), 1) * 8),
                  off_slots = off_mono + up((size_t)(L + 1) * N * 8);
+    // the lanes' workspaces double as the staging buffer of the plaintext upload below
+    size_t max_count = 0;
+    for (const auto *gs : {&b->cts, &b->stc})
+        for (const Group &g : *gs) max_count = std::max(max_count, (size_t)g.lay.count);
+    wsb = std::max(wsb, (max_count * N * sizeof(double) + kLanes - 1) / kLanes);
     const size_t off_ws = off_slots + up(b->nslots * b->slot_words * 8);
     b->qp_words = b->hoist ? 2 * (size_t)(L + 1 + ctx->np) * N : 0;
     const size_t off_qp = off_ws + kLanes * up(wsb);
     b->ws_bytes = up(wsb);
     b->bytes = off_qp + kLanes * b->qp_words * 8;
-    if (hipSetDevice(ctx->device) != hipSuccess || hipMalloc(&b->dev, b->bytes) != hipSuccess) {
-        b->dev = nullptr;
-        return bail(CKKS_E_NOMEM, "device allocation of " + std::to_string(b->bytes) + " bytes failed");
+    if (size_only) {
+        *size_only = b->bytes;
+        ckks_boot_destroy(b);
+        return CKKS_OK;
     }
+    if (desc->device_buffer) {
+        if (((uintptr_t)desc->device_buffer & 255) || desc->device_buffer_bytes < b->bytes)
+            return bail(CKKS_E_ARG, "device_buffer must be 256-byte aligned and hold " + std::to_string(b->bytes) +
+                                        " bytes (ckks_boot_bytes)");
+        b->dev = desc->device_buffer;
+    } else {
+        if (hipSetDevice(ctx->device) != hipSuccess || hipMalloc(&b->dev, b->bytes) != hipSuccess) {
+            b->dev = nullptr;
+            return bail(CKKS_E_NOMEM, "device allocation of " + std::to_string(b->bytes) + " bytes failed");
+        }
+        b->owns_dev = true;
+    }
+    if (hipSetDevice(ctx->device) != hipSuccess) return bail(CKKS_E_DEVICE, "hipSetDevice failed");
     uint8_t *base = (uint8_t *)b->dev;
     b->mono = (uint64_t *)(base + off_mono);
     b->leaf_cst = (uint64_t *)(base + off_cst);
@@ -995,13 +1017,9 @@ extern "C" ckks_status ckks_boot_create(ckks_ctx *ctx, const ckks_boot_desc *des
             return bail(CKKS_E_DEVICE, "event creation failed");
         }
 
-    // plaintexts: integer-valued doubles -> residues -> evaluation domain
-    size_t max_count = 0;
-    for (const auto *gs : {&b->cts, &b->stc})
-        for (const Group &g : *gs) max_count = std::max(max_count, (size_t)g.lay.count);
-    double *stage_buf = nullptr;
-    if (hipMalloc(&stage_buf, max_count * N * sizeof(double)) != hipSuccess)
-        return bail(CKKS_E_NOMEM, "staging allocation failed");
+    // plaintexts: integer-valued doubles -> residues -> evaluation domain, staged in the
+    // lanes' workspaces (unused until the first run)
+    double *stage_buf = (double *)(base + off_ws);
     uint64_t *pt = (uint64_t *)base;
     hipError_t e = hipSuccess;
     std::vector<double> host;
@@ -1017,10 +1035,8 @@ extern "C" ckks_status ckks_boot_create(ckks_ctx *ctx, const ckks_boot_desc *des
             const size_t words = (size_t)g.lay.count * N;
             host.assign(diags[i], diags[i] + words);
             for (double v : host)
-                if (!(v == floor(v)) || fabs(v) > 1e300) {
-                    (void)hipFree(stage_buf);
+                if (!(v == floor(v)) || fabs(v) > 1e300)
                     return bail(CKKS_E_ARG, "plaintext coefficients must be finite integers");
-                }
             g.pt = pt;
             e = hipMemcpy(stage_buf, host.data(), words * sizeof(double), hipMemcpyHostToDevice);
             if (e == hipSuccess) e = launch_reduce_f64(stage_buf, g.pt, ctx->d_primes, g.lay.count, g.level + 1, logn, 0);
@@ -1038,7 +1054,6 @@ extern "C" ckks_status ckks_boot_create(ckks_ctx *ctx, const ckks_boot_desc *des
             pt += (size_t)g.lay.count * (g.level + 1) * N;
         }
     }
-    (void)hipFree(stage_buf);
     if (e == hipSuccess && !cst.empty())
         e = hipMemcpy(b->leaf_cst, cst.data(), cst.size() * 8, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = launch_half_monomial(b->mono, L + 1, logn, 0);
@@ -1054,6 +1069,19 @@ extern "C" ckks_status ckks_boot_create(ckks_ctx *ctx, const ckks_boot_desc *des
     if (e != hipSuccess) return bail(CKKS_E_DEVICE, std::string("plaintext upload: ") + hipGetErrorString(e));
     *out = b;
     return CKKS_OK;
+}
+
+extern "C" ckks_status ckks_boot_create(ckks_ctx *ctx, const ckks_boot_desc *desc, ckks_boot **out)
+{
+    return boot_create(ctx, desc, out, nullptr);
+}
+
+extern "C" ckks_status ckks_boot_bytes(ckks_ctx *ctx, const ckks_boot_desc *desc, size_t *bytes)
+{
+    if (!bytes) return fail(CKKS_E_ARG, "ckks_boot_bytes: null output");
+    *bytes = 0;
+    ckks_boot *unused = nullptr;
+    return boot_create(ctx, desc, &unused, bytes);
 }
 
 extern "C" uint32_t ckks_boot_output_level(const ckks_boot *b) { return b ? b->out_level : 0; }
@@ -1142,6 +1170,6 @@ extern "C" void ckks_boot_destroy(ckks_boot *b)
         if (ev) (void)hipEventDestroy(ev);
     for (uint32_t l = 1; l < kLanes; ++l)
         if (b->lanes[l].aux) (void)hipStreamDestroy(b->lanes[l].aux);
-    if (b->dev) (void)hipFree(b->dev);
+    if (b->dev && b->owns_dev) (void)hipFree(b->dev);
     delete b;
 }

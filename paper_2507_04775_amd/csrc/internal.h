@@ -193,6 +193,58 @@ __device__ __forceinline__ void run_work_queue_uniform(const Args *insts, const 
     }
 }
 
+// The steps of a batch of key switches, in the order of their dependencies
+// (one persistent launch each, or one unit kind each of the one-launch batch
+// kernel).
+enum BatchStep {
+    QI_TENSOR = 0,
+    QI_UP_INTT0_PLAIN,
+    QI_UP_INTT0_GALOIS,
+    QI_UP_INTT1,
+    QI_UP_BCONV,
+    QI_UP_NTT0,
+    QI_UP_NTT1,
+    QI_IP,
+    QI_DN_INTT0,
+    QI_DN_INTT1,
+    QI_DN_NTT0,
+    QI_DN_NTT1,
+    QI_COUNT
+};
+
+// One unit of the one-launch batch kernel: tile `tile` of limb (record)
+// `limb` of instance `inst` of step `step`, which starts once every unit of
+// group `wait` is done and counts itself done in group `signal`.  A group is
+// the set of units of one step of one key switch (one instance).  Units are
+// listed in an order in which every group comes after the group it waits
+// for, and claimed in that order, so the wait of the earliest unfinished unit
+// is always satisfied and the launch cannot deadlock.
+constexpr uint32_t kNoGroup = 0xFFFFFFFFu;
+struct BconvArgs;
+struct IpArgs;
+struct TensorArgs;
+struct FusedUnit {
+    uint32_t inst;
+    uint32_t code;              // limb | tile << 16 | step << 28
+    uint32_t wait;              // group to wait for, or kNoGroup
+    uint32_t signal;            // group of this unit
+};
+static_assert(sizeof(FusedUnit) == 16, "a fused unit is four words");
+
+struct FusedArgs {
+    const FusedUnit *units;
+    const uint32_t *target;     // per group: its number of units
+    uint32_t *claim;            // next unit to claim; zero at launch
+    uint32_t *done;             // per group g: units done, at done[g * done_stride]; zero at launch
+    uint32_t *fault;            // set to 1 when a wait gave up (spin_limit polls)
+    uint32_t nunits, spin_limit, done_stride;
+    uint32_t publish_every;     // completions are published after at most this many groups (1..32)
+    const NttArgs *ntt[4];      // ModUp INTT, ModUp NTT, ModDown INTT, ModDown NTT instances
+    const BconvArgs *bconv;
+    const IpArgs *ip;
+    const TensorArgs *tensor;
+};
+
 enum NttStage {
     STAGE_FWD_PLAIN = 0,
     STAGE_FWD_MODDOWN,
@@ -316,6 +368,8 @@ hipError_t launch_bconv_queue(const BconvArgs *insts, const WorkQueue &q, uint32
 hipError_t launch_inner_product_queue(const IpArgs *insts, const WorkQueue &q, uint32_t grid, hipStream_t stream);
 hipError_t launch_tensor_queue(const TensorArgs *insts, const WorkQueue &q, uint32_t grid, hipStream_t stream);
 hipError_t launch_zero_u32(uint32_t *p, uint32_t n, hipStream_t stream);
+// The one-launch batch kernel (N = 2^16 only): `grid` workgroups of 512 threads.
+hipError_t launch_fused_batch(const FusedArgs &f, uint32_t grid, hipStream_t stream);
 hipError_t launch_inner_product(const IpArgs &a, hipStream_t stream);
 hipError_t launch_tensor(const uint64_t *a0, const uint64_t *a1, const uint64_t *b0, const uint64_t *b1,
                          uint64_t *d0, uint64_t *d1, uint64_t *d2, const Prime *primes, uint32_t nlimbs,

@@ -30,6 +30,7 @@
 // Outputs of every transform are canonical.
 #include <atomic>
 
+#include "coef_units.h"
 #include "internal.h"
 #include "unit_map.h"
 
@@ -997,6 +998,192 @@ NTT_KERNELS(inv12_galois, kLds12, inv12_unit<PRO_GALOIS>, kThreads, false)
 #undef FWD12_BM
 #undef NTT_KERNELS
 
+// ------------------------------------------- one launch for a whole batch
+// The persistent kernel of a batch of key switches in one launch (N = 2^16):
+// every step of every key switch is a group of units in one list, and a unit
+// starts once the group it depends on (the previous step of the same key
+// switch) is done, so the steps of different key switches overlap instead of
+// meeting at eleven launch boundaries.  Dependencies go through per-group
+// counters: a unit's stores are complete in every wave before the workgroup
+// counts it done with an agent-scope release, and a waiting workgroup
+// acquires at agent scope before it reads, which makes the data of other
+// workgroups, on any XCD, visible.  The coefficient-wise steps run their
+// 256-thread units on the two halves of the 512-thread workgroup, each half
+// taking eight of the unit's sixteen 256-coefficient blocks.
+//
+constexpr uint32_t kFusedIpStage = 2 * coef::kIpStage * coef::kCoefThreads;
+constexpr int kFusedLds = kLds16 > (int)kFusedIpStage ? kLds16 : (int)kFusedIpStage;
+static_assert(kQueueBlocks % 2 == 0, "the two halves take half of a unit's blocks each");
+
+__shared__ uint64_t g_fused_lds[kFusedLds];
+__shared__ BconvArgs g_fused_bc;
+
+// Completions a workgroup has not yet published: up to f.publish_every
+// (at most kFusedPending) groups with their unit counts, kept by thread 0.
+// Publishing costs one agent-scope release (a write-back of the XCD's L2), so
+// it is done for several units at once: when publish_every groups are
+// pending, before the workgroup blocks on a wait, and when it runs out of
+// units.  A workgroup that blocks has published everything it finished, so
+// the earliest unfinished unit can always proceed, and a workgroup that does
+// not block publishes within publish_every units.
+constexpr uint32_t kFusedPending = 32;
+constexpr uint32_t kFusedSeen = 4;
+struct Pending {
+    uint32_t group[kFusedPending], count[kFusedPending], n;
+    // groups this workgroup has seen complete (and acquired after): a later unit waiting for one of
+    // them needs neither a poll nor another acquire, since a complete group's data no longer changes
+    uint32_t seen[kFusedSeen], seen_next;
+};
+
+__device__ __forceinline__ void fused_publish(const FusedArgs &f, Pending &p)
+{
+    if (p.n == 0) return;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    for (uint32_t i = 0; i < p.n; ++i)
+        __hip_atomic_fetch_add(f.done + (size_t)p.group[i] * f.done_stride, p.count[i], __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    p.n = 0;
+}
+
+__device__ __forceinline__ void fused_finished(const FusedArgs &f, Pending &p, uint32_t g)
+{
+    for (uint32_t i = 0; i < p.n; ++i)
+        if (p.group[i] == g) {
+            ++p.count[i];
+            return;
+        }
+    p.group[p.n] = g;
+    p.count[p.n] = 1;
+    if (++p.n >= f.publish_every) fused_publish(f, p);
+}
+
+// Waits (thread 0 only) until every unit of group g is done, publishing the
+// workgroup's own completions first if it has to wait; gives up after
+// spin_limit polls and raises the fault flag, so that the launch always ends.
+__device__ __forceinline__ void fused_wait(const FusedArgs &f, Pending &p, uint32_t g)
+{
+    for (uint32_t i = 0; i < kFusedSeen; ++i)
+        if (p.seen[i] == g) return;
+    const uint32_t want = f.target[g];
+    const uint32_t *cnt = f.done + (size_t)g * f.done_stride;
+    if (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < want) {
+        fused_publish(f, p);
+        uint32_t polls = 0;
+        while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < want) {
+            if (++polls > f.spin_limit) {
+                __hip_atomic_store(f.fault, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    p.seen[p.seen_next] = g;
+    p.seen_next = (p.seen_next + 1) % kFusedSeen;
+}
+
+template <class Args>
+__device__ __forceinline__ Args uniform_args(const Args *base, uint32_t inst)
+{
+    typedef const __attribute__((address_space(4))) uint32_t ConstWord;
+    static_assert(sizeof(Args) % 4 == 0, "argument blocks are read as 4-byte words");
+    ConstWord *src = (ConstWord *)((uintptr_t)base + (uintptr_t)inst * sizeof(Args));
+    Args a;
+#pragma unroll
+    for (uint32_t i = 0; i < sizeof(Args) / 4; ++i) ((uint32_t *)&a)[i] = src[i];
+    return a;
+}
+
+// The argument block of the unit's step: the pointer passes through an empty
+// asm statement, so that the scalar loads of one step's block are not
+// hoisted above the switch (speculated for every step, the blocks of all
+// steps would be live at once).
+template <class Args>
+__device__ __forceinline__ Args step_args(const Args *base, uint32_t inst)
+{
+    uint64_t p = (uint64_t)(uintptr_t)base;
+    asm volatile("" : "+s"(p));
+    return uniform_args((const Args *)(uintptr_t)p, inst);
+}
+
+__global__ __launch_bounds__(kThreads16) __attribute__((amdgpu_waves_per_eu(4))) void q_fused16(FusedArgs f)
+{
+    typedef const __attribute__((address_space(4))) uint32_t ConstWord;
+    __shared__ uint32_t claim;
+    __shared__ Pending pend;  // thread 0's
+    if (threadIdx.x == 0) {
+        claim = atomicAdd(f.claim, 1u);
+        pend.n = 0;
+        for (uint32_t i = 0; i < kFusedSeen; ++i) pend.seen[i] = kNoGroup;
+        pend.seen_next = 0;
+    }
+    __syncthreads();
+    uint32_t u = __builtin_amdgcn_readfirstlane(claim);
+    uint32_t have_bc = 0xFFFFFFFFu;
+    while (u < f.nunits) {
+        ConstWord *w = (ConstWord *)((uintptr_t)f.units + (uintptr_t)u * sizeof(FusedUnit));
+        const uint32_t inst = __builtin_amdgcn_readfirstlane(w[0]);
+        const uint32_t code = __builtin_amdgcn_readfirstlane(w[1]);
+        const uint32_t wait = __builtin_amdgcn_readfirstlane(w[2]);
+        const uint32_t signal = __builtin_amdgcn_readfirstlane(w[3]);
+        __syncthreads();  // every thread has read claim and is done with the previous unit's LDS
+        if (threadIdx.x == 0) claim = atomicAdd(f.claim, 1u);
+        if (wait != kNoGroup) {
+            if (threadIdx.x == 0) fused_wait(f, pend, wait);
+            __syncthreads();
+        }
+        const uint32_t step = code >> 28, tile = (code >> 16) & 0xFFFu, limb = code & 0xFFFFu;
+        // the thread index is taken anew for every unit: offsets derived from it and hoisted out of
+        // the loop would stay live across every step's body
+        const uint32_t tx = thread_index();
+        switch (step) {
+        case QI_TENSOR: {
+            const TensorArgs a = step_args(f.tensor, inst);
+            for (uint32_t i = tx / coef::kCoefThreads; i < kQueueBlocks; i += 2)
+                coef::tensor_unit(a, limb, tile * kQueueBlocks + i, tx % coef::kCoefThreads);
+            break;
+        }
+        case QI_UP_INTT0_PLAIN: inv_row_unit<PRO_PLAIN>(step_args(f.ntt[0], inst), limb, tile, g_fused_lds, tx); break;
+        case QI_UP_INTT0_GALOIS: inv_row_unit<PRO_GALOIS>(step_args(f.ntt[0], inst), limb, tile, g_fused_lds, tx); break;
+        case QI_UP_INTT1: inv_col_unit(step_args(f.ntt[0], inst), limb, tile, g_fused_lds, tx); break;
+        case QI_UP_BCONV: {
+            if (inst != have_bc) {  // its job fields are indexed per thread: the block goes through LDS
+                const uint64_t *src = (const uint64_t *)(f.bconv + inst);
+                uint64_t *dst = (uint64_t *)&g_fused_bc;
+                for (uint32_t i = threadIdx.x; i < sizeof(BconvArgs) / 8; i += blockDim.x) dst[i] = src[i];
+                have_bc = inst;
+                __syncthreads();
+            }
+            const uint32_t nb = g_fused_bc.N / (coef::kCoefThreads * kQueueBlocks);
+            for (uint32_t i = tx / coef::kCoefThreads; i < kQueueBlocks; i += 2)
+                coef::bconv_unit(g_fused_bc, limb, (tile % nb) * kQueueBlocks + i, tile / nb, tx % coef::kCoefThreads);
+            break;
+        }
+        case QI_UP_NTT0: fwd_col_unit<PRO_PLAIN>(step_args(f.ntt[1], inst), limb, tile, g_fused_lds, tx); break;
+        case QI_UP_NTT1: fwd_row_unit<EPI_PLAIN>(step_args(f.ntt[1], inst), limb, tile, g_fused_lds, tx); break;
+        case QI_IP: {
+            const uint32_t half = tx / coef::kCoefThreads;
+            coef::ip_blocks(step_args(f.ip, inst), limb, tile * kQueueBlocks + half * (kQueueBlocks / 2),
+                            kQueueBlocks / 2, g_fused_lds + half * coef::kIpStage * coef::kCoefThreads,
+                            tx % coef::kCoefThreads);
+            break;
+        }
+        case QI_DN_INTT0: inv_row_unit<PRO_PLAIN>(step_args(f.ntt[2], inst), limb, tile, g_fused_lds, tx); break;
+        case QI_DN_INTT1: inv_col_unit(step_args(f.ntt[2], inst), limb, tile, g_fused_lds, tx); break;
+        case QI_DN_NTT0: fwd_col_unit<PRO_BCONV>(step_args(f.ntt[3], inst), limb, tile, g_fused_lds, tx); break;
+        case QI_DN_NTT1: fwd_row_unit<EPI_MODDOWN>(step_args(f.ntt[3], inst), limb, tile, g_fused_lds, tx); break;
+        default: break;
+        }
+        // the barrier does not wait for global stores: every wave waits for its own first, so
+        // the unit's stores are complete before thread 0 records (and later publishes) it
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+        __syncthreads();
+        if (threadIdx.x == 0) fused_finished(f, pend, signal);
+        u = __builtin_amdgcn_readfirstlane(claim);
+    }
+    if (threadIdx.x == 0) fused_publish(f, pend);
+}
+
 typedef void (*GridKernel)(NttArgs);
 typedef void (*QueueKernel)(const NttArgs *, WorkQueue);
 
@@ -1134,6 +1321,13 @@ hipError_t launch_ntt_stage_queue(NttStage st, uint32_t logn, uint32_t pass, con
     StageKernels k;
     if (!stage_kernels(st, logn, pass, k)) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k.queue, dim3(grid), dim3(ntt_threads(logn)), 0, stream, insts, q);
+    return hipGetLastError();
+}
+
+hipError_t launch_fused_batch(const FusedArgs &f, uint32_t grid, hipStream_t stream)
+{
+    if (f.nunits == 0) return hipSuccess;
+    hipLaunchKernelGGL(q_fused16, dim3(grid), dim3(kThreads16), 0, stream, f);
     return hipGetLastError();
 }
 

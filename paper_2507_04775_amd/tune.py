@@ -1,12 +1,15 @@
 """Autotuner of the library's launch shapes, with a cache.
 
-Two choices are measured on the GPU and kept:
+Three choices are measured on the GPU and kept:
 - the NTT tile width (16, 8 or 4 columns or rows per workgroup, 512, 256 or
   128 threads) of every N = 2^16 NTT grid launch, per direction and number of
   limbs in the launch (the paper's limb-batch knob, Sec. III-F.1: how much of
   a transform one block takes);
 - the persistent grid (workgroups per CU) of each step of a batch of key
-  switches, per batch (ckks_batch_tune).
+  switches, per batch (ckks_batch_tune);
+- the fusion depth of a batch (ckks_batch_set_schedule): one persistent
+  launch per step, or the whole batch in one launch with its key switches
+  pipelined in windows of 1 to n items, at one or two workgroups per CU.
 
 Each candidate is timed as the median of several bursts of launches on
 rotating buffers larger than the last-level cache.  Results are kept in a JSON
@@ -216,3 +219,44 @@ def tune_batch(batch: ckks.Batch, ctx: ckks.Context, signature: str, stream, cac
     grid = [batch.grid(i) for i in range(ckks.Batch.steps())]
     cache[key] = {"grid": grid}
     return grid
+
+
+def schedule_candidates(n_items: int, logn: int):
+    """(window, workgroups per CU) pairs tried by tune_batch_schedule: per-step
+    launches (window 0), then one launch at windows of 1, 2, 4, ... items up to
+    the whole batch, at two workgroups per CU, and the best-guess window at one."""
+    if logn != 16:
+        return [(0, 2)]
+    ws, w = [], 1
+    while w < n_items:
+        ws.append(w)
+        w *= 2
+    ws.append(n_items)
+    return [(0, 2)] + [(w, 2) for w in ws] + [(8 if n_items > 8 else n_items, 1)]
+
+
+def tune_batch_schedule(batch: ckks.Batch, ctx: ckks.Context, signature: str, n_items: int, stream,
+                        cache: Optional[dict] = None, use_cache: bool = True, samples: int = 3) -> dict:
+    """Schedule of a batch (after tune_batch has set the per-step grids): each
+    candidate of schedule_candidates runs the batch once to warm up, then
+    `samples` times; the one with the smallest median time is applied and
+    recorded.  Returns {"window", "wg", "ms": {candidate: median ms}}."""
+    cache = {} if cache is None else cache
+    key = _key(ctx.logn, ctx.nq, ctx.np, "schedule:" + signature, arch())
+    if use_cache and key in cache:
+        rec = cache[key]
+        batch.set_schedule(int(rec["window"]), int(rec["wg"]))
+        return rec
+    times = {}
+    for window, wg in schedule_candidates(n_items, ctx.logn):
+        batch.set_schedule(window, wg)
+        batch.run(stream)
+        batch.faults(stream)
+        xs = [_burst_ms(lambda: batch.run(stream), stream, 1) for _ in range(samples)]
+        batch.faults(stream)
+        times[(window, wg)] = statistics.median(xs)
+    best = min(times, key=times.get)
+    batch.set_schedule(*best)
+    rec = {"window": best[0], "wg": best[1], "ms": {"%d/%d" % k: round(v, 3) for k, v in times.items()}}
+    cache[key] = rec
+    return rec

@@ -46,3 +46,31 @@ def test_cached_batch_grid_is_applied_without_measuring(monkeypatch):
     b = _FakeBatch()
     assert tune.tune_batch(b, _Ctx(), sig, None, cache) == [3, 2, 4]
     assert b.grids == {0: 3, 1: 2, 2: 4} and not b.tuned
+
+
+class _FakeSchedBatch:
+    def __init__(self):
+        self.set = None
+
+    def set_schedule(self, window, wg):
+        self.set = (window, wg)
+
+    def run(self, stream=None):
+        raise AssertionError("a cached schedule must not be measured")
+
+
+def test_schedule_candidates_cover_steps_and_windows():
+    c = tune.schedule_candidates(128, 16)
+    assert c[0] == (0, 2) and (1, 2) in c and (128, 2) in c and (8, 1) in c
+    windows = [w for w, g in c if g == 2 and w]
+    assert windows == sorted(windows) and all(w & (w - 1) == 0 for w in windows[:-1])
+    assert tune.schedule_candidates(16, 12) == [(0, 2)]  # one launch is N = 2^16 only
+
+
+def test_cached_schedule_is_applied_without_measuring(monkeypatch):
+    monkeypatch.setattr(tune, "arch", lambda: "gfx950")
+    sig = tune.batch_signature([("hmult", 30), ("hoisted", 12)])
+    cache = {tune._key(16, 31, 4, "schedule:" + sig, "gfx950"): {"window": 8, "wg": 2, "ms": {}}}
+    b = _FakeSchedBatch()
+    assert tune.tune_batch_schedule(b, _Ctx(), sig, 2, None, cache)["window"] == 8
+    assert b.set == (8, 2)
