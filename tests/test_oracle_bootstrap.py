@@ -333,3 +333,18 @@ def test_hoisted_coeff_to_slot_and_bootstrap(boot_small):
     out = ex.bootstrap(ct)
     err = max_err_bits(cs.decrypt((out[0], out[1]), out[2], ex.sc[out[2]]), z)
     assert out[2] == 1 and err < -9.5, err
+
+
+def test_error_budget_phases_at_n_2_12():
+    """The phase-by-phase error budget (oracle.error_budget) at N = 2^12 with
+    encapsulation: |I| inside K, CoeffToSlot far below EvalMod, EvalMod below
+    the final error, and the final error within the bootstrap test's bound."""
+    import re
+
+    from oracle import error_budget
+    rows = dict(error_budget.run(logn=12, uniform=False, verbose=False))
+    I, K = map(float, re.findall(r"= ([0-9.]+)", rows["ModRaise"]))
+    assert I < K
+    bits = {k: float(re.search(r"2\^(-[0-9.]+)", v).group(1)) for k, v in rows.items() if k != "ModRaise"}
+    assert bits["CoeffToSlot"] < bits["EvalMod re"] - 5 and bits["CoeffToSlot"] < bits["EvalMod im"] - 5
+    assert max(bits["EvalMod re"], bits["EvalMod im"]) < bits["SlotToCoeff"] < -14
