@@ -51,6 +51,7 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 256 MiB device copy (the reference kernel for HBM counter scaling)")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-w32", action="store_true", help="skip the 32-bit word path")
     ap.add_argument("--serve-requests", type=int, default=500)
     ap.add_argument("--serve-loads", type=str, default="0.25,0.5,0.75,0.9,1.0,1.1")
     ap.add_argument("--serve-boot-handles", type=int, default=2)
@@ -517,6 +518,81 @@ def run_bootstrap(seed, args, sparse=True):
     return res
 
 
+def run_w32(seed, args):
+    """The 32-bit word path at N = 2^16 on 52 + 8 primes of 30 bits (dnum 4; the
+    64-bit "large" set's 1560-bit Q and 240-bit P): the same step (HMult+relin,
+    Rescale, rotation at the top level) and its NTTs, with per-operation
+    latencies."""
+    import torch
+
+    from paper_2507_04775_amd import ckks, inputs
+    ps = inputs.params32("w32-large")
+    ctx = ckks.Context32(ps.logn, ps.q, ps.p, ps.dnum)
+    level = ps.L
+    stream = torch.cuda.current_stream()
+    dev = lambda a: ckks.to_device32(a)
+    a = [dev(x) for x in inputs.random_ct(seed, ps, level)]
+    b = [dev(x) for x in inputs.random_ct(seed + 1, ps, level)]
+    key = inputs.random_key(seed + 2, ps)
+    rlk = dev(key.reshape(-1, ps.N)).reshape(key.shape)
+    key = inputs.random_key(seed + 3, ps)
+    rk = dev(key.reshape(-1, ps.N)).reshape(key.shape)
+    g = pow(5, inputs.rotation_index(seed, ps.logn), 2 * ps.N)
+    m0, m1, r0, r1, o0, o1 = [ctx.empty(level + 1) for _ in range(6)]
+    ws_h, ws_r, ws_g = (ctx.workspace(op, level) for op in (ckks.OP_HMULT, ckks.OP_RESCALE, ckks.OP_ROTATE))
+
+    def hmult():
+        ctx.hmult_relin(a[0], a[1], b[0], b[1], level, rlk, m0, m1, ws_h)
+
+    def rescale():
+        ctx.rescale(m0, m1, level, r0[:level], r1[:level], ws_r)
+
+    def rotate():
+        ctx.apply_galois(a[0], a[1], level, g, rk, o0, o1, ws_g)
+
+    def step():
+        hmult()
+        rescale()
+        rotate()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    n = max(20, args.steps)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(n):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / n
+    nmods = ps.L + 1 + ps.K
+    ring = [ctx.empty(nmods) for _ in range(8)]  # 8 x 15.7 MB
+    for t in ring:
+        t.copy_(dev(inputs.uniform_residues(inputs.rng(seed + 9), list(ps.q) + list(ps.p), ps.N)))
+    turn = [0]
+
+    def ntt_next(inverse):
+        t = ring[turn[0] % len(ring)]
+        turn[0] += 1
+        (ctx.intt if inverse else ctx.ntt)(t, 0, nmods, stream)
+
+    def stats(fn, reps):
+        xs = timed_launches(fn, reps, stream)
+        return {"p50_us": round(percentile(xs, 50) * 1e3, 2), "p99_us": round(percentile(xs, 99) * 1e3, 2)}
+
+    ops = {"hmult_relin": stats(hmult, n), "rescale": stats(rescale, n), "rotate": stats(rotate, n),
+           "ntt_%d_limbs" % nmods: stats(lambda: ntt_next(False), n),
+           "intt_%d_limbs" % nmods: stats(lambda: ntt_next(True), n)}
+    nb = (ps.L + 1) * ps.N * 4
+    res = {"workload": "HMult+relin + Rescale + rotation at level %d, 32-bit words" % level,
+           "logN": ps.logn, "limbs": ps.L + 1, "special_primes": ps.K, "dnum": ps.dnum, "prime_bits": 30,
+           "ms_per_step": round(ms, 4), "key_switches_per_s": round(2 / (ms / 1e3), 1),
+           "ciphertext_bytes": 2 * nb, "ops": ops}
+    ctx.close()
+    return res
+
+
 def run_serving(ctx, ps, seed, args):
     """Served requests (op chains at levels 10..30, 10 % ending in a bootstrap)
     through the continuous-batching server: saturation throughput with every
@@ -829,6 +905,9 @@ def main():
         if not args.no_uniform_boot:
             boot_dense = run_bootstrap(seed + 600, args, sparse=False)
 
+    # ---- the 32-bit word path on the same modulus budget
+    w32 = None if args.no_w32 else run_w32(seed + 800, args)
+
     # ---- served request chains with continuous batching
     serving = None
     if not args.no_serve:
@@ -863,6 +942,7 @@ def main():
         "bootstrap": boot,
         "bootstrap_uniform_secret": boot_dense,
         "serving": serving,
+        "words32": w32,
         "ops": ops,
         "ptmult_rescale_us_by_level": ptmult_rescale,
         "hmult_relin_us_by_level": hmult_by_level,

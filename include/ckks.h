@@ -485,6 +485,52 @@ ckks_status ckks_boot_replay(ckks_boot *boot, void *stream);
 void ckks_boot_destroy(ckks_boot *boot);
 
 /*
+ * 32-bit word limbs (Sec. III-C: the limb type is templated on the word size;
+ * the paper verifies only 64-bit words).  The key-switching path with every
+ * residue in a uint32_t: N = 2^16 (log_n must be 16), every prime below 2^30
+ * and congruent to 1 mod 2N, polynomials limb-major [limbs][N] u32 in the
+ * layouts of the 64-bit calls (evaluation domain in bit-reversed order,
+ * psi the smallest primitive 2N-th root; extended rows q_0..q_l, p_0..p_{K-1};
+ * keys [dnum][2][n_q+n_p][N] u32, passed as device pointers; digits as above).
+ * Every result equals the 64-bit definition of the same operation on the same
+ * primes.  A twiddle product is a 32-bit Shoup multiplication, butterflies
+ * are Harvey's lazy forms (below 4q < 2^32), and sums of products are exact
+ * 64-bit sums reduced once (Barrett).  Pointers: device, 16-byte aligned.
+ * Workspaces: ckks32_workspace_bytes(op, l) with op CKKS_OP_KEYSWITCH (also
+ * ModUp and ModDown), CKKS_OP_HMULT, CKKS_OP_ROTATE, CKKS_OP_RESCALE.  All
+ * calls are asynchronous on `stream`; errors as for the 64-bit calls.
+ *   ckks32_ntt / ckks32_intt: in place on limbs limb0 .. limb0+n_limbs-1 (at most 64).
+ *   ckks32_modup:   d [l+1] -> ext [beta][l+1+K] (each digit's own rows copied from d).
+ *   ckks32_moddown: x [2][l+1+K] -> out_t = P^-1 (x_t - Conv(x_t|P)) [l+1], with the
+ *                   centred conversion of ckks_moddown.
+ *   ckks32_keyswitch: (out0, out1) = ModDown(InnerProduct(ModUp(d), key)).
+ *   ckks32_hmult_relin: (a0 b0, a0 b1 + a1 b0) + KeySwitch(a1 b1, rlk); out may not alias inputs.
+ *   ckks32_apply_galois: (phi_g(c0), 0) + KeySwitch(phi_g(c1), key of g).
+ *   ckks32_rescale: out_t = q_l^-1 (c_t - NTT(SwitchModulo(INTT_{q_l}(c_t[l])))) at level l-1;
+ *                   out may equal c (in place).
+ */
+typedef struct ckks32_ctx ckks32_ctx;
+ckks_status ckks32_ctx_create(uint32_t log_n, const uint32_t *q, uint32_t n_q, const uint32_t *p, uint32_t n_p,
+                              uint32_t dnum, int hip_device, ckks32_ctx **out);
+void ckks32_ctx_destroy(ckks32_ctx *ctx);
+size_t ckks32_workspace_bytes(const ckks32_ctx *ctx, uint32_t op, uint32_t level);
+ckks_status ckks32_ntt(ckks32_ctx *ctx, uint32_t *poly, uint32_t limb0, uint32_t n_limbs, void *stream);
+ckks_status ckks32_intt(ckks32_ctx *ctx, uint32_t *poly, uint32_t limb0, uint32_t n_limbs, void *stream);
+ckks_status ckks32_modup(ckks32_ctx *ctx, const uint32_t *d, uint32_t level, uint32_t *ext, void *ws, void *stream);
+ckks_status ckks32_moddown(ckks32_ctx *ctx, const uint32_t *x, uint32_t level, uint32_t *out0, uint32_t *out1,
+                           void *ws, void *stream);
+ckks_status ckks32_keyswitch(ckks32_ctx *ctx, const uint32_t *d, uint32_t level, const uint32_t *key, uint32_t *out0,
+                             uint32_t *out1, void *ws, void *stream);
+ckks_status ckks32_hmult_relin(ckks32_ctx *ctx, const uint32_t *a0, const uint32_t *a1, const uint32_t *b0,
+                               const uint32_t *b1, uint32_t level, const uint32_t *rlk, uint32_t *out0, uint32_t *out1,
+                               void *ws, void *stream);
+ckks_status ckks32_apply_galois(ckks32_ctx *ctx, const uint32_t *c0, const uint32_t *c1, uint32_t level,
+                                uint32_t galois, const uint32_t *key, uint32_t *out0, uint32_t *out1, void *ws,
+                                void *stream);
+ckks_status ckks32_rescale(ckks32_ctx *ctx, const uint32_t *c0, const uint32_t *c1, uint32_t level, uint32_t *out0,
+                           uint32_t *out1, void *ws, void *stream);
+
+/*
  * Measurement probe (no CKKS operation): one launch of `blocks` workgroups of
  * 256 threads, each thread running 8 independent chains of `iters` dependent
  * 32x32->64 multiply-adds (v_mad_u64_u32), the instruction every 64-bit

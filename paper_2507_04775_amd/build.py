@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "libckks.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["context.cpp", "ks_args.cpp", "api.cpp", "batch.cpp", "boot.cpp", "ntt.hip",
-           "kernels.hip", "probe.hip", "noalloc.hip"]
+           "kernels.hip", "probe.hip", "noalloc.hip", "w32.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-ffp-contract=off", "-Wall", "-Wno-unused-result", "-Wno-unused-function"]

@@ -70,6 +70,18 @@ _sigs = {
     "ckks_keyswitch": (ctypes.c_int, [_vp, _vp, _u32, _vp, _vp, _vp, _vp, _vp]),
     "ckks_keyswitch_noalloc": (ctypes.c_int, [_vp, _vp, _u32, _vp, _vp, _vp, _vp]),
     "ckks_noalloc_scratch_bytes": (ctypes.c_size_t, []),
+    "ckks32_ctx_create": (ctypes.c_int, [_u32, ctypes.POINTER(_u32), _u32, ctypes.POINTER(_u32), _u32, _u32,
+                                         ctypes.c_int, ctypes.POINTER(_vp)]),
+    "ckks32_ctx_destroy": (None, [_vp]),
+    "ckks32_workspace_bytes": (ctypes.c_size_t, [_vp, _u32, _u32]),
+    "ckks32_ntt": (ctypes.c_int, [_vp, _vp, _u32, _u32, _vp]),
+    "ckks32_intt": (ctypes.c_int, [_vp, _vp, _u32, _u32, _vp]),
+    "ckks32_modup": (ctypes.c_int, [_vp, _vp, _u32, _vp, _vp, _vp]),
+    "ckks32_moddown": (ctypes.c_int, [_vp, _vp, _u32, _vp, _vp, _vp, _vp]),
+    "ckks32_keyswitch": (ctypes.c_int, [_vp, _vp, _u32, _vp, _vp, _vp, _vp, _vp]),
+    "ckks32_hmult_relin": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _u32, _vp, _vp, _vp, _vp, _vp]),
+    "ckks32_apply_galois": (ctypes.c_int, [_vp, _vp, _vp, _u32, _u32, _vp, _vp, _vp, _vp, _vp]),
+    "ckks32_rescale": (ctypes.c_int, [_vp, _vp, _vp, _u32, _vp, _vp, _vp, _vp]),
     "ckks_probe_mad64": (ctypes.c_int, [_vp, _u32, _u32, _vp, ctypes.POINTER(ctypes.c_uint64)]),
     "ckks_hmult_relin": (ctypes.c_int, [_vp, ctypes.POINTER(_Ct), ctypes.POINTER(_Ct), _vp, ctypes.POINTER(_Ct), _vp, _vp]),
     "ckks_rescale": (ctypes.c_int, [_vp, ctypes.POINTER(_Ct), ctypes.POINTER(_Ct), _vp, _vp]),
@@ -137,6 +149,13 @@ class CkksError(RuntimeError):
 def _check(status: int, where: str):
     if status != 0:
         raise CkksError(status, where)
+
+
+def _ptr32(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    assert t.dtype == torch.int32 and t.is_contiguous(), "expects contiguous tensors of 32-bit words (torch.int32)"
+    return ctypes.c_void_p(t.data_ptr())
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -591,6 +610,93 @@ class Boot:
 
     def __del__(self):
         self.close()
+
+
+class Context32:
+    """A context of the 32-bit word path (ckks32_* in include/ckks.h): N = 2^16,
+    every prime below 2^30.  Polynomials are [limbs][N] device tensors of
+    32-bit words, held as torch.int32 (to_device32 / to_host32 reinterpret them
+    as unsigned); keys are [dnum][2][n_q+n_p][N] such tensors."""
+
+    def __init__(self, logn: int, q: Sequence[int], p: Sequence[int], dnum: int, device: int = 0):
+        self.logn, self.N = logn, 1 << logn
+        self.q, self.p, self.dnum = [int(x) for x in q], [int(x) for x in p], dnum
+        self.nq, self.np = len(self.q), len(self.p)
+        self.alpha = -(-self.nq // dnum)
+        self.device = torch.device("cuda", device)
+        qa = (_u32 * self.nq)(*self.q)
+        pa = (_u32 * self.np)(*self.p)
+        h = _vp()
+        _check(_lib.ckks32_ctx_create(logn, qa, self.nq, pa, self.np, dnum, device, ctypes.byref(h)),
+               "ckks32_ctx_create")
+        self.handle = h
+
+    def beta(self, level: int) -> int:
+        return -(-(level + 1) // self.alpha)
+
+    def workspace(self, op: int, level: int) -> torch.Tensor:
+        need = int(_lib.ckks32_workspace_bytes(self.handle, op, level))
+        return torch.empty((need + 15) // 16 * 4, dtype=torch.int32, device=self.device)
+
+    def empty(self, *shape) -> torch.Tensor:
+        return torch.empty(shape + (self.N,), dtype=torch.int32, device=self.device)
+
+    def ntt(self, poly, limb0: int = 0, n_limbs: Optional[int] = None, stream=None):
+        n = poly.shape[0] if n_limbs is None else n_limbs
+        _check(_lib.ckks32_ntt(self.handle, _ptr32(poly), limb0, n, _stream(stream)), "ckks32_ntt")
+
+    def intt(self, poly, limb0: int = 0, n_limbs: Optional[int] = None, stream=None):
+        n = poly.shape[0] if n_limbs is None else n_limbs
+        _check(_lib.ckks32_intt(self.handle, _ptr32(poly), limb0, n, _stream(stream)), "ckks32_intt")
+
+    def modup(self, d, level: int, ext, ws=None, stream=None):
+        ws = self.workspace(OP_KEYSWITCH, level) if ws is None else ws
+        _check(_lib.ckks32_modup(self.handle, _ptr32(d), level, _ptr32(ext), _ptr32(ws), _stream(stream)), "ckks32_modup")
+
+    def moddown(self, x, level: int, out0, out1, ws=None, stream=None):
+        ws = self.workspace(OP_KEYSWITCH, level) if ws is None else ws
+        _check(_lib.ckks32_moddown(self.handle, _ptr32(x), level, _ptr32(out0), _ptr32(out1), _ptr32(ws), _stream(stream)),
+               "ckks32_moddown")
+
+    def keyswitch(self, d, level: int, key, out0, out1, ws=None, stream=None):
+        ws = self.workspace(OP_KEYSWITCH, level) if ws is None else ws
+        _check(_lib.ckks32_keyswitch(self.handle, _ptr32(d), level, _ptr32(key), _ptr32(out0), _ptr32(out1), _ptr32(ws),
+                                     _stream(stream)), "ckks32_keyswitch")
+
+    def hmult_relin(self, a0, a1, b0, b1, level: int, rlk, out0, out1, ws=None, stream=None):
+        ws = self.workspace(OP_HMULT, level) if ws is None else ws
+        _check(_lib.ckks32_hmult_relin(self.handle, _ptr32(a0), _ptr32(a1), _ptr32(b0), _ptr32(b1), level, _ptr32(rlk),
+                                       _ptr32(out0), _ptr32(out1), _ptr32(ws), _stream(stream)), "ckks32_hmult_relin")
+
+    def apply_galois(self, c0, c1, level: int, galois: int, key, out0, out1, ws=None, stream=None):
+        ws = self.workspace(OP_ROTATE, level) if ws is None else ws
+        _check(_lib.ckks32_apply_galois(self.handle, _ptr32(c0), _ptr32(c1), level, galois, _ptr32(key), _ptr32(out0),
+                                        _ptr32(out1), _ptr32(ws), _stream(stream)), "ckks32_apply_galois")
+
+    def rescale(self, c0, c1, level: int, out0, out1, ws=None, stream=None):
+        ws = self.workspace(OP_RESCALE, level) if ws is None else ws
+        _check(_lib.ckks32_rescale(self.handle, _ptr32(c0), _ptr32(c1), level, _ptr32(out0), _ptr32(out1), _ptr32(ws),
+                                   _stream(stream)), "ckks32_rescale")
+
+    def close(self, _destroy=_lib.ckks32_ctx_destroy):
+        if getattr(self, "handle", None):
+            _destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        self.close()
+
+
+def to_device32(a, device="cuda") -> torch.Tensor:
+    """numpy array of residues below 2^32 -> contiguous device tensor of 32-bit words (torch.int32)."""
+    import numpy as np
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(a, dtype=np.uint64).astype(np.uint32)).view(np.int32)).to(device)
+
+
+def to_host32(t: torch.Tensor):
+    """Device tensor of 32-bit words -> numpy uint64 residues."""
+    import numpy as np
+    return t.cpu().numpy().view(np.uint32).astype(np.uint64)
 
 
 def to_device(a, device="cuda") -> torch.Tensor:

@@ -22,10 +22,9 @@ ckks_status fail(ckks_status s, const std::string &msg)
 
 hipError_t scratch_setup(int device);  // noalloc.hip
 
-namespace {
-
 typedef unsigned __int128 wide;
 
+// Host modular arithmetic shared by the context builders (internal.h).
 uint64_t mul_mod(uint64_t a, uint64_t b, uint64_t m) { return (uint64_t)((wide)a * b % m); }
 
 uint64_t pow_mod(uint64_t base, uint64_t e, uint64_t m)
@@ -63,6 +62,8 @@ bool probably_prime(uint64_t n)
     return true;
 }
 
+namespace {
+
 uint64_t shoup_of(uint64_t w, uint64_t q) { return (uint64_t)(((wide)w << 64) / q); }
 
 ulonglong2 pair(uint64_t w, uint64_t q)
@@ -72,6 +73,8 @@ ulonglong2 pair(uint64_t w, uint64_t q)
     r.y = shoup_of(w, q);
     return r;
 }
+
+}  // namespace
 
 // Smallest primitive 2N-th root of unity modulo q: a candidate g^((q-1)/2N) of
 // order exactly 2N (its N-th power is -1) generates them all as its odd powers.
@@ -96,6 +99,8 @@ uint32_t reverse_bits(uint32_t x, uint32_t bits)
     for (uint32_t b = 0; b < bits; ++b, x >>= 1) r = (r << 1) | (x & 1);
     return r;
 }
+
+namespace {
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 

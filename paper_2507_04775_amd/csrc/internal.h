@@ -348,6 +348,14 @@ struct ScalarLincombArgs {
     uint32_t n, logn;
 };
 
+// Host modular arithmetic (context.cpp), for the context builders.
+uint64_t mul_mod(uint64_t a, uint64_t b, uint64_t m);
+uint64_t pow_mod(uint64_t base, uint64_t e, uint64_t m);
+uint64_t inv_mod(uint64_t a, uint64_t m);  // m prime
+bool probably_prime(uint64_t n);
+uint64_t smallest_2n_root(uint64_t q, uint64_t two_n);
+uint32_t reverse_bits(uint32_t x, uint32_t bits);
+
 // Launchers (all asynchronous on `stream`).
 hipError_t launch_ntt_fwd(const NttArgs &a, uint32_t nlimbs, NttPro pro, NttEpi epi, hipStream_t stream,
                           uint64_t *mid, int64_t mid_poly_stride);

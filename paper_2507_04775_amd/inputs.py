@@ -110,6 +110,21 @@ def make_params(logn: int, small_bits: int, L: int, K: int, dnum: int, log_scale
     return ParamSet(name=name, logn=logn, q=[big[0]] + small, p=big[1:], dnum=dnum, log_scale=log_scale)
 
 
+def params32(name: str) -> ParamSet:
+    """Parameter sets of the 32-bit word path (N = 2^16, every prime a 30-bit
+    NTT prime, q_0.. first, then p_0..): "w32-small" 10 + 3 primes, dnum 3
+    (digits of 4, 4, 2); "w32-large" 52 + 8 primes, dnum 4 (digits of 13), a
+    1560-bit Q and 240-bit P like the 64-bit "large" set."""
+    if name == "w32-small":
+        nq, K, dnum = 10, 3, 3
+    elif name == "w32-large":
+        nq, K, dnum = 52, 8, 4
+    else:
+        raise KeyError(name)
+    pr = ntt_primes(30, nq + K, 16)
+    return ParamSet(name=name, logn=16, q=pr[:nq], p=pr[nq:], dnum=dnum, log_scale=26)
+
+
 def params(name: str) -> ParamSet:
     if name == "small":
         return make_params(12, 40, 3, 1, 2, 40, name)

@@ -83,3 +83,15 @@ def test_null_context_is_rejected(lib):
         assert f(None, None, 0, 1, None) == -1
     lib.ckks_workspace_bytes.restype = ctypes.c_size_t
     assert lib.ckks_workspace_bytes(None, 3, 0) == 0
+
+
+def test_w32_parameter_sets_are_valid():
+    """The 32-bit word path's sets: distinct primes below 2^30, 1 mod 2N at
+    N = 2^16, digits of at most 16 primes and at most 64 primes in all."""
+    from paper_2507_04775_amd import inputs
+    for name in ("w32-small", "w32-large"):
+        ps = inputs.params32(name)
+        allp = list(ps.q) + list(ps.p)
+        assert len(set(allp)) == len(allp) <= 64
+        assert all(p < 2 ** 30 and p % (2 << 16) == 1 and inputs.is_prime(p) for p in allp)
+        assert ps.alpha <= 16 and ps.K <= 16 and ps.logn == 16
