@@ -262,7 +262,7 @@ def valu_fractions(probe):
     rows = {}
     for line in text.splitlines():
         cells = [c.strip() for c in line.strip().strip("|").split("|")]
-        if len(cells) == 7 and cells[0].startswith("k_") and cells[2].isdigit():
+        if len(cells) >= 7 and cells[0].startswith("k_") and cells[2].isdigit():
             name = "%s %s" % (cells[0], cells[1])
             if name in rows:
                 continue
@@ -272,8 +272,15 @@ def valu_fractions(probe):
                           "frac_of_issue_peak": round(rate / VALU_ISSUE_PEAK, 3)}
     keep = ["k_fwd_col_bconv 8192x62x1", "k_inner_product 65536x35x1", "k_bconv 65536x3x5",
             "k_fwd_row_moddown 8192x62x1", "k_fwd_col_plain 8192x74x1", "k_fwd_row_plain 8192x74x1"]
-    out = {"peak_wave_instr_per_s": VALU_ISSUE_PEAK, "source": os.path.relpath(prof, ROOT),
-           "kernels": {k: rows[k] for k in keep if k in rows}}
+    # the NTT passes appear under the tile width the autotuner chose (suffix _w8 or _w4 for 8 or 4)
+    kernels = {}
+    for k in keep:
+        name, grid = k.split(" ")
+        for v in (name, name + "_w8", name + "_w4"):
+            if "%s %s" % (v, grid) in rows:
+                kernels["%s %s" % (v, grid)] = rows["%s %s" % (v, grid)]
+                break
+    out = {"peak_wave_instr_per_s": VALU_ISSUE_PEAK, "source": os.path.relpath(prof, ROOT), "kernels": kernels}
     if probe:
         out["mad64_wave_instr_per_s_measured"] = probe["wave_instr_per_s"]
     return out
