@@ -96,15 +96,38 @@ namespace ckks {
 // Full key switch of d (gathered through g_in) with `key`; outputs
 // out_t = KS_t + add_t (add gathered through g_add).  The digits' own rows are
 // never copied: the inner product reads them from d directly.
+// tin (N = 2^16, d, add0, add1 null, g_in = g_add = 1): HMult's relinearisation
+// of a x b with the tensor folded in.  d2 = a1 b1 is formed by ModUp's first
+// inverse pass and by the inner product (its digit-own rows), and the inner
+// product adds [P]_q d0 and [P]_q d1 to the accumulators over q_0..q_l, so
+// that ModDown returns KS(d2) + (d0, d1): no tensor kernel and no d0, d1, d2
+// in memory.
 hipError_t keyswitch_core(const ckks_ctx *c, const uint64_t *d, uint32_t g_in, uint32_t level, const uint64_t *key,
                           uint64_t *out0, uint64_t *out1, const uint64_t *add0, const uint64_t *add1, uint32_t g_add,
-                          void *ws, hipStream_t st)
+                          void *ws, hipStream_t st, const TensorIn *tin)
 {
     KsSizes s = ks_sizes(c, level);
     KsWs w = ks_ws(c, level, ws);
-    hipError_t e = modup_intt(c, d, g_in, level, w.dc, st);
+    hipError_t e;
+    if (tin) {
+        if (c->logn != 16 || d || add0 || add1 || g_in != 1 || g_add != 1) return hipErrorInvalidValue;
+        NttArgs ia = args_modup_intt(c, tin->a1, 1, level, w.dc);
+        ia.src2 = tin->b1;
+        e = launch_ntt_stage(STAGE_INV_TENSOR, ia, level + 1, st);
+    } else {
+        e = modup_intt(c, d, g_in, level, w.dc, st);
+    }
     if (e == hipSuccess) e = modup_from_coeffs(c, d, g_in, level, w.dc, w.ext, false, st);
-    if (e == hipSuccess) e = inner_product(c, w.ext, level, key, 1, w.acc, st, d, g_in);
+    if (e != hipSuccess) return e;
+    IpArgs ip = args_ip(c, w.ext, level, key, 1, w.acc, d, g_in);
+    if (tin) {
+        ip.own = nullptr;
+        ip.ta0 = tin->a0;
+        ip.ta1 = tin->a1;
+        ip.tb0 = tin->b0;
+        ip.tb1 = tin->b1;
+    }
+    e = launch_inner_product(ip, st);
     if (e != hipSuccess) return e;
     uint64_t *outs[2] = {out0, out1};
     const uint64_t *adds[2] = {add0, add1};
@@ -382,10 +405,15 @@ extern "C" ckks_status ckks_hmult_relin(ckks_ctx *ctx, const ckks_ct *a, const c
     const size_t N = ctx->N;
     uint64_t *d2 = (uint64_t *)ws;
     void *ks_ws = d2 + (size_t)(level + 1) * N;
-    hipError_t e = launch_tensor(a->c0, a->c1, b->c0, b->c1, o.c0, o.c1, d2, ctx->d_primes, level + 1, ctx->logn,
-                                 S(stream));
-    if (e == hipSuccess)
-        e = keyswitch_core(ctx, d2, 1, level, rlk->data, o.c0, o.c1, o.c0, o.c1, 1, ks_ws, S(stream));
+    hipError_t e;
+    if (ctx->logn == 16) {
+        const TensorIn tin = {a->c0, a->c1, b->c0, b->c1};
+        e = keyswitch_core(ctx, nullptr, 1, level, rlk->data, o.c0, o.c1, nullptr, nullptr, 1, ks_ws, S(stream), &tin);
+    } else {
+        e = launch_tensor(a->c0, a->c1, b->c0, b->c1, o.c0, o.c1, d2, ctx->d_primes, level + 1, ctx->logn, S(stream));
+        if (e == hipSuccess)
+            e = keyswitch_core(ctx, d2, 1, level, rlk->data, o.c0, o.c1, o.c0, o.c1, 1, ks_ws, S(stream));
+    }
     TRY(dev(e, "ckks_hmult_relin"));
     out->level = level;
     out->scale = a->scale * b->scale;

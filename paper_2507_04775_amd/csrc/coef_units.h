@@ -205,6 +205,60 @@ __device__ __forceinline__ void ip_blocks(const IpArgs &a, uint32_t r, uint32_t 
     }
 }
 
+// Row r of HMult's key inner product with the tensor folded in (IpArgs::ta0
+// set; no automorphism).  The key-switched polynomial is d2 = a1 b1: a digit's
+// own rows are formed from a1 and b1 here instead of being read from d2, and
+// a row under q_r (r <= l) also accumulates [P]_{q_r} d0 into half 0 and
+// [P]_{q_r} d1 into half 1, d0 = a0 b0, d1 = a0 b1 + a1 b0, so that ModDown's
+// P^-1 (acc - Conv) leaves KS_t + d_t.  At most kMaxDigits + 1 products below
+// 2^122 each: the 128-bit sums are exact and reduced once.
+__device__ __forceinline__ void ip_unit_tensor(const IpArgs &a, uint32_t r, uint32_t bx, uint32_t tid)
+{
+    const uint32_t N = 1u << a.logn;
+    const uint32_t n = bx * kCoefThreads + tid;
+    const uint32_t pi = row_prime(r, a.level, a.nq);  // also the key row
+    const size_t krows = a.nq + a.np;
+    const Prime P = a.primes[pi];
+    const bool qrow = r <= a.level;
+    uint64_t a0 = 0, a1 = 0, b0 = 0, b1 = 0;
+    if (qrow) {
+        const size_t i = (size_t)r * N + n;
+        a0 = a.ta0[i];
+        a1 = a.ta1[i];
+        b0 = a.tb0[i];
+        b1 = a.tb1[i];
+    }
+    u128 s0 = {0, 0}, s1 = {0, 0};
+    for (uint32_t j0 = 0; j0 < a.beta; j0 += kIpStage) {
+        uint64_t x[kIpStage], k0[kIpStage], k1[kIpStage];
+#pragma unroll
+        for (uint32_t t = 0; t < kIpStage; ++t) {
+            const uint32_t j = j0 + t;
+            if (j >= a.beta) break;
+            const bool own = qrow && r >= j * a.alpha && r < min(j * a.alpha + a.alpha, a.level + 1);
+            x[t] = own ? 0 : a.ext[((size_t)j * a.rows + r) * N + n];
+            k0[t] = a.key[(((size_t)j * 2 + 0) * krows + pi) * N + n];
+            k1[t] = a.key[(((size_t)j * 2 + 1) * krows + pi) * N + n];
+            if (own) x[t] = reduce128(mul_wide(a1, b1), P);
+        }
+#pragma unroll
+        for (uint32_t t = 0; t < kIpStage; ++t) {
+            if (j0 + t >= a.beta) break;
+            s0 = add128(s0, mul_wide(x[t], k0[t]));
+            s1 = add128(s1, mul_wide(x[t], k1[t]));
+        }
+    }
+    if (qrow) {
+        const uint64_t pm = a.pmod[pi];
+        const uint64_t d0 = reduce128(mul_wide(a0, b0), P);
+        const uint64_t d1 = reduce128(add128(mul_wide(a0, b1), mul_wide(a1, b0)), P);
+        s0 = add128(s0, mul_wide(d0, pm));
+        s1 = add128(s1, mul_wide(d1, pm));
+    }
+    a.acc[(size_t)r * N + n] = reduce128(s0, P);
+    a.acc[((size_t)a.rows + r) * N + n] = reduce128(s1, P);
+}
+
 // d0 = a0 b0, d1 = a0 b1 + a1 b0, d2 = a1 b1 (limb l under q_l)
 __device__ __forceinline__ void tensor_unit(const TensorArgs &a, uint32_t l, uint32_t bx, uint32_t tid)
 {

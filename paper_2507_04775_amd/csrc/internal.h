@@ -63,7 +63,7 @@ __device__ __forceinline__ uint32_t galois_src(uint32_t e, uint32_t g, uint32_t 
 }
 
 // Prologue of the first forward pass / epilogue of the last forward pass.
-enum NttPro { PRO_PLAIN = 0, PRO_RESCALE = 1, PRO_GALOIS = 2, PRO_BCONV = 3 };
+enum NttPro { PRO_PLAIN = 0, PRO_RESCALE = 1, PRO_GALOIS = 2, PRO_BCONV = 3, PRO_TENSOR = 4 };
 enum NttEpi { EPI_PLAIN = 0, EPI_MODDOWN = 1, EPI_RESCALE = 2 };
 
 struct NttArgs {
@@ -109,6 +109,8 @@ struct NttArgs {
     uint64_t int_primes;        // bit i: prime i is on the integer path
     uint32_t n_heavy, heavy_pad;
     uint8_t heavy[kMaxHeavy];   // launch limbs on the integer path, ascending (n_heavy of them)
+    // PRO_TENSOR (first inverse pass): the input row is [src * src2]_q, HMult's d2 = a1 b1
+    const uint64_t *src2;
 };
 
 // A unit of work of a persistent stage kernel is one tile of limb `limb` of
@@ -252,7 +254,8 @@ enum NttStage {
     STAGE_FWD_BCONV_MODDOWN,
     STAGE_INV_PLAIN,
     STAGE_INV_GALOIS,
-    STAGE_FWD_LIFT              // centred lift of one source limb into every row, then forward NTT
+    STAGE_FWD_LIFT,             // centred lift of one source limb into every row, then forward NTT
+    STAGE_INV_TENSOR            // inverse NTT of the product of two polynomials (N = 2^16)
 };
 
 struct BconvJob {
@@ -288,6 +291,12 @@ struct IpArgs {
     uint32_t galois;            // every digit row gathered through X -> X^g (hoisted rotation; 1 = none)
     const uint64_t *own;        // non-null: digit j's own rows are read from own[r] (gathered through
     uint32_t own_galois;        // own_galois), not from ext
+    // HMult's tensor folded in (grid launches, galois = own_galois = 1): the key-switched
+    // polynomial is d2 = a1 b1, whose digit-own rows are formed from ta1, tb1 (own unused),
+    // and rows q_0..q_l also accumulate [P]_q d0 (half 0) and [P]_q d1 (half 1),
+    // d0 = a0 b0, d1 = a0 b1 + a1 b0; pmod[prime] = [P]_q.  ta0 null: no tensor.
+    const uint64_t *ta0, *ta1, *tb0, *tb1;
+    const uint64_t *pmod;
 };
 
 enum CtOp { CT_HADD = 0, CT_PTADD, CT_PTMULT, CT_SCALAR_ADD, CT_SCALAR_MULT };
@@ -378,7 +387,7 @@ hipError_t launch_tensor_queue(const TensorArgs *insts, const WorkQueue &q, uint
 hipError_t launch_zero_u32(uint32_t *p, uint32_t n, hipStream_t stream);
 // The one-launch batch kernel (N = 2^16 only): `grid` workgroups of 512 threads.
 hipError_t launch_fused_batch(const FusedArgs &f, uint32_t grid, hipStream_t stream);
-hipError_t launch_inner_product(const IpArgs &a, hipStream_t stream);
+hipError_t launch_inner_product(const IpArgs &a, hipStream_t stream);  // ta0 set: the tensor form
 hipError_t launch_tensor(const uint64_t *a0, const uint64_t *a1, const uint64_t *b0, const uint64_t *b1,
                          uint64_t *d0, uint64_t *d1, uint64_t *d2, const Prime *primes, uint32_t nlimbs,
                          uint32_t logn, hipStream_t stream);
@@ -435,6 +444,18 @@ struct ckks_key {
 };
 
 namespace ckks {
+
+// HMult's operands a = (a0, a1), b = (b0, b1) at the level of the key switch.
+struct TensorIn {
+    const uint64_t *a0, *a1, *b0, *b1;
+};
+
+// Full key switch of phi_{g_in}(d) into out_t = KS_t + phi_{g_add}(add_t) (add_t
+// may be null), workspace of CKKS_OP_KEYSWITCH size; tin: HMult's tensor folded
+// in instead of d and add (N = 2^16).
+hipError_t keyswitch_core(const ckks_ctx *c, const uint64_t *d, uint32_t g_in, uint32_t level, const uint64_t *key,
+                          uint64_t *out0, uint64_t *out1, const uint64_t *add0, const uint64_t *add1, uint32_t g_add,
+                          void *ws, hipStream_t st, const TensorIn *tin = nullptr);
 
 // Key switch of phi_g(d) (d at `level`, eval domain) without the ModDown: the
 // two accumulators [2][l+1+K][N] over q_0..q_l, p_0..p_{K-1} are left in the

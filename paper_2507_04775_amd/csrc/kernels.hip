@@ -37,6 +37,11 @@ __global__ __launch_bounds__(kThreads) void k_inner_product(IpArgs a)
     ip_unit(a, blockIdx.y, blockIdx.x, stage, threadIdx.x);
 }
 
+__global__ __launch_bounds__(kThreads) void k_inner_product_tensor(IpArgs a)
+{
+    ip_unit_tensor(a, blockIdx.y, blockIdx.x, threadIdx.x);
+}
+
 __global__ __launch_bounds__(kThreads) void q_inner_product(const IpArgs *insts, WorkQueue q)
 {
     __shared__ uint64_t stage[kIpStage * kThreads];
@@ -260,7 +265,13 @@ hipError_t launch_bconv(const BconvArgs &a, uint32_t njobs, hipStream_t stream)
 
 hipError_t launch_inner_product(const IpArgs &a, hipStream_t stream)
 {
-    hipLaunchKernelGGL(k_inner_product, dim3((1u << a.logn) / kThreads, a.rows), dim3(kThreads), 0, stream, a);
+    if (a.ta0) {
+        if (a.galois != 1 || !a.ta1 || !a.tb0 || !a.tb1 || !a.pmod) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_inner_product_tensor, dim3((1u << a.logn) / kThreads, a.rows), dim3(kThreads), 0, stream,
+                           a);
+    } else {
+        hipLaunchKernelGGL(k_inner_product, dim3((1u << a.logn) / kThreads, a.rows), dim3(kThreads), 0, stream, a);
+    }
     return hipGetLastError();
 }
 

@@ -134,6 +134,8 @@ IpArgs args_ip(const ckks_ctx *c, const uint64_t *ext, uint32_t level, const uin
     a.galois = g;
     a.own = own;
     a.own_galois = own_galois;
+    a.ta0 = a.ta1 = a.tb0 = a.tb1 = nullptr;
+    a.pmod = c->d_pmod;
     return a;
 }
 

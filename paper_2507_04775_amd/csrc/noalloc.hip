@@ -18,9 +18,6 @@ namespace ckks {
 ckks_status fail(ckks_status s, const std::string &msg);
 ckks_status check_keyswitch_args(ckks_ctx *ctx, const uint64_t *d, uint32_t level, const ckks_key *key,
                                  const uint64_t *out0, const uint64_t *out1, const char *what);
-hipError_t keyswitch_core(const ckks_ctx *c, const uint64_t *d, uint32_t g_in, uint32_t level, const uint64_t *key,
-                          uint64_t *out0, uint64_t *out1, const uint64_t *add0, const uint64_t *add1, uint32_t g_add,
-                          void *ws, hipStream_t st);
 }  // namespace ckks
 
 #define TRY(x)                              \

@@ -658,11 +658,12 @@ __device__ __forceinline__ void fwd_row_unit(const NttArgs &a, uint32_t limb, ui
 }
 
 template <int PRO, int TW, class A>
-__device__ __forceinline__ void inv_row_body(const NttArgs &a, const LimbPos &lp, const A &ar, uint64_t *lds,
-                                             uint32_t tile, uint32_t tx)
+__device__ __forceinline__ void inv_row_body(const NttArgs &a, const LimbPos &lp, const Prime &P, const A &ar,
+                                             uint64_t *lds, uint32_t tile, uint32_t tx)
 {
     const uint32_t blk = tx >> 5, s = tx & 31, b = tile * TW + blk;
-    const uint64_t *src = a.src + (int64_t)lp.poly * a.map.src_poly_stride + (size_t)lp.row * 65536;
+    const size_t row_off = (int64_t)lp.poly * a.map.src_poly_stride + (size_t)lp.row * 65536;
+    const uint64_t *src = a.src + row_off;
     uint64_t *L = lds + blk * 256;
     typename A::W wa[6], wb[7], wc[7];
     tw_inv<2, 256, 1>(wa, 8 * s, ar, 256 + b);
@@ -670,7 +671,10 @@ __device__ __forceinline__ void inv_row_body(const NttArgs &a, const LimbPos &lp
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
         const uint32_t e = b * 256 + pos_wide(s, i);
-        L[row_slot(pos_wide(s, i))] = src[PRO == PRO_GALOIS ? galois_src(e, a.galois, 16) : e];
+        if (PRO == PRO_TENSOR)  // HMult's d2 = a1 b1, formed on the fly
+            L[row_slot(pos_wide(s, i))] = reduce128(mul_wide(src[e], a.src2[row_off + e]), P);
+        else
+            L[row_slot(pos_wide(s, i))] = src[PRO == PRO_GALOIS ? galois_src(e, a.galois, 16) : e];
     }
     wave_sync();
     typename A::V v[8];
@@ -708,9 +712,9 @@ __device__ __forceinline__ void inv_row_unit(const NttArgs &a, uint32_t limb, ui
     if (lp.skip) return;
     const Prime P = a.primes[lp.prime];
     if (P.q < kFpMaxPrime)
-        inv_row_body<PRO, TW>(a, lp, fp_arith(a, P, lp.prime, 65536), lds, tile, tx);
+        inv_row_body<PRO, TW>(a, lp, P, fp_arith(a, P, lp.prime, 65536), lds, tile, tx);
     else
-        inv_row_body<PRO, TW>(a, lp, int_arith(a, P, lp.prime, 65536), lds, tile, tx);
+        inv_row_body<PRO, TW>(a, lp, P, int_arith(a, P, lp.prime, 65536), lds, tile, tx);
 }
 
 template <int TW, class A>
@@ -936,6 +940,7 @@ NTT_KERNELS(fwd_row_moddown, kLds16, fwd_row_unit<EPI_MODDOWN>, kThreads16, true
 NTT_KERNELS(fwd_row_rescale, kLds16, fwd_row_unit<EPI_RESCALE>, kThreads16, true)
 NTT_KERNELS(inv_row_plain, kLds16, inv_row_unit<PRO_PLAIN>, kThreads16, true)
 NTT_KERNELS(inv_row_galois, kLds16, inv_row_unit<PRO_GALOIS>, kThreads16, true)
+NTT_KERNELS(inv_row_tensor, kLds16, inv_row_unit<PRO_TENSOR>, kThreads16, true)
 NTT_KERNELS(inv_col, kLds16, inv_col_unit, kThreads16, true)
 // Grid kernels with narrower tiles (TW = 8, 4 columns or rows per workgroup of
 // 32 TW threads), for launches over few limbs; unit = (blockIdx.x, blockIdx.y).
@@ -958,6 +963,7 @@ NTT_KERNELS(inv_col, kLds16, inv_col_unit, kThreads16, true)
 #define U_FRR(W) fwd_row_unit<EPI_RESCALE, W>
 #define U_IRP(W) inv_row_unit<PRO_PLAIN, W>
 #define U_IRG(W) inv_row_unit<PRO_GALOIS, W>
+#define U_IRT(W) inv_row_unit<PRO_TENSOR, W>
 #define U_IC(W) inv_col_unit<W>
 NTT_NARROW(fwd_col_plain, U_FCP)
 NTT_NARROW(fwd_col_rescale, U_FCR)
@@ -967,6 +973,7 @@ NTT_NARROW(fwd_row_moddown, U_FRM)
 NTT_NARROW(fwd_row_rescale, U_FRR)
 NTT_NARROW(inv_row_plain, U_IRP)
 NTT_NARROW(inv_row_galois, U_IRG)
+NTT_NARROW(inv_row_tensor, U_IRT)
 NTT_NARROW(inv_col, U_IC)
 #undef U_FCP
 #undef U_FCR
@@ -976,6 +983,7 @@ NTT_NARROW(inv_col, U_IC)
 #undef U_FRR
 #undef U_IRP
 #undef U_IRG
+#undef U_IRT
 #undef U_IC
 #undef NTT_NARROW
 
@@ -1232,6 +1240,8 @@ bool stage_kernels(NttStage st, uint32_t logn, int pass, StageKernels &k, uint32
         if (pass == 0) { SK(inv_row_plain) } else { SK(inv_col) }
     case STAGE_INV_GALOIS:
         if (pass == 0) { SK(inv_row_galois) } else { SK(inv_col) }
+    case STAGE_INV_TENSOR:
+        if (pass == 0) { SK(inv_row_tensor) } else { SK(inv_col) }
     default: return false;
     }
 #undef SK
@@ -1281,7 +1291,7 @@ static uint32_t default_tile(uint32_t nlimbs)
 static uint32_t tile_width(NttStage st, uint32_t logn, uint32_t nlimbs)
 {
     if (logn != 16) return 16;
-    const int inv = st == STAGE_INV_PLAIN || st == STAGE_INV_GALOIS;
+    const int inv = st == STAGE_INV_PLAIN || st == STAGE_INV_GALOIS || st == STAGE_INV_TENSOR;
     const uint32_t t = nlimbs <= kMaxTileLimbs ? g_tile[inv][nlimbs].load(std::memory_order_relaxed) : 0;
     return t ? t : default_tile(nlimbs);
 }
