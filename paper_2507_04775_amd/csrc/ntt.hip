@@ -410,52 +410,55 @@ __device__ __forceinline__ BcSrc bc_source(const NttArgs &a, uint32_t poly, uint
 }
 
 // v[i] = Conv(y)[pos(i)]: sum_k y_k[pos] [B/b_k]_q accumulated exactly, reduced
-// once; groups of eight elements keep the 128-bit sums in few registers.
-// The loads of source row k+1 are issued before the products of row k, so
-// the latency of the source rows overlaps the arithmetic.
+// once.  The sums go by 32-bit columns (mac_cols: four multiply-adds and three
+// carry additions per term, the constant in scalar registers); groups of four
+// elements keep the column sums in few registers.  The loads of source row
+// k+1 are issued before the products of row k, so the latency of the source
+// rows overlaps the arithmetic.
 template <int NV, class A, class Pos>
 __device__ __forceinline__ void bconv_load(typename A::V (&v)[NV], const A &ar, const BcSrc &b, const Prime &P,
                                            size_t N, Pos pos)
 {
-    static_assert(NV % 8 == 0, "groups of eight elements");
+    constexpr int G = 4;
+    static_assert(NV % G == 0, "groups of four elements");
 #pragma unroll
-    for (int half = 0; half < NV / 8; ++half) {
-        u128 acc[8];
-        uint32_t high[8];
-        uint64_t cur[8];
+    for (int grp = 0; grp < NV / G; ++grp) {
+        MacCols acc[G];
+        uint32_t high[G];
+        uint64_t cur[G];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            acc[i] = u128{0, 0};
+        for (int i = 0; i < G; ++i) {
             high[i] = 0;
-            cur[i] = b.y[pos(8 * half + i)];
+            cur[i] = b.y[pos(G * grp + i)];
         }
         for (uint32_t k = 0; k < b.ns; ++k) {
             const bool more = k + 1 < b.ns;
-            uint64_t nxt[8];
+            uint64_t nxt[G];
             if (more) {
                 const uint64_t *yn = b.y + (size_t)(k + 1) * N;
 #pragma unroll
-                for (int i = 0; i < 8; ++i) nxt[i] = yn[pos(8 * half + i)];
+                for (int i = 0; i < G; ++i) nxt[i] = yn[pos(G * grp + i)];
             }
             const uint64_t h = ((const __attribute__((address_space(4))) uint64_t *)b.hm)[k];  // scalar cache
             const uint64_t half_k = b.src ? (b.src[k].q - 1) >> 1 : ~0ull;
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                acc[i] = add128(acc[i], mul_wide(cur[i], h));
+            for (int i = 0; i < G; ++i) {
+                mac_cols(acc[i], cur[i], h);
                 high[i] += cur[i] > half_k;
             }
             if (more) {
 #pragma unroll
-                for (int i = 0; i < 8; ++i) cur[i] = nxt[i];
+                for (int i = 0; i < G; ++i) cur[i] = nxt[i];
             }
         }
         // y_k - p_k for the high inputs: subtracting high [P]_q equals adding high (q - [P]_q), which
         // joins the exact sum before its one reduction (high <= 16, so the sum stays below 2^127)
         const uint64_t nbq = b.src ? P.q - b.bq : 0;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const u128 z = b.src ? add128(acc[i], mul_wide((uint64_t)high[i], nbq)) : acc[i];
-            v[8 * half + i] = ar.from_u64(reduce128(z, P));
+        for (int i = 0; i < G; ++i) {
+            const u128 t = mac_total(acc[i]);
+            const u128 z = b.src ? add128(t, mul_wide((uint64_t)high[i], nbq)) : t;
+            v[G * grp + i] = ar.from_u64(reduce128(z, P));
         }
     }
 }
