@@ -55,6 +55,8 @@ struct IntArith {
     __device__ __forceinline__ V from_bits(uint64_t x) const { return x; }
     __device__ __forceinline__ uint64_t to_bits(V x) const { return x; }
     __device__ __forceinline__ W tw(uint32_t i) const { return T[i]; }
+    // the twiddle at hi + k (k below the lowest set bit of hi): read from the table
+    __device__ __forceinline__ W tw_split(uint32_t hi, uint32_t k) const { return T[hi + k]; }
     template <int NV>
     __device__ __forceinline__ void reduce_all(V (&)[NV]) const {}
     // Harvey forward butterfly: x, y in [0, 4q) -> [0, 4q)
@@ -99,6 +101,10 @@ struct FpArith {
     __device__ __forceinline__ V from_bits(uint64_t x) const { return __longlong_as_double((long long)x); }
     __device__ __forceinline__ uint64_t to_bits(V x) const { return (uint64_t)__double_as_longlong(x); }
     __device__ __forceinline__ W tw(uint32_t i) const { return T[i]; }
+    // the twiddle at hi + k, k below the lowest set bit of hi: the table holds psi^br(i) (or its
+    // inverse), and br(hi + k) = br(hi) + br(k) for such k, so it is T[hi] T[k], formed here (a
+    // centred representative) from the row's one entry and the first entries shared by every row
+    __device__ __forceinline__ W tw_split(uint32_t hi, uint32_t k) const { return fp_mulmod(T[hi], T[k], m); }
     template <int NV>
     __device__ __forceinline__ void reduce_all(V (&v)[NV]) const
     {
@@ -137,16 +143,24 @@ struct FpArith {
 // tw_fwd loads the 2^LOG - 1 twiddles a round uses (stage by stage, group by
 // group) and fwd_rw applies them, so a pass can issue a round's twiddle loads
 // before the barrier that precedes the round.
-template <int LOG, int NS, int STRIDE, class A>
+//
+// Row passes (ROW, B = 256 + row) take the stages with NS / 2t >= kTwSplit
+// groups per row as tw_split(m B, j div 2t): one table entry per row and
+// stage, and the first entries of the table, which every row shares.  A row
+// then reads 34 of its 255 twiddles from the table instead of all of them.
+constexpr uint32_t kTwSplit = 32;
+
+template <int LOG, int NS, int STRIDE, class A, bool ROW = false>
 __device__ __forceinline__ void tw_fwd(typename A::W *w, uint32_t base, const A &ar, uint32_t B)
 {
     int k = 0;
 #pragma unroll
     for (int st = 0; st < LOG; ++st) {
         const uint32_t t = ((1u << (LOG - 1)) >> st) * STRIDE;
-        const uint32_t g0 = (NS / (2 * t)) * B + base / (2 * t);
+        const uint32_t hi = (NS / (2 * t)) * B, g0 = base / (2 * t);
 #pragma unroll
-        for (int g = 0; g < (1 << st); ++g) w[k++] = ar.tw(g0 + g);
+        for (int g = 0; g < (1 << st); ++g)
+            w[k++] = ROW && NS / (2 * t) >= kTwSplit ? ar.tw_split(hi, g0 + g) : ar.tw(hi + g0 + g);
     }
 }
 
@@ -177,16 +191,17 @@ __device__ __forceinline__ void fwd_r(typename A::V *v, uint32_t base, const A &
 // LOG inverse stages: t = STRIDE, 2 STRIDE, ..., 2^(LOG-1) STRIDE.  Rounds
 // of four stages re-centre the sums of their third stage (FP64 path); three
 // stages from a centred start stay below 4 q + 8 without it.
-template <int LOG, int NS, int STRIDE, class A>
+template <int LOG, int NS, int STRIDE, class A, bool ROW = false>
 __device__ __forceinline__ void tw_inv(typename A::W *w, uint32_t base, const A &ar, uint32_t B)
 {
     int k = 0;
 #pragma unroll
     for (int st = 0; st < LOG; ++st) {
         const uint32_t t = (1u << st) * STRIDE;
-        const uint32_t g0 = (NS / (2 * t)) * B + base / (2 * t);
+        const uint32_t hi = (NS / (2 * t)) * B, g0 = base / (2 * t);
 #pragma unroll
-        for (int g = 0; g < ((1 << (LOG - 1)) >> st); ++g) w[k++] = ar.tw(g0 + g);
+        for (int g = 0; g < ((1 << (LOG - 1)) >> st); ++g)
+            w[k++] = ROW && NS / (2 * t) >= kTwSplit ? ar.tw_split(hi, g0 + g) : ar.tw(hi + g0 + g);
     }
 }
 
@@ -584,13 +599,13 @@ __device__ __forceinline__ void fwd_row_body(const NttArgs &a, const LimbPos &lp
     const uint64_t *m = a.mid + (int64_t)lp.poly * a.mid_stride + (size_t)lp.row * 65536 + b * 256;
     uint64_t *L = lds + blk * 256;
     typename A::W wa[7], wb[7], wc[6];
-    tw_fwd<3, 256, 32>(wa, s, ar, 256 + b);
+    tw_fwd<3, 256, 32, A, true>(wa, s, ar, 256 + b);
     typename A::V v[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) v[i] = ar.from_bits(m[pos_wide(s, i)]);
     ar.reduce_all(v);
     fwd_rw<3>(v, wa, ar);
-    tw_fwd<3, 256, 4>(wb, pos_mid(s, 0), ar, 256 + b);  // in flight across the exchange
+    tw_fwd<3, 256, 4, A, true>(wb, pos_mid(s, 0), ar, 256 + b);  // in flight across the exchange
 #pragma unroll
     for (int i = 0; i < 8; ++i) L[row_slot(pos_wide(s, i))] = ar.to_bits(v[i]);
     wave_sync();
@@ -617,8 +632,8 @@ __device__ __forceinline__ void fwd_row_body(const NttArgs &a, const LimbPos &lp
 #pragma unroll
         for (int i = 0; i < 8; ++i) addv[i] = add[sb + pos_wide(s, i)];
     }
-    tw_fwd<2, 256, 1>(wc, 8 * s, ar, 256 + b);
-    tw_fwd<2, 256, 1>(wc + 3, 8 * s + 4, ar, 256 + b);
+    tw_fwd<2, 256, 1, A, true>(wc, 8 * s, ar, 256 + b);
+    tw_fwd<2, 256, 1, A, true>(wc + 3, 8 * s + 4, ar, 256 + b);
 #pragma unroll
     for (int i = 0; i < 8; ++i) L[row_slot(pos_mid(s, i))] = ar.to_bits(v[i]);
     wave_sync();
@@ -669,8 +684,8 @@ __device__ __forceinline__ void inv_row_body(const NttArgs &a, const LimbPos &lp
     const uint64_t *src = a.src + row_off;
     uint64_t *L = lds + blk * 256;
     typename A::W wa[6], wb[7], wc[7];
-    tw_inv<2, 256, 1>(wa, 8 * s, ar, 256 + b);
-    tw_inv<2, 256, 1>(wa + 3, 8 * s + 4, ar, 256 + b);
+    tw_inv<2, 256, 1, A, true>(wa, 8 * s, ar, 256 + b);
+    tw_inv<2, 256, 1, A, true>(wa + 3, 8 * s + 4, ar, 256 + b);
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
         const uint32_t e = b * 256 + pos_wide(s, i);
@@ -686,7 +701,7 @@ __device__ __forceinline__ void inv_row_body(const NttArgs &a, const LimbPos &lp
     ar.reduce_all(v);
     inv_rw<2>(v, wa, ar);
     inv_rw<2>(v + 4, wa + 3, ar);
-    tw_inv<3, 256, 4>(wb, pos_mid(s, 0), ar, 256 + b);  // in flight across the exchange
+    tw_inv<3, 256, 4, A, true>(wb, pos_mid(s, 0), ar, 256 + b);  // in flight across the exchange
 #pragma unroll
     for (int i = 0; i < 8; ++i) L[row_slot(pos_narrow(s, i))] = ar.to_bits(v[i]);
     wave_sync();
@@ -694,7 +709,7 @@ __device__ __forceinline__ void inv_row_body(const NttArgs &a, const LimbPos &lp
     for (int i = 0; i < 8; ++i) v[i] = ar.from_bits(L[row_slot(pos_mid(s, i))]);
     ar.reduce_all(v);
     inv_rw<3>(v, wb, ar);
-    tw_inv<3, 256, 32>(wc, s, ar, 256 + b);
+    tw_inv<3, 256, 32, A, true>(wc, s, ar, 256 + b);
 #pragma unroll
     for (int i = 0; i < 8; ++i) L[row_slot(pos_mid(s, i))] = ar.to_bits(v[i]);
     wave_sync();
