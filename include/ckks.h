@@ -118,12 +118,16 @@ ckks_status ckks_intt(ckks_ctx *ctx, uint64_t *poly, uint32_t limb0, uint32_t n_
  * as a column pass and a row pass over the 256 x 256 view): a workgroup takes
  * `tile` columns (rows) with 32 threads on each, tile 16 (512 threads), 8 (256)
  * or 4 (128).  Narrow tiles give a launch over few limbs more workgroups to
- * spread over the CUs.  The choice holds per direction (inverse 0 / 1) and per
- * number of limbs in the launch (1..128), for every NTT launch of every
- * operation in the process; tile 0 restores the default (16 from 24 limbs up,
- * 8 from 6, else 4).  Results do not depend on it.  An autotuner sets it from
- * measurements.  ckks_ntt_tile_get returns the width in effect (0 for bad
- * arguments).  Persistent batch kernels always use 16.
+ * spread over the CUs.  Inverse launches also take tile code 2: 8 columns
+ * (rows) with 64 threads on each, 4 elements per thread (512 threads), twice
+ * the waves for latency-bound launches over few limbs; it applies to the plain
+ * inverse (the ModDown and Rescale INTTs, ckks_intt), other inverse stages then
+ * use 8.  The choice holds per direction (inverse 0 / 1) and per number of
+ * limbs in the launch (1..128), for every NTT launch of every operation in the
+ * process; tile 0 restores the default (16 from 24 limbs up, 8 from 6, else 4;
+ * inverse launches of at most 8 limbs 2).  Results do not depend on it.  An
+ * autotuner sets it from measurements.  ckks_ntt_tile_get returns the code in
+ * effect (0 for bad arguments).  Persistent batch kernels always use 16.
  */
 ckks_status ckks_ntt_tile_set(uint32_t inverse, uint32_t n_limbs, uint32_t tile);
 uint32_t ckks_ntt_tile_get(uint32_t inverse, uint32_t n_limbs);

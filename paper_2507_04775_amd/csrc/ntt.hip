@@ -784,6 +784,138 @@ __device__ __forceinline__ void inv_col_unit(const NttArgs &a, uint32_t limb, ui
         inv_col_body<TW>(a, lp, inv_int_arith(a, lp, P, 65536), lds, tile, tx);
 }
 
+// Inverse passes with 4 elements per thread, 64 threads per 256-point problem,
+// for launches over few limbs: those are latency-bound with one wave per SIMD
+// in the 8-element layout, and this one gives them twice the waves.  A
+// workgroup of 512 threads takes 8 rows (one wave each) or 8 columns.  Rounds
+// of two stages (t = 1, 2 | 4, 8 | 16, 32 | 64, 128) in four layouts, thread
+// s < 64 holding positions
+//   A 4s + i,  B 16 (s/4) + s%4 + 4i,  C 64 (s/16) + s%16 + 16i,  D s + 64i.
+__device__ __forceinline__ uint32_t p4a(uint32_t s, int i) { return 4 * s + i; }
+__device__ __forceinline__ uint32_t p4b(uint32_t s, int i) { return 16 * (s >> 2) + (s & 3) + 4 * i; }
+__device__ __forceinline__ uint32_t p4c(uint32_t s, int i) { return 64 * (s >> 4) + (s & 15) + 16 * i; }
+__device__ __forceinline__ uint32_t p4d(uint32_t s, int i) { return s + 64 * i; }
+// LDS slot of element e of a row (256 words): the low five bits XOR-ed with
+// 9 (e/32) and 4 (e/64) (mod 32), so that each half-wave hits 32 distinct
+// 8-byte banks in all four layouts (checked exhaustively on the host).
+__device__ __forceinline__ uint32_t row4_slot(uint32_t e)
+{
+    return (e & ~31u) | ((e ^ (9 * (e >> 5)) ^ (4 * (e >> 6))) & 31u);
+}
+// LDS slot of element e of column `col` of an 8-column tile: columns
+// interleaved, one word of padding every 4 elements (conflict-free likewise).
+__device__ __forceinline__ uint32_t col4_slot(uint32_t e, uint32_t col) { return 8 * (e + (e >> 2)) + col; }
+constexpr int kLds4 = 8 * (255 + 63 + 1);
+
+template <class A>
+__device__ __forceinline__ void inv_row4_body(const NttArgs &a, const LimbPos &lp, const A &ar, uint64_t *lds,
+                                              uint32_t tile, uint32_t tx)
+{
+    const uint32_t blk = tx >> 6, s = tx & 63, b = tile * 8 + blk;
+    const uint64_t *src = a.src + (int64_t)lp.poly * a.map.src_poly_stride + (size_t)lp.row * 65536 + b * 256;
+    uint64_t *L = lds + blk * 256;
+    typename A::W wa[3], wb[3];
+    typename A::V v[4];
+    tw_inv<2, 256, 1, A, true>(wa, p4a(s, 0), ar, 256 + b);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v[i] = ar.from_u64(src[p4a(s, i)]);
+    ar.reduce_all(v);
+    inv_rw<2>(v, wa, ar);
+    tw_inv<2, 256, 4, A, true>(wb, p4b(s, 0), ar, 256 + b);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) L[row4_slot(p4a(s, i))] = ar.to_bits(v[i]);
+    wave_sync();
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v[i] = ar.from_bits(L[row4_slot(p4b(s, i))]);
+    ar.reduce_all(v);
+    inv_rw<2>(v, wb, ar);
+    tw_inv<2, 256, 16, A, true>(wa, p4c(s, 0), ar, 256 + b);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) L[row4_slot(p4b(s, i))] = ar.to_bits(v[i]);
+    wave_sync();
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v[i] = ar.from_bits(L[row4_slot(p4c(s, i))]);
+    ar.reduce_all(v);
+    inv_rw<2>(v, wa, ar);
+    tw_inv<2, 256, 64, A, true>(wb, p4d(s, 0), ar, 256 + b);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) L[row4_slot(p4c(s, i))] = ar.to_bits(v[i]);
+    wave_sync();
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v[i] = ar.from_bits(L[row4_slot(p4d(s, i))]);
+    ar.reduce_all(v);
+    inv_rw<2>(v, wb, ar);
+    uint64_t *m = a.mid + (int64_t)lp.poly * a.mid_stride + (size_t)lp.row * 65536 + b * 256;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) m[p4d(s, i)] = ar.to_bits(v[i]);
+}
+
+template <class A>
+__device__ __forceinline__ void inv_col4_body(const NttArgs &a, const LimbPos &lp, const A &ar, uint64_t *lds,
+                                              uint32_t tile, uint32_t tx)
+{
+    const uint32_t col = tx & 7, s = tx >> 3, c = tile * 8 + col;
+    const uint64_t *m = a.mid + (int64_t)lp.poly * a.mid_stride + (size_t)lp.row * 65536;
+    typename A::W wa[3], wb[3];
+    typename A::V v[4];
+    tw_inv<2, 256, 1>(wa, p4a(s, 0), ar, 1);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v[i] = ar.from_bits(m[p4a(s, i) * 256 + c]);
+    ar.reduce_all(v);
+    inv_rw<2>(v, wa, ar);
+    tw_inv<2, 256, 4>(wb, p4b(s, 0), ar, 1);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) lds[col4_slot(p4a(s, i), col)] = ar.to_bits(v[i]);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v[i] = ar.from_bits(lds[col4_slot(p4b(s, i), col)]);
+    ar.reduce_all(v);
+    inv_rw<2>(v, wb, ar);
+    tw_inv<2, 256, 16>(wa, p4c(s, 0), ar, 1);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) lds[col4_slot(p4b(s, i), col)] = ar.to_bits(v[i]);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v[i] = ar.from_bits(lds[col4_slot(p4c(s, i), col)]);
+    ar.reduce_all(v);
+    inv_rw<2>(v, wa, ar);
+    tw_inv<2, 256, 64>(wb, p4d(s, 0), ar, 1);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) lds[col4_slot(p4c(s, i), col)] = ar.to_bits(v[i]);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v[i] = ar.from_bits(lds[col4_slot(p4d(s, i), col)]);
+    ar.reduce_all(v);
+    inv_rw<2>(v, wb, ar);
+    uint64_t *dst = a.dst + (int64_t)lp.poly * a.map.dst_poly_stride + (size_t)lp.row * 65536;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) dst[p4d(s, i) * 256 + c] = ar.inv_final(v[i]);
+}
+
+__device__ __forceinline__ void inv_row4_unit(const NttArgs &a, uint32_t limb, uint32_t tile, uint64_t *lds,
+                                              uint32_t tx)
+{
+    const LimbPos lp = limb_pos(a.map, limb);
+    if (lp.skip) return;
+    const Prime P = a.primes[lp.prime];
+    if (P.q < kFpMaxPrime)
+        inv_row4_body(a, lp, fp_arith(a, P, lp.prime, 65536), lds, tile, tx);
+    else
+        inv_row4_body(a, lp, int_arith(a, P, lp.prime, 65536), lds, tile, tx);
+}
+
+__device__ __forceinline__ void inv_col4_unit(const NttArgs &a, uint32_t limb, uint32_t tile, uint64_t *lds,
+                                              uint32_t tx)
+{
+    const LimbPos lp = limb_pos(a.map, limb);
+    if (lp.skip) return;
+    const Prime P = a.primes[lp.prime];
+    if (P.q < kFpMaxPrime)
+        inv_col4_body(a, lp, inv_fp_arith(a, lp, P, 65536), lds, tile, tx);
+    else
+        inv_col4_body(a, lp, inv_int_arith(a, lp, P, 65536), lds, tile, tx);
+}
+
 // ------------------------------------------------------------------ N = 2^12
 
 template <int PRO, int EPI, class A>
@@ -973,6 +1105,17 @@ NTT_KERNELS(inv_col, kLds16, inv_col_unit, kThreads16, true)
         __shared__ uint64_t lds[lds_words<4>()];                                                    \
         UNIT_T(4)(a, blockIdx.y, blockIdx.x, lds, threadIdx.x);                                     \
     }
+// The 4-element inverse passes (tile code 2: 8 rows or columns, 512 threads).
+__global__ __launch_bounds__(512) void k_inv_row4(NttArgs a)
+{
+    __shared__ uint64_t lds[kLds4];
+    inv_row4_unit(a, blockIdx.y, blockIdx.x, lds, threadIdx.x);
+}
+__global__ __launch_bounds__(512) void k_inv_col4(NttArgs a)
+{
+    __shared__ uint64_t lds[kLds4];
+    inv_col4_unit(a, blockIdx.y, blockIdx.x, lds, threadIdx.x);
+}
 #define U_FCP(W) fwd_col_unit<PRO_PLAIN, W>
 #define U_FCR(W) fwd_col_unit<PRO_RESCALE, W>
 #define U_FCB(W) fwd_col_unit<PRO_BCONV, W>
@@ -1243,6 +1386,14 @@ bool stage_kernels(NttStage st, uint32_t logn, int pass, StageKernels &k, uint32
         default: return false;
         }
     }
+    if (tw == 2) {  // 4 elements per thread: the plain inverse only (other stages take tiles of 8)
+        if (st == STAGE_INV_PLAIN) {
+            k.grid = pass == 0 ? k_inv_row4 : k_inv_col4;
+            k.queue = nullptr;
+            return true;
+        }
+        tw = 8;
+    }
     switch (st) {
     case STAGE_FWD_PLAIN:
         if (pass == 0) { SK(fwd_col_plain) } else { SK(fwd_row_plain) }
@@ -1306,25 +1457,30 @@ static uint32_t default_tile(uint32_t nlimbs)
     return nlimbs >= 6 ? 8 : 4;
 }
 
+// tile code 2 (the 4-element inverse passes) applies to STAGE_INV_PLAIN only
+static uint32_t effective_tile(NttStage st, uint32_t tw) { return tw == 2 && st != STAGE_INV_PLAIN ? 8 : tw; }
+
 static uint32_t tile_width(NttStage st, uint32_t logn, uint32_t nlimbs)
 {
     if (logn != 16) return 16;
     const int inv = st == STAGE_INV_PLAIN || st == STAGE_INV_GALOIS || st == STAGE_INV_TENSOR;
     const uint32_t t = nlimbs <= kMaxTileLimbs ? g_tile[inv][nlimbs].load(std::memory_order_relaxed) : 0;
-    return t ? t : default_tile(nlimbs);
+    if (t) return t;
+    return inv && nlimbs <= 8 ? 2 : default_tile(nlimbs);
 }
 
 hipError_t launch_ntt_stage(NttStage st, const NttArgs &a0, uint32_t nlimbs, hipStream_t stream)
 {
     if (nlimbs == 0) return hipSuccess;
     NttArgs a = a0;
-    const uint32_t tw = tile_width(st, a.logn, nlimbs);
+    const uint32_t tw = effective_tile(st, tile_width(st, a.logn, nlimbs));
     if (tw == 16) set_heavy(a, nlimbs);
     else a.n_heavy = 0;
     for (uint32_t pass = 0; pass < ntt_passes(a.logn); ++pass) {
         StageKernels k;
         if (!stage_kernels(st, a.logn, pass, k, tw)) return hipErrorInvalidValue;
-        const uint32_t tiles = a.logn == 12 ? 1 : 256 / tw, threads = a.logn == 12 ? kThreads : 32 * tw;
+        const uint32_t tiles = a.logn == 12 ? 1 : tw == 2 ? 32 : 256 / tw;
+        const uint32_t threads = a.logn == 12 ? kThreads : tw == 2 ? 512 : 32 * tw;
         hipLaunchKernelGGL(k.grid, dim3(tiles, nlimbs), dim3(threads), 0, stream, a);
     }
     return hipGetLastError();
@@ -1332,7 +1488,8 @@ hipError_t launch_ntt_stage(NttStage st, const NttArgs &a0, uint32_t nlimbs, hip
 
 bool ntt_tile_set(uint32_t inverse, uint32_t nlimbs, uint32_t tile)
 {
-    if (inverse > 1 || nlimbs == 0 || nlimbs > kMaxTileLimbs || !(tile == 0 || tile == 4 || tile == 8 || tile == 16))
+    if (inverse > 1 || nlimbs == 0 || nlimbs > kMaxTileLimbs ||
+        !(tile == 0 || tile == 4 || tile == 8 || tile == 16 || (tile == 2 && inverse == 1)))
         return false;
     g_tile[inverse][nlimbs].store((uint8_t)tile, std::memory_order_relaxed);
     return true;

@@ -32,6 +32,8 @@ from . import ckks
 
 CACHE_ENV = "CKKS_TUNE_CACHE"
 TILES = (16, 8, 4)
+# inverse launches also have tile code 2: 8 rows (columns) per workgroup with 4 elements per thread
+INV_TILES = TILES + (2,)
 
 
 def cache_path() -> str:
@@ -108,7 +110,7 @@ def tune_ntt_tiles(ctx: ckks.Context, limb_counts=None, samples: int = 5, burst:
                 out[op][n] = cache[key]
                 continue
             times = {}
-            for tile in TILES:
+            for tile in (INV_TILES if inverse else TILES):
                 ckks.ntt_tile_set(inverse, n, tile)
 
                 def launch():

@@ -289,6 +289,49 @@ def test_table_i_ops_reject_bad_arguments(name):
         s.ctx.ckks_ptadd(ta, s.dev(inputs.random_poly(432, s.ps, 2)), part)
 
 
+def test_four_element_inverse_passes_are_bit_exact():
+    """Tile code 2 on every inverse launch (8 rows or columns per workgroup, 4
+    elements per thread; the default for plain inverse launches of at most 8
+    limbs, other inverse stages fall back to 8-wide tiles): INTT over 35, 8, 2
+    and 1 limbs, and HMult+relin, Rescale, HRotate at l = 30 and 12, against the
+    oracle."""
+    from paper_2507_04775_amd import ckks
+    s = setup("large")
+    try:
+        for n in range(1, 129):
+            ckks.ntt_tile_set(1, n, 2)
+        assert ckks.ntt_tile_get(True, 35) == 2
+        mods = list(s.ps.q) + list(s.ps.p)
+        a = inputs.uniform_residues(inputs.rng(950), mods, s.N)
+        for lo, n in [(0, len(mods)), (s.ps.L + 1, s.ps.K), (3, 2), (0, 8), (s.ps.L, 1)]:
+            t = s.dev(a[lo: lo + n])
+            s.ctx.ckks_intt(t, lo, n)
+            assert_equal(s.host(t), oracle.intt(mods[lo: lo + n], a[lo: lo + n], s.ps.logn), "intt4 %d limbs" % n)
+        key, kh = s.key(960, 0)
+        g = oracle.galois_for_rotation(s.ps.logn, 3)
+        rkey, rkh = s.key(961, g)
+        for level in (30, 12):
+            x, tx = s.ct(970 + level, level)
+            y, ty = s.ct(980 + level, level)
+            out = s.ctx.empty_ct(level)
+            s.ctx.ckks_hmult_relin(tx, ty, kh, out)
+            w0, w1 = oracle.hmult_relin(s.P, x, y, key, level)
+            assert_equal(s.host(out.c0), w0, "hmult level %d" % level)
+            assert_equal(s.host(out.c1), w1, "hmult level %d" % level)
+            low = s.ctx.empty_ct(level - 1)
+            s.ctx.ckks_rescale(tx, low)
+            w0, w1 = oracle.rescale(s.P, x, level)
+            assert_equal(s.host(low.c0), w0, "rescale level %d" % level)
+            assert_equal(s.host(low.c1), w1, "rescale level %d" % level)
+            s.ctx.ckks_hrotate(tx, 3, rkh, out)
+            w0, w1 = oracle.apply_galois(s.P, x, g, rkey, level)
+            assert_equal(s.host(out.c0), w0, "hrotate level %d" % level)
+            assert_equal(s.host(out.c1), w1, "hrotate level %d" % level)
+    finally:
+        for n in range(1, 129):
+            ckks.ntt_tile_set(1, n, 0)
+
+
 @pytest.mark.parametrize("tile", [4, 8, 16])
 def test_every_ntt_tile_width_is_bit_exact(tile):
     """The N = 2^16 passes with 4-, 8- and 16-wide tiles forced on every launch
