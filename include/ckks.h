@@ -120,9 +120,9 @@ ckks_status ckks_intt(ckks_ctx *ctx, uint64_t *poly, uint32_t limb0, uint32_t n_
  * or 4 (128).  Narrow tiles give a launch over few limbs more workgroups to
  * spread over the CUs.  Inverse launches also take tile code 2: 8 columns
  * (rows) with 64 threads on each, 4 elements per thread (512 threads), twice
- * the waves for latency-bound launches over few limbs; it applies to the plain
- * inverse (the ModDown and Rescale INTTs, ckks_intt), other inverse stages then
- * use 8.  The choice holds per direction (inverse 0 / 1) and per number of
+ * the waves for latency-bound launches over few limbs; every inverse column
+ * pass has this form, and the plain inverse row pass (the ModDown and Rescale
+ * INTTs, ckks_intt); the gathered and tensor row passes then use tiles of 8.  The choice holds per direction (inverse 0 / 1) and per number of
  * limbs in the launch (1..128), for every NTT launch of every operation in the
  * process; tile 0 restores the default (16 from 24 limbs up, 8 from 6, else 4;
  * inverse launches of at most 8 limbs 2).  Results do not depend on it.  An

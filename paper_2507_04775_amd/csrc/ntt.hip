@@ -1386,13 +1386,14 @@ bool stage_kernels(NttStage st, uint32_t logn, int pass, StageKernels &k, uint32
         default: return false;
         }
     }
-    if (tw == 2) {  // 4 elements per thread: the plain inverse only (other stages take tiles of 8)
-        if (st == STAGE_INV_PLAIN) {
+    if (tw == 2) {  // 4 elements per thread: the column pass of every inverse, the plain row pass
+        const bool inv = st == STAGE_INV_PLAIN || st == STAGE_INV_GALOIS || st == STAGE_INV_TENSOR;
+        if (inv && (pass == 1 || st == STAGE_INV_PLAIN)) {
             k.grid = pass == 0 ? k_inv_row4 : k_inv_col4;
             k.queue = nullptr;
             return true;
         }
-        tw = 8;
+        tw = 8;  // the other row passes take tiles of 8
     }
     switch (st) {
     case STAGE_FWD_PLAIN:
@@ -1457,8 +1458,17 @@ static uint32_t default_tile(uint32_t nlimbs)
     return nlimbs >= 6 ? 8 : 4;
 }
 
-// tile code 2 (the 4-element inverse passes) applies to STAGE_INV_PLAIN only
-static uint32_t effective_tile(NttStage st, uint32_t tw) { return tw == 2 && st != STAGE_INV_PLAIN ? 8 : tw; }
+// tile code 2 (the 4-element inverse passes) applies to inverse stages only; a pass without a
+// 4-element kernel (the gathered or tensor row passes) runs with tiles of 8
+static uint32_t effective_tile(NttStage st, uint32_t tw)
+{
+    const bool inv = st == STAGE_INV_PLAIN || st == STAGE_INV_GALOIS || st == STAGE_INV_TENSOR;
+    return tw == 2 && !inv ? 8 : tw;
+}
+static bool four_element_pass(NttStage st, uint32_t pass, uint32_t tw)
+{
+    return tw == 2 && (pass == 1 || st == STAGE_INV_PLAIN);
+}
 
 static uint32_t tile_width(NttStage st, uint32_t logn, uint32_t nlimbs)
 {
@@ -1479,8 +1489,10 @@ hipError_t launch_ntt_stage(NttStage st, const NttArgs &a0, uint32_t nlimbs, hip
     for (uint32_t pass = 0; pass < ntt_passes(a.logn); ++pass) {
         StageKernels k;
         if (!stage_kernels(st, a.logn, pass, k, tw)) return hipErrorInvalidValue;
-        const uint32_t tiles = a.logn == 12 ? 1 : tw == 2 ? 32 : 256 / tw;
-        const uint32_t threads = a.logn == 12 ? kThreads : tw == 2 ? 512 : 32 * tw;
+        const bool four = a.logn == 16 && four_element_pass(st, pass, tw);
+        const uint32_t pw = tw == 2 ? 8 : tw;  // rows or columns per workgroup
+        const uint32_t tiles = a.logn == 12 ? 1 : 256 / pw;
+        const uint32_t threads = a.logn == 12 ? kThreads : four ? 512 : 32 * pw;
         hipLaunchKernelGGL(k.grid, dim3(tiles, nlimbs), dim3(threads), 0, stream, a);
     }
     return hipGetLastError();

@@ -292,9 +292,9 @@ def test_table_i_ops_reject_bad_arguments(name):
 def test_four_element_inverse_passes_are_bit_exact():
     """Tile code 2 on every inverse launch (8 rows or columns per workgroup, 4
     elements per thread; the default for plain inverse launches of at most 8
-    limbs, other inverse stages fall back to 8-wide tiles): INTT over 35, 8, 2
-    and 1 limbs, and HMult+relin, Rescale, HRotate at l = 30 and 12, against the
-    oracle."""
+    limbs; the gathered and tensor row passes take 8-wide tiles, their column
+    passes the 4-element form): INTT over 35, 8, 2 and 1 limbs, and HMult+relin,
+    Rescale, HRotate at l = 30 and 12, against the oracle."""
     from paper_2507_04775_amd import ckks
     s = setup("large")
     try:
