@@ -57,6 +57,11 @@ struct IntArith {
     __device__ __forceinline__ W tw(uint32_t i) const { return T[i]; }
     // the twiddle at hi + k (k below the lowest set bit of hi): read from the table
     __device__ __forceinline__ W tw_split(uint32_t hi, uint32_t k) const { return T[hi + k]; }
+    // [x y]_q of two canonical residues (HMult's d2 = a1 b1 as it is loaded)
+    __device__ __forceinline__ V product(uint64_t x, uint64_t y, const Prime &P) const
+    {
+        return reduce128(mul_wide(x, y), P);
+    }
     template <int NV>
     __device__ __forceinline__ void reduce_all(V (&)[NV]) const {}
     // Harvey forward butterfly: x, y in [0, 4q) -> [0, 4q)
@@ -105,6 +110,11 @@ struct FpArith {
     // inverse), and br(hi + k) = br(hi) + br(k) for such k, so it is T[hi] T[k], formed here (a
     // centred representative) from the row's one entry and the first entries shared by every row
     __device__ __forceinline__ W tw_split(uint32_t hi, uint32_t k) const { return fp_mulmod(T[hi], T[k], m); }
+    // [x y]_q of two canonical residues below 2^50, a centred representative
+    __device__ __forceinline__ V product(uint64_t x, uint64_t y, const Prime &) const
+    {
+        return fp_mulmod((double)x, (double)y, m);
+    }
     template <int NV>
     __device__ __forceinline__ void reduce_all(V (&v)[NV]) const
     {
@@ -689,15 +699,16 @@ __device__ __forceinline__ void inv_row_body(const NttArgs &a, const LimbPos &lp
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
         const uint32_t e = b * 256 + pos_wide(s, i);
-        if (PRO == PRO_TENSOR)  // HMult's d2 = a1 b1, formed on the fly
-            L[row_slot(pos_wide(s, i))] = reduce128(mul_wide(src[e], a.src2[row_off + e]), P);
+        if (PRO == PRO_TENSOR)  // HMult's d2 = a1 b1, formed on the fly in the limb's arithmetic
+            L[row_slot(pos_wide(s, i))] = ar.to_bits(ar.product(src[e], a.src2[row_off + e], P));
         else
             L[row_slot(pos_wide(s, i))] = src[PRO == PRO_GALOIS ? galois_src(e, a.galois, 16) : e];
     }
     wave_sync();
     typename A::V v[8];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) v[i] = ar.from_u64(L[row_slot(pos_narrow(s, i))]);
+    for (int i = 0; i < 8; ++i)
+        v[i] = PRO == PRO_TENSOR ? ar.from_bits(L[row_slot(pos_narrow(s, i))]) : ar.from_u64(L[row_slot(pos_narrow(s, i))]);
     ar.reduce_all(v);
     inv_rw<2>(v, wa, ar);
     inv_rw<2>(v + 4, wa + 3, ar);
