@@ -208,6 +208,20 @@ hipError_t keyswitch_extended(ckks_ctx *c, const uint64_t *d, uint32_t g, uint32
     return e;
 }
 
+hipError_t keyswitch_extended_fold(ckks_ctx *c, const uint64_t *d, uint32_t g, uint32_t level, const uint64_t *key,
+                                   void *ws, hipStream_t st, const uint64_t *c0, uint64_t *tot, bool first)
+{
+    KsWs w = ks_ws(c, level, ws);
+    hipError_t e = modup_intt(c, d, g, level, w.dc, st);
+    if (e == hipSuccess) e = modup_from_coeffs(c, d, g, level, w.dc, w.ext, false, st);
+    if (e != hipSuccess) return e;
+    IpArgs ip = args_ip(c, w.ext, level, key, 1, w.acc, d, g);
+    ip.fold_c0 = c0;
+    ip.fold_tot = tot;
+    ip.fold_first = first ? 1 : 0;
+    return launch_inner_product(ip, st);
+}
+
 hipError_t moddown_pair(ckks_ctx *c, const uint64_t *x, uint32_t level, uint64_t *out0, uint64_t *out1, void *ws,
                         hipStream_t st)
 {

@@ -395,25 +395,25 @@ struct Runner {
                 for (uint32_t o = 0; o < cnt; ++o) {
                     const Ct &P = outs[o];
                     const uint32_t G = (uint32_t)(((int64_t)g.giant[pair[o]] % b->n + b->n) % b->n);
-                    FoldArgs fa = base;
-                    fa.tot[0] = tot(ln);
-                    fa.tot[1] = tot(ln) + (size_t)rows * N;
-                    fa.first = !started[ln];
+                    const bool first = !started[ln];
                     started[ln] = true;
-                    fa.s[0] = P.c0;
                     if (G != 0) {
+                        // the giant step's key switch accumulates acc + [P]_q phi_g(c0) into the lane's
+                        // total in its inner product's launch (no acc in memory, no fold launch)
                         const ckks_key *rk = b->rot.at(G);
-                        uint64_t *acc = nullptr;
-                        TRY(dev(keyswitch_extended(ctx(), P.c1, rk->galois, lvl, rk->data, L_.ws, R_.st, &acc),
+                        TRY(dev(keyswitch_extended_fold(ctx(), P.c1, rk->galois, lvl, rk->data, L_.ws, R_.st, P.c0,
+                                                        tot(ln), first),
                                 "ckks_bootstrap giant key switch"));
-                        fa.acc[0] = acc;
-                        fa.acc[1] = acc + (size_t)rows * N;
-                        fa.galois = rk->galois;
                     } else {
+                        FoldArgs fa = base;
+                        fa.tot[0] = tot(ln);
+                        fa.tot[1] = tot(ln) + (size_t)rows * N;
+                        fa.first = first;
+                        fa.s[0] = P.c0;
                         fa.s[1] = P.c1;
                         fa.galois = 1;
+                        TRY(dev(launch_fold_ext(fa, rows, R_.st), "ckks_bootstrap fold"));
                     }
-                    TRY(dev(launch_fold_ext(fa, rows, R_.st), "ckks_bootstrap fold"));
                 }
             }
         }

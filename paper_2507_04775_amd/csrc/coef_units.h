@@ -133,6 +133,25 @@ __device__ __forceinline__ void ip_unit(const IpArgs &a, uint32_t r, uint32_t bx
         }
     }
     const Prime P = a.primes[pi];
+    if (a.fold_tot) {  // a hoisted giant step: add [P]_q phi_g(c0) and accumulate into tot
+        if (a.fold_c0 && r <= a.level) {
+            const uint32_t g = a.own_galois;
+            const uint32_t sb = g == 1 ? bx * kCoefThreads : galois_src(bx * kCoefThreads, g, a.logn) & ~(uint32_t)(kCoefThreads - 1);
+            uint64_t x = a.fold_c0[(size_t)r * N + sb + tid];
+            if (g != 1) {
+                __syncthreads();  // the digits' permuted reads are done
+                stage[tid] = x;
+                __syncthreads();
+                x = stage[galois_src(n, g, a.logn) - sb];
+            }
+            s0 = add128(s0, mul_wide(x, a.pmod[pi]));
+        }
+        uint64_t *t0 = a.fold_tot + (size_t)r * N + n, *t1 = a.fold_tot + ((size_t)a.rows + r) * N + n;
+        const uint64_t v0 = reduce128(s0, P), v1 = reduce128(s1, P);
+        *t0 = a.fold_first ? v0 : addmod(*t0, v0, P.q);
+        *t1 = a.fold_first ? v1 : addmod(*t1, v1, P.q);
+        return;
+    }
     a.acc[(size_t)r * N + n] = reduce128(s0, P);
     a.acc[((size_t)a.rows + r) * N + n] = reduce128(s1, P);
 }

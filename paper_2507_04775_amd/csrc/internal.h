@@ -297,6 +297,12 @@ struct IpArgs {
     // d0 = a0 b0, d1 = a0 b1 + a1 b0; pmod[prime] = [P]_q.  ta0 null: no tensor.
     const uint64_t *ta0, *ta1, *tb0, *tb1;
     const uint64_t *pmod;
+    // A hoisted giant step of the bootstrap folded in (grid launches; fold_tot set): instead of
+    // acc, tot_t = (fold_first ? 0 : tot_t) + acc_t + (t == 0 and r <= l ? [P]_q phi_g(fold_c0) : 0),
+    // g = own_galois, tot laid out as acc ([2][rows][N])
+    const uint64_t *fold_c0;
+    uint64_t *fold_tot;
+    uint32_t fold_first, fold_pad;
 };
 
 enum CtOp { CT_HADD = 0, CT_PTADD, CT_PTMULT, CT_SCALAR_ADD, CT_SCALAR_MULT };
@@ -456,6 +462,12 @@ struct TensorIn {
 hipError_t keyswitch_core(const ckks_ctx *c, const uint64_t *d, uint32_t g_in, uint32_t level, const uint64_t *key,
                           uint64_t *out0, uint64_t *out1, const uint64_t *add0, const uint64_t *add1, uint32_t g_add,
                           void *ws, hipStream_t st, const TensorIn *tin = nullptr);
+
+// keyswitch_extended of a hoisted giant step whose sum with [P]_q phi_g(c0) (rows
+// q_0..q_l of half 0) is accumulated into tot ([2][l+1+K][N], outside the
+// workspace): tot = (first ? 0 : tot) + that, in the inner product's launch.
+hipError_t keyswitch_extended_fold(ckks_ctx *c, const uint64_t *d, uint32_t g, uint32_t level, const uint64_t *key,
+                                   void *ws, hipStream_t st, const uint64_t *c0, uint64_t *tot, bool first);
 
 // Key switch of phi_g(d) (d at `level`, eval domain) without the ModDown: the
 // two accumulators [2][l+1+K][N] over q_0..q_l, p_0..p_{K-1} are left in the

@@ -136,6 +136,9 @@ IpArgs args_ip(const ckks_ctx *c, const uint64_t *ext, uint32_t level, const uin
     a.own_galois = own_galois;
     a.ta0 = a.ta1 = a.tb0 = a.tb1 = nullptr;
     a.pmod = c->d_pmod;
+    a.fold_c0 = nullptr;
+    a.fold_tot = nullptr;
+    a.fold_first = a.fold_pad = 0;
     return a;
 }
 
