@@ -149,13 +149,26 @@ __global__ __launch_bounds__(kThreads) void k_lincomb(LincombArgs a)
     u128 s0[NOUT], s1[NOUT];
 #pragma unroll
     for (int o = 0; o < NOUT; ++o) s0[o] = s1[o] = u128{0, 0};
-    for (uint32_t b = 0; b < a.n; ++b) {
-        const uint64_t x0 = a.a0[b][i], x1 = a.a1[b][i];
+    // the loads of four baby steps are issued before their products, so their latencies overlap
+    constexpr uint32_t G = 4;
+    for (uint32_t b0 = 0; b0 < a.n; b0 += G) {
+        uint64_t x0[G], x1[G], w[NOUT][G];
 #pragma unroll
-        for (int o = 0; o < NOUT; ++o) {
-            const uint64_t w = a.pt[o][b][i];
-            s0[o] = add128(s0[o], mul_wide(x0, w));
-            s1[o] = add128(s1[o], mul_wide(x1, w));
+        for (uint32_t t = 0; t < G; ++t) {
+            if (b0 + t >= a.n) break;
+            x0[t] = a.a0[b0 + t][i];
+            x1[t] = a.a1[b0 + t][i];
+#pragma unroll
+            for (int o = 0; o < NOUT; ++o) w[o][t] = a.pt[o][b0 + t][i];
+        }
+#pragma unroll
+        for (uint32_t t = 0; t < G; ++t) {
+            if (b0 + t >= a.n) break;
+#pragma unroll
+            for (int o = 0; o < NOUT; ++o) {
+                s0[o] = add128(s0[o], mul_wide(x0[t], w[o][t]));
+                s1[o] = add128(s1[o], mul_wide(x1[t], w[o][t]));
+            }
         }
     }
 #pragma unroll
@@ -173,10 +186,22 @@ __global__ __launch_bounds__(kThreads) void k_scalar_lincomb(ScalarLincombArgs a
     const size_t i = ((size_t)l << a.logn) + blockIdx.x * kThreads + threadIdx.x;
     const Prime P = a.primes[l];
     u128 s0 = {a.acc0 ? a.acc0[i] : 0, 0}, s1 = {a.acc1 ? a.acc1[i] : 0, 0};
-    for (uint32_t b = 0; b < a.n; ++b) {
-        const uint64_t w = a.cst[(size_t)b * a.cst_stride + l];
-        s0 = add128(s0, mul_wide(a.a0[b][i], w));
-        s1 = add128(s1, mul_wide(a.a1[b][i], w));
+    constexpr uint32_t G = 4;  // loads of four terms before their products
+    for (uint32_t b0 = 0; b0 < a.n; b0 += G) {
+        uint64_t x0[G], x1[G], w[G];
+#pragma unroll
+        for (uint32_t t = 0; t < G; ++t) {
+            if (b0 + t >= a.n) break;
+            x0[t] = a.a0[b0 + t][i];
+            x1[t] = a.a1[b0 + t][i];
+            w[t] = a.cst[(size_t)(b0 + t) * a.cst_stride + l];
+        }
+#pragma unroll
+        for (uint32_t t = 0; t < G; ++t) {
+            if (b0 + t >= a.n) break;
+            s0 = add128(s0, mul_wide(x0[t], w[t]));
+            s1 = add128(s1, mul_wide(x1[t], w[t]));
+        }
     }
     a.out0[i] = reduce128(s0, P);
     a.out1[i] = reduce128(s1, P);
