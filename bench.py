@@ -71,7 +71,7 @@ def percentile(xs, p):
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
-NTT_SOURCES = ("ntt.hip", "unit_map.h", "internal.h", "modarith.h")
+NTT_SOURCES = ("ntt.hip", "unit_map.h", "internal.h", "modarith.h", "coef_units.h")
 
 
 def ntt_sources_sha256():
@@ -130,7 +130,7 @@ def stats_ms(xs):
             "mean_ms": round(sum(xs) / len(xs), 4), "n": len(xs)}
 
 
-KERNEL_SOURCES = ("kernels.hip", "ntt.hip", "unit_map.h", "internal.h", "modarith.h", "ks_args.cpp", "api.cpp")
+KERNEL_SOURCES = ("kernels.hip", "ntt.hip", "unit_map.h", "internal.h", "modarith.h", "coef_units.h", "ks_args.cpp", "api.cpp")
 
 
 def kernel_sources_sha256():
