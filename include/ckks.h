@@ -205,7 +205,11 @@ size_t ckks_noalloc_scratch_bytes(void);
  * d2 = a1 b1, (k0, k1) = KeySwitch(d2, rlk), out = (d0 + k0, d1 + k1).
  * a, b at the same level (else CKKS_E_LEVEL); rlk must have galois 0
  * (else CKKS_E_KEY).  No rescale; out->level = level, out->scale = a.scale *
- * b.scale.  out may not alias a or b.  ws: CKKS_OP_HMULT.
+ * b.scale.  out may not alias a or b.  ws: CKKS_OP_HMULT.  At N = 2^16 the
+ * tensor is folded into the key switch (d2 formed as it is loaded by ModUp's
+ * inverse NTT and by the inner product, [P]_q d0 and [P]_q d1 added to the
+ * inner product's sums over q_0..q_l), so no d is stored; the result is the
+ * same residues.
  */
 ckks_status ckks_hmult_relin(ckks_ctx *ctx, const ckks_ct *a, const ckks_ct *b, const ckks_key *rlk, ckks_ct *out,
                              void *ws, void *stream);
