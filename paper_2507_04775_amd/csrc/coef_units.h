@@ -26,10 +26,20 @@ typedef const __attribute__((address_space(4))) uint64_t ConstU64;
 // Conv_{B->C}: y_i = [x_i (B/b_i)^-1]_{b_i} (Shoup; skipped when the inverse
 // NTT already produced y_i), then every output row c gets
 // [sum_i y_i [B/b_i]_c]_c, accumulated exactly in 128 bits and reduced once
-// (as the paper does).  `job` selects the digit (or polynomial),
+// (as the paper does): by MacSplit's four carry-free columns when the row's
+// prime is below 2^50 (its constants stored split), else by mac_cols.  `job` selects the digit (or polynomial),
 // `bz` a group of kBconvRowGroup output rows.  The source count NS is a
 // template parameter (no predicated iterations), and the constants [B/b_i]_c,
 // uniform over the workgroup, come through the scalar cache.
+template <class Acc, int NS>
+__device__ __forceinline__ uint64_t conv_sum(const uint64_t (&y)[NS], ConstU64 *h, const Prime &P)
+{
+    Acc acc;
+#pragma unroll
+    for (int i = 0; i < NS; ++i) acc.add(y[i], h[i]);
+    return reduce128(acc.total(), P);
+}
+
 template <int NS>
 __device__ __forceinline__ void bconv_rows(const BconvArgs &a, const BconvJob &J, uint32_t n, uint32_t r0,
                                            uint32_t r1)
@@ -55,10 +65,8 @@ __device__ __forceinline__ void bconv_rows(const BconvArgs &a, const BconvJob &J
         }
         const uint32_t pi = row_prime(r, a.level, a.nq);
         ConstU64 *h = (ConstU64 *)(J.hmod + (size_t)pi * kMaxDigitPrimes);
-        MacCols acc;
-#pragma unroll
-        for (int i = 0; i < NS; ++i) mac_cols(acc, y[i], h[i]);
-        J.dst[(size_t)r * N + n] = reduce128(mac_total(acc), a.primes[pi]);
+        const Prime &P = a.primes[pi];
+        J.dst[(size_t)r * N + n] = P.q < kSplitMaxConst ? conv_sum<MacSplit, NS>(y, h, P) : conv_sum<MacColsAcc, NS>(y, h, P);
     }
 }
 

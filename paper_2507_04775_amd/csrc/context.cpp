@@ -198,7 +198,9 @@ extern "C" ckks_status ckks_ctx_create(uint32_t log_n, const uint64_t *q, uint32
                 uint64_t v = 1;
                 for (uint32_t k = 0; k < ns; ++k)
                     if (k != i) v = mul_mod(v, src[k] % primes[c], primes[c]);
-                bc_hmod[(size_t)set * hm_stride + (size_t)c * kMaxDigitPrimes + i] = v;
+                // targets below 2^50 keep the constant split for the conversions' MacSplit sums
+                bc_hmod[(size_t)set * hm_stride + (size_t)c * kMaxDigitPrimes + i] =
+                    primes[c] < kSplitMaxConst ? split_const(v) : v;
             }
         }
     };

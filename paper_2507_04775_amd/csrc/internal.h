@@ -263,7 +263,7 @@ struct BconvJob {
     uint64_t *dst;              // output rows at dst + r N
     const uint64_t *copy_src;   // rows [lo, hi) copied from here to dst (may be null)
     const ulonglong2 *hinv;     // ns pairs {[(B/b_i)^-1]_{b_i}, shoup}
-    const uint64_t *hmod;       // [n_primes][kMaxDigitPrimes]: [B/b_i]_c
+    const uint64_t *hmod;       // [n_primes][kMaxDigitPrimes]: [B/b_i]_c (split_const form for c < 2^50)
     uint32_t ns;
     uint32_t src_prime0;
     uint32_t lo, hi;            // output rows not converted
@@ -430,7 +430,7 @@ struct ckks_ctx {
     double *d_twd_inv = nullptr;
     // base-conversion sets: digit sets indexed (j * alpha + size - 1), then the P set
     ulonglong2 *d_bc_hinv = nullptr;    // [nsets][kMaxDigitPrimes]
-    uint64_t *d_bc_hmod = nullptr;      // [nsets][n_primes][kMaxDigitPrimes]
+    uint64_t *d_bc_hmod = nullptr;      // [nsets][n_primes][kMaxDigitPrimes], split_const form for c < 2^50
     ulonglong2 *d_bc_ys = nullptr;      // [nsets][kMaxDigitPrimes]: N^-1 [(B/b_i)^-1]_{b_i}
     double *d_bc_ysd = nullptr;         // the same as doubles (primes below 2^50)
     ulonglong2 *d_pinv = nullptr;       // [n_primes] P^-1 mod q_i

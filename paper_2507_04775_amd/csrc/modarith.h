@@ -90,6 +90,63 @@ __host__ __device__ __forceinline__ u128 mac_total(const MacCols &c)
     return r;
 }
 
+// Exact sum of products y_i h_i for constants h_i < 2^50 and inputs y_i < 2^62,
+// at most 16 terms.  h is split at bit 27 and y at bit 32, so the four columns
+// y0 h0 (< 2^59), y0 h1 (< 2^55), y1 h0 (< 2^57) and y1 h1 (< 2^53) each stay
+// below 2^63 over 16 terms: a term is four multiply-adds with no carry to
+// count.  The value is c00 + c01 2^27 + c10 2^32 + c11 2^59.  The constant
+// arrives split (split_const: h0 in the low word, h1 in the high word), so
+// both halves are ready in scalar registers.  On the GPU the four
+// multiply-adds of a term go in one block, so consecutive terms interleave
+// four independent chains (the carry-outs, always zero here, are discarded).
+constexpr uint64_t kSplitMaxConst = 1ull << 50;
+constexpr int kSplitShift = 27;
+
+__host__ __device__ __forceinline__ uint64_t split_const(uint64_t h)
+{
+    return ((h >> kSplitShift) << 32) | (h & ((1ull << kSplitShift) - 1));
+}
+
+struct MacSplit {
+    uint64_t c00 = 0, c01 = 0, c10 = 0, c11 = 0;
+
+    // y < 2^62; hs = split_const(h) with h < 2^50
+    __host__ __device__ __forceinline__ void add(uint64_t y, uint64_t hs)
+    {
+        const uint32_t y0 = (uint32_t)y, y1 = (uint32_t)(y >> 32);
+        const uint32_t h0 = (uint32_t)hs, h1 = (uint32_t)(hs >> 32);
+#if defined(__HIP_DEVICE_COMPILE__)
+        uint64_t k;
+        asm("v_mad_u64_u32 %[c00], %[k], %[y0], %[h0], %[c00]\n\t"
+            "v_mad_u64_u32 %[c01], %[k], %[y0], %[h1], %[c01]\n\t"
+            "v_mad_u64_u32 %[c10], %[k], %[y1], %[h0], %[c10]\n\t"
+            "v_mad_u64_u32 %[c11], %[k], %[y1], %[h1], %[c11]"
+            : [c00] "+v"(c00), [c01] "+v"(c01), [c10] "+v"(c10), [c11] "+v"(c11), [k] "=&s"(k)
+            : [y0] "v"(y0), [y1] "v"(y1), [h0] "s"(h0), [h1] "s"(h1));
+#else
+        c00 = mad32(y0, h0, c00);
+        c01 = mad32(y0, h1, c01);
+        c10 = mad32(y1, h0, c10);
+        c11 = mad32(y1, h1, c11);
+#endif
+    }
+    __host__ __device__ __forceinline__ u128 total() const
+    {
+        u128 r = {c00, 0};
+        r = add128(r, u128{c01 << kSplitShift, c01 >> (64 - kSplitShift)});
+        r = add128(r, u128{c10 << 32, c10 >> 32});
+        r = add128(r, u128{c11 << (kSplitShift + 32), c11 >> (32 - kSplitShift)});
+        return r;
+    }
+};
+
+// The same interface over mac_cols, for constants up to 2^61.
+struct MacColsAcc {
+    MacCols c;
+    __device__ __forceinline__ void add(uint64_t y, uint64_t h) { mac_cols(c, y, h); }
+    __host__ __device__ __forceinline__ u128 total() const { return mac_total(c); }
+};
+
 __host__ __device__ __forceinline__ uint64_t csub(uint64_t x, uint64_t m) { return x >= m ? x - m : x; }
 
 // Shoup: x * w mod q for any 64-bit x, with ws = floor(w 2^64 / q); result in [0, 2q)

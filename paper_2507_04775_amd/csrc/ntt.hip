@@ -83,6 +83,7 @@ struct IntArith {
     }
     __device__ __forceinline__ uint64_t fwd_final(V x) const { return csub(csub(x, q2), q); }
     __device__ __forceinline__ uint64_t inv_final(V x) const { return shoup(x, fc, fc_s, q); }
+    __device__ __forceinline__ uint64_t modulus() const { return q; }
     // key inner product on canonical values
     __device__ __forceinline__ V mac_in(V x) const { return fwd_final(x); }
     __device__ __forceinline__ V own(uint64_t x) const { return x; }
@@ -137,6 +138,7 @@ struct FpArith {
     }
     __device__ __forceinline__ uint64_t fwd_final(V x) const { return fp_canonical(x, m); }
     __device__ __forceinline__ uint64_t inv_final(V x) const { return fp_canonical(fp_mulmod(x, fc, m), m); }
+    __device__ __forceinline__ uint64_t modulus() const { return (uint64_t)m.q; }
     // key inner product: |v| < 5.3 q from a forward round, the running sum re-centred each step
     __device__ __forceinline__ V mac_in(V x) const { return x; }
     __device__ __forceinline__ V own(uint64_t x) const { return (double)x; }
@@ -146,6 +148,28 @@ struct FpArith {
     }
     __device__ __forceinline__ uint64_t acc_final(V acc) const { return fp_canonical(acc, m); }
 };
+
+// Stores the last inverse pass's outputs.  For ModDown's centred conversion
+// (ys_mode 2) each canonical y of the special limb p is stored as y + p when
+// y <= (p - 1)/2, else as y: the centred representative plus p, in
+// [(p + 1)/2, 3 (p - 1)/2], below 2^62, so the conversion's sums take no
+// per-term comparison (bconv_load removes the shift).
+template <int NV, class A, class Idx>
+__device__ __forceinline__ void inv_store(uint64_t *dst, const typename A::V (&v)[NV], const A &ar, uint32_t ys_mode,
+                                          Idx idx)
+{
+    if (ys_mode == 2) {
+        const uint64_t q = ar.modulus(), half = q >> 1;
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            const uint64_t y = ar.inv_final(v[i]);
+            dst[idx(i)] = y <= half ? y + q : y;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) dst[idx(i)] = ar.inv_final(v[i]);
+    }
+}
 
 // LOG forward stages on v[i] = element base + STRIDE i (i < 2^LOG) of an
 // NS-point problem: t = 2^(LOG-1) STRIDE, ..., STRIDE.  base = a 2^LOG STRIDE
@@ -408,7 +432,7 @@ struct BcSrc {
     const uint64_t *y;   // ns scaled source rows, stride N
     const uint64_t *hm;  // [B/b_i] mod the target prime, i < ns
     uint32_t ns;
-    const Prime *src;    // centred conversion (ModDown): the source primes, else null
+    const Prime *src;    // centred conversion (ModDown, inputs shifted by p_k): the source primes, else null
     uint64_t bq;         // [B]_q of the target prime (centred conversion)
 };
 
@@ -435,27 +459,28 @@ __device__ __forceinline__ BcSrc bc_source(const NttArgs &a, uint32_t poly, uint
 }
 
 // v[i] = Conv(y)[pos(i)]: sum_k y_k[pos] [B/b_k]_q accumulated exactly, reduced
-// once.  The sums go by 32-bit columns (mac_cols: four multiply-adds and three
-// carry additions per term, the constant in scalar registers); groups of four
-// elements keep the column sums in few registers.  The loads of source row
-// k+1 are issued before the products of row k, so the latency of the source
-// rows overlaps the arithmetic.
-template <int NV, class A, class Pos>
-__device__ __forceinline__ void bconv_load(typename A::V (&v)[NV], const A &ar, const BcSrc &b, const Prime &P,
-                                           size_t N, Pos pos)
+// once.  Acc sums by 32-bit columns: MacSplit (four multiply-adds per term)
+// when the target prime, and so every constant, is below 2^50 (the table holds
+// those constants split), else MacCols
+// (four multiply-adds and three carry additions; the constants in scalar
+// registers either way).  Groups of four elements keep the column sums in few
+// registers.  The loads of source row k+1 are issued before the products of
+// row k, so the latency of the source rows overlaps the arithmetic.  For
+// ModDown's centred conversion the inverse NTT stored u_k = y_k + p_k with
+// y_k centred: sum_k p_k [P/p_k]_q = K [P]_q (mod q), which `corr` removes
+// after the reduction.
+template <class Acc, int NV, class A, class Pos>
+__device__ __forceinline__ void bconv_sum(typename A::V (&v)[NV], const A &ar, const BcSrc &b, const Prime &P,
+                                          size_t N, Pos pos, uint64_t corr)
 {
     constexpr int G = 4;
     static_assert(NV % G == 0, "groups of four elements");
 #pragma unroll
     for (int grp = 0; grp < NV / G; ++grp) {
-        MacCols acc[G];
-        uint32_t high[G];
+        Acc acc[G];
         uint64_t cur[G];
 #pragma unroll
-        for (int i = 0; i < G; ++i) {
-            high[i] = 0;
-            cur[i] = b.y[pos(G * grp + i)];
-        }
+        for (int i = 0; i < G; ++i) cur[i] = b.y[pos(G * grp + i)];
         for (uint32_t k = 0; k < b.ns; ++k) {
             const bool more = k + 1 < b.ns;
             uint64_t nxt[G];
@@ -465,27 +490,27 @@ __device__ __forceinline__ void bconv_load(typename A::V (&v)[NV], const A &ar, 
                 for (int i = 0; i < G; ++i) nxt[i] = yn[pos(G * grp + i)];
             }
             const uint64_t h = ((const __attribute__((address_space(4))) uint64_t *)b.hm)[k];  // scalar cache
-            const uint64_t half_k = b.src ? (b.src[k].q - 1) >> 1 : ~0ull;
 #pragma unroll
-            for (int i = 0; i < G; ++i) {
-                mac_cols(acc[i], cur[i], h);
-                high[i] += cur[i] > half_k;
-            }
+            for (int i = 0; i < G; ++i) acc[i].add(cur[i], h);
             if (more) {
 #pragma unroll
                 for (int i = 0; i < G; ++i) cur[i] = nxt[i];
             }
         }
-        // y_k - p_k for the high inputs: subtracting high [P]_q equals adding high (q - [P]_q), which
-        // joins the exact sum before its one reduction (high <= 16, so the sum stays below 2^127)
-        const uint64_t nbq = b.src ? P.q - b.bq : 0;
 #pragma unroll
-        for (int i = 0; i < G; ++i) {
-            const u128 t = mac_total(acc[i]);
-            const u128 z = b.src ? add128(t, mul_wide((uint64_t)high[i], nbq)) : t;
-            v[G * grp + i] = ar.from_u64(reduce128(z, P));
-        }
+        for (int i = 0; i < G; ++i) v[G * grp + i] = ar.from_u64(submod(reduce128(acc[i].total(), P), corr, P.q));
     }
+}
+
+template <int NV, class A, class Pos>
+__device__ __forceinline__ void bconv_load(typename A::V (&v)[NV], const A &ar, const BcSrc &b, const Prime &P,
+                                           size_t N, Pos pos)
+{
+    const uint64_t corr = b.src ? reduce128(mul_wide((uint64_t)b.ns, b.bq), P) : 0;
+    if (P.q < kSplitMaxConst)
+        bconv_sum<MacSplit>(v, ar, b, P, N, pos, corr);
+    else
+        bconv_sum<MacColsAcc>(v, ar, b, P, N, pos, corr);
 }
 
 // ------------------------------------------------------------------ N = 2^16
@@ -778,8 +803,7 @@ __device__ __forceinline__ void inv_col_body(const NttArgs &a, const LimbPos &lp
     ar.reduce_all(v);
     inv_rw<3>(v, wc, ar);
     uint64_t *dst = a.dst + (int64_t)lp.poly * a.map.dst_poly_stride + (size_t)lp.row * 65536;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) dst[pos_wide(s, i) * 256 + c] = ar.inv_final(v[i]);
+    inv_store(dst, v, ar, a.ys_mode, [&](int i) { return pos_wide(s, i) * 256 + c; });
 }
 
 template <int TW = 16>
@@ -899,8 +923,7 @@ __device__ __forceinline__ void inv_col4_body(const NttArgs &a, const LimbPos &l
     ar.reduce_all(v);
     inv_rw<2>(v, wb, ar);
     uint64_t *dst = a.dst + (int64_t)lp.poly * a.map.dst_poly_stride + (size_t)lp.row * 65536;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) dst[p4d(s, i) * 256 + c] = ar.inv_final(v[i]);
+    inv_store(dst, v, ar, a.ys_mode, [&](int i) { return p4d(s, i) * 256 + c; });
 }
 
 __device__ __forceinline__ void inv_row4_unit(const NttArgs &a, uint32_t limb, uint32_t tile, uint64_t *lds,
@@ -1032,8 +1055,7 @@ __device__ __forceinline__ void inv12_body(const NttArgs &a, const LimbPos &lp, 
     ar.reduce_all(v);
     inv16<4096, 256>(v, t, ar, 1);
     uint64_t *dst = a.dst + (int64_t)lp.poly * a.map.dst_poly_stride + (size_t)lp.row * 4096;
-#pragma unroll
-    for (int i = 0; i < 16; ++i) dst[t + 256 * i] = ar.inv_final(v[i]);
+    inv_store(dst, v, ar, a.ys_mode, [&](int i) { return t + 256 * i; });
 }
 
 template <int PRO>

@@ -8,7 +8,11 @@
 // their instruction sequence: each v_mad_u64_u32 is a 32x32+64 product with a
 // carry-out bit, each v_addc_co_u32 a 32-bit add with carry-in; mac_total of
 // the emulated columns must equal the exact 128-bit sum, with operands at
-// 2^61 - 1 and up to 2^16 - 1 terms.  Prints "ok" and exits 0 on success.
+// 2^61 - 1 and up to 2^16 - 1 terms.  The split columns (MacSplit) are checked
+// at their limits (constants below 2^50, inputs below 2^62, 16 terms), and
+// ModDown's centred conversion from inputs shifted by p_k against the exact
+// signed sum.  Prints "ok" and exits 0 on success.
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <random>
@@ -208,6 +212,95 @@ int main()
             want += (u128x)yh.first * yh.second;
         }
         CHECK(emu_total(e) == want, "mac_cols columns, %zu terms", t.size());
+    }
+
+    // split columns (MacSplit): constants below 2^50, inputs below 2^62, up to 16 terms
+    {
+        const uint64_t hmax = (1ull << 50) - 1, ymax = (1ull << 62) - 1;
+        const std::vector<uint64_t> hs = {0, 1, (1ull << 27) - 1, 1ull << 27, (1ull << 27) + 1, 0xFFFFFFFFull, hmax};
+        const std::vector<uint64_t> ys = {0, 1, 0xFFFFFFFFull, 1ull << 32, ymax, (1ull << 61) + (1ull << 60) - 1};
+        for (int n : {1, 2, 4, 11, 15, 16}) {
+            for (uint64_t h : hs)
+                for (uint64_t y : ys) {
+                    MacSplit m;
+                    u128x want = 0;
+                    for (int i = 0; i < n; ++i) {
+                        m.add(y, split_const(h));
+                        want += (u128x)y * h;
+                    }
+                    CHECK(to128(m.total()) == want, "MacSplit %d terms of %llx * %llx", n, (unsigned long long)y,
+                          (unsigned long long)h);
+                }
+            for (int rep = 0; rep < 200; ++rep) {
+                MacSplit m;
+                u128x want = 0;
+                for (int i = 0; i < n; ++i) {
+                    const uint64_t y = rep % 4 ? rng() & ymax : ymax - (rng() & 0xFF);
+                    const uint64_t h = rep % 3 ? rng() & hmax : hmax - (rng() & 0xFF);
+                    m.add(y, split_const(h));
+                    want += (u128x)y * h;
+                }
+                CHECK(to128(m.total()) == want, "MacSplit %d seeded terms", n);
+            }
+        }
+    }
+
+    // ModDown's centred conversion from shifted inputs: the inverse NTT stores u_k = y_k + p_k
+    // when y_k <= (p_k - 1)/2, else y_k; the conversion sums u_k [P/p_k]_q exactly, reduces, and
+    // subtracts K [P]_q.  That must equal sum_k yc_k [P/p_k]_q mod q with yc_k the centred
+    // representative, for 50-bit targets (split columns) and 60-bit ones (mac_cols).
+    {
+        auto mulm = [](uint64_t a, uint64_t b, uint64_t m) { return (uint64_t)((u128x)a * b % m); };
+        const std::vector<uint64_t> sp = primes_of(60, 16);
+        std::vector<uint64_t> targets = primes_of(50, 2);
+        for (uint64_t q : primes_of(60, 18))
+            if (std::find(sp.begin(), sp.end(), q) == sp.end()) targets.push_back(q);
+        for (int K : {1, 2, 4, 10, 16})
+            for (uint64_t q : targets) {
+                const Prime P = prime_of(q);
+                uint64_t pq = 1;  // [P]_q
+                for (int k = 0; k < K; ++k) pq = mulm(pq, sp[k] % q, q);
+                std::vector<uint64_t> h(K);  // [P/p_k]_q
+                for (int k = 0; k < K; ++k) {
+                    h[k] = 1;
+                    for (int j = 0; j < K; ++j)
+                        if (j != k) h[k] = mulm(h[k], sp[j] % q, q);
+                }
+                const uint64_t corr = reduce128(mul_wide((uint64_t)K, pq), P);
+                for (int rep = 0; rep < 300; ++rep) {
+                    std::vector<uint64_t> y(K);
+                    for (int k = 0; k < K; ++k) {
+                        const uint64_t p = sp[k];
+                        const uint64_t edge[] = {0, 1, (p - 1) / 2, (p + 1) / 2, p - 1};
+                        y[k] = rep < 5 ? edge[rep] : (rep % 7 == 0 ? edge[rng() % 5] : rng() % p);
+                    }
+                    // exact centred sum, reduced
+                    __int128 exact = 0;
+                    for (int k = 0; k < K; ++k) {
+                        const __int128 yc = y[k] <= (sp[k] - 1) / 2 ? (__int128)y[k] : (__int128)y[k] - sp[k];
+                        exact += yc * (__int128)h[k];
+                    }
+                    __int128 rm = exact % (__int128)q;
+                    if (rm < 0) rm += q;
+                    u128x z = 0;
+                    MacSplit ms;
+                    Emu e;
+                    for (int k = 0; k < K; ++k) {
+                        const uint64_t u = y[k] <= (sp[k] >> 1) ? y[k] + sp[k] : y[k];
+                        CHECK(u < (1ull << 62), "shifted input below 2^62");
+                        z += (u128x)u * h[k];
+                        if (q < kSplitMaxConst)
+                            ms.add(u, split_const(h[k]));
+                        else
+                            emu_mac(e, u, h[k]);
+                    }
+                    const u128x tot = q < kSplitMaxConst ? to128(ms.total()) : emu_total(e);
+                    CHECK(tot == z, "conversion sum, K=%d q=%llu", K, (unsigned long long)q);
+                    const uint64_t got = submod(reduce128(from128(tot), P), corr, q);
+                    CHECK(got == (uint64_t)rm, "centred conversion from shifted inputs, K=%d q=%llu", K,
+                          (unsigned long long)q);
+                }
+            }
     }
 
     if (fails) {
