@@ -502,15 +502,53 @@ __device__ __forceinline__ void bconv_sum(typename A::V (&v)[NV], const A &ar, c
     }
 }
 
+// The same for at most kConvBatch source rows: every load of a group is
+// issued before its first product, one wait per group instead of one per row.
+constexpr uint32_t kConvBatch = 4;
+
+template <class Acc, int NV, class A, class Pos>
+__device__ __forceinline__ void bconv_sum_few(typename A::V (&v)[NV], const A &ar, const BcSrc &b, const Prime &P,
+                                              size_t N, Pos pos, uint64_t corr)
+{
+    constexpr int G = 4;
+    static_assert(NV % G == 0, "groups of four elements");
+#pragma unroll
+    for (int grp = 0; grp < NV / G; ++grp) {
+        uint64_t y[kConvBatch][G];
+#pragma unroll
+        for (uint32_t k = 0; k < kConvBatch; ++k)
+            if (k < b.ns) {
+#pragma unroll
+                for (int i = 0; i < G; ++i) y[k][i] = b.y[(size_t)k * N + pos(G * grp + i)];
+            }
+        Acc acc[G];
+#pragma unroll
+        for (uint32_t k = 0; k < kConvBatch; ++k)
+            if (k < b.ns) {
+                const uint64_t h = ((const __attribute__((address_space(4))) uint64_t *)b.hm)[k];  // scalar cache
+#pragma unroll
+                for (int i = 0; i < G; ++i) acc[i].add(y[k][i], h);
+            }
+#pragma unroll
+        for (int i = 0; i < G; ++i) v[G * grp + i] = ar.from_u64(submod(reduce128(acc[i].total(), P), corr, P.q));
+    }
+}
+
 template <int NV, class A, class Pos>
 __device__ __forceinline__ void bconv_load(typename A::V (&v)[NV], const A &ar, const BcSrc &b, const Prime &P,
                                            size_t N, Pos pos)
 {
     const uint64_t corr = b.src ? reduce128(mul_wide((uint64_t)b.ns, b.bq), P) : 0;
-    if (P.q < kSplitMaxConst)
+    if (b.ns <= kConvBatch) {
+        if (P.q < kSplitMaxConst)
+            bconv_sum_few<MacSplit>(v, ar, b, P, N, pos, corr);
+        else
+            bconv_sum_few<MacColsAcc>(v, ar, b, P, N, pos, corr);
+    } else if (P.q < kSplitMaxConst) {
         bconv_sum<MacSplit>(v, ar, b, P, N, pos, corr);
-    else
+    } else {
         bconv_sum<MacColsAcc>(v, ar, b, P, N, pos, corr);
+    }
 }
 
 // ------------------------------------------------------------------ N = 2^16
