@@ -1131,19 +1131,19 @@ constexpr int kLds12 = 4352;
 // (run_work_queue_uniform).  Those at N = 2^12 keep it in LDS: with 16
 // elements per thread they already need close to the scalar register file,
 // and a scalar copy would spill to scratch.
-#define NTT_KERNELS(NAME, LDS, UNIT, THREADS, UNIFORM)                                          \
-    __global__ __launch_bounds__(THREADS) void k_##NAME(NttArgs a)                               \
+#define NTT_KERNELS(NAME, LDS, THREADS, UNIFORM, GRID_ATTR, ...)                                \
+    __global__ __launch_bounds__(THREADS) GRID_ATTR void k_##NAME(NttArgs a)                     \
     {                                                                                             \
         __shared__ uint64_t lds[LDS];                                                             \
         const UnitId u = grid_unit(a);                                                            \
-        UNIT(a, u.limb, u.tile, lds, threadIdx.x);                                                \
+        __VA_ARGS__(a, u.limb, u.tile, lds, threadIdx.x);                                         \
     }                                                                                             \
     __global__ __launch_bounds__(THREADS) void q_##NAME(const NttArgs *insts, WorkQueue q)        \
     {                                                                                             \
         __shared__ uint64_t lds[LDS];                                                             \
         __shared__ uint32_t claim;                                                                \
         auto body = [&](const NttArgs &a, uint32_t limb, uint32_t tile) {                        \
-            UNIT(a, limb, tile, lds, UNIFORM ? thread_index() : threadIdx.x);                     \
+            __VA_ARGS__(a, limb, tile, lds, UNIFORM ? thread_index() : threadIdx.x);              \
         };                                                                                        \
         if constexpr (UNIFORM) {                                                                  \
             run_work_queue_uniform(insts, q, &claim, body);                                       \
@@ -1153,16 +1153,18 @@ constexpr int kLds12 = 4352;
         }                                                                                         \
     }
 
-NTT_KERNELS(fwd_col_plain, kLds16, fwd_col_unit<PRO_PLAIN>, kThreads16, true)
-NTT_KERNELS(fwd_col_rescale, kLds16, fwd_col_unit<PRO_RESCALE>, kThreads16, true)
-NTT_KERNELS(fwd_col_bconv, kLds16, fwd_col_unit<PRO_BCONV>, kThreads16, true)
-NTT_KERNELS(fwd_row_plain, kLds16, fwd_row_unit<EPI_PLAIN>, kThreads16, true)
-NTT_KERNELS(fwd_row_moddown, kLds16, fwd_row_unit<EPI_MODDOWN>, kThreads16, true)
-NTT_KERNELS(fwd_row_rescale, kLds16, fwd_row_unit<EPI_RESCALE>, kThreads16, true)
-NTT_KERNELS(inv_row_plain, kLds16, inv_row_unit<PRO_PLAIN>, kThreads16, true)
-NTT_KERNELS(inv_row_galois, kLds16, inv_row_unit<PRO_GALOIS>, kThreads16, true)
-NTT_KERNELS(inv_row_tensor, kLds16, inv_row_unit<PRO_TENSOR>, kThreads16, true)
-NTT_KERNELS(inv_col, kLds16, inv_col_unit, kThreads16, true)
+#define OCC6 __attribute__((amdgpu_waves_per_eu(6)))
+
+NTT_KERNELS(fwd_col_plain, kLds16, kThreads16, true, OCC6, fwd_col_unit<PRO_PLAIN>)
+NTT_KERNELS(fwd_col_rescale, kLds16, kThreads16, true, , fwd_col_unit<PRO_RESCALE>)
+NTT_KERNELS(fwd_col_bconv, kLds16, kThreads16, true, , fwd_col_unit<PRO_BCONV>)
+NTT_KERNELS(fwd_row_plain, kLds16, kThreads16, true, , fwd_row_unit<EPI_PLAIN>)
+NTT_KERNELS(fwd_row_moddown, kLds16, kThreads16, true, , fwd_row_unit<EPI_MODDOWN>)
+NTT_KERNELS(fwd_row_rescale, kLds16, kThreads16, true, , fwd_row_unit<EPI_RESCALE>)
+NTT_KERNELS(inv_row_plain, kLds16, kThreads16, true, , inv_row_unit<PRO_PLAIN>)
+NTT_KERNELS(inv_row_galois, kLds16, kThreads16, true, , inv_row_unit<PRO_GALOIS>)
+NTT_KERNELS(inv_row_tensor, kLds16, kThreads16, true, , inv_row_unit<PRO_TENSOR>)
+NTT_KERNELS(inv_col, kLds16, kThreads16, true, OCC6, inv_col_unit)
 // Grid kernels with narrower tiles (TW = 8, 4 columns or rows per workgroup of
 // 32 TW threads), for launches over few limbs; unit = (blockIdx.x, blockIdx.y).
 #define NTT_NARROW(NAME, UNIT_T)                                                                    \
@@ -1224,19 +1226,20 @@ NTT_NARROW(inv_col, U_IC)
 #define FWD12_RR fwd12_unit<PRO_RESCALE, EPI_RESCALE>
 #define FWD12_RP fwd12_unit<PRO_RESCALE, EPI_PLAIN>
 #define FWD12_BM fwd12_unit<PRO_BCONV, EPI_MODDOWN>
-NTT_KERNELS(fwd12_plain, kLds12, FWD12_PP, kThreads, false)
-NTT_KERNELS(fwd12_moddown, kLds12, FWD12_PM, kThreads, false)
-NTT_KERNELS(fwd12_rescale, kLds12, FWD12_RR, kThreads, false)
-NTT_KERNELS(fwd12_lift, kLds12, FWD12_RP, kThreads, false)
-NTT_KERNELS(fwd12_bconv_moddown, kLds12, FWD12_BM, kThreads, false)
-NTT_KERNELS(inv12_plain, kLds12, inv12_unit<PRO_PLAIN>, kThreads, false)
-NTT_KERNELS(inv12_galois, kLds12, inv12_unit<PRO_GALOIS>, kThreads, false)
+NTT_KERNELS(fwd12_plain, kLds12, kThreads, false, , FWD12_PP)
+NTT_KERNELS(fwd12_moddown, kLds12, kThreads, false, , FWD12_PM)
+NTT_KERNELS(fwd12_rescale, kLds12, kThreads, false, , FWD12_RR)
+NTT_KERNELS(fwd12_lift, kLds12, kThreads, false, , FWD12_RP)
+NTT_KERNELS(fwd12_bconv_moddown, kLds12, kThreads, false, , FWD12_BM)
+NTT_KERNELS(inv12_plain, kLds12, kThreads, false, , inv12_unit<PRO_PLAIN>)
+NTT_KERNELS(inv12_galois, kLds12, kThreads, false, , inv12_unit<PRO_GALOIS>)
 #undef FWD12_PP
 #undef FWD12_PM
 #undef FWD12_RR
 #undef FWD12_RP
 #undef FWD12_BM
 #undef NTT_KERNELS
+#undef OCC6
 
 // ------------------------------------------- one launch for a whole batch
 // The persistent kernel of a batch of key switches in one launch (N = 2^16):
