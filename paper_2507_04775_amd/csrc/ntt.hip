@@ -1153,15 +1153,19 @@ constexpr int kLds12 = 4352;
         }                                                                                         \
     }
 
+// Three 512-thread workgroups per CU for the plain passes: the column passes
+// fit in 72 VGPRs; the row passes spill 12 to 16 bytes per lane and still gain
+// over 35 limbs (not over 74, and the tensor prologue's pass loses, so it
+// keeps two workgroups per CU).
 #define OCC6 __attribute__((amdgpu_waves_per_eu(6)))
 
 NTT_KERNELS(fwd_col_plain, kLds16, kThreads16, true, OCC6, fwd_col_unit<PRO_PLAIN>)
 NTT_KERNELS(fwd_col_rescale, kLds16, kThreads16, true, , fwd_col_unit<PRO_RESCALE>)
 NTT_KERNELS(fwd_col_bconv, kLds16, kThreads16, true, , fwd_col_unit<PRO_BCONV>)
-NTT_KERNELS(fwd_row_plain, kLds16, kThreads16, true, , fwd_row_unit<EPI_PLAIN>)
+NTT_KERNELS(fwd_row_plain, kLds16, kThreads16, true, OCC6, fwd_row_unit<EPI_PLAIN>)
 NTT_KERNELS(fwd_row_moddown, kLds16, kThreads16, true, , fwd_row_unit<EPI_MODDOWN>)
 NTT_KERNELS(fwd_row_rescale, kLds16, kThreads16, true, , fwd_row_unit<EPI_RESCALE>)
-NTT_KERNELS(inv_row_plain, kLds16, kThreads16, true, , inv_row_unit<PRO_PLAIN>)
+NTT_KERNELS(inv_row_plain, kLds16, kThreads16, true, OCC6, inv_row_unit<PRO_PLAIN>)
 NTT_KERNELS(inv_row_galois, kLds16, kThreads16, true, , inv_row_unit<PRO_GALOIS>)
 NTT_KERNELS(inv_row_tensor, kLds16, kThreads16, true, , inv_row_unit<PRO_TENSOR>)
 NTT_KERNELS(inv_col, kLds16, kThreads16, true, OCC6, inv_col_unit)
