@@ -78,12 +78,14 @@ hipError_t inner_product(const ckks_ctx *c, const uint64_t *ext, uint32_t level,
 // conversion inputs y_k = [a_k (P/p_k)^-1] (N^-1 folded into the same
 // constant); the forward NTT computes the conversion in its first pass and the
 // P^-1 (x - .) + add sequence in its last (III-F.5 ModDown fusion).
+// row_done: the inner product already ran the INTT's first pass (launch_inner_product_rowpass).
 hipError_t moddown(const ckks_ctx *c, const uint64_t *acc, int64_t acc_stride, uint32_t npoly, uint32_t level,
                    uint64_t *const *out, const uint64_t *const *add, uint32_t g, uint64_t *pc, uint64_t *conv,
-                   hipStream_t st)
+                   hipStream_t st, bool row_done = false)
 {
     KsSizes s = ks_sizes(c, level);
-    hipError_t e = launch_ntt_stage(STAGE_INV_PLAIN, args_moddown_intt(c, acc, acc_stride, level, pc), npoly * c->np, st);
+    hipError_t e = launch_ntt_stage(STAGE_INV_PLAIN, args_moddown_intt(c, acc, acc_stride, level, pc), npoly * c->np, st,
+                                    row_done ? 1 : 0);
     if (e != hipSuccess) return e;
     return launch_ntt_stage(STAGE_FWD_BCONV_MODDOWN,
                             args_moddown_ntt(c, acc, acc_stride, npoly, level, out, add, g, pc, conv), npoly * s.n, st);
@@ -127,11 +129,15 @@ hipError_t keyswitch_core(const ckks_ctx *c, const uint64_t *d, uint32_t g_in, u
         ip.tb0 = tin->b0;
         ip.tb1 = tin->b1;
     }
-    e = launch_inner_product(ip, st);
+    // at N = 2^16 the inner product also runs the first pass of ModDown's INTT on the special rows
+    const int64_t acc_stride = (int64_t)s.rows * s.N;
+    const bool rowpass = c->logn == 16;
+    e = rowpass ? launch_inner_product_rowpass(ip, args_moddown_intt(c, w.acc, acc_stride, level, w.pc), st)
+                : launch_inner_product(ip, st);
     if (e != hipSuccess) return e;
     uint64_t *outs[2] = {out0, out1};
     const uint64_t *adds[2] = {add0, add1};
-    return moddown(c, w.acc, (int64_t)s.rows * s.N, 2, level, outs, adds, g_add, w.pc, w.conv, st);
+    return moddown(c, w.acc, acc_stride, 2, level, outs, adds, g_add, w.pc, w.conv, st, rowpass);
 }
 
 }  // namespace ckks

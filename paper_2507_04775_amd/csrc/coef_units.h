@@ -96,9 +96,31 @@ __device__ __forceinline__ void bconv_unit(const BconvArgs &a, uint32_t job, uin
 // would expose one HBM round trip per digit and block.
 constexpr uint32_t kIpStage = 4;
 
+// Where a unit's two reduced sums go: the accumulator rows by default, or the
+// caller's registers (RegStore: the inner product that also runs the first
+// inverse pass of ModDown's special rows).
+struct AccStore {
+    __device__ __forceinline__ void operator()(const IpArgs &a, uint32_t r, uint32_t n, uint64_t v0, uint64_t v1) const
+    {
+        const size_t N = (size_t)1 << a.logn;
+        a.acc[(size_t)r * N + n] = v0;
+        a.acc[((size_t)a.rows + r) * N + n] = v1;
+    }
+};
+struct RegStore {
+    uint64_t *v0, *v1;
+    __device__ __forceinline__ void operator()(const IpArgs &, uint32_t, uint32_t, uint64_t x0, uint64_t x1) const
+    {
+        *v0 = x0;
+        *v1 = x1;
+    }
+};
+
 // Row r of one key switch's inner product on block bx; stage holds
 // kIpStage * kCoefThreads words.
-__device__ __forceinline__ void ip_unit(const IpArgs &a, uint32_t r, uint32_t bx, uint64_t *stage, uint32_t tid)
+template <class Store = AccStore>
+__device__ __forceinline__ void ip_unit(const IpArgs &a, uint32_t r, uint32_t bx, uint64_t *stage, uint32_t tid,
+                                        Store store = Store())
 {
     const uint32_t N = 1u << a.logn;
     const uint32_t n = bx * kCoefThreads + tid;
@@ -160,8 +182,7 @@ __device__ __forceinline__ void ip_unit(const IpArgs &a, uint32_t r, uint32_t bx
         *t1 = a.fold_first ? v1 : addmod(*t1, v1, P.q);
         return;
     }
-    a.acc[(size_t)r * N + n] = reduce128(s0, P);
-    a.acc[((size_t)a.rows + r) * N + n] = reduce128(s1, P);
+    store(a, r, n, reduce128(s0, P), reduce128(s1, P));
 }
 
 // Blocks bx0 .. bx0 + nb - 1 of row r, software-pipelined when all digits fit
@@ -239,7 +260,9 @@ __device__ __forceinline__ void ip_blocks(const IpArgs &a, uint32_t r, uint32_t 
 // [P]_{q_r} d1 into half 1, d0 = a0 b0, d1 = a0 b1 + a1 b0, so that ModDown's
 // P^-1 (acc - Conv) leaves KS_t + d_t.  At most kMaxDigits + 1 products below
 // 2^122 each: the 128-bit sums are exact and reduced once.
-__device__ __forceinline__ void ip_unit_tensor(const IpArgs &a, uint32_t r, uint32_t bx, uint32_t tid)
+template <class Store = AccStore>
+__device__ __forceinline__ void ip_unit_tensor(const IpArgs &a, uint32_t r, uint32_t bx, uint32_t tid,
+                                               Store store = Store())
 {
     const uint32_t N = 1u << a.logn;
     const uint32_t n = bx * kCoefThreads + tid;
@@ -282,8 +305,7 @@ __device__ __forceinline__ void ip_unit_tensor(const IpArgs &a, uint32_t r, uint
         s0 = add128(s0, mul_wide(d0, pm));
         s1 = add128(s1, mul_wide(d1, pm));
     }
-    a.acc[(size_t)r * N + n] = reduce128(s0, P);
-    a.acc[((size_t)a.rows + r) * N + n] = reduce128(s1, P);
+    store(a, r, n, reduce128(s0, P), reduce128(s1, P));
 }
 
 // d0 = a0 b0, d1 = a0 b1 + a1 b0, d2 = a1 b1 (limb l under q_l)

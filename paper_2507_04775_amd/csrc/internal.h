@@ -383,7 +383,9 @@ uint32_t ntt_tiles(uint32_t logn);  // tiles per limb of the persistent passes
 constexpr uint32_t kMaxTileLimbs = 128;
 bool ntt_tile_set(uint32_t inverse, uint32_t nlimbs, uint32_t tile);
 uint32_t ntt_tile_get(uint32_t inverse, uint32_t nlimbs);
-hipError_t launch_ntt_stage(NttStage st, const NttArgs &a, uint32_t nlimbs, hipStream_t stream);
+// first_pass 1 (N = 2^16): the second pass only, the first pass's output already in a.mid
+hipError_t launch_ntt_stage(NttStage st, const NttArgs &a, uint32_t nlimbs, hipStream_t stream,
+                            uint32_t first_pass = 0);
 hipError_t launch_ntt_stage_queue(NttStage st, uint32_t logn, uint32_t pass, const NttArgs *insts,
                                   const WorkQueue &q, uint32_t grid, hipStream_t stream);
 hipError_t launch_bconv(const BconvArgs &a, uint32_t njobs, hipStream_t stream);
@@ -394,6 +396,10 @@ hipError_t launch_zero_u32(uint32_t *p, uint32_t n, hipStream_t stream);
 // The one-launch batch kernel (N = 2^16 only): `grid` workgroups of 512 threads.
 hipError_t launch_fused_batch(const FusedArgs &f, uint32_t grid, hipStream_t stream);
 hipError_t launch_inner_product(const IpArgs &a, hipStream_t stream);  // ta0 set: the tensor form
+// N = 2^16: the inner product of a key switch whose ModDown INTT is `ia` (args_moddown_intt over the
+// same accumulators), with that INTT's first pass on the special rows run by the same launch; the
+// INTT then runs with first_pass 1.  The special rows of ip.acc are not written.
+hipError_t launch_inner_product_rowpass(const IpArgs &ip, const NttArgs &ia, hipStream_t stream);
 hipError_t launch_tensor(const uint64_t *a0, const uint64_t *a1, const uint64_t *b0, const uint64_t *b1,
                          uint64_t *d0, uint64_t *d1, uint64_t *d2, const Prime *primes, uint32_t nlimbs,
                          uint32_t logn, hipStream_t stream);

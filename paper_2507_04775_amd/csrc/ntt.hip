@@ -880,18 +880,17 @@ __device__ __forceinline__ uint32_t row4_slot(uint32_t e)
 __device__ __forceinline__ uint32_t col4_slot(uint32_t e, uint32_t col) { return 8 * (e + (e >> 2)) + col; }
 constexpr int kLds4 = 8 * (255 + 63 + 1);
 
-template <class A>
-__device__ __forceinline__ void inv_row4_body(const NttArgs &a, const LimbPos &lp, const A &ar, uint64_t *lds,
-                                              uint32_t tile, uint32_t tx)
+// The rounds of one row: thread s < 64 of the row's wave, element loads
+// load(i) at position p4a(s, i), scratch L (256 words), output row m.
+template <class A, class Load>
+__device__ __forceinline__ void inv_row4_rounds(const A &ar, uint64_t *L, uint32_t s, uint32_t b, Load load,
+                                                uint64_t *m)
 {
-    const uint32_t blk = tx >> 6, s = tx & 63, b = tile * 8 + blk;
-    const uint64_t *src = a.src + (int64_t)lp.poly * a.map.src_poly_stride + (size_t)lp.row * 65536 + b * 256;
-    uint64_t *L = lds + blk * 256;
     typename A::W wa[3], wb[3];
     typename A::V v[4];
     tw_inv<2, 256, 1, A, true>(wa, p4a(s, 0), ar, 256 + b);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) v[i] = ar.from_u64(src[p4a(s, i)]);
+    for (int i = 0; i < 4; ++i) v[i] = ar.from_u64(load(i));
     ar.reduce_all(v);
     inv_rw<2>(v, wa, ar);
     tw_inv<2, 256, 4, A, true>(wb, p4b(s, 0), ar, 256 + b);
@@ -918,9 +917,18 @@ __device__ __forceinline__ void inv_row4_body(const NttArgs &a, const LimbPos &l
     for (int i = 0; i < 4; ++i) v[i] = ar.from_bits(L[row4_slot(p4d(s, i))]);
     ar.reduce_all(v);
     inv_rw<2>(v, wb, ar);
-    uint64_t *m = a.mid + (int64_t)lp.poly * a.mid_stride + (size_t)lp.row * 65536 + b * 256;
 #pragma unroll
     for (int i = 0; i < 4; ++i) m[p4d(s, i)] = ar.to_bits(v[i]);
+}
+
+template <class A>
+__device__ __forceinline__ void inv_row4_body(const NttArgs &a, const LimbPos &lp, const A &ar, uint64_t *lds,
+                                              uint32_t tile, uint32_t tx)
+{
+    const uint32_t blk = tx >> 6, s = tx & 63, b = tile * 8 + blk;
+    const uint64_t *src = a.src + (int64_t)lp.poly * a.map.src_poly_stride + (size_t)lp.row * 65536 + b * 256;
+    uint64_t *m = a.mid + (int64_t)lp.poly * a.mid_stride + (size_t)lp.row * 65536 + b * 256;
+    inv_row4_rounds(ar, lds + blk * 256, s, b, [&](int i) { return src[p4a(s, i)]; }, m);
 }
 
 template <class A>
@@ -1439,6 +1447,67 @@ struct StageKernels {
     QueueKernel queue;
 };
 
+// The key inner product (N = 2^16) with the first inverse pass of ModDown's
+// special rows run by the same workgroups (Sec. III-F.5: the inner product
+// feeds ModDown directly).  A block bx of 256 coefficients of a row is the
+// 256-point row problem b = bx of that row's inverse NTT, so a workgroup of a
+// special row reduces its two sums, stages them in LDS, and two of its waves
+// run the row pass (4 elements per thread) on them, writing the pass's output
+// where ModDown's INTT keeps it; the INTT then runs its column pass only.  The
+// special rows' accumulators never reach memory.  Their workgroups come first
+// in the launch, so their longer units overlap the q-rows' streaming instead
+// of forming its tail.  `ia` is ModDown's INTT (the rows p_0..p_{K-1} of both
+// accumulators, in that order).
+constexpr uint32_t kIpRowpassLds = coef::kIpStage * coef::kCoefThreads + 4 * 256;
+
+template <bool TENSOR>
+__device__ __forceinline__ void ip_rowpass_unit(const IpArgs &ip, const NttArgs &ia, uint32_t y, uint32_t bx,
+                                                uint64_t *lds, uint32_t tid)
+{
+    const uint32_t nqr = ip.level + 1, nsp = ip.rows - nqr;
+    const uint32_t r = y < nsp ? nqr + y : y - nsp;
+    if (r < nqr) {
+        if (TENSOR)
+            coef::ip_unit_tensor(ip, r, bx, tid);
+        else
+            coef::ip_unit(ip, r, bx, lds, tid);
+        return;
+    }
+    uint64_t v0, v1;
+    const coef::RegStore st{&v0, &v1};
+    if (TENSOR)
+        coef::ip_unit_tensor(ip, r, bx, tid, st);
+    else
+        coef::ip_unit(ip, r, bx, lds, tid, st);
+    uint64_t *in = lds + coef::kIpStage * coef::kCoefThreads;  // the two rows' inputs
+    in[tid] = v0;
+    in[coef::kCoefThreads + tid] = v1;
+    __syncthreads();
+    if (tid >= 128) return;
+    const uint32_t w = tid >> 6, s = tid & 63, k = r - nqr, prime = ip.nq + k;
+    const Prime P = ia.primes[prime];
+    const uint64_t *x = in + w * coef::kCoefThreads;
+    uint64_t *L = in + 2 * coef::kCoefThreads + w * 256;
+    uint64_t *m = ia.mid + (int64_t)w * ia.mid_stride + (size_t)k * 65536 + bx * 256;
+    auto load = [&](int i) { return x[p4a(s, i)]; };
+    if (P.q < kFpMaxPrime)
+        inv_row4_rounds(fp_arith(ia, P, prime, 65536), L, s, bx, load, m);
+    else
+        inv_row4_rounds(int_arith(ia, P, prime, 65536), L, s, bx, load, m);
+}
+
+__global__ __launch_bounds__(coef::kCoefThreads) void k_inner_product_rowpass(IpArgs ip, NttArgs ia)
+{
+    __shared__ uint64_t lds[kIpRowpassLds];
+    ip_rowpass_unit<false>(ip, ia, blockIdx.y, blockIdx.x, lds, threadIdx.x);
+}
+
+__global__ __launch_bounds__(coef::kCoefThreads) void k_inner_product_tensor_rowpass(IpArgs ip, NttArgs ia)
+{
+    __shared__ uint64_t lds[kIpRowpassLds];
+    ip_rowpass_unit<true>(ip, ia, blockIdx.y, blockIdx.x, lds, threadIdx.x);
+}
+
 // The kernel that runs one pass of a stage (pass 0 = first, 1 = second at N =
 // 2^16) with tiles of tw columns (rows); the narrow tiles have grid kernels only.
 bool stage_kernels(NttStage st, uint32_t logn, int pass, StageKernels &k, uint32_t tw = 16)
@@ -1557,14 +1626,15 @@ static uint32_t tile_width(NttStage st, uint32_t logn, uint32_t nlimbs)
     return inv && nlimbs <= 8 ? 2 : default_tile(nlimbs);
 }
 
-hipError_t launch_ntt_stage(NttStage st, const NttArgs &a0, uint32_t nlimbs, hipStream_t stream)
+hipError_t launch_ntt_stage(NttStage st, const NttArgs &a0, uint32_t nlimbs, hipStream_t stream, uint32_t first_pass)
 {
     if (nlimbs == 0) return hipSuccess;
+    if (first_pass >= ntt_passes(a0.logn)) return hipErrorInvalidValue;
     NttArgs a = a0;
     const uint32_t tw = effective_tile(st, tile_width(st, a.logn, nlimbs));
     if (tw == 16) set_heavy(a, nlimbs);
     else a.n_heavy = 0;
-    for (uint32_t pass = 0; pass < ntt_passes(a.logn); ++pass) {
+    for (uint32_t pass = first_pass; pass < ntt_passes(a.logn); ++pass) {
         StageKernels k;
         if (!stage_kernels(st, a.logn, pass, k, tw)) return hipErrorInvalidValue;
         const bool four = a.logn == 16 && four_element_pass(st, pass, tw);
@@ -1588,6 +1658,21 @@ bool ntt_tile_set(uint32_t inverse, uint32_t nlimbs, uint32_t tile)
 uint32_t ntt_tile_get(uint32_t inverse, uint32_t nlimbs)
 {
     return tile_width(inverse ? STAGE_INV_PLAIN : STAGE_FWD_PLAIN, 16, nlimbs);
+}
+
+hipError_t launch_inner_product_rowpass(const IpArgs &ip, const NttArgs &ia, hipStream_t stream)
+{
+    if (ip.logn != 16 || ia.logn != 16 || ip.fold_tot || ip.rows != ip.level + 1 + ip.np || ia.map.rows != ip.np ||
+        ia.ys_mode != 2 || !ia.mid)
+        return hipErrorInvalidValue;
+    const dim3 grid((1u << ip.logn) / coef::kCoefThreads, ip.rows);
+    if (ip.ta0) {
+        if (ip.galois != 1 || !ip.ta1 || !ip.tb0 || !ip.tb1 || !ip.pmod) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_inner_product_tensor_rowpass, grid, dim3(coef::kCoefThreads), 0, stream, ip, ia);
+    } else {
+        hipLaunchKernelGGL(k_inner_product_rowpass, grid, dim3(coef::kCoefThreads), 0, stream, ip, ia);
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_ntt_stage_queue(NttStage st, uint32_t logn, uint32_t pass, const NttArgs *insts,
