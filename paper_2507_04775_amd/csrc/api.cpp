@@ -575,12 +575,16 @@ extern "C" ckks_status ckks_hrotate_hoisted(ckks_ctx *ctx, const ckks_ct *in, ui
     KsWs w = ks_ws(ctx, level, ws);
     hipError_t e = modup_intt(ctx, in->c1, 1, level, w.dc, S(stream));
     if (e == hipSuccess) e = modup_from_coeffs(ctx, in->c1, 1, level, w.dc, w.ext, false, S(stream));
+    const int64_t acc_stride = (int64_t)s.rows * s.N;
+    const bool rowpass = ctx->logn == 16;  // the inner product runs the special rows' first INTT pass
     for (uint32_t i = 0; i < n && e == hipSuccess; ++i) {
-        e = inner_product(ctx, w.ext, level, keys[i]->data, gs[i], w.acc, S(stream), in->c1, gs[i]);
+        const IpArgs ip = args_ip(ctx, w.ext, level, keys[i]->data, gs[i], w.acc, in->c1, gs[i]);
+        e = rowpass ? launch_inner_product_rowpass(ip, args_moddown_intt(ctx, w.acc, acc_stride, level, w.pc), S(stream))
+                    : launch_inner_product(ip, S(stream));
         if (e != hipSuccess) break;
         uint64_t *outs[2] = {out[i].c0, out[i].c1};
         const uint64_t *adds[2] = {in->c0, nullptr};
-        e = moddown(ctx, w.acc, (int64_t)s.rows * s.N, 2, level, outs, adds, gs[i], w.pc, w.conv, S(stream));
+        e = moddown(ctx, w.acc, acc_stride, 2, level, outs, adds, gs[i], w.pc, w.conv, S(stream), rowpass);
     }
     TRY(dev(e, "ckks_hrotate_hoisted"));
     for (uint32_t i = 0; i < n; ++i) {
