@@ -270,8 +270,9 @@ def valu_fractions(probe):
             rate = waves * per / (us / 1e6)
             rows[name] = {"wave_instr_per_launch": waves * per, "avg_us": us,
                           "frac_of_issue_peak": round(rate / VALU_ISSUE_PEAK, 3)}
-    keep = ["k_fwd_col_bconv 8192x62x1", "k_inner_product 65536x35x1", "k_bconv 65536x3x5",
-            "k_fwd_row_moddown 8192x62x1", "k_fwd_col_plain 8192x74x1", "k_fwd_row_plain 8192x74x1"]
+    keep = ["k_fwd_col_bconv 8192x62x1", "k_inner_product 65536x35x1", "k_inner_product_tensor_rowpass 65536x35x1",
+            "k_inner_product_rowpass 65536x35x1", "k_bconv 65536x3x5", "k_fwd_row_moddown 8192x62x1",
+            "k_fwd_col_plain 8192x74x1", "k_fwd_row_plain 8192x74x1"]
     # the NTT passes appear under the tile width the autotuner chose (suffix _w8 or _w4 for 8 or 4)
     kernels = {}
     for k in keep:
