@@ -14,6 +14,9 @@ this library is measured on):
                  largest digit, so decryptions after key switching are meaningful).
 * ``large``    : N = 2^16, q = 1 x 60-bit + 30 x 50-bit, dnum = 3, K = 4.
 * ``large-nv`` : as ``large`` with K = 10.
+* ``large-fp`` : N = 2^16, q = 7 x 50-bit, K = 3 special primes of 50 bits, dnum = 3:
+                 every prime below 2^50, so every limb (the special ones
+                 included) takes the FP64 arithmetic.
 * ``boot-small``: N = 2^12, q = 1 x 60-bit + 20 x 50-bit, dnum = 3, K = 7: the
                  smallest set with room for a full-slot bootstrap (18 levels).
 """
@@ -134,6 +137,9 @@ def params(name: str) -> ParamSet:
         return make_params(16, 50, 30, 4, 3, 50, name)
     if name == "large-nv":
         return make_params(16, 50, 30, 10, 3, 50, name)
+    if name == "large-fp":
+        pr = ntt_primes(50, 10, 16)
+        return ParamSet(name=name, logn=16, q=pr[:7], p=pr[7:], dnum=3, log_scale=40)
     if name == "boot-small":
         return make_params(12, 50, 20, 7, 3, 50, name)
     if name == "tiny":  # N = 2^6, for brute-force pins

@@ -182,6 +182,41 @@ def test_hoisted_rotations(name):
         assert_equal(s.host(outs[i].c1), w1[i], "hoisted %d c1" % ks[i])
 
 
+def test_key_switching_with_every_prime_below_2_50():
+    """N = 2^16 with every prime below 2^50 (seven ciphertext primes, three
+    special ones): the special limbs take the FP64 arithmetic too, in the
+    inner product's run of ModDown's first INTT pass and in ModDown's
+    conversions, whose targets are all below 2^50 (split columns)."""
+    s = setup("large-fp")
+    assert all(q < 2 ** 50 for q in s.ps.q + s.ps.p) and len(set(s.ps.q + s.ps.p)) == 10
+    key, kh = s.key(300, 0)
+    g = oracle.galois_for_rotation(s.ps.logn, 3)
+    rkey, rkh = s.key(301, g)
+    for level in (6, 4, 0):
+        d = inputs.random_poly(310 + level, s.ps, level)
+        o0, o1 = s.ctx.empty_poly(level), s.ctx.empty_poly(level)
+        s.ctx.ckks_keyswitch(s.dev(d), level, kh, o0, o1)
+        w0, w1 = oracle.keyswitch(s.P, d, key, level)
+        assert_equal(s.host(o0), w0, "ks0 level %d" % level)
+        assert_equal(s.host(o1), w1, "ks1 level %d" % level)
+        a, ta = s.ct(320 + level, level)
+        b, tb = s.ct(330 + level, level)
+        out = s.ctx.empty_ct(level)
+        s.ctx.ckks_hmult_relin(ta, tb, kh, out)
+        w0, w1 = oracle.hmult_relin(s.P, a, b, key, level)
+        assert_equal(s.host(out.c0), w0, "hmult c0 level %d" % level)
+        assert_equal(s.host(out.c1), w1, "hmult c1 level %d" % level)
+        s.ctx.ckks_hrotate(ta, 3, rkh, out)
+        w0, w1 = oracle.apply_galois(s.P, a, g, rkey, level)
+        assert_equal(s.host(out.c0), w0, "rotate c0 level %d" % level)
+        assert_equal(s.host(out.c1), w1, "rotate c1 level %d" % level)
+        outs = [s.ctx.empty_ct(level)]
+        s.ctx.ckks_hrotate_hoisted(ta, [3], [rkh], outs)
+        w0, w1 = oracle.hoisted_rotate(s.P, a, [g], [rkey], level)
+        assert_equal(s.host(outs[0].c0), w0[0], "hoisted c0 level %d" % level)
+        assert_equal(s.host(outs[0].c1), w1[0], "hoisted c1 level %d" % level)
+
+
 def test_hoisted_rotations_ten_special_primes_all_levels():
     """Hoisted rotations with K = 10 (ten-source ModDown conversions, 41-row
     extended polynomials) at l = 30, 12 and 0."""
