@@ -161,6 +161,33 @@ def measured_ip_traffic():
         return None
 
 
+def step_inner_products():
+    """The timed step's inner products (the fused forms of k_inner_product that
+    HMult+relin and HRotate launch) from the committed counter and trace
+    summaries, while the kernel sources are the profiled ones (else None): their
+    algorithmic bytes, measured HBM bytes and profiled duration per launch."""
+    prof = os.path.join(ROOT, "profiles", "inner_product_logn16_l30_hbm_counters.md")
+    try:
+        lines = open(prof).read().splitlines()
+    except OSError:
+        return None
+    sha = next((l.split(":", 1)[1].strip() for l in lines if l.startswith("kernel_sources_sha256:")), None)
+    if sha != kernel_sources_sha256():
+        return None
+    out = []
+    for l in lines:
+        if not l.startswith("step_kernel:"):
+            continue
+        name, grid, *kv = l.split(":", 1)[1].split()
+        f = dict(x.split("=") for x in kv)
+        alg, us = int(f["algorithmic_bytes"]), float(f["avg_us"])
+        gbs = alg / (us / 1e6) / 1e9
+        out.append({"kernel": name, "grid": grid, "algorithmic_bytes_per_launch": alg,
+                    "traffic": int(f["traffic_bytes"]), "profiled_us": us, "achieved": round(gbs, 1),
+                    "frac": round(gbs / HBM_PEAK_GBS, 4), "source": os.path.relpath(prof, ROOT)})
+    return out or None
+
+
 def measured_traffic():
     """HBM bytes per launch of the roofline kernel, from the committed counter
     summary, valid only while the NTT sources (the kernel file and the headers
@@ -215,7 +242,8 @@ def inner_product_roofline(ctx, ps, seed, stream):
     gbs = nbytes / (us / 1e6) / 1e9
     return {"bound": "hbm", "kernel": "k_inner_product (key inner product, l = 30: 3 digits x 35 rows)",
             "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
-            "traffic": measured_ip_traffic(), "algorithmic_bytes_per_launch": nbytes, "launch_us": round(us, 2)}
+            "traffic": measured_ip_traffic(), "algorithmic_bytes_per_launch": nbytes, "launch_us": round(us, 2),
+            "step_kernels": step_inner_products()}
 
 
 def run_probe(stream):
