@@ -1451,8 +1451,8 @@ struct StageKernels {
 // special rows run by the same workgroups (Sec. III-F.5: the inner product
 // feeds ModDown directly).  A block bx of 256 coefficients of a row is the
 // 256-point row problem b = bx of that row's inverse NTT, so a workgroup of a
-// special row reduces its two sums, stages them in LDS, and two of its waves
-// run the row pass (4 elements per thread) on them, writing the pass's output
+// special row reduces its sums over two blocks, stages them in LDS, and its
+// four waves run the row passes (4 elements per thread), writing their output
 // where ModDown's INTT keeps it; the INTT then runs its column pass only.  The
 // special rows' accumulators never reach memory.  Their workgroups come first
 // in the launch, so their longer units overlap the q-rows' streaming instead
@@ -1473,27 +1473,34 @@ __device__ __forceinline__ void ip_rowpass_unit(const IpArgs &ip, const NttArgs 
             coef::ip_unit(ip, r, bx, lds, tid);
         return;
     }
-    uint64_t v0, v1;
-    const coef::RegStore st{&v0, &v1};
-    if (TENSOR)
-        coef::ip_unit_tensor(ip, r, bx, tid, st);
-    else
-        coef::ip_unit(ip, r, bx, lds, tid, st);
-    uint64_t *in = lds + coef::kIpStage * coef::kCoefThreads;  // the two rows' inputs
-    in[tid] = v0;
-    in[coef::kCoefThreads + tid] = v1;
+    // a special row: blocks 2 bx and 2 bx + 1 (the upper half of the grid row has no work), so
+    // that all four waves run a row pass (block 2 bx + w / 2, polynomial w % 2)
+    if (bx >= (1u << ip.logn) / (2 * coef::kCoefThreads)) return;
+    uint64_t v[4];
+#pragma unroll
+    for (uint32_t h = 0; h < 2; ++h) {
+        const coef::RegStore st{&v[2 * h], &v[2 * h + 1]};
+        if (TENSOR)
+            coef::ip_unit_tensor(ip, r, 2 * bx + h, tid, st);
+        else
+            coef::ip_unit(ip, r, 2 * bx + h, lds, tid, st);
+    }
+    // the four rows' inputs; after the barrier the staging area is the row passes' scratch
+    uint64_t *in = lds + coef::kIpStage * coef::kCoefThreads;
+#pragma unroll
+    for (uint32_t i = 0; i < 4; ++i) in[i * coef::kCoefThreads + tid] = v[i];
     __syncthreads();
-    if (tid >= 128) return;
     const uint32_t w = tid >> 6, s = tid & 63, k = r - nqr, prime = ip.nq + k;
+    const uint32_t poly = w & 1, b = 2 * bx + (w >> 1);
     const Prime P = ia.primes[prime];
-    const uint64_t *x = in + w * coef::kCoefThreads;
-    uint64_t *L = in + 2 * coef::kCoefThreads + w * 256;
-    uint64_t *m = ia.mid + (int64_t)w * ia.mid_stride + (size_t)k * 65536 + bx * 256;
+    const uint64_t *x = in + ((w >> 1) * 2 + poly) * coef::kCoefThreads;
+    uint64_t *L = lds + w * 256;
+    uint64_t *m = ia.mid + (int64_t)poly * ia.mid_stride + (size_t)k * 65536 + b * 256;
     auto load = [&](int i) { return x[p4a(s, i)]; };
     if (P.q < kFpMaxPrime)
-        inv_row4_rounds(fp_arith(ia, P, prime, 65536), L, s, bx, load, m);
+        inv_row4_rounds(fp_arith(ia, P, prime, 65536), L, s, b, load, m);
     else
-        inv_row4_rounds(int_arith(ia, P, prime, 65536), L, s, bx, load, m);
+        inv_row4_rounds(int_arith(ia, P, prime, 65536), L, s, b, load, m);
 }
 
 __global__ __launch_bounds__(coef::kCoefThreads) void k_inner_product_rowpass(IpArgs ip, NttArgs ia)
